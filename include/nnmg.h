@@ -1,0 +1,254 @@
+/*
+ * nnmg.h -- C ABI of the matrix-free non-nested multigrid library for gfx950.
+ *
+ * The library solves continuous Lagrange Q_k (k = 1..4) finite-element Poisson
+ * problems -Laplace(u) = f with homogeneous Dirichlet conditions on
+ * quadrilateral (d = 2) and hexahedral (d = 3) meshes, using a multigrid
+ * preconditioner whose levels are independent, non-nested meshes of the same
+ * domain (paper §2, "Non-nested multigrid method").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status: every int-returning call returns NNMG_OK (0) or a negative
+ *   NNMG_ERR_* code; nnmg_last_error() returns a thread-local message for the
+ *   last failure.  No C++ exception crosses this boundary.  Output handles are
+ *   written only on success; destroy(NULL) is a no-op.
+ * - Meshes are host arrays, copied during *_create.  Vertices: float64
+ *   [n_vertices][dim].  Cells: int32 [n_cells][2^dim]; local vertex b of a cell
+ *   sits at the reference corner whose coordinate along axis a is bit a of b
+ *   (x fastest).  Cells must be positively oriented.  dirichlet_vertex: uint8
+ *   [n_vertices] or NULL (no Dirichlet boundary).
+ * - A DoF is constrained (fixed to zero) iff it lies on the closure of a
+ *   boundary face whose vertices are all flagged Dirichlet.
+ * - Vectors are device pointers of length n_dofs (all DoFs, constrained
+ *   included) in the library's DoF numbering, contiguous, on the context's
+ *   device, float64 for NNMG_FP64 and float32 for NNMG_FP32.  Constrained
+ *   entries of right-hand sides and residuals must be zero.  Input and output
+ *   vectors of one call must not alias.
+ * - Streams are hipStream_t values passed as void* (NULL = default stream).
+ *   vmult, prolongate, restrict and vcycle are asynchronous on that stream;
+ *   *_create, pcg_solve and the query calls are synchronous.
+ * - A hierarchy is not re-entrant: calls on one hierarchy must not overlap.
+ *   Different hierarchies may run concurrently on different streams.
+ * - Transfers and hierarchies keep references to their levels, so handles may
+ *   be destroyed in any order.
+ */
+#ifndef NNMG_H
+#define NNMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    NNMG_OK = 0,
+    NNMG_ERR_INVALID_ARG = -1,     /* bad pointer, size, dimension or option */
+    NNMG_ERR_UNSUPPORTED = -2,     /* degree outside 1..4, dim outside 2..3 */
+    NNMG_ERR_OOM = -3,             /* a device allocation failed */
+    NNMG_ERR_MESH = -4,            /* invalid mesh (index range, inverted cell) */
+    NNMG_ERR_POINT_NOT_FOUND = -5, /* a fine point has no coarse owner cell */
+    NNMG_ERR_NOT_CONVERGED = -6,   /* CG hit max_it before the tolerance */
+    NNMG_ERR_BREAKDOWN = -7,       /* NaN or non-positive curvature in CG */
+    NNMG_ERR_HIP = -8              /* a HIP runtime call failed */
+};
+
+typedef enum { NNMG_FP64 = 0, NNMG_FP32 = 1 } nnmg_prec;
+
+typedef struct nnmg_ctx nnmg_ctx;
+typedef struct nnmg_level nnmg_level;
+typedef struct nnmg_transfer nnmg_transfer;
+typedef struct nnmg_hierarchy nnmg_hierarchy;
+
+/* Device memory provider.  alloc returns a device pointer of at least `bytes`
+ * bytes (256-byte aligned) or NULL; free releases it.  A NULL allocator in
+ * nnmg_ctx_create means hipMalloc / hipFree. */
+typedef struct {
+    void* user;
+    void* (*alloc)(void* user, size_t bytes, void* stream);
+    void (*free)(void* user, void* ptr, void* stream);
+} nnmg_allocator;
+
+typedef struct {
+    int dim;                         /* 2 or 3 */
+    int64_t n_vertices;
+    const double* vertices;          /* host [n_vertices][dim] */
+    int64_t n_cells;
+    const int32_t* cells;            /* host [n_cells][2^dim] */
+    const uint8_t* dirichlet_vertex; /* host [n_vertices] or NULL */
+} nnmg_mesh;
+
+/* Point location settings of nnmg_transfer_create (paper §3.1 and §3.3). */
+typedef struct {
+    double bbox_expand;   /* candidate cells: vertex bounding box grown on every side by
+                             bbox_expand times its diagonal (default 0.25) */
+    double inside_tol;    /* a pre-image within this max-norm distance of [0,1]^d is
+                             inside the cell (default 1e-10) */
+    double newton_tol;    /* Newton stops when the update's max-norm is <= this (1e-12) */
+    int newton_max_it;    /* Newton gives up after this many steps (default 50) */
+    int allow_projection; /* 1: points outside every candidate are projected onto the
+                             nearest candidate's reference cell (eq. closest_point);
+                             0: such points are an error (default 1) */
+} nnmg_transfer_opts;
+
+/* Multigrid settings of nnmg_hierarchy_create (paper §4 solver recipe). */
+typedef struct {
+    int cheb_degree;          /* Chebyshev degree per smoothing sweep (default 3) */
+    double smoothing_range;   /* interval [lambda_max / range, lambda_max] (default 20) */
+    double eig_safety;        /* lambda_max = safety * Lanczos estimate (default 1.2) */
+    int eig_iters;            /* Lanczos (Jacobi-CG) steps (default 12) */
+    const void* const* eig_start; /* NULL, or one entry per level (coarse -> fine): a float64
+                                     device vector [n_dofs] used as the Lanczos start vector,
+                                     or NULL for the library's seeded SplitMix64 vector */
+} nnmg_mg_opts;
+
+/* Settings of nnmg_pcg_solve. */
+typedef struct {
+    double rtol;            /* stop when ||r_k||_2 <= rtol ||b||_2 (default 1e-8) */
+    int max_it;             /* iteration limit (default 200) */
+    nnmg_prec vcycle_prec;  /* precision of the V-cycle preconditioner (default FP32) */
+    double* history;        /* host [max_it + 1] or NULL: ||r_k||_2 / ||b||_2, k = 0.. */
+} nnmg_cg_opts;
+
+typedef struct {
+    int iterations;  /* CG iterations performed */
+    double relres;   /* final ||r||_2 / ||b||_2 */
+    int status;      /* NNMG_OK, NNMG_ERR_NOT_CONVERGED or NNMG_ERR_BREAKDOWN */
+} nnmg_cg_result;
+
+/* ------------------------------------------------------------------------ */
+/* Context and error reporting                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Binds the library to HIP device `device`.  allocator may be NULL. */
+int nnmg_ctx_create(int device, const nnmg_allocator* allocator, nnmg_ctx** out);
+void nnmg_ctx_destroy(nnmg_ctx* ctx);
+/* Message of the last failing call on this thread ("" if none). */
+const char* nnmg_last_error(void);
+
+void nnmg_default_transfer_opts(nnmg_transfer_opts* opts);
+void nnmg_default_mg_opts(nnmg_mg_opts* opts);
+void nnmg_default_cg_opts(nnmg_cg_opts* opts);
+
+/* ------------------------------------------------------------------------ */
+/* Levels (paper §2: one mesh T_l and its space V_l with Q^p elements)       */
+/* ------------------------------------------------------------------------ */
+
+/* Sets up one level: DoF numbering (Gauss-Lobatto support points), the
+ * cell-to-DoF map, the constrained set, the geometry at the (k+1)^d Gauss
+ * points (paper §4) and the inverse Jacobi diagonal.  Synchronous.
+ * Errors: UNSUPPORTED (degree or dim), INVALID_ARG, MESH (vertex index out
+ * of range, repeated vertex in a cell, non-positive Jacobian at a Gauss
+ * point), OOM, HIP. */
+int nnmg_level_create(nnmg_ctx* ctx, const nnmg_mesh* mesh, int degree, nnmg_level** out);
+void nnmg_level_destroy(nnmg_level* level);
+
+int nnmg_level_info(const nnmg_level* level, int64_t* n_dofs, int64_t* n_free, int64_t* n_cells);
+
+/* Support point of every DoF: host [n_dofs][dim] (paper §2, eq. pointwise). */
+int nnmg_level_support_points(const nnmg_level* level, double* host_xyz);
+
+/* Constrained flag of every DoF: host uint8 [n_dofs]. */
+int nnmg_level_constrained(const nnmg_level* level, uint8_t* host_mask);
+
+/* Physical Gauss points: host [n_cells][(k+1)^dim][dim], cells in input order,
+ * points lexicographic (x fastest). */
+int nnmg_level_quadrature_points(const nnmg_level* level, double* host_xyz);
+
+/* b_i = sum over cells and Gauss points of f_q phi_i(x_q) |det J_q| w_q
+ * (paper §2: the load functional b(v) of eq. problem, with the Gauss rule of
+ * §4).  f_qp_dev: float64 device [n_cells][(k+1)^dim] values of f at the points
+ * of nnmg_level_quadrature_points.  b_dev is overwritten; its constrained
+ * entries are zero.  Asynchronous on `stream`. */
+int nnmg_level_assemble_rhs(nnmg_level* level, const double* f_qp_dev, double* b_dev, void* stream);
+
+/* dst = A_l src by sum factorisation (paper §3.2: tensor-product evaluation at
+ * Gauss points; the operator of eq. linear_system).  Constrained rows are the
+ * identity (dst_c = src_c); constrained entries of src do not enter the
+ * unconstrained rows.  src and dst must not alias.  Asynchronous. */
+int nnmg_vmult(const nnmg_level* level, nnmg_prec prec, const void* src_dev, void* dst_dev, void* stream);
+
+/* Diagonal of A_l (1 on constrained rows) into diag_dev.  Asynchronous. */
+int nnmg_level_diagonal(const nnmg_level* level, nnmg_prec prec, void* diag_dev, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Non-nested transfer between two levels (paper §2 eq. residual2; §3)        */
+/* ------------------------------------------------------------------------ */
+
+/* Locates every unconstrained fine support point in the coarse mesh: bucket
+ * grid over the grown coarse-cell boxes, Newton inversion of the trilinear
+ * cell map, owner = lowest-numbered cell containing the point, otherwise
+ * projection onto the nearest reference cell (eq. closest_point); stores the
+ * points grouped by owner cell with their clamped reference coordinates.
+ * opts may be NULL (defaults).  Synchronous (timed setup).
+ * Errors: INVALID_ARG (dim/device mismatch), POINT_NOT_FOUND, OOM, HIP. */
+int nnmg_transfer_create(nnmg_ctx* ctx, const nnmg_level* fine, const nnmg_level* coarse,
+                         const nnmg_transfer_opts* opts, nnmg_transfer** out);
+void nnmg_transfer_destroy(nnmg_transfer* transfer);
+
+/* Location results, in the order of the unconstrained fine DoFs:
+ * fine_dof_host int32 [n_points] (may be NULL), owner_host int32 [n_points]
+ * (may be NULL), xi_host float64 [n_points][dim] (may be NULL).  n_points and
+ * n_projected may be NULL. */
+int nnmg_transfer_points(const nnmg_transfer* transfer, int64_t* n_points, int32_t* fine_dof_host,
+                         int32_t* owner_host, double* xi_host, int64_t* n_projected);
+
+/* fine += P coarse, P_ij = phi_j^{coarse}(x_i) (paper §2 after eq. residual2;
+ * §3.2 eqs. local_evaluation and tensor_product_evaluation).  Only
+ * unconstrained fine entries change; constrained coarse entries are read as
+ * zero.  Asynchronous. */
+int nnmg_prolongate(const nnmg_transfer* transfer, nnmg_prec prec, const void* coarse_dev,
+                    void* fine_dev_add, void* stream);
+
+/* coarse += P^T fine (paper §2, eq. residual2), an atomic scatter-add.  Only
+ * unconstrained coarse entries change.  Asynchronous. */
+int nnmg_restrict(const nnmg_transfer* transfer, nnmg_prec prec, const void* fine_dev,
+                  void* coarse_dev_add, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Hierarchy, V-cycle and PCG (paper §2 Algorithm V_cycle; §4 recipe)          */
+/* ------------------------------------------------------------------------ */
+
+/* levels: n_levels handles, coarse -> fine; transfers: n_levels - 1 handles,
+ * transfers[i] between levels[i+1] (fine) and levels[i] (coarse).  Estimates
+ * the Chebyshev interval of every level above the coarsest (Jacobi-CG
+ * Lanczos), and factorises the coarsest operator into a dense float64
+ * inverse.  opts may be NULL.  Synchronous. */
+int nnmg_hierarchy_create(nnmg_ctx* ctx, nnmg_level* const* levels, int n_levels,
+                          nnmg_transfer* const* transfers, const nnmg_mg_opts* opts,
+                          nnmg_hierarchy** out);
+void nnmg_hierarchy_destroy(nnmg_hierarchy* hierarchy);
+
+int nnmg_get_cheb_bounds(const nnmg_hierarchy* h, int level, double* lo, double* hi);
+int nnmg_set_cheb_bounds(nnmg_hierarchy* h, int level, double lo, double hi);
+
+/* z = V(r): one V-cycle on the finest level with a zero initial guess
+ * (Algorithm V_cycle): Chebyshev-Jacobi pre-smoothing, residual, restriction,
+ * recursion, exact float64 coarse solve plus one refinement step,
+ * prolongation, post-smoothing from the current iterate.  r and z are vectors
+ * of the finest level in `prec`.  Asynchronous. */
+int nnmg_vcycle(nnmg_hierarchy* h, nnmg_prec prec, const void* r_dev, void* z_dev, void* stream);
+
+/* Float64 CG from x0 = 0 preconditioned by one V-cycle in opts->vcycle_prec
+ * (paper §4: V-cycle in single, CG in double precision).  b_dev and x_dev are
+ * float64 vectors of the finest level.  Synchronous.  Returns NNMG_OK,
+ * NNMG_ERR_NOT_CONVERGED or NNMG_ERR_BREAKDOWN (res->status says the same;
+ * x_dev then holds the last iterate). */
+int nnmg_pcg_solve(nnmg_hierarchy* h, const double* b_dev, double* x_dev, const nnmg_cg_opts* opts,
+                   nnmg_cg_result* res, void* stream);
+
+/* Per-component times: when enabled, every V-cycle records HIP events around
+ * its components.  nnmg_hierarchy_profile writes the accumulated milliseconds
+ * ms[level][c] (host [n_levels][6], levels coarse -> fine; c = pre-smoother,
+ * residual, restriction, coarse solve, prolongation, post-smoother) and
+ * resets the accumulators; it synchronises the hierarchy's last stream. */
+int nnmg_hierarchy_set_profiling(nnmg_hierarchy* h, int enabled);
+int nnmg_hierarchy_profile(nnmg_hierarchy* h, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNMG_H */

@@ -1,0 +1,12 @@
+"""Matrix-free non-nested multigrid for continuous Q_k elements on gfx950.
+
+The compute path is the HIP library ``libnnmg.so`` (C ABI in include/nnmg.h);
+this package only marshals arguments to it.  Importing the package fails if
+the library has not been built.
+"""
+
+from ._lib import NNMGError, lib  # noqa: F401
+
+lib()  # load now: no silent fallback when the HIP library is missing
+
+from .api import Context, Hierarchy, Level, Transfer  # noqa: E402,F401

@@ -1,0 +1,323 @@
+"""Python binding of libnnmg: argument marshalling only.
+
+Every computation runs in the HIP library.  PyTorch supplies device memory
+(vectors are CUDA/HIP tensors passed as raw pointers) and streams (the current
+torch stream is passed to every asynchronous call).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FP32, FP64, check, lib
+
+_DTYPE_PREC = {torch.float64: FP64, torch.float32: FP32}
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _vec(t: torch.Tensor, n: int, device: int, dtype=None, name="vector") -> C.c_void_p:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name} must live on cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if t.dtype not in _DTYPE_PREC:
+        raise ValueError(f"{name} must be float32 or float64")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Binds the library to one GPU.
+
+    With ``torch_allocator=True`` the library's persistent buffers come from
+    PyTorch's caching allocator; otherwise the library calls hipMalloc.
+    """
+
+    def __init__(self, device: int = 0, torch_allocator: bool = False):
+        self.device = int(device)
+        self._keep = []
+        alloc = None
+        if torch_allocator:
+            dev = self.device
+
+            def _alloc(user, nbytes, stream):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev)
+                except Exception:  # out of memory -> NULL -> NNMG_ERR_OOM
+                    return None
+
+            def _free(user, ptr, stream):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            af, ff = _lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free)
+            alloc = _lib.Allocator(None, af, ff)
+            self._keep = [af, ff, alloc]
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().nnmg_ctx_create(self.device, C.byref(alloc) if alloc is not None else None, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nnmg_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Level:
+    """One mesh level and its Q_k space (nnmg_level_create)."""
+
+    def __init__(self, ctx: Context, vertices, cells, dirichlet=None, degree: int = 1):
+        self.ctx = ctx
+        v = np.ascontiguousarray(vertices, dtype=np.float64)
+        c = np.ascontiguousarray(cells, dtype=np.int32)
+        d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        if v.ndim != 2 or c.ndim != 2 or c.shape[1] != 2 ** v.shape[1]:
+            raise ValueError("vertices must be [V, dim] and cells [C, 2^dim]")
+        if d is not None and d.shape != (v.shape[0],):
+            raise ValueError("dirichlet must have one flag per vertex")
+        mesh = _lib.Mesh(
+            v.shape[1], v.shape[0], v.ctypes.data_as(C.POINTER(C.c_double)), c.shape[0],
+            c.ctypes.data_as(C.POINTER(C.c_int32)),
+            d.ctypes.data_as(C.POINTER(C.c_uint8)) if d is not None else None)
+        h = C.c_void_p()
+        with torch.cuda.device(ctx.device):
+            check(lib().nnmg_level_create(ctx.handle, C.byref(mesh), int(degree), C.byref(h)))
+        self.handle = h
+        self.dim = int(v.shape[1])
+        self.degree = int(degree)
+        nd, nf, nc = C.c_int64(), C.c_int64(), C.c_int64()
+        check(lib().nnmg_level_info(h, C.byref(nd), C.byref(nf), C.byref(nc)))
+        self.n_dofs, self.n_free, self.n_cells = nd.value, nf.value, nc.value
+
+    @classmethod
+    def from_mesh(cls, ctx: Context, mesh, degree: int):
+        return cls(ctx, mesh.vertices, mesh.cells, mesh.dirichlet, degree)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nnmg_level_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- host queries ---------------------------------------------------------
+    def support_points(self) -> np.ndarray:
+        out = np.empty((self.n_dofs, self.dim), dtype=np.float64)
+        check(lib().nnmg_level_support_points(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def constrained(self) -> np.ndarray:
+        out = np.empty(self.n_dofs, dtype=np.uint8)
+        check(lib().nnmg_level_constrained(self.handle, out.ctypes.data_as(C.POINTER(C.c_uint8))))
+        return out.astype(bool)
+
+    def quadrature_points(self) -> np.ndarray:
+        q = (self.degree + 1) ** self.dim
+        out = np.empty((self.n_cells, q, self.dim), dtype=np.float64)
+        check(lib().nnmg_level_quadrature_points(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    # -- device operations ----------------------------------------------------
+    def empty(self, dtype=torch.float64) -> torch.Tensor:
+        return torch.zeros(self.n_dofs, dtype=dtype, device=f"cuda:{self.ctx.device}")
+
+    def assemble_rhs(self, f_qp: torch.Tensor, b: torch.Tensor | None = None) -> torch.Tensor:
+        q = (self.degree + 1) ** self.dim
+        fq = _vec(f_qp, self.n_cells * q, self.ctx.device, torch.float64, "f_qp")
+        b = self.empty(torch.float64) if b is None else b
+        check(lib().nnmg_level_assemble_rhs(self.handle, fq, _vec(b, self.n_dofs, self.ctx.device,
+                                                                   torch.float64, "b"), _stream()))
+        return b
+
+    def vmult(self, src: torch.Tensor, dst: torch.Tensor | None = None) -> torch.Tensor:
+        dst = torch.empty_like(src) if dst is None else dst
+        if dst.dtype != src.dtype:
+            raise ValueError("src and dst must have the same dtype")
+        s = _vec(src, self.n_dofs, self.ctx.device, name="src")
+        d = _vec(dst, self.n_dofs, self.ctx.device, name="dst")
+        check(lib().nnmg_vmult(self.handle, _DTYPE_PREC[src.dtype], s, d, _stream()))
+        return dst
+
+    def diagonal(self, dtype=torch.float64) -> torch.Tensor:
+        out = self.empty(dtype)
+        check(lib().nnmg_level_diagonal(self.handle, _DTYPE_PREC[dtype], _vec(out, self.n_dofs, self.ctx.device),
+                                        _stream()))
+        return out
+
+
+class Transfer:
+    """Non-nested transfer between a fine and a coarse level (nnmg_transfer_create)."""
+
+    def __init__(self, ctx: Context, fine: Level, coarse: Level, bbox_expand=None, inside_tol=None,
+                 newton_tol=None, newton_max_it=None, allow_projection=None):
+        self.ctx, self.fine, self.coarse = ctx, fine, coarse
+        o = _lib.TransferOpts()
+        lib().nnmg_default_transfer_opts(C.byref(o))
+        for name, val in (("bbox_expand", bbox_expand), ("inside_tol", inside_tol), ("newton_tol", newton_tol),
+                          ("newton_max_it", newton_max_it), ("allow_projection", allow_projection)):
+            if val is not None:
+                setattr(o, name, type(getattr(o, name))(val))
+        h = C.c_void_p()
+        with torch.cuda.device(ctx.device):
+            check(lib().nnmg_transfer_create(ctx.handle, fine.handle, coarse.handle, C.byref(o), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nnmg_transfer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def points(self) -> dict:
+        n, npj = C.c_int64(), C.c_int64()
+        check(lib().nnmg_transfer_points(self.handle, C.byref(n), None, None, None, C.byref(npj)))
+        dof = np.empty(n.value, dtype=np.int32)
+        own = np.empty(n.value, dtype=np.int32)
+        xi = np.empty((n.value, self.fine.dim), dtype=np.float64)
+        check(lib().nnmg_transfer_points(self.handle, None, dof.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         own.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         xi.ctypes.data_as(C.POINTER(C.c_double)), None))
+        return dict(fine_dof=dof, owner=own, xi=xi, n_projected=npj.value)
+
+    def prolongate(self, coarse_vec: torch.Tensor, fine_vec: torch.Tensor) -> torch.Tensor:
+        """fine_vec += P coarse_vec."""
+        if coarse_vec.dtype != fine_vec.dtype:
+            raise ValueError("dtype mismatch")
+        check(lib().nnmg_prolongate(self.handle, _DTYPE_PREC[coarse_vec.dtype],
+                                    _vec(coarse_vec, self.coarse.n_dofs, self.ctx.device, name="coarse"),
+                                    _vec(fine_vec, self.fine.n_dofs, self.ctx.device, name="fine"), _stream()))
+        return fine_vec
+
+    def restrict(self, fine_vec: torch.Tensor, coarse_vec: torch.Tensor) -> torch.Tensor:
+        """coarse_vec += P^T fine_vec."""
+        if coarse_vec.dtype != fine_vec.dtype:
+            raise ValueError("dtype mismatch")
+        check(lib().nnmg_restrict(self.handle, _DTYPE_PREC[fine_vec.dtype],
+                                  _vec(fine_vec, self.fine.n_dofs, self.ctx.device, name="fine"),
+                                  _vec(coarse_vec, self.coarse.n_dofs, self.ctx.device, name="coarse"), _stream()))
+        return coarse_vec
+
+
+class Hierarchy:
+    """Levels coarse -> fine and the transfers between them (nnmg_hierarchy_create)."""
+
+    COMPONENTS = ("pre_smoother", "residual", "restriction", "coarse_solve", "prolongation", "post_smoother")
+
+    def __init__(self, ctx: Context, levels, transfers, eig_start=None, cheb_degree=None, smoothing_range=None,
+                 eig_safety=None, eig_iters=None):
+        self.ctx = ctx
+        self.levels = list(levels)
+        self.transfers = list(transfers)
+        L = len(self.levels)
+        o = _lib.MgOpts()
+        lib().nnmg_default_mg_opts(C.byref(o))
+        for name, val in (("cheb_degree", cheb_degree), ("smoothing_range", smoothing_range),
+                          ("eig_safety", eig_safety), ("eig_iters", eig_iters)):
+            if val is not None:
+                setattr(o, name, type(getattr(o, name))(val))
+        starts = None
+        if eig_start is not None:
+            if len(eig_start) != L:
+                raise ValueError("eig_start needs one entry per level")
+            ptrs = []
+            for lv, v in zip(self.levels, eig_start):
+                ptrs.append(None if v is None else _vec(v, lv.n_dofs, ctx.device, torch.float64, "eig_start").value)
+            starts = (C.c_void_p * L)(*ptrs)
+            o.eig_start = C.cast(starts, C.POINTER(C.c_void_p))
+        lv = (C.c_void_p * L)(*[l.handle.value for l in self.levels])
+        tr = (C.c_void_p * max(L - 1, 1))(*[t.handle.value for t in self.transfers])
+        h = C.c_void_p()
+        with torch.cuda.device(ctx.device):
+            torch.cuda.synchronize(ctx.device)
+            check(lib().nnmg_hierarchy_create(ctx.handle, lv, L, tr, C.byref(o), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nnmg_hierarchy_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def fine(self) -> Level:
+        return self.levels[-1]
+
+    def cheb_bounds(self, level: int):
+        lo, hi = C.c_double(), C.c_double()
+        check(lib().nnmg_get_cheb_bounds(self.handle, int(level), C.byref(lo), C.byref(hi)))
+        return lo.value, hi.value
+
+    def set_cheb_bounds(self, level: int, lo: float, hi: float):
+        check(lib().nnmg_set_cheb_bounds(self.handle, int(level), float(lo), float(hi)))
+
+    def vcycle(self, r: torch.Tensor, z: torch.Tensor | None = None) -> torch.Tensor:
+        z = torch.empty_like(r) if z is None else z
+        if z.dtype != r.dtype:
+            raise ValueError("dtype mismatch")
+        n = self.fine.n_dofs
+        check(lib().nnmg_vcycle(self.handle, _DTYPE_PREC[r.dtype], _vec(r, n, self.ctx.device, name="r"),
+                                _vec(z, n, self.ctx.device, name="z"), _stream()))
+        return z
+
+    def pcg_solve(self, b: torch.Tensor, x: torch.Tensor | None = None, rtol: float = 1e-8, max_it: int = 200,
+                  vcycle_dtype=torch.float32, history: bool = True, raise_on_failure: bool = True):
+        n = self.fine.n_dofs
+        x = torch.empty_like(b) if x is None else x
+        o = _lib.CgOpts()
+        lib().nnmg_default_cg_opts(C.byref(o))
+        o.rtol = float(rtol)
+        o.max_it = int(max_it)
+        o.vcycle_prec = _DTYPE_PREC[vcycle_dtype]
+        hist = np.full(max_it + 1, np.nan) if history else None
+        o.history = hist.ctypes.data_as(C.POINTER(C.c_double)) if history else None
+        res = _lib.CgResult()
+        code = lib().nnmg_pcg_solve(self.handle, _vec(b, n, self.ctx.device, torch.float64, "b"),
+                                    _vec(x, n, self.ctx.device, torch.float64, "x"), C.byref(o), C.byref(res),
+                                    _stream())
+        info = dict(iterations=res.iterations, relres=res.relres, status=_lib.ERRORS.get(res.status, "OK")
+                    if res.status else "OK")
+        if history:
+            info["history"] = hist[: res.iterations + 1].copy()
+        if code != 0 and raise_on_failure:
+            check(code)
+        return x, info
+
+    def set_profiling(self, enabled: bool):
+        check(lib().nnmg_hierarchy_set_profiling(self.handle, int(bool(enabled))))
+
+    def profile(self) -> np.ndarray:
+        out = np.zeros((len(self.levels), 6), dtype=np.float64)
+        check(lib().nnmg_hierarchy_profile(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out

@@ -1,0 +1,344 @@
+// The extern "C" boundary: argument checks, error codes and the thread-local
+// error message.  No C++ exception crosses this file.
+#include <cstring>
+#include <new>
+
+#include "../internal.hpp"
+
+namespace nnmg {
+
+Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree);
+void level_diagonal(const Level& L, int prec, void* out, hipStream_t s);
+void level_quadrature_points(const Level& L, double* out);
+Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_transfer_opts& o);
+struct Hierarchy;
+Hierarchy* hierarchy_create(Ctx* ctx, nnmg_level* const* levels, int nl, nnmg_transfer* const* transfers,
+                            const nnmg_mg_opts& o);
+void hierarchy_destroy(Hierarchy* h);
+void get_bounds(const Hierarchy& H, int l, double* lo, double* hi);
+void set_bounds(Hierarchy& H, int l, double lo, double hi);
+void vcycle(Hierarchy& H, int prec, const void* r, void* z, hipStream_t s);
+int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg_result* res, hipStream_t s);
+void set_profiling(Hierarchy& H, bool on);
+void profile(Hierarchy& H, double* ms);
+
+namespace {
+thread_local std::string g_last_error;
+
+int report(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error& e) {
+        return report(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+        return report(NNMG_ERR_OOM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return report(NNMG_ERR_INVALID_ARG, e.what());
+    } catch (...) {
+        return report(NNMG_ERR_INVALID_ARG, "unknown error");
+    }
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void* Ctx::allocate(size_t bytes) {
+    if (bytes == 0) return nullptr;
+    void* p = nullptr;
+    if (custom) {
+        p = alloc.alloc(alloc.user, bytes, nullptr);
+        if (!p) fail(NNMG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    } else {
+        if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            fail(NNMG_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
+    }
+    return p;
+}
+
+void Ctx::release(void* p) {
+    if (!p) return;
+    if (custom)
+        alloc.free(alloc.user, p, nullptr);
+    else
+        (void)hipFree(p);
+}
+
+}  // namespace nnmg
+
+using namespace nnmg;
+
+struct nnmg_hierarchy;
+
+extern "C" {
+
+const char* nnmg_last_error(void) { return g_last_error.c_str(); }
+
+void nnmg_default_transfer_opts(nnmg_transfer_opts* o) {
+    if (!o) return;
+    o->bbox_expand = 0.25;
+    o->inside_tol = 1e-10;
+    o->newton_tol = 1e-12;
+    o->newton_max_it = 50;
+    o->allow_projection = 1;
+}
+
+void nnmg_default_mg_opts(nnmg_mg_opts* o) {
+    if (!o) return;
+    o->cheb_degree = 3;
+    o->smoothing_range = 20.0;
+    o->eig_safety = 1.2;
+    o->eig_iters = 12;
+    o->eig_start = nullptr;
+}
+
+void nnmg_default_cg_opts(nnmg_cg_opts* o) {
+    if (!o) return;
+    o->rtol = 1e-8;
+    o->max_it = 200;
+    o->vcycle_prec = NNMG_FP32;
+    o->history = nullptr;
+}
+
+int nnmg_ctx_create(int device, const nnmg_allocator* allocator, nnmg_ctx** out) {
+    return guarded([&] {
+        if (!out) fail(NNMG_ERR_INVALID_ARG, "out is NULL");
+        int count = 0;
+        NNMG_HIP(hipGetDeviceCount(&count));
+        if (device < 0 || device >= count) fail(NNMG_ERR_INVALID_ARG, "no such device");
+        if (allocator && (!allocator->alloc || !allocator->free))
+            fail(NNMG_ERR_INVALID_ARG, "allocator needs both alloc and free");
+        NNMG_HIP(hipSetDevice(device));
+        auto* c = new nnmg_ctx();
+        c->device = device;
+        if (allocator) {
+            c->alloc = *allocator;
+            c->custom = true;
+        }
+        *out = c;
+        return NNMG_OK;
+    });
+}
+
+void nnmg_ctx_destroy(nnmg_ctx* ctx) { delete ctx; }
+
+int nnmg_level_create(nnmg_ctx* ctx, const nnmg_mesh* mesh, int degree, nnmg_level** out) {
+    return guarded([&] {
+        if (!ctx || !out) fail(NNMG_ERR_INVALID_ARG, "ctx or out is NULL");
+        NNMG_HIP(hipSetDevice(ctx->device));
+        *out = static_cast<nnmg_level*>(level_create(ctx, mesh, degree));
+        return NNMG_OK;
+    });
+}
+
+void nnmg_level_destroy(nnmg_level* level) {
+    if (level) level_release(level);
+}
+
+int nnmg_level_info(const nnmg_level* l, int64_t* n_dofs, int64_t* n_free, int64_t* n_cells) {
+    return guarded([&] {
+        if (!l) fail(NNMG_ERR_INVALID_ARG, "level is NULL");
+        if (n_dofs) *n_dofs = l->n_dofs;
+        if (n_free) *n_free = l->n_free;
+        if (n_cells) *n_cells = l->n_cells;
+        return NNMG_OK;
+    });
+}
+
+int nnmg_level_support_points(const nnmg_level* l, double* xyz) {
+    return guarded([&] {
+        if (!l || !xyz) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        std::memcpy(xyz, l->support.data(), l->support.size() * sizeof(double));
+        return NNMG_OK;
+    });
+}
+
+int nnmg_level_constrained(const nnmg_level* l, uint8_t* mask) {
+    return guarded([&] {
+        if (!l || !mask) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        std::memcpy(mask, l->constrained.data(), l->constrained.size());
+        return NNMG_OK;
+    });
+}
+
+int nnmg_level_quadrature_points(const nnmg_level* l, double* xyz) {
+    return guarded([&] {
+        if (!l || !xyz) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        level_quadrature_points(*l, xyz);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_level_assemble_rhs(nnmg_level* l, const double* fq, double* b, void* stream) {
+    return guarded([&] {
+        if (!l || !fq || !b) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        NNMG_HIP(hipSetDevice(l->ctx->device));
+        launch_fill(b, (size_t)l->n_dofs, NNMG_FP64, as_stream(stream));
+        launch_assemble_rhs(*l, fq, b, as_stream(stream));
+        return NNMG_OK;
+    });
+}
+
+int nnmg_vmult(const nnmg_level* l, nnmg_prec prec, const void* src, void* dst, void* stream) {
+    return guarded([&] {
+        if (!l || !src || !dst) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (src == dst) fail(NNMG_ERR_INVALID_ARG, "src and dst alias");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        NNMG_HIP(hipSetDevice(l->ctx->device));
+        const hipStream_t s = as_stream(stream);
+        launch_fill(dst, (size_t)l->n_dofs, prec, s);
+        launch_vmult_cells(*l, prec, src, dst, s);
+        launch_copy_constrained(l->d_constrained.ptr, l->constrained_idx.size(), src, dst, prec, s);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_level_diagonal(const nnmg_level* l, nnmg_prec prec, void* diag, void* stream) {
+    return guarded([&] {
+        if (!l || !diag) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        NNMG_HIP(hipSetDevice(l->ctx->device));
+        level_diagonal(*l, prec, diag, as_stream(stream));
+        return NNMG_OK;
+    });
+}
+
+int nnmg_transfer_create(nnmg_ctx* ctx, const nnmg_level* fine, const nnmg_level* coarse,
+                         const nnmg_transfer_opts* opts, nnmg_transfer** out) {
+    return guarded([&] {
+        if (!ctx || !out) fail(NNMG_ERR_INVALID_ARG, "ctx or out is NULL");
+        nnmg_transfer_opts o;
+        nnmg_default_transfer_opts(&o);
+        if (opts) o = *opts;
+        NNMG_HIP(hipSetDevice(ctx->device));
+        *out = static_cast<nnmg_transfer*>(
+            transfer_create(ctx, const_cast<nnmg_level*>(fine), const_cast<nnmg_level*>(coarse), o));
+        return NNMG_OK;
+    });
+}
+
+void nnmg_transfer_destroy(nnmg_transfer* t) {
+    if (t) transfer_release(t);
+}
+
+int nnmg_transfer_points(const nnmg_transfer* t, int64_t* n_points, int32_t* fine_dof, int32_t* owner, double* xi,
+                         int64_t* n_projected) {
+    return guarded([&] {
+        if (!t) fail(NNMG_ERR_INVALID_ARG, "transfer is NULL");
+        if (n_points) *n_points = t->n_points;
+        if (n_projected) *n_projected = t->n_projected;
+        if (fine_dof) std::memcpy(fine_dof, t->h_point_dof.data(), t->h_point_dof.size() * sizeof(int32_t));
+        if (owner) std::memcpy(owner, t->h_point_owner.data(), t->h_point_owner.size() * sizeof(int32_t));
+        if (xi) std::memcpy(xi, t->h_point_xi.data(), t->h_point_xi.size() * sizeof(double));
+        return NNMG_OK;
+    });
+}
+
+int nnmg_prolongate(const nnmg_transfer* t, nnmg_prec prec, const void* coarse, void* fine, void* stream) {
+    return guarded([&] {
+        if (!t || !coarse || !fine) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (coarse == fine) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        NNMG_HIP(hipSetDevice(t->ctx->device));
+        launch_prolongate(*t, prec, coarse, fine, as_stream(stream));
+        return NNMG_OK;
+    });
+}
+
+int nnmg_restrict(const nnmg_transfer* t, nnmg_prec prec, const void* fine, void* coarse, void* stream) {
+    return guarded([&] {
+        if (!t || !coarse || !fine) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (coarse == fine) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        NNMG_HIP(hipSetDevice(t->ctx->device));
+        launch_restrict(*t, prec, fine, coarse, as_stream(stream));
+        return NNMG_OK;
+    });
+}
+
+int nnmg_hierarchy_create(nnmg_ctx* ctx, nnmg_level* const* levels, int n_levels, nnmg_transfer* const* transfers,
+                          const nnmg_mg_opts* opts, nnmg_hierarchy** out) {
+    return guarded([&] {
+        if (!ctx || !out) fail(NNMG_ERR_INVALID_ARG, "ctx or out is NULL");
+        nnmg_mg_opts o;
+        nnmg_default_mg_opts(&o);
+        if (opts) o = *opts;
+        NNMG_HIP(hipSetDevice(ctx->device));
+        *out = reinterpret_cast<nnmg_hierarchy*>(hierarchy_create(ctx, levels, n_levels, transfers, o));
+        return NNMG_OK;
+    });
+}
+
+void nnmg_hierarchy_destroy(nnmg_hierarchy* h) {
+    if (h) hierarchy_destroy(reinterpret_cast<Hierarchy*>(h));
+}
+
+int nnmg_get_cheb_bounds(const nnmg_hierarchy* h, int level, double* lo, double* hi) {
+    return guarded([&] {
+        if (!h) fail(NNMG_ERR_INVALID_ARG, "hierarchy is NULL");
+        get_bounds(*reinterpret_cast<const Hierarchy*>(h), level, lo, hi);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_set_cheb_bounds(nnmg_hierarchy* h, int level, double lo, double hi) {
+    return guarded([&] {
+        if (!h) fail(NNMG_ERR_INVALID_ARG, "hierarchy is NULL");
+        set_bounds(*reinterpret_cast<Hierarchy*>(h), level, lo, hi);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_vcycle(nnmg_hierarchy* h, nnmg_prec prec, const void* r, void* z, void* stream) {
+    return guarded([&] {
+        if (!h || !r || !z) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (r == z) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        vcycle(*reinterpret_cast<Hierarchy*>(h), prec, r, z, as_stream(stream));
+        return NNMG_OK;
+    });
+}
+
+int nnmg_pcg_solve(nnmg_hierarchy* h, const double* b, double* x, const nnmg_cg_opts* opts, nnmg_cg_result* res,
+                   void* stream) {
+    return guarded([&] {
+        if (!h || !b || !x || !res) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (b == x) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
+        nnmg_cg_opts o;
+        nnmg_default_cg_opts(&o);
+        if (opts) o = *opts;
+        const int st = pcg(*reinterpret_cast<Hierarchy*>(h), b, x, o, res, as_stream(stream));
+        if (st == NNMG_ERR_NOT_CONVERGED) report(st, "CG reached max_it before the tolerance");
+        if (st == NNMG_ERR_BREAKDOWN) report(st, "CG breakdown (non-positive curvature or NaN)");
+        return st;
+    });
+}
+
+int nnmg_hierarchy_set_profiling(nnmg_hierarchy* h, int enabled) {
+    return guarded([&] {
+        if (!h) fail(NNMG_ERR_INVALID_ARG, "hierarchy is NULL");
+        set_profiling(*reinterpret_cast<Hierarchy*>(h), enabled != 0);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_hierarchy_profile(nnmg_hierarchy* h, double* ms) {
+    return guarded([&] {
+        if (!h || !ms) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        profile(*reinterpret_cast<Hierarchy*>(h), ms);
+        return NNMG_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,516 @@
+// Multigrid hierarchy: Chebyshev-Jacobi smoothing, the non-nested V-cycle of
+// Algorithm V_cycle (paper §2), the exact float64 coarse solve and the float64
+// preconditioned CG of the paper's solver recipe (§4).
+//
+// V-cycle on level l >= 1 with right-hand side f and zero initial guess:
+//   x   <- Chebyshev sweep from 0          (degree-1 operator products)
+//   r   <- f - A x
+//   f_c <- P^T r                           (restriction, paper eq. residual2)
+//   x_c <- V-cycle(l-1, f_c)
+//   x   <- x + P x_c                       (prolongation)
+//   x   <- Chebyshev sweep from x          (degree operator products)
+// The post-smoother starts from the current iterate (Algorithm V_cycle writes
+// a zero initial guess there, which would discard the correction).  On level 0
+// the coarse problem is solved with the explicit inverse of the unconstrained
+// block plus one step of iterative refinement, always in float64.
+//
+// The Chebyshev sweep is the three-term recurrence on D^{-1} A over
+// [lambda_max / range, lambda_max] (Saad, Alg. 12.1), with the residual
+// recomputed as f - A x at every step; lambda_max is eig_safety times the
+// largest Ritz value of eig_iters steps of Jacobi-preconditioned CG (Lanczos).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "../internal.hpp"
+
+namespace nnmg {
+
+
+enum { kPre = 0, kRes = 1, kRestrict = 2, kCoarse = 3, kProlong = 4, kPost = 5, kComponents = 6 };
+
+struct WorkVectors {
+    DeviceArray<char> f, x, d, ax, r;
+};
+
+struct ProfileRecord {
+    int level, comp;
+    hipEvent_t a, b;
+};
+
+struct Hierarchy {
+    Ctx* ctx = nullptr;
+    std::vector<Level*> levels;
+    std::vector<Transfer*> transfers;
+    nnmg_mg_opts opts{};
+    std::vector<double> lo, hi;
+
+    // coarse solve
+    int64_t m = 0;
+    DeviceArray<int32_t> free_idx;
+    DeviceArray<double> inv, bf, xf, yf, cx, cax, cr, cf;
+
+    WorkVectors work[2][16];  // [prec][level]
+
+    // CG
+    DeviceArray<double> r, p, qv, z, partial, scal;
+    double* hscal = nullptr;  // pinned
+
+    bool profiling = false;
+    std::vector<ProfileRecord> records;
+    std::vector<hipEvent_t> pool;
+    std::vector<double> acc;
+    hipStream_t last = nullptr;
+
+    ~Hierarchy() {
+        for (auto& rec : records) {
+            (void)hipEventDestroy(rec.a);
+            (void)hipEventDestroy(rec.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+        if (hscal) (void)hipHostFree(hscal);
+        for (auto* t : transfers) transfer_release(t);
+        for (auto* l : levels) level_release(l);
+    }
+};
+
+}  // namespace nnmg
+
+struct nnmg_hierarchy : nnmg::Hierarchy {};
+
+namespace nnmg {
+
+static size_t wsize(int prec) { return prec == NNMG_FP64 ? 8 : 4; }
+
+static void alloc_work(Hierarchy& H, int prec) {
+    for (size_t l = 0; l < H.levels.size(); ++l) {
+        WorkVectors& w = H.work[prec][l];
+        if (w.f.ptr || H.levels[l]->n_dofs == 0) continue;
+        const size_t b = (size_t)H.levels[l]->n_dofs * wsize(prec);
+        w.f.alloc(H.ctx, b);
+        w.x.alloc(H.ctx, b);
+        w.d.alloc(H.ctx, b);
+        w.ax.alloc(H.ctx, b);
+        w.r.alloc(H.ctx, b);
+        for (auto* a : {&w.f, &w.x, &w.d, &w.ax, &w.r}) NNMG_HIP(hipMemset(a->ptr, 0, b));
+    }
+}
+
+static hipEvent_t take_event(Hierarchy& H) {
+    if (!H.pool.empty()) {
+        hipEvent_t e = H.pool.back();
+        H.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    NNMG_HIP(hipEventCreate(&e));
+    return e;
+}
+
+struct Scope {
+    Hierarchy& H;
+    int level, comp;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    Scope(Hierarchy& h, int l, int c, hipStream_t st) : H(h), level(l), comp(c), s(st) {
+        if (H.profiling) {
+            a = take_event(H);
+            NNMG_HIP(hipEventRecord(a, s));
+        }
+    }
+    ~Scope() noexcept(false) {
+        if (H.profiling && a) {
+            hipEvent_t b = take_event(H);
+            NNMG_HIP(hipEventRecord(b, s));
+            H.records.push_back({level, comp, a, b});
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// coarse solve
+// ---------------------------------------------------------------------------
+static void setup_coarse(Hierarchy& H) {
+    Level& C = *H.levels[0];
+    Ctx* ctx = H.ctx;
+    std::vector<int32_t> idx;
+    for (int64_t i = 0; i < C.n_dofs; ++i)
+        if (!C.constrained[(size_t)i]) idx.push_back((int32_t)i);
+    H.m = (int64_t)idx.size();
+    const size_t N = (size_t)C.n_dofs, m = (size_t)H.m;
+    H.cx.alloc(ctx, N);
+    H.cax.alloc(ctx, N);
+    H.cr.alloc(ctx, N);
+    H.cf.alloc(ctx, N);
+    for (auto* a : {&H.cx, &H.cax, &H.cr, &H.cf}) NNMG_HIP(hipMemset(a->ptr, 0, a->bytes()));
+    if (m == 0) return;
+    H.free_idx.upload(ctx, idx);
+    H.bf.alloc(ctx, m);
+    H.xf.alloc(ctx, m);
+    H.yf.alloc(ctx, m);
+    H.inv.alloc(ctx, m * m);
+    // columns of A on the unconstrained block: A e_j by the operator kernel
+    for (size_t j = 0; j < m; ++j) {
+        launch_set_unit(H.cx.ptr, N, idx[j], 1.0, nullptr);
+        launch_vmult_cells(C, NNMG_FP64, H.cx.ptr, H.cax.ptr, nullptr);
+        launch_column_from_unit(H.free_idx.ptr, m, H.cax.ptr, H.inv.ptr, j, nullptr);
+        launch_fill(H.cax.ptr, N, NNMG_FP64, nullptr);
+        launch_set_unit(H.cx.ptr, N, idx[j], 0.0, nullptr);
+    }
+    DeviceArray<double> rowbuf, colbuf;
+    rowbuf.alloc(ctx, m);
+    colbuf.alloc(ctx, m);
+    launch_gauss_jordan(H.inv.ptr, m, rowbuf.ptr, colbuf.ptr, nullptr);
+    NNMG_HIP(hipDeviceSynchronize());
+}
+
+// x = A_0^{-1} f (one refinement step), f and x in `prec`
+static void coarse_solve(Hierarchy& H, int prec, const void* f, void* x, hipStream_t s) {
+    Level& C = *H.levels[0];
+    const size_t N = (size_t)C.n_dofs, m = (size_t)H.m;
+    const double* src = (const double*)f;
+    if (prec == NNMG_FP32) {
+        launch_cast_32_to_64((const float*)f, H.cf.ptr, N, s);
+        src = H.cf.ptr;
+    }
+    double* out = prec == NNMG_FP64 ? (double*)x : H.cx.ptr;
+    launch_fill(out, N, NNMG_FP64, s);
+    if (m > 0) {
+        launch_gather_free(H.free_idx.ptr, m, src, H.bf.ptr, s);
+        launch_gemv(H.inv.ptr, m, H.bf.ptr, H.xf.ptr, s);
+        launch_scatter_free(H.free_idx.ptr, m, H.xf.ptr, out, s);
+        // refinement: x += A^{-1} (f - A x)
+        launch_vmult_cells(C, NNMG_FP64, out, H.cax.ptr, s);
+        launch_residual(NNMG_FP64, N, src, H.cax.ptr, H.cr.ptr, s);
+        launch_gather_free(H.free_idx.ptr, m, H.cr.ptr, H.bf.ptr, s);
+        launch_gemv(H.inv.ptr, m, H.bf.ptr, H.yf.ptr, s);
+        launch_add(NNMG_FP64, m, H.yf.ptr, H.xf.ptr, s);
+        launch_scatter_free(H.free_idx.ptr, m, H.xf.ptr, out, s);
+    }
+    if (prec == NNMG_FP32) launch_cast_64_to_32(H.cx.ptr, (float*)x, N, s);
+}
+
+// ---------------------------------------------------------------------------
+// smoother and V-cycle
+// ---------------------------------------------------------------------------
+static void chebyshev(Hierarchy& H, int l, int prec, const void* f, void* x, bool zero_start, hipStream_t s) {
+    Level& L = *H.levels[l];
+    WorkVectors& w = H.work[prec][l];
+    const size_t n = (size_t)L.n_dofs;
+    const void* dinv = prec == NNMG_FP64 ? (const void*)L.d_dinv64.ptr : (const void*)L.d_dinv32.ptr;
+    const double lo = H.lo[l], hi = H.hi[l];
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    if (zero_start) {
+        launch_cheb_first_zero(prec, n, f, dinv, x, w.d.ptr, 1.0 / theta, s);
+    } else {
+        launch_vmult_cells(L, prec, x, w.ax.ptr, s);
+        launch_cheb_step(prec, n, f, w.ax.ptr, dinv, x, w.d.ptr, 0.0, 1.0 / theta, s);
+    }
+    for (int j = 1; j < H.opts.cheb_degree; ++j) {
+        launch_vmult_cells(L, prec, x, w.ax.ptr, s);
+        const double rho_new = 1.0 / (2.0 * sigma - rho);
+        launch_cheb_step(prec, n, f, w.ax.ptr, dinv, x, w.d.ptr, rho_new * rho, 2.0 * rho_new / delta, s);
+        rho = rho_new;
+    }
+}
+
+static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, hipStream_t s) {
+    if (l == 0) {
+        Scope sc(H, 0, kCoarse, s);
+        coarse_solve(H, prec, f, x, s);
+        return;
+    }
+    Level& L = *H.levels[l];
+    WorkVectors& w = H.work[prec][l];
+    WorkVectors& wc = H.work[prec][l - 1];
+    const Transfer& T = *H.transfers[l - 1];
+    const size_t n = (size_t)L.n_dofs;
+    {
+        Scope sc(H, l, kPre, s);
+        chebyshev(H, l, prec, f, x, true, s);
+    }
+    {
+        Scope sc(H, l, kRes, s);
+        launch_vmult_cells(L, prec, x, w.ax.ptr, s);
+        launch_residual(prec, n, f, w.ax.ptr, w.r.ptr, s);
+    }
+    {
+        Scope sc(H, l, kRestrict, s);
+        launch_fill(wc.f.ptr, (size_t)H.levels[l - 1]->n_dofs, prec, s);
+        launch_restrict(T, prec, w.r.ptr, wc.f.ptr, s);
+    }
+    vcycle_level(H, l - 1, prec, wc.f.ptr, wc.x.ptr, s);
+    {
+        Scope sc(H, l, kProlong, s);
+        launch_prolongate(T, prec, wc.x.ptr, x, s);
+    }
+    {
+        Scope sc(H, l, kPost, s);
+        chebyshev(H, l, prec, f, x, false, s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos estimate of lambda_max(D^{-1} A)
+// ---------------------------------------------------------------------------
+static double tridiagonal_max_eig(const std::vector<double>& d, const std::vector<double>& e) {
+    // Sturm-sequence bisection for the largest eigenvalue of a symmetric tridiagonal matrix
+    const int m = (int)d.size();
+    if (m == 0) return 0.0;
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(e[(size_t)i - 1]) : 0.0) + (i + 1 < m ? std::fabs(e[(size_t)i]) : 0.0);
+        lo = std::min(lo, d[(size_t)i] - r);
+        hi = std::max(hi, d[(size_t)i] + r);
+    }
+    auto count_below = [&](double x) {  // eigenvalues < x
+        int cnt = 0;
+        double q = 1.0;
+        for (int i = 0; i < m; ++i) {
+            const double off = i > 0 ? e[(size_t)i - 1] * e[(size_t)i - 1] : 0.0;
+            q = d[(size_t)i] - x - (i > 0 ? off / q : 0.0);
+            if (q == 0.0) q = -1e-300;
+            if (q < 0) ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (count_below(mid) >= m)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+static double host_dot(Hierarchy& H, const double* a, const double* b, size_t n) {
+    launch_dot(a, b, n, H.partial.ptr, H.scal.ptr + 7, nullptr);
+    double v = 0.0;
+    NNMG_HIP(hipMemcpy(&v, H.scal.ptr + 7, sizeof(double), hipMemcpyDeviceToHost));
+    return v;
+}
+
+static double estimate_lambda_max(Hierarchy& H, int l) {
+    Level& L = *H.levels[l];
+    const size_t n = (size_t)L.n_dofs;
+    DeviceArray<double> r, z, p, q;
+    r.alloc(H.ctx, n);
+    z.alloc(H.ctx, n);
+    p.alloc(H.ctx, n);
+    q.alloc(H.ctx, n);
+    const void* start = H.opts.eig_start ? H.opts.eig_start[l] : nullptr;
+    if (start)
+        NNMG_HIP(hipMemcpy(r.ptr, start, n * sizeof(double), hipMemcpyDeviceToDevice));
+    else
+        launch_splitmix_vector(r.ptr, nullptr, n, 0x5EEDull + (uint64_t)l, nullptr);
+    launch_set_constrained(L.d_constrained.ptr, L.constrained_idx.size(), 0.0, r.ptr, NNMG_FP64, nullptr);
+    launch_jacobi(n, L.d_dinv64.ptr, r.ptr, z.ptr, nullptr);
+    NNMG_HIP(hipMemcpy(p.ptr, z.ptr, n * sizeof(double), hipMemcpyDeviceToDevice));
+    double rz = host_dot(H, r.ptr, z.ptr, n);
+    const double r0 = std::sqrt(host_dot(H, r.ptr, r.ptr, n));
+    std::vector<double> alphas, betas;
+    for (int it = 0; it < H.opts.eig_iters; ++it) {
+        launch_fill(q.ptr, n, NNMG_FP64, nullptr);
+        launch_vmult_cells(L, NNMG_FP64, p.ptr, q.ptr, nullptr);
+        const double pq = host_dot(H, p.ptr, q.ptr, n);
+        if (!(pq > 0.0)) break;
+        const double alpha = rz / pq;
+        alphas.push_back(alpha);
+        launch_lincomb(n, -alpha, q.ptr, 1.0, r.ptr, nullptr);
+        if (std::sqrt(host_dot(H, r.ptr, r.ptr, n)) <= 1e-14 * r0) break;
+        launch_jacobi(n, L.d_dinv64.ptr, r.ptr, z.ptr, nullptr);
+        const double rz_new = host_dot(H, r.ptr, z.ptr, n);
+        const double beta = rz_new / rz;
+        betas.push_back(beta);
+        launch_lincomb(n, 1.0, z.ptr, beta, p.ptr, nullptr);
+        rz = rz_new;
+    }
+    const size_t k = alphas.size();
+    std::vector<double> d(k), e(k > 0 ? k - 1 : 0);
+    for (size_t j = 0; j < k; ++j) {
+        d[j] = 1.0 / alphas[j] + (j > 0 ? betas[j - 1] / alphas[j - 1] : 0.0);
+        if (j + 1 < k) e[j] = std::sqrt(betas[j]) / alphas[j];
+    }
+    return tridiagonal_max_eig(d, e);
+}
+
+// ---------------------------------------------------------------------------
+// creation
+// ---------------------------------------------------------------------------
+Hierarchy* hierarchy_create(Ctx* ctx, nnmg_level* const* levels, int nl, nnmg_transfer* const* transfers,
+                            const nnmg_mg_opts& o) {
+    if (nl < 1 || nl > 16 || !levels) fail(NNMG_ERR_INVALID_ARG, "n_levels must be in 1..16");
+    if (nl > 1 && !transfers) fail(NNMG_ERR_INVALID_ARG, "transfers is NULL");
+    if (o.cheb_degree < 1 || !(o.smoothing_range > 1.0) || !(o.eig_safety > 0.0) || o.eig_iters < 1)
+        fail(NNMG_ERR_INVALID_ARG, "multigrid options");
+    for (int i = 0; i < nl; ++i)
+        if (!levels[i]) fail(NNMG_ERR_INVALID_ARG, "level is NULL");
+    for (int i = 0; i + 1 < nl; ++i) {
+        const Transfer* t = transfers[i];
+        if (!t || t->fine != levels[i + 1] || t->coarse != levels[i])
+            fail(NNMG_ERR_INVALID_ARG, "transfers[i] must connect levels[i+1] (fine) to levels[i] (coarse)");
+    }
+    NNMG_HIP(hipSetDevice(ctx->device));
+    auto* H = new nnmg_hierarchy();
+    try {
+        H->ctx = ctx;
+        H->opts = o;
+        for (int i = 0; i < nl; ++i) {
+            level_retain(levels[i]);
+            H->levels.push_back(levels[i]);
+        }
+        for (int i = 0; i + 1 < nl; ++i) {
+            transfer_retain(transfers[i]);
+            H->transfers.push_back(transfers[i]);
+        }
+        H->opts.eig_start = nullptr;
+        const size_t nmax = (size_t)H->levels.back()->n_dofs;
+        H->partial.alloc(ctx, dot_partials(nmax > 0 ? nmax : 1) + 8);
+        H->scal.alloc(ctx, 8);
+        NNMG_HIP(hipMemset(H->scal.ptr, 0, 8 * sizeof(double)));
+        NNMG_HIP(hipHostMalloc((void**)&H->hscal, 8 * sizeof(double), hipHostMallocDefault));
+        H->lo.assign((size_t)nl, 0.0);
+        H->hi.assign((size_t)nl, 0.0);
+        H->opts.eig_start = o.eig_start;
+        for (int l = 1; l < nl; ++l) {
+            const double lam = estimate_lambda_max(*H, l);
+            H->hi[(size_t)l] = o.eig_safety * lam;
+            H->lo[(size_t)l] = H->hi[(size_t)l] / o.smoothing_range;
+        }
+        H->opts.eig_start = nullptr;  // the caller's vectors are not kept
+        setup_coarse(*H);
+        alloc_work(*H, NNMG_FP64);
+        alloc_work(*H, NNMG_FP32);
+        const size_t n = (size_t)H->levels.back()->n_dofs;
+        H->r.alloc(ctx, n);
+        H->p.alloc(ctx, n);
+        H->qv.alloc(ctx, n);
+        H->z.alloc(ctx, n);
+        H->acc.assign((size_t)nl * kComponents, 0.0);
+        NNMG_HIP(hipDeviceSynchronize());
+    } catch (...) {
+        delete H;
+        throw;
+    }
+    return H;
+}
+
+void hierarchy_destroy(Hierarchy* h) { delete static_cast<nnmg_hierarchy*>(h); }
+
+void get_bounds(const Hierarchy& H, int l, double* lo, double* hi) {
+    if (l < 0 || l >= (int)H.levels.size()) fail(NNMG_ERR_INVALID_ARG, "level index");
+    if (lo) *lo = H.lo[(size_t)l];
+    if (hi) *hi = H.hi[(size_t)l];
+}
+
+void set_bounds(Hierarchy& H, int l, double lo, double hi) {
+    if (l < 1 || l >= (int)H.levels.size()) fail(NNMG_ERR_INVALID_ARG, "level index (the coarsest has no smoother)");
+    if (!(lo > 0.0) || !(hi > lo)) fail(NNMG_ERR_INVALID_ARG, "bounds must satisfy 0 < lo < hi");
+    H.lo[(size_t)l] = lo;
+    H.hi[(size_t)l] = hi;
+}
+
+void vcycle(Hierarchy& H, int prec, const void* r, void* z, hipStream_t s) {
+    H.last = s;
+    vcycle_level(H, (int)H.levels.size() - 1, prec, r, z, s);
+}
+
+// ---------------------------------------------------------------------------
+// PCG (float64), Saad Alg. 9.1 with x0 = 0
+// ---------------------------------------------------------------------------
+int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg_result* res, hipStream_t s) {
+    if (o.max_it < 0 || !(o.rtol >= 0.0)) fail(NNMG_ERR_INVALID_ARG, "CG options");
+    if (o.vcycle_prec != NNMG_FP64 && o.vcycle_prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "vcycle_prec");
+    H.last = s;
+    Level& L = *H.levels.back();
+    const int top = (int)H.levels.size() - 1;
+    const size_t n = (size_t)L.n_dofs;
+    const int prec = o.vcycle_prec;
+    WorkVectors& w32 = H.work[NNMG_FP32][top];
+    auto precondition = [&]() {
+        if (prec == NNMG_FP64) {
+            vcycle_level(H, top, NNMG_FP64, H.r.ptr, H.z.ptr, s);
+        } else {
+            launch_cast_64_to_32(H.r.ptr, (float*)w32.f.ptr, n, s);
+            vcycle_level(H, top, NNMG_FP32, w32.f.ptr, w32.x.ptr, s);
+            launch_cast_32_to_64((const float*)w32.x.ptr, H.z.ptr, n, s);
+        }
+    };
+    double* sc = H.scal.ptr;
+    NNMG_HIP(hipMemcpyAsync(H.r.ptr, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_fill(x, n, NNMG_FP64, s);
+    launch_dot(b, b, n, H.partial.ptr, sc + 6, s);
+    NNMG_HIP(hipMemcpyAsync(H.hscal + 6, sc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+    NNMG_HIP(hipStreamSynchronize(s));
+    const double bnorm = std::sqrt(H.hscal[6]);
+    if (o.history) o.history[0] = 1.0;
+    res->iterations = 0;
+    res->relres = bnorm > 0 ? 1.0 : 0.0;
+    res->status = NNMG_OK;
+    if (!(bnorm > 0.0)) {
+        if (std::isnan(bnorm)) {
+            res->status = NNMG_ERR_BREAKDOWN;
+            return NNMG_ERR_BREAKDOWN;
+        }
+        res->relres = 0.0;
+        return NNMG_OK;
+    }
+    precondition();
+    launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 0, s);
+    NNMG_HIP(hipMemcpyAsync(H.p.ptr, H.z.ptr, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int status = NNMG_ERR_NOT_CONVERGED;
+    for (int it = 1; it <= o.max_it; ++it) {
+        launch_fill(H.qv.ptr, n, NNMG_FP64, s);
+        launch_vmult_cells(L, NNMG_FP64, H.p.ptr, H.qv.ptr, s);
+        launch_dot(H.p.ptr, H.qv.ptr, n, H.partial.ptr, sc + 1, s);
+        launch_scalar_op(sc, 0, s);
+        launch_cg_update(n, x, H.r.ptr, H.p.ptr, H.qv.ptr, sc, H.partial.ptr, sc + 3, s);
+        NNMG_HIP(hipMemcpyAsync(H.hscal, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        NNMG_HIP(hipStreamSynchronize(s));
+        const double pq = H.hscal[1], rr = H.hscal[3];
+        res->iterations = it;
+        if (!(pq > 0.0) || !std::isfinite(rr)) {
+            status = NNMG_ERR_BREAKDOWN;
+            break;
+        }
+        const double rel = std::sqrt(rr) / bnorm;
+        res->relres = rel;
+        if (o.history) o.history[it] = rel;
+        if (rel <= o.rtol) {
+            status = NNMG_OK;
+            break;
+        }
+        if (it == o.max_it) break;
+        precondition();
+        launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 4, s);
+        launch_scalar_op(sc, 1, s);
+        launch_cg_direction(n, H.z.ptr, H.p.ptr, sc, s);
+    }
+    res->status = status;
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// profiling
+// ---------------------------------------------------------------------------
+void set_profiling(Hierarchy& H, bool on) { H.profiling = on; }
+
+void profile(Hierarchy& H, double* ms) {
+    if (H.last) NNMG_HIP(hipStreamSynchronize(H.last));
+    NNMG_HIP(hipDeviceSynchronize());
+    for (auto& rec : H.records) {
+        float t = 0.f;
+        NNMG_HIP(hipEventElapsedTime(&t, rec.a, rec.b));
+        H.acc[(size_t)(rec.level * kComponents + rec.comp)] += t;
+        H.pool.push_back(rec.a);
+        H.pool.push_back(rec.b);
+    }
+    H.records.clear();
+    std::memcpy(ms, H.acc.data(), H.acc.size() * sizeof(double));
+    std::fill(H.acc.begin(), H.acc.end(), 0.0);
+}
+
+}  // namespace nnmg

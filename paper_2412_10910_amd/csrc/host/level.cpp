@@ -1,0 +1,342 @@
+// Level setup: DoF numbering of continuous Q_k on an unstructured quad/hex
+// mesh, the constrained set, device layouts and the setup kernels.
+//
+// Every local node of a cell belongs to one mesh entity (vertex, edge, face or
+// cell interior).  Shared entities are identified by their global vertex ids,
+// and their interior nodes are numbered in an orientation that every cell can
+// reproduce from those ids alone:
+//   edge: from the endpoint with the lower vertex id to the other one;
+//   face: origin at the corner with the lowest id, first axis towards the
+//         origin's face-neighbour corner with the lower id.
+// DoFs are numbered entity by entity in order of first touch (cells in input
+// order, local nodes lexicographic), which keeps the DoFs of neighbouring
+// cells close in memory.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+#include "../internal.hpp"
+
+namespace nnmg {
+
+namespace {
+
+struct Key4Hash {
+    size_t operator()(const std::array<int32_t, 4>& k) const {
+        uint64_t h = 1469598103934665603ull;
+        for (int32_t v : k) {
+            h ^= (uint32_t)v;
+            h *= 1099511628211ull;
+        }
+        return (size_t)h;
+    }
+};
+
+inline uint64_t edge_key(int32_t a, int32_t b) {
+    const uint32_t lo = (uint32_t)std::min(a, b), hi = (uint32_t)std::max(a, b);
+    return ((uint64_t)lo << 32) | hi;
+}
+
+}  // namespace
+
+void level_retain(Level* l) { l->refs.fetch_add(1); }
+
+void level_release(Level* l) {
+    if (l && l->refs.fetch_sub(1) == 1) delete static_cast<nnmg_level*>(l);
+}
+
+static void number_dofs(Level& L) {
+    const int dim = L.dim, k = L.degree, n = L.n, q = L.q, nv = 1 << dim;
+    const int64_t C = L.n_cells;
+    const int64_t V = (int64_t)L.vertices.size() / dim;
+    const int32_t* cells = L.cells.data();
+
+    std::vector<int64_t> vertex_base(V, -1);
+    std::unordered_map<uint64_t, int64_t> edge_base;
+    std::unordered_map<std::array<int32_t, 4>, int64_t, Key4Hash> face_base;
+    edge_base.reserve((size_t)(C * (dim == 3 ? 3 : 2) + 16));
+    if (dim == 3) face_base.reserve((size_t)(C * 3 + 16));
+    int64_t next = 0;
+    const int ke = k - 1;  // interior nodes per edge direction
+
+    L.dofmap.assign((size_t)(C * q), -1);
+    for (int64_t c = 0; c < C; ++c) {
+        const int32_t* cv = cells + c * nv;
+        int64_t interior_base = -1;
+        for (int a = 0; a < q; ++a) {
+            int id[3] = {a % n, (a / n) % n, dim == 3 ? a / (n * n) : 0};
+            int n_int = 0, int_axes[3];
+            for (int d = 0; d < dim; ++d)
+                if (id[d] > 0 && id[d] < k) int_axes[n_int++] = d;
+            int64_t dof;
+            if (n_int == 0) {
+                int b = 0;
+                for (int d = 0; d < dim; ++d) b |= (id[d] == k ? 1 : 0) << d;
+                const int32_t v = cv[b];
+                if (vertex_base[v] < 0) vertex_base[v] = next++;
+                dof = vertex_base[v];
+            } else if (n_int == 1 && n_int < dim) {
+                const int ax = int_axes[0];
+                int b0 = 0;
+                for (int d = 0; d < dim; ++d)
+                    if (d != ax) b0 |= (id[d] == k ? 1 : 0) << d;
+                const int32_t v0 = cv[b0], v1 = cv[b0 | (1 << ax)];
+                const uint64_t key = edge_key(v0, v1);
+                auto it = edge_base.find(key);
+                int64_t base;
+                if (it == edge_base.end()) {
+                    base = next;
+                    next += ke;
+                    edge_base.emplace(key, base);
+                } else {
+                    base = it->second;
+                }
+                const int t = id[ax];
+                const int pos = v0 < v1 ? t - 1 : k - t - 1;
+                dof = base + pos;
+            } else if (n_int == 2 && dim == 3) {
+                const int a0 = int_axes[0], a1 = int_axes[1];
+                int fixed = 3 - a0 - a1;
+                const int bf = (id[fixed] == k ? 1 : 0) << fixed;
+                auto corner = [&](int s, int t) { return cv[bf | (s << a0) | (t << a1)]; };
+                const int32_t c00 = corner(0, 0), c10 = corner(1, 0), c01 = corner(0, 1), c11 = corner(1, 1);
+                std::array<int32_t, 4> key{c00, c10, c01, c11};
+                std::sort(key.begin(), key.end());
+                auto it = face_base.find(key);
+                int64_t base;
+                if (it == face_base.end()) {
+                    base = next;
+                    next += (int64_t)ke * ke;
+                    face_base.emplace(key, base);
+                } else {
+                    base = it->second;
+                }
+                // origin corner: lowest vertex id
+                int os = 0, ot = 0;
+                int32_t best = c00;
+                if (c10 < best) { best = c10; os = 1; ot = 0; }
+                if (c01 < best) { best = c01; os = 0; ot = 1; }
+                if (c11 < best) { best = c11; os = 1; ot = 1; }
+                const int32_t nb_s = corner(1 - os, ot);  // neighbour along axis a0
+                const int32_t nb_t = corner(os, 1 - ot);  // neighbour along axis a1
+                const int ds = os == 0 ? id[a0] : k - id[a0];
+                const int dt = ot == 0 ? id[a1] : k - id[a1];
+                int u, w;
+                if (nb_s < nb_t) {
+                    u = ds;
+                    w = dt;
+                } else {
+                    u = dt;
+                    w = ds;
+                }
+                dof = base + (u - 1) + (int64_t)(w - 1) * ke;
+            } else {
+                // cell interior: the block is reserved when its first node is met
+                if (interior_base < 0) {
+                    interior_base = next;
+                    int64_t cnt = 1;
+                    for (int d = 0; d < dim; ++d) cnt *= ke;
+                    next += cnt;
+                }
+                int64_t pos = 0, stride = 1;
+                for (int d = 0; d < dim; ++d) {
+                    pos += (id[d] - 1) * stride;
+                    stride *= ke;
+                }
+                dof = interior_base + pos;
+            }
+            L.dofmap[(size_t)(c * q + a)] = (int32_t)dof;
+        }
+    }
+    if (next > INT32_MAX) fail(NNMG_ERR_UNSUPPORTED, "more than 2^31 DoFs");
+    L.n_dofs = next;
+}
+
+static void find_constraints(Level& L, const uint8_t* dirichlet) {
+    const int dim = L.dim, k = L.degree, n = L.n, q = L.q, nv = 1 << dim;
+    const int64_t C = L.n_cells;
+    L.constrained.assign((size_t)L.n_dofs, 0);
+    if (!dirichlet) return;
+    const int fv = 1 << (dim - 1);
+    std::unordered_map<std::array<int32_t, 4>, int, Key4Hash> count;
+    count.reserve((size_t)(C * dim + 16));
+    auto facet_key = [&](int64_t c, int ax, int side) {
+        std::array<int32_t, 4> key{-1, -1, -1, -1};
+        int m = 0;
+        for (int b = 0; b < nv; ++b)
+            if (((b >> ax) & 1) == side) key[m++] = L.cells[(size_t)(c * nv + b)];
+        std::sort(key.begin(), key.begin() + fv);
+        return key;
+    };
+    for (int64_t c = 0; c < C; ++c)
+        for (int ax = 0; ax < dim; ++ax)
+            for (int side = 0; side < 2; ++side) count[facet_key(c, ax, side)]++;
+    for (int64_t c = 0; c < C; ++c)
+        for (int ax = 0; ax < dim; ++ax)
+            for (int side = 0; side < 2; ++side) {
+                const auto key = facet_key(c, ax, side);
+                if (count[key] != 1) continue;
+                bool all = true;
+                for (int m = 0; m < fv; ++m) all = all && dirichlet[key[m]];
+                if (!all) continue;
+                for (int a = 0; a < q; ++a) {
+                    const int id = ax == 0 ? a % n : (ax == 1 ? (a / n) % n : a / (n * n));
+                    if (id == side * k) L.constrained[(size_t)L.dofmap[(size_t)(c * q + a)]] = 1;
+                }
+            }
+}
+
+static void compute_support_points(Level& L) {
+    const int dim = L.dim, n = L.n, q = L.q, nv = 1 << dim;
+    L.support.assign((size_t)(L.n_dofs * dim), 0.0);
+    std::vector<char> done((size_t)L.n_dofs, 0);
+    for (int64_t c = 0; c < L.n_cells; ++c) {
+        const int32_t* cv = &L.cells[(size_t)(c * nv)];
+        for (int a = 0; a < q; ++a) {
+            const int32_t dof = L.dofmap[(size_t)(c * q + a)];
+            if (done[(size_t)dof]) continue;
+            done[(size_t)dof] = 1;
+            double xi[3] = {L.basis.node[a % n], L.basis.node[(a / n) % n], dim == 3 ? L.basis.node[a / (n * n)] : 0.0};
+            for (int i = 0; i < dim; ++i) {
+                double x = 0.0;
+                for (int b = 0; b < nv; ++b) {
+                    double N = 1.0;
+                    for (int d = 0; d < dim; ++d) N *= ((b >> d) & 1) ? xi[d] : 1.0 - xi[d];
+                    x += N * L.vertices[(size_t)(cv[b] * dim + i)];
+                }
+                L.support[(size_t)(dof * dim + i)] = x;
+            }
+        }
+    }
+}
+
+Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
+    if (!mesh) fail(NNMG_ERR_INVALID_ARG, "mesh is NULL");
+    if (mesh->dim != 2 && mesh->dim != 3) fail(NNMG_ERR_UNSUPPORTED, "dim must be 2 or 3");
+    if (degree < 1 || degree > 4) fail(NNMG_ERR_UNSUPPORTED, "degree must be in 1..4");
+    if (mesh->n_vertices <= 0 || mesh->n_cells <= 0 || !mesh->vertices || !mesh->cells)
+        fail(NNMG_ERR_INVALID_ARG, "empty mesh");
+    if (mesh->n_vertices > INT32_MAX || mesh->n_cells > INT32_MAX / 125)
+        fail(NNMG_ERR_UNSUPPORTED, "mesh too large for 32-bit indices");
+    const int dim = mesh->dim, nv = 1 << dim;
+    for (int64_t i = 0; i < mesh->n_vertices * dim; ++i)
+        if (!std::isfinite(mesh->vertices[i])) fail(NNMG_ERR_MESH, "non-finite vertex coordinate");
+    for (int64_t c = 0; c < mesh->n_cells; ++c) {
+        for (int b = 0; b < nv; ++b) {
+            const int32_t v = mesh->cells[c * nv + b];
+            if (v < 0 || v >= mesh->n_vertices) fail(NNMG_ERR_MESH, "cell vertex index out of range");
+            for (int b2 = 0; b2 < b; ++b2)
+                if (mesh->cells[c * nv + b2] == v) fail(NNMG_ERR_MESH, "repeated vertex in a cell");
+        }
+    }
+
+    auto* L = new nnmg_level();
+    try {
+        L->ctx = ctx;
+        L->dim = dim;
+        L->degree = degree;
+        L->n = degree + 1;
+        L->q = dim == 3 ? L->n * L->n * L->n : L->n * L->n;
+        L->cpw = 64 / L->n;
+        L->n_cells = mesh->n_cells;
+        L->nblocks = (L->n_cells + L->cpw - 1) / L->cpw;
+        L->basis = make_basis(degree);
+        L->vertices.assign(mesh->vertices, mesh->vertices + mesh->n_vertices * dim);
+        L->cells.assign(mesh->cells, mesh->cells + mesh->n_cells * nv);
+
+        number_dofs(*L);
+        find_constraints(*L, mesh->dirichlet_vertex);
+        compute_support_points(*L);
+        for (int64_t i = 0; i < L->n_dofs; ++i)
+            if (L->constrained[(size_t)i]) L->constrained_idx.push_back((int32_t)i);
+        L->n_free = L->n_dofs - (int64_t)L->constrained_idx.size();
+
+        NNMG_HIP(hipSetDevice(ctx->device));
+        // device cell->DoF maps, constrained DoFs encoded as -1
+        const int q = L->q, n = L->n, P = dim == 3 ? n * n : n, M = dim * (dim + 1) / 2;
+        std::vector<int32_t> enc(L->dofmap.size());
+        for (size_t i = 0; i < enc.size(); ++i) enc[i] = L->constrained[(size_t)L->dofmap[i]] ? -1 : L->dofmap[i];
+        L->d_dofmap.upload(ctx, enc);
+        std::vector<int32_t> blk((size_t)(L->nblocks * P * 64), -1);
+        for (int64_t c = 0; c < L->n_cells; ++c) {
+            const int64_t b = c / L->cpw;
+            const int team = (int)(c - b * L->cpw);
+            for (int a = 0; a < q; ++a) {
+                const int t = a / P;  // slab along the last coordinate
+                const int ij = a % P;
+                blk[(size_t)((b * P + ij) * 64 + team * n + t)] = enc[(size_t)(c * q + a)];
+            }
+        }
+        L->d_dofmap_blk.upload(ctx, blk);
+        L->d_constrained.upload(ctx, L->constrained_idx);
+        std::vector<double> cv((size_t)(L->n_cells * nv * dim));
+        for (int64_t c = 0; c < L->n_cells; ++c)
+            for (int b = 0; b < nv; ++b)
+                for (int i = 0; i < dim; ++i)
+                    cv[(size_t)((c * nv + b) * dim + i)] = L->vertices[(size_t)(L->cells[(size_t)(c * nv + b)] * dim + i)];
+        L->d_cellverts.upload(ctx, cv);
+
+        const size_t mlen = (size_t)(L->nblocks * M * P * 64);
+        L->d_metric64.alloc(ctx, mlen);
+        L->d_metric32.alloc(ctx, mlen);
+        NNMG_HIP(hipMemset(L->d_metric64.ptr, 0, L->d_metric64.bytes()));
+        NNMG_HIP(hipMemset(L->d_metric32.ptr, 0, L->d_metric32.bytes()));
+        DeviceArray<int> bad;
+        bad.alloc(ctx, 1);
+        NNMG_HIP(hipMemset(bad.ptr, 0, sizeof(int)));
+        launch_geometry(*L, bad.ptr, nullptr);
+        int hbad = 0;
+        NNMG_HIP(hipMemcpy(&hbad, bad.ptr, sizeof(int), hipMemcpyDeviceToHost));
+        if (hbad) fail(NNMG_ERR_MESH, "cell with non-positive Jacobian determinant at a Gauss point");
+
+        DeviceArray<double> diag;
+        diag.alloc(ctx, (size_t)L->n_dofs);
+        NNMG_HIP(hipMemset(diag.ptr, 0, diag.bytes()));
+        launch_diagonal(*L, diag.ptr, nullptr);
+        L->d_dinv64.alloc(ctx, (size_t)L->n_dofs);
+        L->d_dinv32.alloc(ctx, (size_t)L->n_dofs);
+        launch_invert_diagonal(*L, diag.ptr, nullptr);
+        NNMG_HIP(hipDeviceSynchronize());
+    } catch (...) {
+        delete L;
+        throw;
+    }
+    return L;
+}
+
+void level_diagonal(const Level& L, int prec, void* out, hipStream_t s) {
+    // diag = 1 / dinv on free rows, 1 on constrained rows
+    DeviceArray<double> diag;
+    diag.alloc(L.ctx, (size_t)L.n_dofs);
+    NNMG_HIP(hipMemsetAsync(diag.ptr, 0, diag.bytes(), s));
+    launch_diagonal(L, diag.ptr, s);
+    launch_set_constrained(L.d_constrained.ptr, L.constrained_idx.size(), 1.0, diag.ptr, NNMG_FP64, s);
+    if (prec == NNMG_FP64)
+        NNMG_HIP(hipMemcpyAsync(out, diag.ptr, diag.bytes(), hipMemcpyDeviceToDevice, s));
+    else
+        launch_cast_64_to_32(diag.ptr, (float*)out, (size_t)L.n_dofs, s);
+    NNMG_HIP(hipStreamSynchronize(s));
+}
+
+void level_quadrature_points(const Level& L, double* out) {
+    const int dim = L.dim, n = L.n, q = L.q, nv = 1 << dim;
+    for (int64_t c = 0; c < L.n_cells; ++c) {
+        const int32_t* cv = &L.cells[(size_t)(c * nv)];
+        for (int a = 0; a < q; ++a) {
+            double xi[3] = {L.basis.gauss[a % n], L.basis.gauss[(a / n) % n], dim == 3 ? L.basis.gauss[a / (n * n)] : 0.0};
+            for (int i = 0; i < dim; ++i) {
+                double x = 0.0;
+                for (int b = 0; b < nv; ++b) {
+                    double N = 1.0;
+                    for (int d = 0; d < dim; ++d) N *= ((b >> d) & 1) ? xi[d] : 1.0 - xi[d];
+                    x += N * L.vertices[(size_t)(cv[b] * dim + i)];
+                }
+                out[(size_t)((c * q + a) * dim + i)] = x;
+            }
+        }
+    }
+}
+
+}  // namespace nnmg

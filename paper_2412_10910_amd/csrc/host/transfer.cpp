@@ -1,0 +1,199 @@
+// Transfer setup (timed setup of the non-nested transfer, paper §3.1 and §3.3).
+//
+// 1. The unconstrained fine support points are the query points.
+// 2. Every coarse cell's vertex bounding box is grown on every side by
+//    bbox_expand times its diagonal; a uniform bucket grid over the grown
+//    boxes lists, per bucket, the cells whose grown box overlaps it, in
+//    increasing cell number (the GPU replacement of a bounding-box tree).
+// 3. On the GPU, each point visits the cells of its bucket in increasing
+//    number, keeps those whose grown box contains it, inverts their Q1 maps by
+//    Newton's method and stops at the first cell that contains the pre-image;
+//    otherwise it keeps the candidate with the nearest clamped pre-image
+//    (eq. closest_point).
+// 4. The points are counting-sorted by owner cell (stable, so fine DoF order
+//    within a cell), and the reference coordinates are stored per coordinate
+//    in float64 and float32.
+#include <algorithm>
+#include <cmath>
+
+#include "../internal.hpp"
+
+namespace nnmg {
+
+Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_transfer_opts& o) {
+    if (!fine || !coarse) fail(NNMG_ERR_INVALID_ARG, "level is NULL");
+    if (fine->dim != coarse->dim) fail(NNMG_ERR_INVALID_ARG, "levels of different dimension");
+    if (fine->ctx->device != ctx->device || coarse->ctx->device != ctx->device)
+        fail(NNMG_ERR_INVALID_ARG, "levels on another device");
+    if (!(o.bbox_expand >= 0.0) || !(o.inside_tol >= 0.0) || !(o.newton_tol > 0.0) || o.newton_max_it < 1)
+        fail(NNMG_ERR_INVALID_ARG, "transfer options");
+    const int dim = fine->dim, nv = 1 << dim;
+    NNMG_HIP(hipSetDevice(ctx->device));
+
+    auto* T = new nnmg_transfer();
+    try {
+        T->ctx = ctx;
+        T->fine = fine;
+        T->coarse = coarse;
+        level_retain(fine);
+        level_retain(coarse);
+
+        // query points
+        std::vector<double> pts;
+        for (int64_t i = 0; i < fine->n_dofs; ++i) {
+            if (fine->constrained[(size_t)i]) continue;
+            T->h_point_dof.push_back((int32_t)i);
+            for (int a = 0; a < dim; ++a) pts.push_back(fine->support[(size_t)(i * dim + a)]);
+        }
+        const int64_t np = (int64_t)T->h_point_dof.size();
+        T->n_points = np;
+        if (np > INT32_MAX) fail(NNMG_ERR_UNSUPPORTED, "too many points");
+
+        // grown boxes of the coarse cells
+        const int64_t C = coarse->n_cells;
+        std::vector<double> boxes((size_t)(C * 2 * dim));
+        double glo[3] = {1e300, 1e300, 1e300}, ghi[3] = {-1e300, -1e300, -1e300};
+        std::vector<double> ext[3];
+        for (int a = 0; a < dim; ++a) ext[a].resize((size_t)C);
+        for (int64_t c = 0; c < C; ++c) {
+            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+            for (int b = 0; b < nv; ++b) {
+                const int32_t v = coarse->cells[(size_t)(c * nv + b)];
+                for (int a = 0; a < dim; ++a) {
+                    const double x = coarse->vertices[(size_t)(v * dim + a)];
+                    lo[a] = std::min(lo[a], x);
+                    hi[a] = std::max(hi[a], x);
+                }
+            }
+            double d2 = 0.0;
+            for (int a = 0; a < dim; ++a) d2 = d2 + (hi[a] - lo[a]) * (hi[a] - lo[a]);
+            const double diag = std::sqrt(d2);
+            for (int a = 0; a < dim; ++a) {
+                const double l = lo[a] - o.bbox_expand * diag, h = hi[a] + o.bbox_expand * diag;
+                boxes[(size_t)((c * 2 + 0) * dim + a)] = l;
+                boxes[(size_t)((c * 2 + 1) * dim + a)] = h;
+                glo[a] = std::min(glo[a], l);
+                ghi[a] = std::max(ghi[a], h);
+                ext[a][(size_t)c] = h - l;
+            }
+        }
+        for (int64_t i = 0; i < np; ++i)
+            for (int a = 0; a < dim; ++a) {
+                glo[a] = std::min(glo[a], pts[(size_t)(i * dim + a)]);
+                ghi[a] = std::max(ghi[a], pts[(size_t)(i * dim + a)]);
+            }
+        // bucket size: half the median grown-box extent per axis
+        double step[3];
+        int nb[3] = {1, 1, 1};
+        for (int a = 0; a < dim; ++a) {
+            std::vector<double> e = ext[a];
+            std::nth_element(e.begin(), e.begin() + e.size() / 2, e.end());
+            const double size = std::max(0.5 * e[e.size() / 2], 1e-300);
+            const double span = std::max(ghi[a] - glo[a], 1e-300);
+            nb[a] = (int)std::min(1024.0, std::max(1.0, std::ceil(span / size)));
+            step[a] = span / nb[a];
+        }
+        int64_t nbt = 1;
+        for (int a = 0; a < dim; ++a) nbt *= nb[a];
+        auto bidx = [&](double x, int a) {
+            int k = (int)std::floor((x - glo[a]) / step[a]);
+            return std::min(std::max(k, 0), nb[a] - 1);
+        };
+        std::vector<int32_t> boff((size_t)(nbt + 1), 0);
+        std::vector<int> lo_b((size_t)(C * dim)), hi_b((size_t)(C * dim));
+        for (int64_t c = 0; c < C; ++c)
+            for (int a = 0; a < dim; ++a) {
+                lo_b[(size_t)(c * dim + a)] = bidx(boxes[(size_t)((c * 2 + 0) * dim + a)], a);
+                hi_b[(size_t)(c * dim + a)] = bidx(boxes[(size_t)((c * 2 + 1) * dim + a)], a);
+            }
+        auto for_buckets = [&](int64_t c, auto&& fn) {
+            const int* l = &lo_b[(size_t)(c * dim)];
+            const int* h = &hi_b[(size_t)(c * dim)];
+            for (int z = (dim == 3 ? l[2] : 0); z <= (dim == 3 ? h[2] : 0); ++z)
+                for (int y = l[1]; y <= h[1]; ++y)
+                    for (int x = l[0]; x <= h[0]; ++x) fn((int64_t)x + (int64_t)nb[0] * (y + (int64_t)nb[1] * z));
+        };
+        for (int64_t c = 0; c < C; ++c) for_buckets(c, [&](int64_t b) { boff[(size_t)(b + 1)]++; });
+        for (int64_t b = 0; b < nbt; ++b) boff[(size_t)(b + 1)] += boff[(size_t)b];
+        std::vector<int32_t> bcells((size_t)boff[(size_t)nbt]);
+        {
+            std::vector<int32_t> cur(boff.begin(), boff.end() - 1);
+            for (int64_t c = 0; c < C; ++c) for_buckets(c, [&](int64_t b) { bcells[(size_t)cur[(size_t)b]++] = (int32_t)c; });
+        }
+
+        // locate on the GPU
+        DeviceArray<double> d_pts, d_boxes, d_xi;
+        DeviceArray<int32_t> d_boff, d_bcells, d_owner, d_flags;
+        d_pts.upload(ctx, pts);
+        d_boxes.upload(ctx, boxes);
+        d_boff.upload(ctx, boff);
+        d_bcells.upload(ctx, bcells);
+        d_owner.alloc(ctx, (size_t)np);
+        d_flags.alloc(ctx, (size_t)np);
+        d_xi.alloc(ctx, (size_t)(np * dim));
+        launch_locate(dim, d_pts.ptr, (int)np, coarse->d_cellverts.ptr, d_boxes.ptr, d_boff.ptr, d_bcells.ptr, glo,
+                      step, nb, o.inside_tol, o.newton_tol, o.newton_max_it, d_owner.ptr, d_xi.ptr, d_flags.ptr,
+                      nullptr);
+        NNMG_HIP(hipDeviceSynchronize());
+        T->h_point_owner = d_owner.download();
+        T->h_point_xi = d_xi.download();
+        const std::vector<int32_t> flags = d_flags.download();
+        int64_t missing = 0, projected = 0;
+        for (int64_t i = 0; i < np; ++i) {
+            if (T->h_point_owner[(size_t)i] < 0) ++missing;
+            if (flags[(size_t)i]) ++projected;
+        }
+        if (missing) fail(NNMG_ERR_POINT_NOT_FOUND, std::to_string(missing) + " fine points have no candidate coarse cell");
+        if (projected && !o.allow_projection)
+            fail(NNMG_ERR_POINT_NOT_FOUND, std::to_string(projected) + " fine points lie outside the coarse mesh");
+        T->n_projected = projected;
+
+        // group by owner (stable counting sort)
+        std::vector<int32_t> off((size_t)(C + 1), 0);
+        for (int64_t i = 0; i < np; ++i) off[(size_t)T->h_point_owner[(size_t)i] + 1]++;
+        for (int64_t c = 0; c < C; ++c) off[(size_t)(c + 1)] += off[(size_t)c];
+        std::vector<int32_t> fidx((size_t)np);
+        std::vector<double> xi64((size_t)(np * dim));
+        std::vector<float> xi32((size_t)(np * dim));
+        {
+            std::vector<int32_t> cur(off.begin(), off.end() - 1);
+            for (int64_t i = 0; i < np; ++i) {
+                const int32_t p = cur[(size_t)T->h_point_owner[(size_t)i]]++;
+                fidx[(size_t)p] = T->h_point_dof[(size_t)i];
+                for (int a = 0; a < dim; ++a) {
+                    const double x = T->h_point_xi[(size_t)(i * dim + a)];
+                    xi64[(size_t)(a * np + p)] = x;
+                    xi32[(size_t)(a * np + p)] = (float)x;
+                }
+            }
+        }
+        T->d_off.upload(ctx, off);
+        T->d_fine.upload(ctx, fidx);
+        T->d_xi64.upload(ctx, xi64);
+        T->d_xi32.upload(ctx, xi32);
+        // lanes per coarse cell: about half the average number of points, 4..64
+        const double avg = C ? (double)np / (double)C : 0.0;
+        int team = 4;
+        while (team < 64 && 2.0 * (2 * team) <= avg) team *= 2;
+        T->team = team;
+    } catch (...) {
+        level_release(T->fine);
+        level_release(T->coarse);
+        delete T;
+        throw;
+    }
+    return T;
+}
+
+void transfer_retain(Transfer* t) { t->refs.fetch_add(1); }
+
+void transfer_release(Transfer* t) {
+    if (!t || t->refs.fetch_sub(1) != 1) return;
+    Level* f = t->fine;
+    Level* c = t->coarse;
+    delete static_cast<nnmg_transfer*>(t);
+    level_release(f);
+    level_release(c);
+}
+
+}  // namespace nnmg

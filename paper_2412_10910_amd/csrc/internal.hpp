@@ -1,0 +1,226 @@
+// Internal declarations shared by the host orchestration and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nnmg.h"
+
+namespace nnmg {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+
+#define NNMG_HIP(call)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            ::nnmg::fail(NNMG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// context and device memory
+// ---------------------------------------------------------------------------
+struct Ctx {
+    int device = 0;
+    nnmg_allocator alloc{};
+    bool custom = false;
+    void* allocate(size_t bytes);
+    void release(void* p);
+};
+
+template <class T>
+struct DeviceArray {
+    Ctx* ctx = nullptr;
+    T* ptr = nullptr;
+    size_t n = 0;
+    DeviceArray() = default;
+    DeviceArray(const DeviceArray&) = delete;
+    DeviceArray& operator=(const DeviceArray&) = delete;
+    DeviceArray(DeviceArray&& o) noexcept { swap(o); }
+    DeviceArray& operator=(DeviceArray&& o) noexcept {
+        reset();
+        swap(o);
+        return *this;
+    }
+    ~DeviceArray() { reset(); }
+    void swap(DeviceArray& o) noexcept {
+        std::swap(ctx, o.ctx);
+        std::swap(ptr, o.ptr);
+        std::swap(n, o.n);
+    }
+    void reset() {
+        if (ptr) ctx->release(ptr);
+        ptr = nullptr;
+        n = 0;
+    }
+    void alloc(Ctx* c, size_t count) {
+        reset();
+        ctx = c;
+        n = count;
+        if (count) ptr = static_cast<T*>(c->allocate(count * sizeof(T)));
+    }
+    void upload(Ctx* c, const T* host, size_t count) {
+        alloc(c, count);
+        if (count) NNMG_HIP(hipMemcpy(ptr, host, count * sizeof(T), hipMemcpyHostToDevice));
+    }
+    void upload(Ctx* c, const std::vector<T>& v) { upload(c, v.data(), v.size()); }
+    std::vector<T> download() const {
+        std::vector<T> out(n);
+        if (n) NNMG_HIP(hipMemcpy(out.data(), ptr, n * sizeof(T), hipMemcpyDeviceToHost));
+        return out;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+// ---------------------------------------------------------------------------
+// 1D tables of the Q_k element (Gauss points, Gauss-Lobatto nodes)
+// ---------------------------------------------------------------------------
+constexpr int kMaxN = 5;
+
+struct Basis1D {
+    int n = 0;                      // k + 1
+    double gauss[kMaxN]{};          // Gauss-Legendre points on [0,1]
+    double weight[kMaxN]{};         // and weights
+    double node[kMaxN]{};           // Gauss-Lobatto support points on [0,1]
+    double bary[kMaxN]{};           // barycentric weights 1 / prod_{m!=a}(x_a - x_m)
+    double S[kMaxN][kMaxN]{};       // S[q][a]  = phi_a(g_q)   nodal basis at Gauss points
+    double DS[kMaxN][kMaxN]{};      // DS[q][a] = phi_a'(g_q)
+    double D[kMaxN][kMaxN]{};       // D[q][p]  = psi_p'(g_q)  collocation derivative on Gauss points
+};
+
+Basis1D make_basis(int degree);
+
+// ---------------------------------------------------------------------------
+// a level: one mesh and its Q_k space
+// ---------------------------------------------------------------------------
+struct Level {
+    Ctx* ctx = nullptr;
+    std::atomic<int> refs{1};
+    int dim = 0, degree = 0, n = 0, q = 0;
+    int cpw = 0;        // cells per 64-lane block in the operator kernel layout
+    int64_t nblocks = 0;
+    int64_t n_cells = 0, n_dofs = 0, n_free = 0;
+    Basis1D basis;
+
+    std::vector<double> vertices;    // [V][dim]
+    std::vector<int32_t> cells;      // [C][2^dim]
+    std::vector<double> support;     // [N][dim]
+    std::vector<int32_t> dofmap;     // [C][q] global DoF of every local node
+    std::vector<uint8_t> constrained;  // [N]
+    std::vector<int32_t> constrained_idx;
+
+    DeviceArray<int32_t> d_dofmap;      // [C][q], -1 for constrained DoFs
+    DeviceArray<int32_t> d_dofmap_blk;  // operator layout, -1 for constrained / padding
+    DeviceArray<double> d_metric64;     // operator layout [blk][M][q/n][64]
+    DeviceArray<float> d_metric32;
+    DeviceArray<double> d_cellverts;    // [C][2^dim][dim]
+    DeviceArray<int32_t> d_constrained;
+    DeviceArray<double> d_dinv64;       // inverse diagonal, 0 on constrained
+    DeviceArray<float> d_dinv32;
+};
+
+void level_retain(Level* l);
+void level_release(Level* l);
+
+// ---------------------------------------------------------------------------
+// a transfer between a fine and a coarse level
+// ---------------------------------------------------------------------------
+struct Transfer {
+    Ctx* ctx = nullptr;
+    std::atomic<int> refs{1};
+    Level* fine = nullptr;
+    Level* coarse = nullptr;
+    int64_t n_points = 0, n_projected = 0;
+    int max_newton = 0;
+    int team = 16;  // lanes per coarse cell in the transfer kernels
+    std::vector<int32_t> h_point_dof;    // fine DoF per point, fine-DoF order
+    std::vector<int32_t> h_point_owner;  // owner per point, fine-DoF order
+    std::vector<double> h_point_xi;      // [n_points][dim], fine-DoF order
+    DeviceArray<int32_t> d_off;          // [C_coarse + 1] points grouped by owner
+    DeviceArray<int32_t> d_fine;         // [n_points] fine DoF, grouped by owner
+    DeviceArray<double> d_xi64;          // [dim][n_points], grouped by owner
+    DeviceArray<float> d_xi32;
+};
+
+void transfer_retain(Transfer* t);
+void transfer_release(Transfer* t);
+
+// ---------------------------------------------------------------------------
+// kernel launchers (kernels/*.hip)
+// ---------------------------------------------------------------------------
+void launch_fill(void* x, size_t n, int prec, hipStream_t s);  // prec: 0 double, 1 float
+void launch_cast_64_to_32(const double* a, float* b, size_t n, hipStream_t s);
+void launch_cast_32_to_64(const float* a, double* b, size_t n, hipStream_t s);
+void launch_set_constrained(const int32_t* idx, size_t n, double v, void* dst, int prec, hipStream_t s);
+void launch_lincomb(size_t n, double a, const double* x, double b, double* y, hipStream_t s);  // y = a x + b y
+void launch_copy_constrained(const int32_t* idx, size_t n, const void* src, void* dst, int prec,
+                             hipStream_t s);
+
+// operator apply: dst += A src over the cells (constrained rows untouched)
+void launch_vmult_cells(const Level& L, int prec, const void* src, void* dst, hipStream_t s);
+// geometry, diagonal, right-hand side (setup kernels)
+void launch_geometry(Level& L, int* d_bad, hipStream_t s);
+void launch_diagonal(const Level& L, double* diag, hipStream_t s);
+void launch_invert_diagonal(const Level& L, const double* diag, hipStream_t s);
+void launch_assemble_rhs(const Level& L, const double* fq, double* b, hipStream_t s);
+
+// transfer
+void launch_locate(int dim, const double* pts, int np, const double* cverts, const double* boxes,
+                   const int32_t* boff, const int32_t* bcells, const double* glo, const double* gstep,
+                   const int* gnb, double inside_tol, double newton_tol, int newton_max_it,
+                   int32_t* owner, double* xi, int32_t* flags, hipStream_t s);
+void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fine, hipStream_t s);
+void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, hipStream_t s);
+
+// vector kernels for the smoother and CG
+// x = d = dinv * f * c0   (first step from a zero guess)
+void launch_cheb_first_zero(int prec, size_t n, const void* f, const void* dinv, void* x, void* d,
+                            double c0, hipStream_t s);
+// r = f - ax; ax = 0; d = c1 d + c2 dinv r (c1 = 0 for a first step); x += d
+void launch_cheb_step(int prec, size_t n, const void* f, void* ax, const void* dinv, void* x, void* d,
+                      double c1, double c2, hipStream_t s);
+// r = f - ax; ax = 0
+void launch_residual(int prec, size_t n, const void* f, void* ax, void* r, hipStream_t s);
+// y += x
+void launch_add(int prec, size_t n, const void* x, void* y, hipStream_t s);
+void launch_splitmix_vector(double* v, const uint8_t* mask_free, size_t n, uint64_t seed, hipStream_t s);
+
+// float64 reductions: out = sum_i a_i b_i (two-stage, deterministic)
+void launch_dot(const double* a, const double* b, size_t n, double* partial, double* out, hipStream_t s);
+size_t dot_partials(size_t n);
+// CG kernels; scal layout documented in hierarchy.cpp
+void launch_cg_update(size_t n, double* x, double* r, const double* p, const double* q, const double* scal,
+                      double* partial, double* rr_out, hipStream_t s);
+void launch_cg_direction(size_t n, const double* z, double* p, const double* scal, hipStream_t s);
+void launch_scalar_op(double* scal, int op, hipStream_t s);
+void launch_jacobi(size_t n, const double* dinv, const double* r, double* z, hipStream_t s);
+void launch_axpy(size_t n, double a_sign, const double* scal_a, int idx, const double* x, double* y,
+                 hipStream_t s);
+
+// dense coarse solve
+void launch_gather_free(const int32_t* free_idx, size_t m, const double* x, double* xf, hipStream_t s);
+void launch_scatter_free(const int32_t* free_idx, size_t m, const double* xf, double* x, hipStream_t s);
+void launch_gemv(const double* M, size_t m, const double* x, double* y, hipStream_t s);
+void launch_gauss_jordan(double* M, size_t m, double* rowbuf, double* colbuf, hipStream_t s);
+void launch_column_from_unit(const int32_t* free_idx, size_t m, const double* ax, double* M, size_t col,
+                             hipStream_t s);
+void launch_set_unit(double* x, size_t n, int64_t idx, double val, hipStream_t s);
+
+}  // namespace nnmg
+
+// the opaque handles of the C ABI are the internal objects themselves
+struct nnmg_ctx : nnmg::Ctx {};
+struct nnmg_level : nnmg::Level {};
+struct nnmg_transfer : nnmg::Transfer {};

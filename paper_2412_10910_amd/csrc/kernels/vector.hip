@@ -1,0 +1,445 @@
+// Vector kernels of the smoother, the V-cycle and CG, and the dense
+// float64 coarse solve.
+//
+// The Chebyshev-Jacobi smoother (paper §4: point Jacobi inside a degree-3
+// Chebyshev iteration) is the three-term recurrence of the Chebyshev
+// semi-iteration on D^{-1} A (Saad, Iterative Methods for Sparse Linear
+// Systems, Alg. 12.1); every step fuses residual, direction and solution
+// updates into one pass and clears the operator output buffer for the next
+// product.
+#include "../internal.hpp"
+#include "common.hpp"
+
+namespace nnmg {
+
+static dim3 grid_for(size_t n, int threads = 256, size_t cap = 1 << 20) {
+    size_t g = (n + threads - 1) / threads;
+    if (g > cap) g = cap;
+    if (g == 0) g = 1;
+    return dim3((unsigned)g);
+}
+
+template <class T>
+__global__ void fill_kernel(T* __restrict__ x, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        x[i] = T(0);
+}
+
+void launch_fill(void* x, size_t n, int prec, hipStream_t s) {
+    if (n == 0) return;
+    if (prec == NNMG_FP64)
+        hipLaunchKernelGGL(fill_kernel<double>, grid_for(n), dim3(256), 0, s, (double*)x, n);
+    else
+        hipLaunchKernelGGL(fill_kernel<float>, grid_for(n), dim3(256), 0, s, (float*)x, n);
+    NNMG_HIP(hipGetLastError());
+}
+
+template <class A, class B>
+__global__ void cast_kernel(const A* __restrict__ a, B* __restrict__ b, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = (B)a[i];
+}
+
+void launch_cast_64_to_32(const double* a, float* b, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL((cast_kernel<double, float>), grid_for(n), dim3(256), 0, s, a, b, n);
+    NNMG_HIP(hipGetLastError());
+}
+
+void launch_cast_32_to_64(const float* a, double* b, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL((cast_kernel<float, double>), grid_for(n), dim3(256), 0, s, a, b, n);
+    NNMG_HIP(hipGetLastError());
+}
+
+template <class T>
+__global__ void copy_idx_kernel(const int32_t* __restrict__ idx, size_t n, const T* __restrict__ src,
+                                T* __restrict__ dst) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < n) dst[idx[i]] = src[idx[i]];
+}
+
+void launch_copy_constrained(const int32_t* idx, size_t n, const void* src, void* dst, int prec, hipStream_t s) {
+    if (n == 0) return;
+    const dim3 g((unsigned)((n + 255) / 256));
+    if (prec == NNMG_FP64)
+        hipLaunchKernelGGL(copy_idx_kernel<double>, g, dim3(256), 0, s, idx, n, (const double*)src, (double*)dst);
+    else
+        hipLaunchKernelGGL(copy_idx_kernel<float>, g, dim3(256), 0, s, idx, n, (const float*)src, (float*)dst);
+    NNMG_HIP(hipGetLastError());
+}
+
+template <class T>
+__global__ void set_idx_kernel(const int32_t* __restrict__ idx, size_t n, T v, T* __restrict__ dst) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < n) dst[idx[i]] = v;
+}
+
+void launch_set_constrained(const int32_t* idx, size_t n, double v, void* dst, int prec, hipStream_t s) {
+    if (n == 0) return;
+    const dim3 g((unsigned)((n + 255) / 256));
+    if (prec == NNMG_FP64)
+        hipLaunchKernelGGL(set_idx_kernel<double>, g, dim3(256), 0, s, idx, n, v, (double*)dst);
+    else
+        hipLaunchKernelGGL(set_idx_kernel<float>, g, dim3(256), 0, s, idx, n, (float)v, (float*)dst);
+    NNMG_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev smoother steps
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void cheb_first_zero_kernel(size_t n, const T* __restrict__ f, const T* __restrict__ dinv,
+                                       T* __restrict__ x, T* __restrict__ d, T c0) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const T v = dinv[i] * f[i] * c0;
+        d[i] = v;
+        x[i] = v;
+    }
+}
+
+void launch_cheb_first_zero(int prec, size_t n, const void* f, const void* dinv, void* x, void* d, double c0,
+                            hipStream_t s) {
+    if (n == 0) return;
+    if (prec == NNMG_FP64)
+        hipLaunchKernelGGL(cheb_first_zero_kernel<double>, grid_for(n), dim3(256), 0, s, n, (const double*)f,
+                           (const double*)dinv, (double*)x, (double*)d, c0);
+    else
+        hipLaunchKernelGGL(cheb_first_zero_kernel<float>, grid_for(n), dim3(256), 0, s, n, (const float*)f,
+                           (const float*)dinv, (float*)x, (float*)d, (float)c0);
+    NNMG_HIP(hipGetLastError());
+}
+
+template <class T>
+__global__ void cheb_step_kernel(size_t n, const T* __restrict__ f, T* __restrict__ ax, const T* __restrict__ dinv,
+                                 T* __restrict__ x, T* __restrict__ d, T c1, T c2) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const T r = f[i] - ax[i];
+        ax[i] = T(0);
+        const T dn = c1 * d[i] + c2 * (dinv[i] * r);
+        d[i] = dn;
+        x[i] += dn;
+    }
+}
+
+void launch_cheb_step(int prec, size_t n, const void* f, void* ax, const void* dinv, void* x, void* d, double c1,
+                      double c2, hipStream_t s) {
+    if (n == 0) return;
+    if (prec == NNMG_FP64)
+        hipLaunchKernelGGL(cheb_step_kernel<double>, grid_for(n), dim3(256), 0, s, n, (const double*)f,
+                           (double*)ax, (const double*)dinv, (double*)x, (double*)d, c1, c2);
+    else
+        hipLaunchKernelGGL(cheb_step_kernel<float>, grid_for(n), dim3(256), 0, s, n, (const float*)f, (float*)ax,
+                           (const float*)dinv, (float*)x, (float*)d, (float)c1, (float)c2);
+    NNMG_HIP(hipGetLastError());
+}
+
+template <class T>
+__global__ void residual_kernel(size_t n, const T* __restrict__ f, T* __restrict__ ax, T* __restrict__ r) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        r[i] = f[i] - ax[i];
+        ax[i] = T(0);
+    }
+}
+
+void launch_residual(int prec, size_t n, const void* f, void* ax, void* r, hipStream_t s) {
+    if (n == 0) return;
+    if (prec == NNMG_FP64)
+        hipLaunchKernelGGL(residual_kernel<double>, grid_for(n), dim3(256), 0, s, n, (const double*)f, (double*)ax,
+                           (double*)r);
+    else
+        hipLaunchKernelGGL(residual_kernel<float>, grid_for(n), dim3(256), 0, s, n, (const float*)f, (float*)ax,
+                           (float*)r);
+    NNMG_HIP(hipGetLastError());
+}
+
+template <class T>
+__global__ void add_kernel(size_t n, const T* __restrict__ x, T* __restrict__ y) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] += x[i];
+}
+
+void launch_add(int prec, size_t n, const void* x, void* y, hipStream_t s) {
+    if (n == 0) return;
+    if (prec == NNMG_FP64)
+        hipLaunchKernelGGL(add_kernel<double>, grid_for(n), dim3(256), 0, s, n, (const double*)x, (double*)y);
+    else
+        hipLaunchKernelGGL(add_kernel<float>, grid_for(n), dim3(256), 0, s, n, (const float*)x, (float*)y);
+    NNMG_HIP(hipGetLastError());
+}
+
+__global__ void lincomb_kernel(size_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = a * x[i] + b * y[i];
+}
+
+void launch_lincomb(size_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(lincomb_kernel, grid_for(n), dim3(256), 0, s, n, a, x, b, y);
+    NNMG_HIP(hipGetLastError());
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): z = seed + (i+1) * golden gamma, then
+// the mixing function; mapped to [-1, 1) from the top 53 bits.
+__global__ void splitmix_kernel(double* __restrict__ v, const int32_t* __restrict__ dm_unused, size_t n,
+                                uint64_t seed) {
+    (void)dm_unused;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z = z ^ (z >> 31);
+        v[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+}
+
+void launch_splitmix_vector(double* v, const uint8_t* unused, size_t n, uint64_t seed, hipStream_t s) {
+    (void)unused;
+    if (n == 0) return;
+    hipLaunchKernelGGL(splitmix_kernel, grid_for(n), dim3(256), 0, s, v, nullptr, n, seed);
+    NNMG_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// float64 reductions, two stages with a fixed partition: deterministic
+// ---------------------------------------------------------------------------
+constexpr int kRedThreads = 256;
+constexpr size_t kRedMaxBlocks = 1024;
+
+size_t dot_partials(size_t n) {
+    size_t g = (n + kRedThreads * 4 - 1) / (kRedThreads * 4);
+    if (g > kRedMaxBlocks) g = kRedMaxBlocks;
+    if (g == 0) g = 1;
+    return g;
+}
+
+__device__ inline double block_sum(double v) {
+    __shared__ double sh[kRedThreads / kWave];
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kRedThreads / kWave; ++i) s += sh[i];
+    return s;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(kRedThreads) void dot_stage1(const double* __restrict__ a, const double* __restrict__ b,
+                                                          size_t n, double* __restrict__ partial) {
+    double s = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        s += a[i] * b[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kRedThreads) void sum_stage2(const double* __restrict__ partial, size_t m,
+                                                          double* __restrict__ out) {
+    double s = 0.0;
+    for (size_t i = threadIdx.x; i < m; i += blockDim.x) s += partial[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) *out = s;
+}
+
+void launch_dot(const double* a, const double* b, size_t n, double* partial, double* out, hipStream_t s) {
+    const size_t g = dot_partials(n);
+    hipLaunchKernelGGL(dot_stage1, dim3((unsigned)g), dim3(kRedThreads), 0, s, a, b, n, partial);
+    hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(kRedThreads), 0, s, partial, g, out);
+    NNMG_HIP(hipGetLastError());
+}
+
+// scal: [0] rz, [1] pq, [2] alpha, [3] rr, [4] rz_new, [5] beta
+__global__ __launch_bounds__(kRedThreads) void cg_update_stage1(size_t n, double* __restrict__ x,
+                                                                double* __restrict__ r, const double* __restrict__ p,
+                                                                const double* __restrict__ q,
+                                                                const double* __restrict__ scal,
+                                                                double* __restrict__ partial) {
+    const double alpha = scal[2];
+    double s = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        x[i] += alpha * p[i];
+        const double rn = r[i] - alpha * q[i];
+        r[i] = rn;
+        s += rn * rn;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+void launch_cg_update(size_t n, double* x, double* r, const double* p, const double* q, const double* scal,
+                      double* partial, double* rr_out, hipStream_t s) {
+    const size_t g = dot_partials(n);
+    hipLaunchKernelGGL(cg_update_stage1, dim3((unsigned)g), dim3(kRedThreads), 0, s, n, x, r, p, q, scal, partial);
+    hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(kRedThreads), 0, s, partial, g, rr_out);
+    NNMG_HIP(hipGetLastError());
+}
+
+__global__ void cg_direction_kernel(size_t n, const double* __restrict__ z, double* __restrict__ p,
+                                    const double* __restrict__ scal) {
+    const double beta = scal[5];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + beta * p[i];
+}
+
+void launch_cg_direction(size_t n, const double* z, double* p, const double* scal, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(cg_direction_kernel, grid_for(n), dim3(256), 0, s, n, z, p, scal);
+    NNMG_HIP(hipGetLastError());
+}
+
+// op 0: alpha = rz / pq;  op 1: beta = rz_new / rz, rz = rz_new
+__global__ void scalar_kernel(double* scal, int op) {
+    if (threadIdx.x != 0) return;
+    if (op == 0) {
+        scal[2] = scal[0] / scal[1];
+    } else {
+        scal[5] = scal[4] / scal[0];
+        scal[0] = scal[4];
+    }
+}
+
+void launch_scalar_op(double* scal, int op, hipStream_t s) {
+    hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(1), 0, s, scal, op);
+    NNMG_HIP(hipGetLastError());
+}
+
+__global__ void jacobi_kernel(size_t n, const double* __restrict__ dinv, const double* __restrict__ r,
+                              double* __restrict__ z) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        z[i] = dinv[i] * r[i];
+}
+
+void launch_jacobi(size_t n, const double* dinv, const double* r, double* z, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(jacobi_kernel, grid_for(n), dim3(256), 0, s, n, dinv, r, z);
+    NNMG_HIP(hipGetLastError());
+}
+
+// y += sign * scal[idx] * x
+__global__ void axpy_kernel(size_t n, double sign, const double* __restrict__ scal, int idx,
+                            const double* __restrict__ x, double* __restrict__ y) {
+    const double a = sign * scal[idx];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] += a * x[i];
+}
+
+void launch_axpy(size_t n, double a_sign, const double* scal_a, int idx, const double* x, double* y,
+                 hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(axpy_kernel, grid_for(n), dim3(256), 0, s, n, a_sign, scal_a, idx, x, y);
+    NNMG_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// dense coarse solve: explicit inverse of the unconstrained block
+// ---------------------------------------------------------------------------
+__global__ void gather_free_kernel(const int32_t* __restrict__ idx, size_t m, const double* __restrict__ x,
+                                   double* __restrict__ xf) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < m) xf[i] = x[idx[i]];
+}
+
+void launch_gather_free(const int32_t* free_idx, size_t m, const double* x, double* xf, hipStream_t s) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(gather_free_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, free_idx, m, x, xf);
+    NNMG_HIP(hipGetLastError());
+}
+
+__global__ void scatter_free_kernel(const int32_t* __restrict__ idx, size_t m, const double* __restrict__ xf,
+                                    double* __restrict__ x) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < m) x[idx[i]] = xf[i];
+}
+
+void launch_scatter_free(const int32_t* free_idx, size_t m, const double* xf, double* x, hipStream_t s) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(scatter_free_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, free_idx, m, xf, x);
+    NNMG_HIP(hipGetLastError());
+}
+
+// y = M x, M row-major m x m; one wavefront per row, coalesced row reads
+__global__ __launch_bounds__(256) void gemv_kernel(const double* __restrict__ M, size_t m,
+                                                   const double* __restrict__ x, double* __restrict__ y) {
+    const size_t row = blockIdx.x * (size_t)(blockDim.x / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    if (row >= m) return;
+    const double* a = M + row * m;
+    double s = 0.0;
+    for (size_t j = lane; j < m; j += kWave) s += a[j] * x[j];
+    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kWave);
+    if (lane == 0) y[row] = s;
+}
+
+void launch_gemv(const double* M, size_t m, const double* x, double* y, hipStream_t s) {
+    if (m == 0) return;
+    const size_t rows_per_block = 256 / kWave;
+    hipLaunchKernelGGL(gemv_kernel, dim3((unsigned)((m + rows_per_block - 1) / rows_per_block)), dim3(256), 0, s,
+                       M, m, x, y);
+    NNMG_HIP(hipGetLastError());
+}
+
+// in-place Gauss-Jordan inversion of a symmetric positive definite matrix
+// (no pivoting needed: every pivot is a Schur-complement diagonal entry)
+__global__ void gj_save_kernel(const double* __restrict__ M, size_t m, size_t k, double* __restrict__ row,
+                               double* __restrict__ col) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < m) {
+        row[i] = M[k * m + i];
+        col[i] = M[i * m + k];
+    }
+}
+
+__global__ void gj_update_kernel(double* __restrict__ M, size_t m, size_t k, const double* __restrict__ row,
+                                 const double* __restrict__ col) {
+    const size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t i = blockIdx.y;
+    if (j >= m) return;
+    const double piv = row[k];
+    double v;
+    if (i == k && j == k)
+        v = 1.0 / piv;
+    else if (i == k)
+        v = row[j] / piv;
+    else if (j == k)
+        v = -col[i] / piv;
+    else
+        v = M[i * m + j] - col[i] * row[j] / piv;
+    M[i * m + j] = v;
+}
+
+void launch_gauss_jordan(double* M, size_t m, double* rowbuf, double* colbuf, hipStream_t s) {
+    if (m == 0) return;
+    const dim3 g1((unsigned)((m + 255) / 256));
+    const dim3 g2((unsigned)((m + 255) / 256), (unsigned)m);
+    for (size_t k = 0; k < m; ++k) {
+        hipLaunchKernelGGL(gj_save_kernel, g1, dim3(256), 0, s, M, m, k, rowbuf, colbuf);
+        hipLaunchKernelGGL(gj_update_kernel, g2, dim3(256), 0, s, M, m, k, rowbuf, colbuf);
+    }
+    NNMG_HIP(hipGetLastError());
+}
+
+__global__ void column_kernel(const int32_t* __restrict__ idx, size_t m, const double* __restrict__ ax,
+                              double* __restrict__ M, size_t col) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < m) M[i * m + col] = ax[idx[i]];
+}
+
+void launch_column_from_unit(const int32_t* free_idx, size_t m, const double* ax, double* M, size_t col,
+                             hipStream_t s) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(column_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, free_idx, m, ax, M, col);
+    NNMG_HIP(hipGetLastError());
+}
+
+__global__ void set_unit_kernel(double* x, int64_t idx, double val) {
+    if (threadIdx.x == 0) x[idx] = val;
+}
+
+void launch_set_unit(double* x, size_t n, int64_t idx, double val, hipStream_t s) {
+    (void)n;
+    hipLaunchKernelGGL(set_unit_kernel, dim3(1), dim3(64), 0, s, x, idx, val);
+    NNMG_HIP(hipGetLastError());
+}
+
+}  // namespace nnmg

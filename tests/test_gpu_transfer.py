@@ -1,0 +1,116 @@
+"""GPU parity of point location, prolongation and restriction against the oracle.
+
+Bar: float64 within 1e-12 relative to the largest reference entry; the owner
+cells agree exactly except where a point lies on a shared face, edge or vertex
+within rounding (then the FE function is continuous and the values agree);
+float32 within 2e-5.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import transfer
+from workloads import ball_map, config_levels, perturb_interior, random_vector, scramble, structured_box
+
+from _parity import Pair, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 2e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2412_10910_amd as nn
+    return nn.Context(0)
+
+
+def _mesh(dim, n, alpha, seed, scram=False, ball=False):
+    if ball:
+        m = ball_map(structured_box(dim, n, -1.0, 1.0))
+    else:
+        m = structured_box(dim, n)
+        if alpha:
+            m = perturb_interior(m, alpha, 1.0 / n, np.random.default_rng(seed))
+    if scram:
+        m = scramble(m, np.random.default_rng(seed + 1))
+    return m
+
+
+TRANSFER_CASES = [
+    (2, 1, 17, 7, False), (2, 2, 9, 4, True), (2, 4, 7, 3, False),
+    (3, 1, 9, 4, True), (3, 2, 8, 3, False), (3, 3, 5, 2, True), (3, 4, 4, 2, False),
+]
+
+
+def _check_transfer(ctx, fm, cm, k):
+    import paper_2412_10910_amd as nn
+    f, c = Pair(ctx, fm, k), Pair(ctx, cm, k)
+    tr = nn.Transfer(ctx, f.lib, c.lib)
+    P, info = transfer.prolongation(f.orc, c.orc)
+    # point data: the same points, owners and reference coordinates
+    pts = tr.points()
+    assert pts["fine_dof"].size == info["points"].size
+    orc_of = f.perm[pts["fine_dof"]]
+    order = np.argsort(info["points"])
+    pos = order[np.searchsorted(info["points"], orc_of, sorter=order)]
+    assert np.array_equal(info["points"][pos], orc_of)
+    same = pts["owner"] == info["owner"][pos]
+    assert same.mean() > 0.5
+    assert np.abs(pts["xi"][same] - info["ref"][pos][same]).max() <= 1e-12
+    assert pts["n_projected"] == int(info["projected"].sum())
+    # prolongation and restriction
+    vc = np.where(c.orc.free, random_vector(c.orc.n_dofs, 5), 0.0)
+    rf = np.where(f.orc.free, random_vector(f.orc.n_dofs, 6), 0.0)
+    base = random_vector(f.orc.n_dofs, 7)
+    out = f.to_lib(base)
+    tr.prolongate(c.to_lib(vc), out)
+    assert rel_err(f.to_orc(out) - base, P @ vc) <= TOL64
+    rc = c.to_lib(np.zeros(c.orc.n_dofs))
+    tr.restrict(f.to_lib(rf), rc)
+    assert rel_err(c.to_orc(rc), P.T @ rf) <= TOL64
+    # float32
+    out32 = f.to_lib(np.zeros(f.orc.n_dofs), torch.float32)
+    tr.prolongate(c.to_lib(vc, torch.float32), out32)
+    assert rel_err(f.to_orc(out32), P @ vc) <= TOL32
+    rc32 = c.to_lib(np.zeros(c.orc.n_dofs), torch.float32)
+    tr.restrict(f.to_lib(rf, torch.float32), rc32)
+    assert rel_err(c.to_orc(rc32), P.T @ rf) <= TOL32
+    # adjoint of the library's own pair of kernels
+    a = float(torch.dot(f.to_lib(rf), tr.prolongate(c.to_lib(vc), f.to_lib(np.zeros(f.orc.n_dofs)))))
+    b = float(torch.dot(c.to_lib(vc), tr.restrict(f.to_lib(rf), c.to_lib(np.zeros(c.orc.n_dofs)))))
+    assert abs(a - b) <= 1e-13 * max(abs(a), 1.0)
+    return tr, pts
+
+
+@pytest.mark.parametrize("dim,k,nf,nc,scram", TRANSFER_CASES)
+def test_transfer_nonnested_perturbed(ctx, dim, k, nf, nc, scram):
+    _check_transfer(ctx, _mesh(dim, nf, 0.2, 3 * nf, scram), _mesh(dim, nc, 0.2, 5 * nc, scram), k)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_transfer_ball_with_projection(ctx, k):
+    fm = _mesh(3, 7, 0.0, 0, ball=True)
+    cm = _mesh(3, 3, 0.0, 0, ball=True)
+    fm.dirichlet[:] = 0  # keep the boundary points: they need the projection
+    cm.dirichlet[:] = 0
+    tr, pts = _check_transfer(ctx, fm, cm, k)
+    assert pts["n_projected"] > 0
+
+
+def test_transfer_config1_coarse_pair(ctx):
+    """13^3 -> 6^3 of the 3D Q2 workload."""
+    ms = config_levels(1, cells=[6, 13])
+    _check_transfer(ctx, ms[1], ms[0], 2)
+
+
+def test_transfer_point_outside_is_an_error(ctx):
+    import paper_2412_10910_amd as nn
+    f = nn.Level.from_mesh(ctx, structured_box(2, 4, 0.0, 1.0), 1)
+    m = structured_box(2, 2, 0.0, 0.5)
+    c = nn.Level.from_mesh(ctx, m, 1)
+    with pytest.raises(nn.NNMGError) as e:
+        nn.Transfer(ctx, f, c)
+    assert e.value.name == "POINT_NOT_FOUND"
