@@ -170,6 +170,13 @@ int nnmg_level_assemble_rhs(nnmg_level* level, const double* f_qp_dev, double* b
  * unconstrained rows.  src and dst must not alias.  Asynchronous. */
 int nnmg_vmult(const nnmg_level* level, nnmg_prec prec, const void* src_dev, void* dst_dev, void* stream);
 
+/* dst += A_l src restricted to the unconstrained rows and columns: the cell
+ * loop of nnmg_vmult alone (constrained entries of src are read as zero and
+ * constrained entries of dst are left unchanged).  One kernel launch; used to
+ * accumulate several operator applications into one vector.  src and dst must
+ * not alias.  Asynchronous. */
+int nnmg_vmult_add(const nnmg_level* level, nnmg_prec prec, const void* src_dev, void* dst_dev, void* stream);
+
 /* Diagonal of A_l (1 on constrained rows) into diag_dev.  Asynchronous. */
 int nnmg_level_diagonal(const nnmg_level* level, nnmg_prec prec, void* diag_dev, void* stream);
 

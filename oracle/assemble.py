@@ -31,7 +31,11 @@ def element_matrices(space, cells: np.ndarray) -> np.ndarray:
     # physical gradient: grad phi = J^{-T} grad_ref  -> g[c, Q, i_dof, x]
     g = np.einsum("Qja,cQax->cQjx", grad_ref, Jinv)
     scale = detJ * wq[None, :]
-    return np.einsum("cQix,cQjx,cQ->cij", g, g, scale)
+    # K_ij = sum_{Q,x} g[Q,i,x] g[Q,j,x] scale[Q], as a batched product over cells
+    c, Q, q, d = g.shape
+    gt = g.transpose(0, 2, 1, 3).reshape(c, q, Q * d)
+    gs = (g * scale[:, :, None, None]).transpose(0, 2, 1, 3).reshape(c, q, Q * d)
+    return gt @ gs.transpose(0, 2, 1)
 
 
 def stiffness(space, constrain: bool = True) -> sp.csr_matrix:

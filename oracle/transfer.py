@@ -120,12 +120,19 @@ def candidate_pairs_bucketed(points, space, expand=EXPAND):
     blo = bucket(lo)
     bhi = bucket(hi)
     strides = np.cumprod(np.concatenate([[1], nb[:-1]]))
-    cell_ids, bucket_ids = [], []
-    for c in range(lo.shape[0]):
-        rng = [np.arange(blo[c, a], bhi[c, a] + 1) for a in range(d)]
-        grid = np.stack(np.meshgrid(*rng, indexing="ij"), axis=-1).reshape(-1, d)
-        bucket_ids.append(grid @ strides)
-        cell_ids.append(np.full(grid.shape[0], c))
+    # every (cell, bucket) pair with the bucket inside the cell's bucket range
+    span = bhi - blo + 1
+    count = np.prod(span, axis=1)
+    cell_ids = np.repeat(np.arange(lo.shape[0]), count)
+    local = np.arange(cell_ids.size) - np.repeat(np.cumsum(count) - count, count)
+    coords = np.empty((cell_ids.size, d), dtype=np.int64)
+    rem = local.copy()
+    for a in range(d):
+        sa = span[cell_ids, a]
+        coords[:, a] = blo[cell_ids, a] + rem % sa
+        rem //= sa
+    bucket_ids = [coords @ strides]
+    cell_ids = [cell_ids]
     bucket_ids = np.concatenate(bucket_ids)
     cell_ids = np.concatenate(cell_ids)
     order = np.lexsort((cell_ids, bucket_ids))

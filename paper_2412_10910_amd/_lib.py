@@ -103,6 +103,7 @@ SIGNATURES = {
     "nnmg_level_quadrature_points": (C.c_int, [_vp, C.POINTER(C.c_double)]),
     "nnmg_level_assemble_rhs": (C.c_int, [_vp, _vp, _vp, _vp]),
     "nnmg_vmult": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "nnmg_vmult_add": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "nnmg_level_diagonal": (C.c_int, [_vp, C.c_int, _vp, _vp]),
     "nnmg_transfer_create": (C.c_int, [_vp, _vp, _vp, C.POINTER(TransferOpts), C.POINTER(_vp)]),
     "nnmg_transfer_destroy": (None, [_vp]),

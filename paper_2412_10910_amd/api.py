@@ -160,6 +160,15 @@ class Level:
         check(lib().nnmg_vmult(self.handle, _DTYPE_PREC[src.dtype], s, d, _stream()))
         return dst
 
+    def vmult_add(self, src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:
+        """dst += A src over the unconstrained rows and columns (one kernel launch)."""
+        if dst.dtype != src.dtype:
+            raise ValueError("src and dst must have the same dtype")
+        s = _vec(src, self.n_dofs, self.ctx.device, name="src")
+        d = _vec(dst, self.n_dofs, self.ctx.device, name="dst")
+        check(lib().nnmg_vmult_add(self.handle, _DTYPE_PREC[src.dtype], s, d, _stream()))
+        return dst
+
     def diagonal(self, dtype=torch.float64) -> torch.Tensor:
         out = self.empty(dtype)
         check(lib().nnmg_level_diagonal(self.handle, _DTYPE_PREC[dtype], _vec(out, self.n_dofs, self.ctx.device),

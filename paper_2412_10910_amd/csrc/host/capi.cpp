@@ -204,6 +204,17 @@ int nnmg_vmult(const nnmg_level* l, nnmg_prec prec, const void* src, void* dst, 
     });
 }
 
+int nnmg_vmult_add(const nnmg_level* l, nnmg_prec prec, const void* src, void* dst, void* stream) {
+    return guarded([&] {
+        if (!l || !src || !dst) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (src == dst) fail(NNMG_ERR_INVALID_ARG, "src and dst alias");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        NNMG_HIP(hipSetDevice(l->ctx->device));
+        launch_vmult_cells(*l, prec, src, dst, as_stream(stream));
+        return NNMG_OK;
+    });
+}
+
 int nnmg_level_diagonal(const nnmg_level* l, nnmg_prec prec, void* diag, void* stream) {
     return guarded([&] {
         if (!l || !diag) fail(NNMG_ERR_INVALID_ARG, "NULL argument");

@@ -48,6 +48,13 @@ def test_vmult_matches_assembled_operator(ctx, dim, k, n, scram):
     assert rel_err(p.to_orc(y), ref) <= TOL64
     y32 = p.lib.vmult(p.to_lib(x, torch.float32))
     assert rel_err(p.to_orc(y32), ref) <= TOL32
+    # accumulate form: unconstrained block only, added to dst
+    free = p.orc.free
+    xf = np.where(free, x, 0.0)
+    base = random_vector(p.orc.n_dofs, 4)
+    acc = p.lib.vmult_add(p.to_lib(x), p.to_lib(base))
+    expect = base + np.where(free, p.A @ xf, 0.0)
+    assert rel_err(p.to_orc(acc), expect) <= TOL64
 
 
 @pytest.mark.parametrize("dim,k,n", CASES)
