@@ -111,7 +111,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", help="also print the per-component V-cycle times")
     ap.add_argument("--roofline-reps", type=int, default=100)
+    ap.add_argument("--geometry", choices=["trilinear", "metric"], default=None,
+                    help="operator geometry source (default: the library's choice)")
     args = ap.parse_args()
+    if args.geometry:
+        os.environ["NNMG_GEOMETRY"] = args.geometry
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
               file=sys.stderr)

@@ -32,6 +32,7 @@ SOURCES = [
     "kernels/geometry.hip",
     "kernels/transfer.hip",
     "kernels/vector.hip",
+    "kernels/gather.hip",
 ]
 
 ARCH = os.environ.get("NNMG_OFFLOAD_ARCH", "gfx950")

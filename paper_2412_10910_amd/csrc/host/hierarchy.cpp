@@ -30,7 +30,8 @@ namespace nnmg {
 enum { kPre = 0, kRes = 1, kRestrict = 2, kCoarse = 3, kProlong = 4, kPost = 5, kComponents = 6 };
 
 struct WorkVectors {
-    DeviceArray<char> f, x, d, ax, r;
+    DeviceArray<char> f, x, d, r;
+    DeviceArray<char> elem;  // operator element buffer of this level
 };
 
 struct ProfileRecord {
@@ -90,9 +91,9 @@ static void alloc_work(Hierarchy& H, int prec) {
         w.f.alloc(H.ctx, b);
         w.x.alloc(H.ctx, b);
         w.d.alloc(H.ctx, b);
-        w.ax.alloc(H.ctx, b);
         w.r.alloc(H.ctx, b);
-        for (auto* a : {&w.f, &w.x, &w.d, &w.ax, &w.r}) NNMG_HIP(hipMemset(a->ptr, 0, b));
+        for (auto* a : {&w.f, &w.x, &w.d, &w.r}) NNMG_HIP(hipMemset(a->ptr, 0, b));
+        w.elem.alloc(H.ctx, H.levels[l]->elem_len * wsize(prec));
     }
 }
 
@@ -204,13 +205,14 @@ static void chebyshev(Hierarchy& H, int l, int prec, const void* f, void* x, boo
     if (zero_start) {
         launch_cheb_first_zero(prec, n, f, dinv, x, w.d.ptr, 1.0 / theta, s);
     } else {
-        launch_vmult_cells(L, prec, x, w.ax.ptr, s);
-        launch_cheb_step(prec, n, f, w.ax.ptr, dinv, x, w.d.ptr, 0.0, 1.0 / theta, s);
+        launch_vmult_elements(L, prec, x, w.elem.ptr, s);
+        launch_cheb_step_gather(L, prec, w.elem.ptr, f, dinv, x, w.d.ptr, 0.0, 1.0 / theta, true, s);
     }
     for (int j = 1; j < H.opts.cheb_degree; ++j) {
-        launch_vmult_cells(L, prec, x, w.ax.ptr, s);
+        launch_vmult_elements(L, prec, x, w.elem.ptr, s);
         const double rho_new = 1.0 / (2.0 * sigma - rho);
-        launch_cheb_step(prec, n, f, w.ax.ptr, dinv, x, w.d.ptr, rho_new * rho, 2.0 * rho_new / delta, s);
+        launch_cheb_step_gather(L, prec, w.elem.ptr, f, dinv, x, w.d.ptr, rho_new * rho, 2.0 * rho_new / delta,
+                                false, s);
         rho = rho_new;
     }
 }
@@ -232,8 +234,8 @@ static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, 
     }
     {
         Scope sc(H, l, kRes, s);
-        launch_vmult_cells(L, prec, x, w.ax.ptr, s);
-        launch_residual(prec, n, f, w.ax.ptr, w.r.ptr, s);
+        launch_vmult_elements(L, prec, x, w.elem.ptr, s);
+        launch_residual_gather(L, prec, w.elem.ptr, f, w.r.ptr, s);
     }
     {
         Scope sc(H, l, kRestrict, s);
@@ -463,9 +465,9 @@ int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg
     NNMG_HIP(hipMemcpyAsync(H.p.ptr, H.z.ptr, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     int status = NNMG_ERR_NOT_CONVERGED;
     for (int it = 1; it <= o.max_it; ++it) {
-        launch_fill(H.qv.ptr, n, NNMG_FP64, s);
-        launch_vmult_cells(L, NNMG_FP64, H.p.ptr, H.qv.ptr, s);
-        launch_dot(H.p.ptr, H.qv.ptr, n, H.partial.ptr, sc + 1, s);
+        launch_vmult_elements(L, NNMG_FP64, H.p.ptr, H.work[NNMG_FP64][top].elem.ptr, s);
+        launch_gather_dot(L, (const double*)H.work[NNMG_FP64][top].elem.ptr, H.p.ptr, H.qv.ptr, H.partial.ptr,
+                          sc + 1, s);
         launch_scalar_op(sc, 0, s);
         launch_cg_update(n, x, H.r.ptr, H.p.ptr, H.qv.ptr, sc, H.partial.ptr, sc + 3, s);
         NNMG_HIP(hipMemcpyAsync(H.hscal, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, s));

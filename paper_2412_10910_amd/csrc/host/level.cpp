@@ -14,7 +14,9 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <unordered_map>
 
 #include "../internal.hpp"
@@ -239,9 +241,9 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
         L->degree = degree;
         L->n = degree + 1;
         L->q = dim == 3 ? L->n * L->n * L->n : L->n * L->n;
-        L->cpw = 64 / L->n;
+        vmult_shape(dim, L->n, &L->wg, &L->cpb);
         L->n_cells = mesh->n_cells;
-        L->nblocks = (L->n_cells + L->cpw - 1) / L->cpw;
+        L->nblocks = (L->n_cells + L->cpb - 1) / L->cpb;
         L->basis = make_basis(degree);
         L->vertices.assign(mesh->vertices, mesh->vertices + mesh->n_vertices * dim);
         L->cells.assign(mesh->cells, mesh->cells + mesh->n_cells * nv);
@@ -259,17 +261,34 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
         std::vector<int32_t> enc(L->dofmap.size());
         for (size_t i = 0; i < enc.size(); ++i) enc[i] = L->constrained[(size_t)L->dofmap[i]] ? -1 : L->dofmap[i];
         L->d_dofmap.upload(ctx, enc);
-        std::vector<int32_t> blk((size_t)(L->nblocks * P * 64), -1);
+        // operator layout: lane (cell_in_block, line) holds the x-line `line` of its cell
+        const int Lc = dim == 3 ? n * n : n, WG = L->wg;
+        std::vector<int32_t> blk((size_t)(L->nblocks * n * WG), -1);
         for (int64_t c = 0; c < L->n_cells; ++c) {
-            const int64_t b = c / L->cpw;
-            const int team = (int)(c - b * L->cpw);
+            const int64_t b = c / L->cpb;
+            const int cell = (int)(c - b * L->cpb);
             for (int a = 0; a < q; ++a) {
-                const int t = a / P;  // slab along the last coordinate
-                const int ij = a % P;
-                blk[(size_t)((b * P + ij) * 64 + team * n + t)] = enc[(size_t)(c * q + a)];
+                const int i = a % n, line = a / n;
+                blk[(size_t)((b * n + i) * WG + cell * Lc + line)] = enc[(size_t)(c * q + a)];
             }
         }
         L->d_dofmap_blk.upload(ctx, blk);
+        // inverse map: for every DoF, the element-buffer slots that hold its contributions
+        {
+            std::vector<int32_t> off((size_t)L->n_dofs + 1, 0);
+            for (size_t k = 0; k < blk.size(); ++k)
+                if (blk[k] >= 0) off[(size_t)blk[k] + 1]++;
+            for (int64_t i = 0; i < L->n_dofs; ++i) off[(size_t)i + 1] += off[(size_t)i];
+            std::vector<int32_t> slot((size_t)off[(size_t)L->n_dofs]);
+            std::vector<int32_t> cur(off.begin(), off.end() - 1);
+            for (size_t k = 0; k < blk.size(); ++k)
+                if (blk[k] >= 0) slot[(size_t)cur[(size_t)blk[k]]++] = (int32_t)k;
+            if (blk.size() > (size_t)INT32_MAX) fail(NNMG_ERR_UNSUPPORTED, "element buffer exceeds 32-bit slots");
+            L->d_inv_off.upload(ctx, off);
+            L->d_inv_slot.upload(ctx, slot);
+            L->elem_len = blk.size();
+            L->d_elem.alloc(ctx, L->elem_len * sizeof(double));
+        }
         L->d_constrained.upload(ctx, L->constrained_idx);
         std::vector<double> cv((size_t)(L->n_cells * nv * dim));
         for (int64_t c = 0; c < L->n_cells; ++c)
@@ -278,7 +297,7 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
                     cv[(size_t)((c * nv + b) * dim + i)] = L->vertices[(size_t)(L->cells[(size_t)(c * nv + b)] * dim + i)];
         L->d_cellverts.upload(ctx, cv);
 
-        const size_t mlen = (size_t)(L->nblocks * M * P * 64);
+        const size_t mlen = (size_t)(L->nblocks * M * n * WG);
         L->d_metric64.alloc(ctx, mlen);
         L->d_metric32.alloc(ctx, mlen);
         NNMG_HIP(hipMemset(L->d_metric64.ptr, 0, L->d_metric64.bytes()));
@@ -291,13 +310,61 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
         NNMG_HIP(hipMemcpy(&hbad, bad.ptr, sizeof(int), hipMemcpyDeviceToHost));
         if (hbad) fail(NNMG_ERR_MESH, "cell with non-positive Jacobian determinant at a Gauss point");
 
-        DeviceArray<double> diag;
-        diag.alloc(ctx, (size_t)L->n_dofs);
-        NNMG_HIP(hipMemset(diag.ptr, 0, diag.bytes()));
-        launch_diagonal(*L, diag.ptr, nullptr);
+        L->d_diag64.alloc(ctx, (size_t)L->n_dofs);
+        NNMG_HIP(hipMemset(L->d_diag64.ptr, 0, L->d_diag64.bytes()));
+        launch_diagonal(*L, L->d_diag64.ptr, nullptr);
         L->d_dinv64.alloc(ctx, (size_t)L->n_dofs);
         L->d_dinv32.alloc(ctx, (size_t)L->n_dofs);
-        launch_invert_diagonal(*L, diag.ptr, nullptr);
+        launch_invert_diagonal(*L, L->d_diag64.ptr, nullptr);
+        launch_set_constrained(L->d_constrained.ptr, L->constrained_idx.size(), 1.0, L->d_diag64.ptr, NNMG_FP64,
+                               nullptr);
+
+        // coefficients of the Q1 map per cell, for the operator kernel that
+        // rebuilds the geometry at the Gauss points
+        const int NC = dim == 3 ? 21 : 6;
+        std::vector<double> coef((size_t)(L->nblocks * NC * L->cpb), 0.0);
+        for (int64_t c = 0; c < L->nblocks * L->cpb; ++c) {
+            const int64_t b = c / L->cpb;
+            const int cell = (int)(c - b * L->cpb);
+            double X[8][3] = {};
+            if (c < L->n_cells) {
+                for (int v = 0; v < nv; ++v)
+                    for (int i = 0; i < dim; ++i) X[v][i] = cv[(size_t)((c * nv + v) * dim + i)];
+            } else {
+                // padding: the unit cell, so that the unused lanes see det J = 1
+                for (int v = 0; v < nv; ++v)
+                    for (int i = 0; i < dim; ++i) X[v][i] = (v >> i) & 1;
+            }
+            double vals[21];
+            if (dim == 3) {
+                for (int i = 0; i < 3; ++i) {
+                    vals[0 + i] = X[1][i] - X[0][i];                                                // b
+                    vals[3 + i] = X[2][i] - X[0][i];                                                // c
+                    vals[6 + i] = X[4][i] - X[0][i];                                                // d
+                    vals[9 + i] = X[3][i] - X[1][i] - X[2][i] + X[0][i];                            // e
+                    vals[12 + i] = X[5][i] - X[1][i] - X[4][i] + X[0][i];                           // f
+                    vals[15 + i] = X[6][i] - X[2][i] - X[4][i] + X[0][i];                           // g
+                    vals[18 + i] = X[7][i] - X[3][i] - X[5][i] - X[6][i] + X[1][i] + X[2][i] + X[4][i] - X[0][i];  // h
+                }
+            } else {
+                for (int i = 0; i < 2; ++i) {
+                    vals[0 + i] = X[1][i] - X[0][i];                      // b
+                    vals[2 + i] = X[2][i] - X[0][i];                      // c
+                    vals[4 + i] = X[3][i] - X[1][i] - X[2][i] + X[0][i];  // d
+                }
+            }
+            for (int m = 0; m < NC; ++m) coef[(size_t)((b * NC + m) * L->cpb + cell)] = vals[m];
+        }
+        L->d_coef64.upload(ctx, coef);
+        std::vector<float> coef32(coef.begin(), coef.end());
+        L->d_coef32.upload(ctx, coef32);
+        const char* mode = std::getenv("NNMG_GEOMETRY");
+        L->geometry_mode = (mode && std::string(mode) == "metric") ? 0 : 1;
+        if (L->geometry_mode == 1) {
+            NNMG_HIP(hipDeviceSynchronize());
+            L->d_metric64.reset();
+            L->d_metric32.reset();
+        }
         NNMG_HIP(hipDeviceSynchronize());
     } catch (...) {
         delete L;
@@ -307,17 +374,11 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
 }
 
 void level_diagonal(const Level& L, int prec, void* out, hipStream_t s) {
-    // diag = 1 / dinv on free rows, 1 on constrained rows
-    DeviceArray<double> diag;
-    diag.alloc(L.ctx, (size_t)L.n_dofs);
-    NNMG_HIP(hipMemsetAsync(diag.ptr, 0, diag.bytes(), s));
-    launch_diagonal(L, diag.ptr, s);
-    launch_set_constrained(L.d_constrained.ptr, L.constrained_idx.size(), 1.0, diag.ptr, NNMG_FP64, s);
+    // the diagonal is assembled once at setup (1 on constrained rows)
     if (prec == NNMG_FP64)
-        NNMG_HIP(hipMemcpyAsync(out, diag.ptr, diag.bytes(), hipMemcpyDeviceToDevice, s));
+        NNMG_HIP(hipMemcpyAsync(out, L.d_diag64.ptr, L.d_diag64.bytes(), hipMemcpyDeviceToDevice, s));
     else
-        launch_cast_64_to_32(diag.ptr, (float*)out, (size_t)L.n_dofs, s);
-    NNMG_HIP(hipStreamSynchronize(s));
+        launch_cast_64_to_32(L.d_diag64.ptr, (float*)out, (size_t)L.n_dofs, s);
 }
 
 void level_quadrature_points(const Level& L, double* out) {

@@ -109,7 +109,8 @@ struct Level {
     Ctx* ctx = nullptr;
     std::atomic<int> refs{1};
     int dim = 0, degree = 0, n = 0, q = 0;
-    int cpw = 0;        // cells per 64-lane block in the operator kernel layout
+    int wg = 64;        // lanes per block of the operator kernel
+    int cpb = 0;        // cells per block of the operator kernel
     int64_t nblocks = 0;
     int64_t n_cells = 0, n_dofs = 0, n_free = 0;
     Basis1D basis;
@@ -122,11 +123,19 @@ struct Level {
     std::vector<int32_t> constrained_idx;
 
     DeviceArray<int32_t> d_dofmap;      // [C][q], -1 for constrained DoFs
-    DeviceArray<int32_t> d_dofmap_blk;  // operator layout, -1 for constrained / padding
-    DeviceArray<double> d_metric64;     // operator layout [blk][M][q/n][64]
+    DeviceArray<int32_t> d_dofmap_blk;  // operator layout [blk][n][wg], -1 for constrained / padding
+    int geometry_mode = 1;              // 0: stored metric per Gauss point, 1: trilinear coefficients
+    DeviceArray<double> d_metric64;     // operator layout [blk][M][n][wg] (kept after setup in mode 0)
     DeviceArray<float> d_metric32;
+    DeviceArray<double> d_coef64;       // [blk][NC][cpb] Q1 map coefficients (mode 1)
+    DeviceArray<float> d_coef32;
     DeviceArray<double> d_cellverts;    // [C][2^dim][dim]
     DeviceArray<int32_t> d_constrained;
+    DeviceArray<int32_t> d_inv_off;     // [N+1] contributions of DoF i: inv_slot[off[i] .. off[i+1])
+    DeviceArray<int32_t> d_inv_slot;    // element-buffer slots, in a fixed order
+    DeviceArray<char> d_elem;           // element buffer of the level's own operator calls
+    size_t elem_len = 0;                // entries of an element buffer: nblocks * n * wg
+    DeviceArray<double> d_diag64;       // operator diagonal, 1 on constrained
     DeviceArray<double> d_dinv64;       // inverse diagonal, 0 on constrained
     DeviceArray<float> d_dinv32;
 };
@@ -169,6 +178,18 @@ void launch_copy_constrained(const int32_t* idx, size_t n, const void* src, void
                              hipStream_t s);
 
 // operator apply: dst += A src over the cells (constrained rows untouched)
+void vmult_shape(int dim, int n, int* wg, int* cells_per_block);
+// elem = cell contributions of A src in the element-buffer layout
+void launch_vmult_elements(const Level& L, int prec, const void* src, void* elem, hipStream_t s);
+// consumers of an element buffer (kernels/gather.hip); constrained rows are not written
+void launch_gather(const Level& L, int prec, const void* elem, void* dst, bool accumulate, hipStream_t s);
+void launch_cheb_step_gather(const Level& L, int prec, const void* elem, const void* f, const void* dinv, void* x,
+                             void* d, double c1, double c2, bool first, hipStream_t s);
+void launch_residual_gather(const Level& L, int prec, const void* elem, const void* f, void* r, hipStream_t s);
+void launch_gather_dot(const Level& L, const double* elem, const double* p, double* q, double* partial,
+                       double* out, hipStream_t s);
+void launch_sum_partials(const double* partial, size_t m, double* out, hipStream_t s);
+// dst += A src using the level's own element buffer (not for concurrent use on one level)
 void launch_vmult_cells(const Level& L, int prec, const void* src, void* dst, hipStream_t s);
 // geometry, diagonal, right-hand side (setup kernels)
 void launch_geometry(Level& L, int* d_bad, hipStream_t s);

@@ -85,20 +85,21 @@ __device__ inline double det_inv(const double J[DIM][DIM], double Ji[DIM][DIM]) 
     }
 }
 
-// index of (cell, Gauss point) in the blocked operator layout for component m
+// index of (cell, Gauss point) in the block layout of the operator kernel for
+// component m: [blk][m][qx][wg], lane = cell_in_block * n^(d-1) + line with
+// line = qy + n qz (3D) or qy (2D)
 template <int DIM>
-__device__ inline int64_t blk_index(int64_t c, int qx, int qy, int qz, int n, int cpw, int m) {
+__device__ inline int64_t blk_index(int64_t c, int qx, int qy, int qz, int n, int cpb, int wg, int m) {
     const int M = DIM * (DIM + 1) / 2;
-    const int P = DIM == 3 ? n * n : n;
-    const int64_t b = c / cpw;
-    const int team = (int)(c - b * cpw);
-    const int t = DIM == 3 ? qz : qy;
-    const int ij = DIM == 3 ? qy * n + qx : qx;
-    return ((b * M + m) * P + ij) * kWave + team * n + t;
+    const int Lc = DIM == 3 ? n * n : n;
+    const int64_t b = c / cpb;
+    const int cell = (int)(c - b * cpb);
+    const int line = DIM == 3 ? qy + n * qz : qy;
+    return ((b * M + m) * n + qx) * wg + cell * Lc + line;
 }
 
 template <int DIM>
-__global__ void geometry_kernel(const double* __restrict__ cverts, int64_t ncells, int n, int cpw,
+__global__ void geometry_kernel(const double* __restrict__ cverts, int64_t ncells, int n, int cpb, int wg,
                                 GaussTable gt, double* __restrict__ m64, float* __restrict__ m32,
                                 int* __restrict__ bad) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -130,7 +131,7 @@ __global__ void geometry_kernel(const double* __restrict__ cverts, int64_t ncell
         const double vals[6] = {G(0, 0), G(1, 1), G(2, 2), G(0, 1), G(0, 2), G(1, 2)};
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
-            const int64_t k = blk_index<3>(c, qx, qy, qz, n, cpw, m);
+            const int64_t k = blk_index<3>(c, qx, qy, qz, n, cpb, wg, m);
             m64[k] = vals[m];
             m32[k] = (float)vals[m];
         }
@@ -138,7 +139,7 @@ __global__ void geometry_kernel(const double* __restrict__ cverts, int64_t ncell
         const double vals[3] = {G(0, 0), G(1, 1), G(0, 1)};
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            const int64_t k = blk_index<2>(c, qx, qy, 0, n, cpw, m);
+            const int64_t k = blk_index<2>(c, qx, qy, 0, n, cpb, wg, m);
             m64[k] = vals[m];
             m32[k] = (float)vals[m];
         }
@@ -148,22 +149,23 @@ __global__ void geometry_kernel(const double* __restrict__ cverts, int64_t ncell
 void launch_geometry(Level& L, int* d_bad, hipStream_t s) {
     const int64_t total = L.n_cells * L.q;
     if (total == 0) return;
+    if (!L.d_metric64.ptr || !L.d_metric32.ptr) fail(NNMG_ERR_INVALID_ARG, "metric arrays are not allocated");
     const int threads = 256;
     const dim3 grid((unsigned)((total + threads - 1) / threads));
     const GaussTable gt = gauss_table(L.basis);
     if (L.dim == 3)
         hipLaunchKernelGGL(geometry_kernel<3>, grid, dim3(threads), 0, s, L.d_cellverts.ptr, L.n_cells, L.n,
-                           L.cpw, gt, L.d_metric64.ptr, L.d_metric32.ptr, d_bad);
+                           L.cpb, L.wg, gt, L.d_metric64.ptr, L.d_metric32.ptr, d_bad);
     else
         hipLaunchKernelGGL(geometry_kernel<2>, grid, dim3(threads), 0, s, L.d_cellverts.ptr, L.n_cells, L.n,
-                           L.cpw, gt, L.d_metric64.ptr, L.d_metric32.ptr, d_bad);
+                           L.cpb, L.wg, gt, L.d_metric64.ptr, L.d_metric32.ptr, d_bad);
     NNMG_HIP(hipGetLastError());
 }
 
 // diag_i += sum_q grad_ref(phi_a)(q)^T G_q grad_ref(phi_a)(q), one thread per (cell, local node)
 template <int DIM>
 __global__ void diagonal_kernel(const int32_t* __restrict__ dofmap, const double* __restrict__ m64,
-                                int64_t ncells, int n, int cpw, GaussTable gt, double* __restrict__ diag) {
+                                int64_t ncells, int n, int cpb, int wg, GaussTable gt, double* __restrict__ diag) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int qn = 1;
     for (int a = 0; a < DIM; ++a) qn *= n;
@@ -180,20 +182,20 @@ __global__ void diagonal_kernel(const int32_t* __restrict__ dofmap, const double
             const double g0 = gt.DS[qx][ax] * gt.S[qy][ay] * gt.S[qz][az];
             const double g1 = gt.S[qx][ax] * gt.DS[qy][ay] * gt.S[qz][az];
             const double g2 = gt.S[qx][ax] * gt.S[qy][ay] * gt.DS[qz][az];
-            const double G00 = m64[blk_index<3>(c, qx, qy, qz, n, cpw, 0)];
-            const double G11 = m64[blk_index<3>(c, qx, qy, qz, n, cpw, 1)];
-            const double G22 = m64[blk_index<3>(c, qx, qy, qz, n, cpw, 2)];
-            const double G01 = m64[blk_index<3>(c, qx, qy, qz, n, cpw, 3)];
-            const double G02 = m64[blk_index<3>(c, qx, qy, qz, n, cpw, 4)];
-            const double G12 = m64[blk_index<3>(c, qx, qy, qz, n, cpw, 5)];
+            const double G00 = m64[blk_index<3>(c, qx, qy, qz, n, cpb, wg, 0)];
+            const double G11 = m64[blk_index<3>(c, qx, qy, qz, n, cpb, wg, 1)];
+            const double G22 = m64[blk_index<3>(c, qx, qy, qz, n, cpb, wg, 2)];
+            const double G01 = m64[blk_index<3>(c, qx, qy, qz, n, cpb, wg, 3)];
+            const double G02 = m64[blk_index<3>(c, qx, qy, qz, n, cpb, wg, 4)];
+            const double G12 = m64[blk_index<3>(c, qx, qy, qz, n, cpb, wg, 5)];
             sum += G00 * g0 * g0 + G11 * g1 * g1 + G22 * g2 * g2 +
                    2.0 * (G01 * g0 * g1 + G02 * g0 * g2 + G12 * g1 * g2);
         } else {
             const double g0 = gt.DS[qx][ax] * gt.S[qy][ay];
             const double g1 = gt.S[qx][ax] * gt.DS[qy][ay];
-            const double G00 = m64[blk_index<2>(c, qx, qy, 0, n, cpw, 0)];
-            const double G11 = m64[blk_index<2>(c, qx, qy, 0, n, cpw, 1)];
-            const double G01 = m64[blk_index<2>(c, qx, qy, 0, n, cpw, 2)];
+            const double G00 = m64[blk_index<2>(c, qx, qy, 0, n, cpb, wg, 0)];
+            const double G11 = m64[blk_index<2>(c, qx, qy, 0, n, cpb, wg, 1)];
+            const double G01 = m64[blk_index<2>(c, qx, qy, 0, n, cpb, wg, 2)];
             sum += G00 * g0 * g0 + G11 * g1 * g1 + 2.0 * G01 * g0 * g1;
         }
     }
@@ -203,15 +205,16 @@ __global__ void diagonal_kernel(const int32_t* __restrict__ dofmap, const double
 void launch_diagonal(const Level& L, double* diag, hipStream_t s) {
     const int64_t total = L.n_cells * L.q;
     if (total == 0) return;
+    if (!L.d_metric64.ptr) fail(NNMG_ERR_INVALID_ARG, "diagonal needs the stored metric (level setup only)");
     const int threads = 256;
     const dim3 grid((unsigned)((total + threads - 1) / threads));
     const GaussTable gt = gauss_table(L.basis);
     if (L.dim == 3)
         hipLaunchKernelGGL(diagonal_kernel<3>, grid, dim3(threads), 0, s, L.d_dofmap.ptr, L.d_metric64.ptr,
-                           L.n_cells, L.n, L.cpw, gt, diag);
+                           L.n_cells, L.n, L.cpb, L.wg, gt, diag);
     else
         hipLaunchKernelGGL(diagonal_kernel<2>, grid, dim3(threads), 0, s, L.d_dofmap.ptr, L.d_metric64.ptr,
-                           L.n_cells, L.n, L.cpw, gt, diag);
+                           L.n_cells, L.n, L.cpb, L.wg, gt, diag);
     NNMG_HIP(hipGetLastError());
 }
 

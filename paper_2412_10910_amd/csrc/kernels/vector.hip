@@ -242,6 +242,11 @@ __global__ __launch_bounds__(kRedThreads) void sum_stage2(const double* __restri
     if (threadIdx.x == 0) *out = s;
 }
 
+void launch_sum_partials(const double* partial, size_t m, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(kRedThreads), 0, s, partial, m, out);
+    NNMG_HIP(hipGetLastError());
+}
+
 void launch_dot(const double* a, const double* b, size_t n, double* partial, double* out, hipStream_t s) {
     const size_t g = dot_partials(n);
     hipLaunchKernelGGL(dot_stage1, dim3((unsigned)g), dim3(kRedThreads), 0, s, a, b, n, partial);

@@ -2,318 +2,422 @@
 // evaluation; the operator A_l of §2, eq. linear_system, for the Poisson
 // bilinear form with the (k+1)^d Gauss rule of §4).
 //
-// Work decomposition (gfx950, 64-lane wavefronts).  A team of N = k+1 lanes
-// handles one cell; lane t of the team owns slab t along the last coordinate
-// (z in 3D, y in 2D) and keeps that slab's N^(d-1) values in registers.  The
-// in-slab 1D contractions (x, and y in 3D) run in registers; the contraction
-// along the slab direction goes through one LDS round trip forward and one
-// backward.  64 / N cells share a wavefront and a 64-lane block of the cell
-// data layout, so every gather index and every geometry word is a coalesced
-// 64-wide load:
+// Work decomposition (gfx950).  A team of L = N^(d-1) lanes (N = k+1) handles
+// one cell; each lane owns one x-line of N nodal values / Gauss points, held
+// in registers.  Contractions along x run in registers, those along y and z
+// (3D) or y (2D) go through LDS, with per-cell tiles of N^d values.  A block
+// of WG lanes holds CPB = WG / L cells; WG is 64, or 128 for 3D Q4 so that
+// five 25-lane teams fill two wavefronts.  Every per-cell array is stored in
+// the block layout of the lanes that read it, so each load is coalesced:
 //
-//   dofmap_blk[(blk * P + ij) * 64 + lane]        P = N^(d-1)
-//   metric_blk[((blk * M + m) * P + ij) * 64 + lane]  M = d(d+1)/2
+//   dofmap_blk[(blk * N + i) * WG + lane]          node i of the lane's x-line
 //
-// with lane = team * N + t.  The stored geometry at Gauss point q is the
-// merged metric G_q = w_q det(J_q) J_q^{-1} J_q^{-T} (components 00,11,22,01,02,12
-// in 3D; 00,11,01 in 2D), so that the integrand is grad_ref(v)^T G grad_ref(u).
+// Forward: nodal values -> Gauss points (S in each direction), reference
+// gradient by collocation (D on the Gauss points; along z in 3D / y in 2D the
+// derivative DS = D S is fused with the interpolation).  At each Gauss point
+// the flux is G grad_ref(u), G = w det(J) J^{-1} J^{-T} the merged metric.
+// Backward: the transposes.  The cell results are not scattered with
+// atomics: every lane stores its N values, coalesced, into a per-level element
+// buffer laid out like the cell-to-DoF map,
 //
-// Forward: u -> values at Gauss points (S in each direction), reference
-// gradient by collocation (D on the Gauss points; the slab direction uses
-// DS = D S directly).  Backward: the transposes, w = D^T f_x + D^T f_y in
-// registers, then S^T / DS^T along the slab direction through LDS, then S^T in
-// registers.  Results are scatter-added with hardware float atomics.
+//   elem_blk[(blk * N + i) * WG + lane],
+//
+// and the consumers (gather kernels, Chebyshev step, residual, CG update) sum
+// each DoF's contributions through an inverse map built at setup.  The sum
+// order is fixed, so the operator is deterministic.
+//
+// Two geometry sources:
+//  * kStoredMetric: G read per Gauss point from
+//      metric_blk[((blk * M + m) * N + i) * WG + lane],  M = d(d+1)/2
+//    (components 00,11,22,01,02,12 in 3D; 00,11,01 in 2D);
+//  * kTrilinear: the Q1 map x(xi) = a + b xi + c eta + d zeta + e xi eta
+//    + f xi zeta + g eta zeta + h xi eta zeta kept as its 7 (2D: 3) vector
+//    coefficients per cell, coef_blk[(blk * NC + m) * CPB + cell_in_block],
+//    and J rebuilt at every Gauss point.  The rows of det(J) J^{-1} are the
+//    cross products of the columns of J, so G grad = (w / det J) R^T (R grad)
+//    with R the matrix of those rows.  This moves 21 words per cell instead
+//    of 6 per Gauss point, for about 60 flops per Gauss point.
 #include "../internal.hpp"
 #include "common.hpp"
 
 namespace nnmg {
 
 template <int N, class T>
-__global__ __launch_bounds__(64) void vmult3_kernel(const int32_t* __restrict__ dmap,
-                                                    const T* __restrict__ metric,
-                                                    const T* __restrict__ src, T* __restrict__ dst,
-                                                    Tables<N, T> tb) {
-    constexpr int P = N * N;
-    constexpr int CPW = kWave / N;
-    __shared__ T lds[CPW][2][N][P];
+struct OpTables {
+    T S[N][N];   // S[q][a]  = phi_a(g_q)
+    T DS[N][N];  // DS[q][a] = phi_a'(g_q)
+    T D[N][N];   // D[q][p]  = psi_p'(g_q)
+    T g[N];      // Gauss points on [0,1]
+    T w[N];      // Gauss weights
+};
+
+__device__ __forceinline__ double recip(double x) {
+    // hardware estimate refined by two Newton steps
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+__device__ __forceinline__ float recip(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// out[i] = sum_a M[i][a] in[a]  (or M^T)
+template <int N, class T, bool TRANS>
+__device__ __forceinline__ void line_apply(const T (&M)[N][N], const T* in, T* out) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        T s = (TRANS ? M[0][i] : M[i][0]) * in[0];
+#pragma unroll
+        for (int a = 1; a < N; ++a) s += (TRANS ? M[a][i] : M[i][a]) * in[a];
+        out[i] = s;
+    }
+}
+
+template <int DIM, int N>
+struct OpShape {
+    static constexpr int L = DIM == 3 ? N * N : N;   // lanes per cell
+    static constexpr int WG = (DIM == 3 && N == 5) ? 128 : 64;
+    static constexpr int CPB = WG / L;               // cells per block
+    static constexpr int TILE = DIM == 3 ? N * N * N : N * N;
+};
+
+constexpr int kStoredMetric = 0;
+constexpr int kTrilinear = 1;
+
+template <int DIM, int N, class T, int GEO>
+__global__ __launch_bounds__((OpShape<DIM, N>::WG)) void vmult_kernel(const int32_t* __restrict__ dmap,
+                                                                    const T* __restrict__ geo,
+                                                                    const T* __restrict__ src,
+                                                                    T* __restrict__ elem, OpTables<N, T> tb) {
+    using Sh = OpShape<DIM, N>;
+    constexpr int L = Sh::L, WG = Sh::WG, CPB = Sh::CPB, TILE = Sh::TILE;
+    constexpr int M = DIM * (DIM + 1) / 2;
+    constexpr int NC = DIM == 3 ? 21 : 6;
+    __shared__ T lds[3][CPB][TILE];
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
-    const int team = lane / N;
-    const int t = lane - team * N;
-    const bool act = team < CPW;
-    const int tm = act ? team : 0;
+    const int cell = lane / L;
+    const int line = lane - cell * L;
+    const bool act = cell < CPB;
+    const int cb = act ? cell : 0;
+    // 3D: line = j + N t (y index j, z index t); 2D: line = t (y index)
+    const int j = DIM == 3 ? line % N : 0;
+    const int t = DIM == 3 ? line / N : line;
+    const int row = line * N;  // offset of this lane's x-line in a cell tile
 
-    const int32_t* dm = dmap + b * (P * kWave) + lane;
-    int32_t idx[P];
-    T u[P], v[P];
+    // geometry constants of this lane's line
+    T c0[DIM], C1[DIM], E1[DIM], D2[DIM], F2[DIM];
+    if constexpr (GEO == kTrilinear) {
+        T cf[NC];
+        const T* gc = geo + b * (NC * CPB) + cb;
 #pragma unroll
-    for (int ij = 0; ij < P; ++ij) idx[ij] = dm[ij * kWave];
+        for (int m = 0; m < NC; ++m) cf[m] = gc[m * CPB];
+        if constexpr (DIM == 3) {
+            const T eta = tb.g[j], zeta = tb.g[t];
 #pragma unroll
-    for (int ij = 0; ij < P; ++ij) u[ij] = idx[ij] >= 0 ? src[idx[ij]] : T(0);
+            for (int k = 0; k < 3; ++k) {
+                // d/dxi = b + e eta + f zeta + h eta zeta          (constant on the line)
+                c0[k] = cf[0 + k] + cf[9 + k] * eta + (cf[12 + k] + cf[18 + k] * eta) * zeta;
+                // d/deta = (c + g zeta) + (e + h zeta) xi
+                C1[k] = cf[3 + k] + cf[15 + k] * zeta;
+                E1[k] = cf[9 + k] + cf[18 + k] * zeta;
+                // d/dzeta = (d + g eta) + (f + h eta) xi
+                D2[k] = cf[6 + k] + cf[15 + k] * eta;
+                F2[k] = cf[12 + k] + cf[18 + k] * eta;
+            }
+        } else {
+            const T eta = tb.g[t];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                c0[k] = cf[0 + k] + cf[4 + k] * eta;  // d/dxi = b + d eta
+                C1[k] = cf[2 + k];                    // d/deta = c + d xi
+                E1[k] = cf[4 + k];
+            }
+        }
+    }
 
-    // x then y: nodal values -> Gauss points within the slab
+    const int32_t* dm = dmap + b * (N * WG) + lane;
+    int32_t idx[N];
+    T u[N], v[N];
 #pragma unroll
-    for (int j = 0; j < N; ++j)
+    for (int i = 0; i < N; ++i) idx[i] = dm[i * WG];
+#pragma unroll
+    for (int i = 0; i < N; ++i) u[i] = idx[i] >= 0 ? src[idx[i]] : T(0);
+
+    T* A = lds[0][cb];
+    T* B = lds[1][cb];
+    T* Cc = lds[2][cb];
+
+    // ---- forward --------------------------------------------------------
+    line_apply<N, T, false>(tb.S, u, v);  // x: nodes -> Gauss points
+    T gz[N];                              // derivative along the last direction
+    if constexpr (DIM == 3) {
+        // y: interpolate
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) A[row + i] = v[i];
+        }
+        __syncthreads();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            T s = T(0);
+            T s = tb.S[j][0] * A[(t * N + 0) * N + i];
 #pragma unroll
-            for (int a = 0; a < N; ++a) s += tb.S[i][a] * u[j * N + a];
-            v[j * N + i] = s;
+            for (int c = 1; c < N; ++c) s += tb.S[j][c] * A[(t * N + c) * N + i];
+            u[i] = s;
         }
+        // z: interpolate and differentiate
+        if (act) {
 #pragma unroll
-    for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) B[row + i] = u[i];
+        }
+        __syncthreads();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            T s = T(0);
+            const T w0 = B[(0 * N + j) * N + i];
+            T s0 = tb.S[t][0] * w0, s1 = tb.DS[t][0] * w0;
 #pragma unroll
-            for (int c = 0; c < N; ++c) s += tb.S[j][c] * v[c * N + i];
-            u[j * N + i] = s;
-        }
-    // z: values and z-derivative at the Gauss points of slab t
-    if (act) {
-#pragma unroll
-        for (int ij = 0; ij < P; ++ij) lds[tm][0][t][ij] = u[ij];
-    }
-    __syncthreads();
-    T gz[P];
-#pragma unroll
-    for (int ij = 0; ij < P; ++ij) {
-        T s0 = T(0), s1 = T(0);
-#pragma unroll
-        for (int c = 0; c < N; ++c) {
-            const T w = lds[tm][0][c][ij];
-            s0 += tb.S[t][c] * w;
-            s1 += tb.DS[t][c] * w;
-        }
-        u[ij] = s0;
-        gz[ij] = s1;
-    }
-    // x and y derivatives by collocation at the Gauss points
-    T gx[P], gy[P];
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T sx = T(0), sy = T(0);
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-                sx += tb.D[i][a] * u[j * N + a];
-                sy += tb.D[j][a] * u[a * N + i];
+            for (int c = 1; c < N; ++c) {
+                const T w = B[(c * N + j) * N + i];
+                s0 += tb.S[t][c] * w;
+                s1 += tb.DS[t][c] * w;
             }
-            gx[j * N + i] = sx;
-            gy[j * N + i] = sy;
+            v[i] = s0;
+            gz[i] = s1;
         }
-    // apply the merged metric
-    const T* mt = metric + b * (6 * P * kWave) + lane;
+    } else {
+        if (act) {
 #pragma unroll
-    for (int ij = 0; ij < P; ++ij) {
-        const T g00 = mt[(0 * P + ij) * kWave];
-        const T g11 = mt[(1 * P + ij) * kWave];
-        const T g22 = mt[(2 * P + ij) * kWave];
-        const T g01 = mt[(3 * P + ij) * kWave];
-        const T g02 = mt[(4 * P + ij) * kWave];
-        const T g12 = mt[(5 * P + ij) * kWave];
-        const T x = gx[ij], y = gy[ij], z = gz[ij];
-        gx[ij] = g00 * x + g01 * y + g02 * z;
-        gy[ij] = g01 * x + g11 * y + g12 * z;
-        gz[ij] = g02 * x + g12 * y + g22 * z;
-    }
-    // backward in the slab: w = Dx^T fx + Dy^T fy
-#pragma unroll
-    for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) A[row + i] = v[i];
+        }
+        __syncthreads();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            T s = T(0);
+            const T w0 = A[0 * N + i];
+            T s0 = tb.S[t][0] * w0, s1 = tb.DS[t][0] * w0;
 #pragma unroll
-            for (int a = 0; a < N; ++a) {
-                s += tb.D[a][i] * gx[j * N + a];
-                s += tb.D[a][j] * gy[a * N + i];
+            for (int c = 1; c < N; ++c) {
+                const T w = A[c * N + i];
+                s0 += tb.S[t][c] * w;
+                s1 += tb.DS[t][c] * w;
             }
-            u[j * N + i] = s;
-        }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-        for (int ij = 0; ij < P; ++ij) {
-            lds[tm][0][t][ij] = u[ij];
-            lds[tm][1][t][ij] = gz[ij];
+            v[i] = s0;
+            gz[i] = s1;
         }
     }
-    __syncthreads();
-    // z transpose: lane t now holds nodal slab t
+    // v: values at the Gauss points of the line; x (and y) derivatives
+    T gx[N], gy[N];
+    line_apply<N, T, false>(tb.D, v, gx);
+    if constexpr (DIM == 3) {
+        if (act) {
 #pragma unroll
-    for (int ij = 0; ij < P; ++ij) {
-        T s = T(0);
+            for (int i = 0; i < N; ++i) Cc[row + i] = v[i];
+        }
+        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < N; ++q) s += tb.S[q][t] * lds[tm][0][q][ij] + tb.DS[q][t] * lds[tm][1][q][ij];
-        v[ij] = s;
+        for (int i = 0; i < N; ++i) {
+            T s = tb.D[j][0] * Cc[(t * N + 0) * N + i];
+#pragma unroll
+            for (int c = 1; c < N; ++c) s += tb.D[j][c] * Cc[(t * N + c) * N + i];
+            gy[i] = s;
+        }
     }
-    // y then x transposes back to the nodes
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T s = T(0);
-#pragma unroll
-            for (int q = 0; q < N; ++q) s += tb.S[q][j] * v[q * N + i];
-            u[j * N + i] = s;
-        }
-#pragma unroll
-    for (int j = 0; j < N; ++j)
+
+    // ---- geometry at the Gauss points of the line ------------------------
+    if constexpr (GEO == kStoredMetric) {
+        const T* mt = geo + b * (M * N * WG) + lane;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            T s = T(0);
-#pragma unroll
-            for (int q = 0; q < N; ++q) s += tb.S[q][i] * u[j * N + q];
-            v[j * N + i] = s;
+            if constexpr (DIM == 3) {
+                const T g00 = mt[(0 * N + i) * WG], g11 = mt[(1 * N + i) * WG], g22 = mt[(2 * N + i) * WG];
+                const T g01 = mt[(3 * N + i) * WG], g02 = mt[(4 * N + i) * WG], g12 = mt[(5 * N + i) * WG];
+                const T x = gx[i], y = gy[i], z = gz[i];
+                gx[i] = g00 * x + g01 * y + g02 * z;
+                gy[i] = g01 * x + g11 * y + g12 * z;
+                gz[i] = g02 * x + g12 * y + g22 * z;
+            } else {
+                const T g00 = mt[(0 * N + i) * WG], g11 = mt[(1 * N + i) * WG], g01 = mt[(2 * N + i) * WG];
+                const T x = gx[i], y = gz[i];
+                gx[i] = g00 * x + g01 * y;
+                gz[i] = g01 * x + g11 * y;
+            }
         }
+    } else {
+        const T wl = DIM == 3 ? tb.w[j] * tb.w[t] : tb.w[t];
 #pragma unroll
-    for (int ij = 0; ij < P; ++ij)
-        if (idx[ij] >= 0) atomic_add(dst + idx[ij], v[ij]);
+        for (int i = 0; i < N; ++i) {
+            const T xi = tb.g[i];
+            if constexpr (DIM == 3) {
+                T c1[3], c2[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    c1[k] = C1[k] + E1[k] * xi;
+                    c2[k] = D2[k] + F2[k] * xi;
+                }
+                const T r0[3] = {c1[1] * c2[2] - c1[2] * c2[1], c1[2] * c2[0] - c1[0] * c2[2],
+                                 c1[0] * c2[1] - c1[1] * c2[0]};
+                const T r1[3] = {c2[1] * c0[2] - c2[2] * c0[1], c2[2] * c0[0] - c2[0] * c0[2],
+                                 c2[0] * c0[1] - c2[1] * c0[0]};
+                const T r2[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2],
+                                 c0[0] * c1[1] - c0[1] * c1[0]};
+                const T det = c0[0] * r0[0] + c0[1] * r0[1] + c0[2] * r0[2];
+                const T s = tb.w[i] * wl * recip(det);
+                const T x = gx[i], y = gy[i], z = gz[i];
+                T p[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) p[k] = (r0[k] * x + r1[k] * y + r2[k] * z) * s;
+                gx[i] = r0[0] * p[0] + r0[1] * p[1] + r0[2] * p[2];
+                gy[i] = r1[0] * p[0] + r1[1] * p[1] + r1[2] * p[2];
+                gz[i] = r2[0] * p[0] + r2[1] * p[1] + r2[2] * p[2];
+            } else {
+                const T c1[2] = {C1[0] + E1[0] * xi, C1[1] + E1[1] * xi};
+                const T det = c0[0] * c1[1] - c0[1] * c1[0];
+                const T s = tb.w[i] * wl * recip(det);
+                // rows of det(J) J^{-1}: (c1.y, -c1.x) and (-c0.y, c0.x)
+                const T x = gx[i], y = gz[i];
+                const T p0 = (c1[1] * x - c0[1] * y) * s;
+                const T p1 = (-c1[0] * x + c0[0] * y) * s;
+                gx[i] = c1[1] * p0 - c1[0] * p1;
+                gz[i] = -c0[1] * p0 + c0[0] * p1;
+            }
+        }
+    }
+
+    // ---- backward -------------------------------------------------------
+    line_apply<N, T, true>(tb.D, gx, u);  // Dx^T fx
+    if constexpr (DIM == 3) {
+        // + Dy^T fy
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) A[row + i] = gy[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = u[i];
+#pragma unroll
+            for (int c = 0; c < N; ++c) s += tb.D[c][j] * A[(t * N + c) * N + i];
+            u[i] = s;
+        }
+        // z: S^T (sum) + DS^T fz
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                B[row + i] = u[i];
+                Cc[row + i] = gz[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = tb.S[0][t] * B[(0 * N + j) * N + i] + tb.DS[0][t] * Cc[(0 * N + j) * N + i];
+#pragma unroll
+            for (int q = 1; q < N; ++q)
+                s += tb.S[q][t] * B[(q * N + j) * N + i] + tb.DS[q][t] * Cc[(q * N + j) * N + i];
+            v[i] = s;
+        }
+        // y: S^T
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) A[row + i] = v[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = tb.S[0][j] * A[(t * N + 0) * N + i];
+#pragma unroll
+            for (int q = 1; q < N; ++q) s += tb.S[q][j] * A[(t * N + q) * N + i];
+            u[i] = s;
+        }
+    } else {
+        // y: S^T (sum) + DS^T fy
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                B[row + i] = u[i];
+                Cc[row + i] = gz[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = tb.S[0][t] * B[0 * N + i] + tb.DS[0][t] * Cc[0 * N + i];
+#pragma unroll
+            for (int q = 1; q < N; ++q) s += tb.S[q][t] * B[q * N + i] + tb.DS[q][t] * Cc[q * N + i];
+            u[i] = s;
+        }
+    }
+    line_apply<N, T, true>(tb.S, u, v);  // x: S^T
+    T* out = elem + b * (N * WG) + lane;
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i * WG] = v[i];
 }
 
 template <int N, class T>
-__global__ __launch_bounds__(64) void vmult2_kernel(const int32_t* __restrict__ dmap,
-                                                    const T* __restrict__ metric,
-                                                    const T* __restrict__ src, T* __restrict__ dst,
-                                                    Tables<N, T> tb) {
-    constexpr int P = N;
-    constexpr int CPW = kWave / N;
-    __shared__ T lds[CPW][2][N][P];
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x;
-    const int team = lane / N;
-    const int t = lane - team * N;
-    const bool act = team < CPW;
-    const int tm = act ? team : 0;
-
-    const int32_t* dm = dmap + b * (P * kWave) + lane;
-    int32_t idx[P];
-    T u[P], v[P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) idx[i] = dm[i * kWave];
-#pragma unroll
-    for (int i = 0; i < P; ++i) u[i] = idx[i] >= 0 ? src[idx[i]] : T(0);
-#pragma unroll
+static OpTables<N, T> make_tables(const Basis1D& b) {
+    OpTables<N, T> t;
     for (int i = 0; i < N; ++i) {
-        T s = T(0);
-#pragma unroll
-        for (int a = 0; a < N; ++a) s += tb.S[i][a] * u[a];
-        v[i] = s;
-    }
-    if (act) {
-#pragma unroll
-        for (int i = 0; i < P; ++i) lds[tm][0][t][i] = v[i];
-    }
-    __syncthreads();
-    T gy[P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        T s0 = T(0), s1 = T(0);
-#pragma unroll
-        for (int c = 0; c < N; ++c) {
-            const T w = lds[tm][0][c][i];
-            s0 += tb.S[t][c] * w;
-            s1 += tb.DS[t][c] * w;
-        }
-        u[i] = s0;
-        gy[i] = s1;
-    }
-    T gx[P];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        T s = T(0);
-#pragma unroll
-        for (int a = 0; a < N; ++a) s += tb.D[i][a] * u[a];
-        gx[i] = s;
-    }
-    const T* mt = metric + b * (3 * P * kWave) + lane;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const T g00 = mt[(0 * P + i) * kWave];
-        const T g11 = mt[(1 * P + i) * kWave];
-        const T g01 = mt[(2 * P + i) * kWave];
-        const T x = gx[i], y = gy[i];
-        gx[i] = g00 * x + g01 * y;
-        gy[i] = g01 * x + g11 * y;
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        T s = T(0);
-#pragma unroll
-        for (int a = 0; a < N; ++a) s += tb.D[a][i] * gx[a];
-        u[i] = s;
-    }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-            lds[tm][0][t][i] = u[i];
-            lds[tm][1][t][i] = gy[i];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        T s = T(0);
-#pragma unroll
-        for (int q = 0; q < N; ++q) s += tb.S[q][t] * lds[tm][0][q][i] + tb.DS[q][t] * lds[tm][1][q][i];
-        v[i] = s;
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        T s = T(0);
-#pragma unroll
-        for (int q = 0; q < N; ++q) s += tb.S[q][i] * v[q];
-        u[i] = s;
-    }
-#pragma unroll
-    for (int i = 0; i < P; ++i)
-        if (idx[i] >= 0) atomic_add(dst + idx[i], u[i]);
-}
-
-template <int N, class T>
-Tables<N, T> make_tables(const Basis1D& b) {
-    Tables<N, T> t;
-    for (int i = 0; i < N; ++i)
+        t.g[i] = (T)b.gauss[i];
+        t.w[i] = (T)b.weight[i];
         for (int j = 0; j < N; ++j) {
             t.S[i][j] = (T)b.S[i][j];
             t.DS[i][j] = (T)b.DS[i][j];
             t.D[i][j] = (T)b.D[i][j];
         }
+    }
     return t;
 }
 
-template <int N, class T>
-static void vmult_dispatch(const Level& L, const T* metric, const void* src, void* dst, hipStream_t s) {
+template <int DIM, int N, class T>
+static void vmult_dispatch(const Level& L, const T* geo, int mode, const void* src, void* elem, hipStream_t s) {
     if (L.nblocks == 0) return;
-    const dim3 grid((unsigned)L.nblocks), block(kWave);
-    if (L.dim == 3)
-        hipLaunchKernelGGL((vmult3_kernel<N, T>), grid, block, 0, s, L.d_dofmap_blk.ptr, metric,
-                           (const T*)src, (T*)dst, make_tables<N, T>(L.basis));
+    using Sh = OpShape<DIM, N>;
+    const dim3 grid((unsigned)L.nblocks), block(Sh::WG);
+    const OpTables<N, T> tb = make_tables<N, T>(L.basis);
+    if (mode == kTrilinear)
+        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, kTrilinear>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
+                           (const T*)src, (T*)elem, tb);
     else
-        hipLaunchKernelGGL((vmult2_kernel<N, T>), grid, block, 0, s, L.d_dofmap_blk.ptr, metric,
-                           (const T*)src, (T*)dst, make_tables<N, T>(L.basis));
+        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, kStoredMetric>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
+                           (const T*)src, (T*)elem, tb);
     NNMG_HIP(hipGetLastError());
 }
 
 template <class T>
-static void vmult_prec(const Level& L, const T* metric, const void* src, void* dst, hipStream_t s) {
-    switch (L.n) {
-        case 2: vmult_dispatch<2, T>(L, metric, src, dst, s); break;
-        case 3: vmult_dispatch<3, T>(L, metric, src, dst, s); break;
-        case 4: vmult_dispatch<4, T>(L, metric, src, dst, s); break;
-        case 5: vmult_dispatch<5, T>(L, metric, src, dst, s); break;
-        default: fail(NNMG_ERR_UNSUPPORTED, "degree");
-    }
+static void vmult_prec(const Level& L, const T* geo, int mode, const void* src, void* elem, hipStream_t s) {
+#define NNMG_CASE(D, NN) \
+    if (L.dim == D && L.n == NN) return vmult_dispatch<D, NN, T>(L, geo, mode, src, elem, s);
+    NNMG_CASE(2, 2) NNMG_CASE(2, 3) NNMG_CASE(2, 4) NNMG_CASE(2, 5)
+    NNMG_CASE(3, 2) NNMG_CASE(3, 3) NNMG_CASE(3, 4) NNMG_CASE(3, 5)
+#undef NNMG_CASE
+    fail(NNMG_ERR_UNSUPPORTED, "operator degree/dimension");
+}
+
+void launch_vmult_elements(const Level& L, int prec, const void* src, void* elem, hipStream_t s) {
+    const int mode = L.geometry_mode;
+    const void* geo = mode == kTrilinear ? (prec == NNMG_FP64 ? (const void*)L.d_coef64.ptr : (const void*)L.d_coef32.ptr)
+                                         : (prec == NNMG_FP64 ? (const void*)L.d_metric64.ptr
+                                                              : (const void*)L.d_metric32.ptr);
+    if (L.nblocks > 0 && (!geo || !L.d_dofmap_blk.ptr || !elem)) fail(NNMG_ERR_INVALID_ARG, "operator data missing");
+    if (prec == NNMG_FP64)
+        vmult_prec<double>(L, (const double*)geo, mode, src, elem, s);
+    else
+        vmult_prec<float>(L, (const float*)geo, mode, src, elem, s);
 }
 
 void launch_vmult_cells(const Level& L, int prec, const void* src, void* dst, hipStream_t s) {
-    if (prec == NNMG_FP64)
-        vmult_prec<double>(L, L.d_metric64.ptr, src, dst, s);
-    else
-        vmult_prec<float>(L, L.d_metric32.ptr, src, dst, s);
+    launch_vmult_elements(L, prec, src, L.d_elem.ptr, s);
+    launch_gather(L, prec, L.d_elem.ptr, dst, true, s);
+}
+
+// block shape of the operator kernel, shared with the layout code of the level setup
+void vmult_shape(int dim, int n, int* wg, int* cells_per_block) {
+    const int L = dim == 3 ? n * n : n;
+    const int w = (dim == 3 && n == 5) ? 128 : 64;
+    *wg = w;
+    *cells_per_block = w / L;
 }
 
 }  // namespace nnmg
