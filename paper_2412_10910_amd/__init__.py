@@ -5,7 +5,9 @@ this package only marshals arguments to it.  Importing the package fails if
 the library has not been built.
 """
 
-from ._lib import NNMGError, lib  # noqa: F401
+import torch  # noqa: F401  (its HIP runtime is the one the library binds to)
+
+from ._lib import NNMGError, lib  # noqa: F401,E402
 
 lib()  # load now: no silent fallback when the HIP library is missing
 

@@ -124,6 +124,11 @@ SIGNATURES = {
 
 
 def load(path: str = LIB_PATH) -> C.CDLL:
+    # PyTorch's HIP runtime must be the one in the process before the library
+    # is loaded: both carry the soname libamdhip64.so.7, so the library then
+    # binds to torch's runtime, and the streams and pointers torch hands over
+    # belong to the same runtime as the library's kernel launches
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build it first (python paper_2412_10910_amd/csrc/build.py); "

@@ -30,8 +30,8 @@ namespace nnmg {
 enum { kPre = 0, kRes = 1, kRestrict = 2, kCoarse = 3, kProlong = 4, kPost = 5, kComponents = 6 };
 
 struct WorkVectors {
-    DeviceArray<char> f, x, d, r;
-    DeviceArray<char> elem;  // operator element buffer of this level
+    DeviceArray<char> f, x, d, ax, r;  // ax: operator output of atomic-scatter levels, kept zero between uses
+    DeviceArray<char> contrib;         // operator contribution slots of this level
 };
 
 struct ProfileRecord {
@@ -92,8 +92,9 @@ static void alloc_work(Hierarchy& H, int prec) {
         w.x.alloc(H.ctx, b);
         w.d.alloc(H.ctx, b);
         w.r.alloc(H.ctx, b);
-        for (auto* a : {&w.f, &w.x, &w.d, &w.r}) NNMG_HIP(hipMemset(a->ptr, 0, b));
-        w.elem.alloc(H.ctx, H.levels[l]->elem_len * wsize(prec));
+        w.ax.alloc(H.ctx, b);
+        for (auto* a : {&w.f, &w.x, &w.d, &w.r, &w.ax}) NNMG_HIP(hipMemset(a->ptr, 0, b));
+        w.contrib.alloc(H.ctx, std::max<size_t>(H.levels[l]->contrib_len, 1) * wsize(prec));
     }
 }
 
@@ -194,25 +195,47 @@ static void coarse_solve(Hierarchy& H, int prec, const void* f, void* x, hipStre
 // ---------------------------------------------------------------------------
 // smoother and V-cycle
 // ---------------------------------------------------------------------------
+// x <- x + d with d <- c1 d + c2 D^{-1} (f - A x)   (c1 unused when first)
+static void op_cheb_step(Hierarchy& H, int l, int prec, const void* f, const void* dinv, void* x, double c1,
+                         double c2, bool first, hipStream_t s) {
+    Level& L = *H.levels[l];
+    WorkVectors& w = H.work[prec][l];
+    if (L.atomic_scatter) {
+        launch_vmult_cells(L, prec, x, w.ax.ptr, s);
+        launch_cheb_step(prec, (size_t)L.n_dofs, f, w.ax.ptr, dinv, x, w.d.ptr, first ? 0.0 : c1, c2, s);
+    } else {
+        launch_vmult_contrib(L, prec, x, w.contrib.ptr, s);
+        launch_cheb_step_gather(L, prec, w.contrib.ptr, f, dinv, x, w.d.ptr, c1, c2, first, s);
+    }
+}
+
+// r = f - A x
+static void op_residual(Hierarchy& H, int l, int prec, const void* f, const void* x, void* r, hipStream_t s) {
+    Level& L = *H.levels[l];
+    WorkVectors& w = H.work[prec][l];
+    if (L.atomic_scatter) {
+        launch_vmult_cells(L, prec, x, w.ax.ptr, s);
+        launch_residual(prec, (size_t)L.n_dofs, f, w.ax.ptr, r, s);
+    } else {
+        launch_vmult_contrib(L, prec, x, w.contrib.ptr, s);
+        launch_residual_gather(L, prec, w.contrib.ptr, f, r, s);
+    }
+}
+
 static void chebyshev(Hierarchy& H, int l, int prec, const void* f, void* x, bool zero_start, hipStream_t s) {
     Level& L = *H.levels[l];
     WorkVectors& w = H.work[prec][l];
-    const size_t n = (size_t)L.n_dofs;
     const void* dinv = prec == NNMG_FP64 ? (const void*)L.d_dinv64.ptr : (const void*)L.d_dinv32.ptr;
     const double lo = H.lo[l], hi = H.hi[l];
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
-    if (zero_start) {
-        launch_cheb_first_zero(prec, n, f, dinv, x, w.d.ptr, 1.0 / theta, s);
-    } else {
-        launch_vmult_elements(L, prec, x, w.elem.ptr, s);
-        launch_cheb_step_gather(L, prec, w.elem.ptr, f, dinv, x, w.d.ptr, 0.0, 1.0 / theta, true, s);
-    }
+    if (zero_start)
+        launch_cheb_first_zero(prec, (size_t)L.n_dofs, f, dinv, x, w.d.ptr, 1.0 / theta, s);
+    else
+        op_cheb_step(H, l, prec, f, dinv, x, 0.0, 1.0 / theta, true, s);
     for (int j = 1; j < H.opts.cheb_degree; ++j) {
-        launch_vmult_elements(L, prec, x, w.elem.ptr, s);
         const double rho_new = 1.0 / (2.0 * sigma - rho);
-        launch_cheb_step_gather(L, prec, w.elem.ptr, f, dinv, x, w.d.ptr, rho_new * rho, 2.0 * rho_new / delta,
-                                false, s);
+        op_cheb_step(H, l, prec, f, dinv, x, rho_new * rho, 2.0 * rho_new / delta, false, s);
         rho = rho_new;
     }
 }
@@ -227,15 +250,13 @@ static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, 
     WorkVectors& w = H.work[prec][l];
     WorkVectors& wc = H.work[prec][l - 1];
     const Transfer& T = *H.transfers[l - 1];
-    const size_t n = (size_t)L.n_dofs;
     {
         Scope sc(H, l, kPre, s);
         chebyshev(H, l, prec, f, x, true, s);
     }
     {
         Scope sc(H, l, kRes, s);
-        launch_vmult_elements(L, prec, x, w.elem.ptr, s);
-        launch_residual_gather(L, prec, w.elem.ptr, f, w.r.ptr, s);
+        op_residual(H, l, prec, f, x, w.r.ptr, s);
     }
     {
         Scope sc(H, l, kRestrict, s);
@@ -465,9 +486,15 @@ int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg
     NNMG_HIP(hipMemcpyAsync(H.p.ptr, H.z.ptr, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     int status = NNMG_ERR_NOT_CONVERGED;
     for (int it = 1; it <= o.max_it; ++it) {
-        launch_vmult_elements(L, NNMG_FP64, H.p.ptr, H.work[NNMG_FP64][top].elem.ptr, s);
-        launch_gather_dot(L, (const double*)H.work[NNMG_FP64][top].elem.ptr, H.p.ptr, H.qv.ptr, H.partial.ptr,
-                          sc + 1, s);
+        if (L.atomic_scatter) {
+            launch_fill(H.qv.ptr, n, NNMG_FP64, s);
+            launch_vmult_cells(L, NNMG_FP64, H.p.ptr, H.qv.ptr, s);
+            launch_dot(H.p.ptr, H.qv.ptr, n, H.partial.ptr, sc + 1, s);
+        } else {
+            double* cb = (double*)H.work[NNMG_FP64][top].contrib.ptr;
+            launch_vmult_contrib(L, NNMG_FP64, H.p.ptr, cb, s);
+            launch_gather_dot(L, cb, H.p.ptr, H.qv.ptr, H.partial.ptr, sc + 1, s);
+        }
         launch_scalar_op(sc, 0, s);
         launch_cg_update(n, x, H.r.ptr, H.p.ptr, H.qv.ptr, sc, H.partial.ptr, sc + 3, s);
         NNMG_HIP(hipMemcpyAsync(H.hscal, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, s));

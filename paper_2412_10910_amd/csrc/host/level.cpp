@@ -12,6 +12,7 @@
 // order, local nodes lexicographic), which keeps the DoFs of neighbouring
 // cells close in memory.
 #include <algorithm>
+#include <cstdint>
 #include <array>
 #include <cmath>
 #include <cstdlib>
@@ -243,7 +244,6 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
         L->q = dim == 3 ? L->n * L->n * L->n : L->n * L->n;
         vmult_shape(dim, L->n, &L->wg, &L->cpb);
         L->n_cells = mesh->n_cells;
-        L->nblocks = (L->n_cells + L->cpb - 1) / L->cpb;
         L->basis = make_basis(degree);
         L->vertices.assign(mesh->vertices, mesh->vertices + mesh->n_vertices * dim);
         L->cells.assign(mesh->cells, mesh->cells + mesh->n_cells * nv);
@@ -257,37 +257,46 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
 
         NNMG_HIP(hipSetDevice(ctx->device));
         // device cell->DoF maps, constrained DoFs encoded as -1
-        const int q = L->q, n = L->n, P = dim == 3 ? n * n : n, M = dim * (dim + 1) / 2;
+        const int q = L->q, n = L->n, M = dim * (dim + 1) / 2;
         std::vector<int32_t> enc(L->dofmap.size());
         for (size_t i = 0; i < enc.size(); ++i) enc[i] = L->constrained[(size_t)L->dofmap[i]] ? -1 : L->dofmap[i];
         L->d_dofmap.upload(ctx, enc);
+        // block positions: cell c at position c (the order array leaves room for a
+        // locality-improving permutation), the last block padded
+        L->nblocks = (L->n_cells + L->cpb - 1) / L->cpb;
+        L->order.assign((size_t)(L->nblocks * L->cpb), -1);
+        for (int64_t c = 0; c < L->n_cells; ++c) L->order[(size_t)c] = (int32_t)c;
+        L->d_order.upload(ctx, L->order);
         // operator layout: lane (cell_in_block, line) holds the x-line `line` of its cell
         const int Lc = dim == 3 ? n * n : n, WG = L->wg;
         std::vector<int32_t> blk((size_t)(L->nblocks * n * WG), -1);
-        for (int64_t c = 0; c < L->n_cells; ++c) {
-            const int64_t b = c / L->cpb;
-            const int cell = (int)(c - b * L->cpb);
+        for (int64_t p = 0; p < L->nblocks * L->cpb; ++p) {
+            const int64_t c = L->order[(size_t)p];
+            if (c < 0) continue;
+            const int64_t b = p / L->cpb;
+            const int cell = (int)(p - b * L->cpb);
             for (int a = 0; a < q; ++a) {
                 const int i = a % n, line = a / n;
                 blk[(size_t)((b * n + i) * WG + cell * Lc + line)] = enc[(size_t)(c * q + a)];
             }
         }
         L->d_dofmap_blk.upload(ctx, blk);
-        // inverse map: for every DoF, the element-buffer slots that hold its contributions
+        // contribution slots: the (cell, node) contributions of DoF i occupy
+        // [off[i], off[i+1]) of a DoF-sorted buffer; pos_blk gives each lane's slots
         {
             std::vector<int32_t> off((size_t)L->n_dofs + 1, 0);
             for (size_t k = 0; k < blk.size(); ++k)
                 if (blk[k] >= 0) off[(size_t)blk[k] + 1]++;
             for (int64_t i = 0; i < L->n_dofs; ++i) off[(size_t)i + 1] += off[(size_t)i];
-            std::vector<int32_t> slot((size_t)off[(size_t)L->n_dofs]);
+            if ((int64_t)off[(size_t)L->n_dofs] > (int64_t)INT32_MAX) fail(NNMG_ERR_UNSUPPORTED, "too many contributions");
             std::vector<int32_t> cur(off.begin(), off.end() - 1);
+            std::vector<int32_t> pos(blk.size(), -1);
             for (size_t k = 0; k < blk.size(); ++k)
-                if (blk[k] >= 0) slot[(size_t)cur[(size_t)blk[k]]++] = (int32_t)k;
-            if (blk.size() > (size_t)INT32_MAX) fail(NNMG_ERR_UNSUPPORTED, "element buffer exceeds 32-bit slots");
+                if (blk[k] >= 0) pos[k] = cur[(size_t)blk[k]]++;
             L->d_inv_off.upload(ctx, off);
-            L->d_inv_slot.upload(ctx, slot);
-            L->elem_len = blk.size();
-            L->d_elem.alloc(ctx, L->elem_len * sizeof(double));
+            L->d_pos_blk.upload(ctx, pos);
+            L->contrib_len = (size_t)off[(size_t)L->n_dofs];
+            L->d_contrib.alloc(ctx, std::max<size_t>(L->contrib_len, 1) * sizeof(double));
         }
         L->d_constrained.upload(ctx, L->constrained_idx);
         std::vector<double> cv((size_t)(L->n_cells * nv * dim));
@@ -323,11 +332,12 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
         // rebuilds the geometry at the Gauss points
         const int NC = dim == 3 ? 21 : 6;
         std::vector<double> coef((size_t)(L->nblocks * NC * L->cpb), 0.0);
-        for (int64_t c = 0; c < L->nblocks * L->cpb; ++c) {
-            const int64_t b = c / L->cpb;
-            const int cell = (int)(c - b * L->cpb);
+        for (int64_t p = 0; p < L->nblocks * L->cpb; ++p) {
+            const int64_t b = p / L->cpb;
+            const int cell = (int)(p - b * L->cpb);
+            const int64_t c = L->order[(size_t)p];
             double X[8][3] = {};
-            if (c < L->n_cells) {
+            if (c >= 0) {
                 for (int v = 0; v < nv; ++v)
                     for (int i = 0; i < dim; ++i) X[v][i] = cv[(size_t)((c * nv + v) * dim + i)];
             } else {
@@ -360,6 +370,8 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
         L->d_coef32.upload(ctx, coef32);
         const char* mode = std::getenv("NNMG_GEOMETRY");
         L->geometry_mode = (mode && std::string(mode) == "metric") ? 0 : 1;
+        const char* scatter = std::getenv("NNMG_SCATTER");
+        L->atomic_scatter = scatter && std::string(scatter) == "atomic";
         if (L->geometry_mode == 1) {
             NNMG_HIP(hipDeviceSynchronize());
             L->d_metric64.reset();

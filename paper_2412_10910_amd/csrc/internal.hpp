@@ -131,10 +131,13 @@ struct Level {
     DeviceArray<float> d_coef32;
     DeviceArray<double> d_cellverts;    // [C][2^dim][dim]
     DeviceArray<int32_t> d_constrained;
-    DeviceArray<int32_t> d_inv_off;     // [N+1] contributions of DoF i: inv_slot[off[i] .. off[i+1])
-    DeviceArray<int32_t> d_inv_slot;    // element-buffer slots, in a fixed order
-    DeviceArray<char> d_elem;           // element buffer of the level's own operator calls
-    size_t elem_len = 0;                // entries of an element buffer: nblocks * n * wg
+    std::vector<int32_t> order;         // [nblocks * cpb] cell at each block position, -1 = padding
+    DeviceArray<int32_t> d_order;
+    DeviceArray<int32_t> d_inv_off;     // [N+1] contributions of DoF i: contrib[off[i] .. off[i+1])
+    DeviceArray<int32_t> d_pos_blk;     // operator layout: contribution slot of each (lane, node), -1 = none
+    size_t contrib_len = 0;             // number of contribution slots
+    DeviceArray<char> d_contrib;        // contribution buffer of the level's own operator calls
+    bool atomic_scatter = false;        // float atomics into the output instead of contribution slots
     DeviceArray<double> d_diag64;       // operator diagonal, 1 on constrained
     DeviceArray<double> d_dinv64;       // inverse diagonal, 0 on constrained
     DeviceArray<float> d_dinv32;
@@ -179,17 +182,18 @@ void launch_copy_constrained(const int32_t* idx, size_t n, const void* src, void
 
 // operator apply: dst += A src over the cells (constrained rows untouched)
 void vmult_shape(int dim, int n, int* wg, int* cells_per_block);
-// elem = cell contributions of A src in the element-buffer layout
-void launch_vmult_elements(const Level& L, int prec, const void* src, void* elem, hipStream_t s);
-// consumers of an element buffer (kernels/gather.hip); constrained rows are not written
-void launch_gather(const Level& L, int prec, const void* elem, void* dst, bool accumulate, hipStream_t s);
-void launch_cheb_step_gather(const Level& L, int prec, const void* elem, const void* f, const void* dinv, void* x,
-                             void* d, double c1, double c2, bool first, hipStream_t s);
-void launch_residual_gather(const Level& L, int prec, const void* elem, const void* f, void* r, hipStream_t s);
-void launch_gather_dot(const Level& L, const double* elem, const double* p, double* q, double* partial,
+// contrib = the (cell, node) contributions of A src, in DoF-sorted slots
+void launch_vmult_contrib(const Level& L, int prec, const void* src, void* contrib, hipStream_t s);
+// consumers of a contribution buffer (kernels/gather.hip); constrained rows are not written
+void launch_gather(const Level& L, int prec, const void* contrib, void* dst, bool accumulate, hipStream_t s);
+void launch_cheb_step_gather(const Level& L, int prec, const void* contrib, const void* f, const void* dinv,
+                             void* x, void* d, double c1, double c2, bool first, hipStream_t s);
+void launch_residual_gather(const Level& L, int prec, const void* contrib, const void* f, void* r, hipStream_t s);
+void launch_gather_dot(const Level& L, const double* contrib, const double* p, double* q, double* partial,
                        double* out, hipStream_t s);
 void launch_sum_partials(const double* partial, size_t m, double* out, hipStream_t s);
-// dst += A src using the level's own element buffer (not for concurrent use on one level)
+// dst += A src on the unconstrained rows and columns (constrained entries untouched);
+// uses the level's own contribution buffer: not for concurrent calls on one level
 void launch_vmult_cells(const Level& L, int prec, const void* src, void* dst, hipStream_t s);
 // geometry, diagonal, right-hand side (setup kernels)
 void launch_geometry(Level& L, int* d_bad, hipStream_t s);

@@ -1,20 +1,19 @@
-// Consumers of the operator's element buffer.  Each DoF i sums the
-// contributions of its cells, elem[slot[k]] for k in [off[i], off[i+1]), in a
-// fixed order (the inverse of the cell-to-DoF map, built at level setup), and
-// the sum feeds the consumer directly: plain gather, the Chebyshev step, the
-// residual, or the CG product with its dot product.  Constrained DoFs have no
-// contributions.
+// Consumers of the operator's contribution buffer.  The operator kernel
+// writes the contribution of every (cell, local node) to its own slot of a
+// buffer sorted by DoF, so DoF i sums the contiguous run contrib[off[i] ..
+// off[i+1]) in a fixed order; the sum feeds the consumer directly: plain
+// gather, the Chebyshev step, the residual, or the CG product with its dot
+// product.  Constrained DoFs have no contributions.
 #include "../internal.hpp"
 #include "common.hpp"
 
 namespace nnmg {
 
 template <class T>
-__device__ __forceinline__ T gather_sum(const int32_t* __restrict__ off, const int32_t* __restrict__ slot,
-                                        const T* __restrict__ elem, size_t i) {
+__device__ __forceinline__ T gather_sum(const int32_t* __restrict__ off, const T* __restrict__ contrib, size_t i) {
     const int k0 = off[i], k1 = off[i + 1];
     T s = T(0);
-    for (int k = k0; k < k1; ++k) s += elem[slot[k]];
+    for (int k = k0; k < k1; ++k) s += contrib[k];
     return s;
 }
 
@@ -26,11 +25,11 @@ static dim3 grid_n(size_t n, int threads = 256, size_t cap = 1 << 20) {
 }
 
 template <class T>
-__global__ void gather_kernel(size_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ slot,
+__global__ void gather_kernel(size_t n, const int32_t* __restrict__ off,
                               const T* __restrict__ elem, T* __restrict__ dst, int accumulate) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         if (off[i] == off[i + 1]) continue;  // constrained: untouched
-        const T s = gather_sum(off, slot, elem, i);
+        const T s = gather_sum(off, elem, i);
         dst[i] = accumulate ? dst[i] + s : s;
     }
 }
@@ -39,22 +38,22 @@ void launch_gather(const Level& L, int prec, const void* elem, void* dst, bool a
     const size_t n = (size_t)L.n_dofs;
     if (n == 0) return;
     if (prec == NNMG_FP64)
-        hipLaunchKernelGGL(gather_kernel<double>, grid_n(n), dim3(256), 0, s, n, L.d_inv_off.ptr, L.d_inv_slot.ptr,
+        hipLaunchKernelGGL(gather_kernel<double>, grid_n(n), dim3(256), 0, s, n, L.d_inv_off.ptr,
                            (const double*)elem, (double*)dst, (int)accumulate);
     else
-        hipLaunchKernelGGL(gather_kernel<float>, grid_n(n), dim3(256), 0, s, n, L.d_inv_off.ptr, L.d_inv_slot.ptr,
+        hipLaunchKernelGGL(gather_kernel<float>, grid_n(n), dim3(256), 0, s, n, L.d_inv_off.ptr,
                            (const float*)elem, (float*)dst, (int)accumulate);
     NNMG_HIP(hipGetLastError());
 }
 
 // r = f - A x;  d = c1 d + c2 dinv r;  x += d      (Chebyshev step, Saad Alg. 12.1)
 template <class T>
-__global__ void cheb_step_gather_kernel(size_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ slot,
+__global__ void cheb_step_gather_kernel(size_t n, const int32_t* __restrict__ off,
                                         const T* __restrict__ elem, const T* __restrict__ f,
                                         const T* __restrict__ dinv, T* __restrict__ x, T* __restrict__ d, T c1,
                                         T c2, int first) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const T r = f[i] - gather_sum(off, slot, elem, i);
+        const T r = f[i] - gather_sum(off, elem, i);
         const T dn = first ? c2 * (dinv[i] * r) : c1 * d[i] + c2 * (dinv[i] * r);
         d[i] = dn;
         x[i] += dn;
@@ -67,21 +66,21 @@ void launch_cheb_step_gather(const Level& L, int prec, const void* elem, const v
     if (n == 0) return;
     if (prec == NNMG_FP64)
         hipLaunchKernelGGL(cheb_step_gather_kernel<double>, grid_n(n), dim3(256), 0, s, n, L.d_inv_off.ptr,
-                           L.d_inv_slot.ptr, (const double*)elem, (const double*)f, (const double*)dinv, (double*)x,
+                           (const double*)elem, (const double*)f, (const double*)dinv, (double*)x,
                            (double*)d, c1, c2, (int)first);
     else
         hipLaunchKernelGGL(cheb_step_gather_kernel<float>, grid_n(n), dim3(256), 0, s, n, L.d_inv_off.ptr,
-                           L.d_inv_slot.ptr, (const float*)elem, (const float*)f, (const float*)dinv, (float*)x,
+                           (const float*)elem, (const float*)f, (const float*)dinv, (float*)x,
                            (float*)d, (float)c1, (float)c2, (int)first);
     NNMG_HIP(hipGetLastError());
 }
 
 // r = f - A x
 template <class T>
-__global__ void residual_gather_kernel(size_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ slot,
+__global__ void residual_gather_kernel(size_t n, const int32_t* __restrict__ off,
                                        const T* __restrict__ elem, const T* __restrict__ f, T* __restrict__ r) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        r[i] = f[i] - gather_sum(off, slot, elem, i);
+        r[i] = f[i] - gather_sum(off, elem, i);
 }
 
 void launch_residual_gather(const Level& L, int prec, const void* elem, const void* f, void* r, hipStream_t s) {
@@ -89,10 +88,10 @@ void launch_residual_gather(const Level& L, int prec, const void* elem, const vo
     if (n == 0) return;
     if (prec == NNMG_FP64)
         hipLaunchKernelGGL(residual_gather_kernel<double>, grid_n(n), dim3(256), 0, s, n, L.d_inv_off.ptr,
-                           L.d_inv_slot.ptr, (const double*)elem, (const double*)f, (double*)r);
+                           (const double*)elem, (const double*)f, (double*)r);
     else
         hipLaunchKernelGGL(residual_gather_kernel<float>, grid_n(n), dim3(256), 0, s, n, L.d_inv_off.ptr,
-                           L.d_inv_slot.ptr, (const float*)elem, (const float*)f, (float*)r);
+                           (const float*)elem, (const float*)f, (float*)r);
     NNMG_HIP(hipGetLastError());
 }
 
@@ -101,14 +100,13 @@ void launch_residual_gather(const Level& L, int prec, const void* elem, const vo
 constexpr int kRed = 256;
 
 __global__ __launch_bounds__(kRed) void gather_dot_kernel(size_t n, const int32_t* __restrict__ off,
-                                                          const int32_t* __restrict__ slot,
-                                                          const double* __restrict__ elem,
+                                                                            const double* __restrict__ elem,
                                                           const double* __restrict__ p, double* __restrict__ q,
                                                           double* __restrict__ partial) {
     __shared__ double sh[kRed / kWave];
     double acc = 0.0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const double v = gather_sum(off, slot, elem, i);
+        const double v = gather_sum(off, elem, i);
         q[i] = v;
         acc += p[i] * v;
     }
@@ -126,7 +124,7 @@ void launch_gather_dot(const Level& L, const double* elem, const double* p, doub
                        double* out, hipStream_t s) {
     const size_t n = (size_t)L.n_dofs;
     const size_t g = dot_partials(n);
-    hipLaunchKernelGGL(gather_dot_kernel, dim3((unsigned)g), dim3(kRed), 0, s, n, L.d_inv_off.ptr, L.d_inv_slot.ptr,
+    hipLaunchKernelGGL(gather_dot_kernel, dim3((unsigned)g), dim3(kRed), 0, s, n, L.d_inv_off.ptr,
                        elem, p, q, partial);
     launch_sum_partials(partial, g, out, s);
     NNMG_HIP(hipGetLastError());

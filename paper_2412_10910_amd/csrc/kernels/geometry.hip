@@ -98,16 +98,19 @@ __device__ inline int64_t blk_index(int64_t c, int qx, int qy, int qz, int n, in
     return ((b * M + m) * n + qx) * wg + cell * Lc + line;
 }
 
+// one thread per (block position, Gauss point); padding positions are skipped
 template <int DIM>
-__global__ void geometry_kernel(const double* __restrict__ cverts, int64_t ncells, int n, int cpb, int wg,
-                                GaussTable gt, double* __restrict__ m64, float* __restrict__ m32,
-                                int* __restrict__ bad) {
+__global__ void geometry_kernel(const double* __restrict__ cverts, const int32_t* __restrict__ order,
+                                int64_t npos, int n, int cpb, int wg, GaussTable gt, double* __restrict__ m64,
+                                float* __restrict__ m32, int* __restrict__ bad) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int qn = 1;
     for (int a = 0; a < DIM; ++a) qn *= n;
-    if (gid >= ncells * qn) return;
-    const int64_t c = gid / qn;
-    const int q = (int)(gid - c * qn);
+    if (gid >= npos * qn) return;
+    const int64_t pos = gid / qn;
+    const int q = (int)(gid - pos * qn);
+    const int64_t c = order[pos];
+    if (c < 0) return;
     const int qx = q % n, qy = (q / n) % n, qz = DIM == 3 ? q / (n * n) : 0;
     double xi[DIM];
     xi[0] = gt.g[qx];
@@ -131,7 +134,7 @@ __global__ void geometry_kernel(const double* __restrict__ cverts, int64_t ncell
         const double vals[6] = {G(0, 0), G(1, 1), G(2, 2), G(0, 1), G(0, 2), G(1, 2)};
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
-            const int64_t k = blk_index<3>(c, qx, qy, qz, n, cpb, wg, m);
+            const int64_t k = blk_index<3>(pos, qx, qy, qz, n, cpb, wg, m);
             m64[k] = vals[m];
             m32[k] = (float)vals[m];
         }
@@ -139,7 +142,7 @@ __global__ void geometry_kernel(const double* __restrict__ cverts, int64_t ncell
         const double vals[3] = {G(0, 0), G(1, 1), G(0, 1)};
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            const int64_t k = blk_index<2>(c, qx, qy, 0, n, cpb, wg, m);
+            const int64_t k = blk_index<2>(pos, qx, qy, 0, n, cpb, wg, m);
             m64[k] = vals[m];
             m32[k] = (float)vals[m];
         }
@@ -147,31 +150,35 @@ __global__ void geometry_kernel(const double* __restrict__ cverts, int64_t ncell
 }
 
 void launch_geometry(Level& L, int* d_bad, hipStream_t s) {
-    const int64_t total = L.n_cells * L.q;
+    const int64_t npos = L.nblocks * L.cpb;
+    const int64_t total = npos * L.q;
     if (total == 0) return;
     if (!L.d_metric64.ptr || !L.d_metric32.ptr) fail(NNMG_ERR_INVALID_ARG, "metric arrays are not allocated");
     const int threads = 256;
     const dim3 grid((unsigned)((total + threads - 1) / threads));
     const GaussTable gt = gauss_table(L.basis);
     if (L.dim == 3)
-        hipLaunchKernelGGL(geometry_kernel<3>, grid, dim3(threads), 0, s, L.d_cellverts.ptr, L.n_cells, L.n,
-                           L.cpb, L.wg, gt, L.d_metric64.ptr, L.d_metric32.ptr, d_bad);
+        hipLaunchKernelGGL(geometry_kernel<3>, grid, dim3(threads), 0, s, L.d_cellverts.ptr, L.d_order.ptr, npos,
+                           L.n, L.cpb, L.wg, gt, L.d_metric64.ptr, L.d_metric32.ptr, d_bad);
     else
-        hipLaunchKernelGGL(geometry_kernel<2>, grid, dim3(threads), 0, s, L.d_cellverts.ptr, L.n_cells, L.n,
-                           L.cpb, L.wg, gt, L.d_metric64.ptr, L.d_metric32.ptr, d_bad);
+        hipLaunchKernelGGL(geometry_kernel<2>, grid, dim3(threads), 0, s, L.d_cellverts.ptr, L.d_order.ptr, npos,
+                           L.n, L.cpb, L.wg, gt, L.d_metric64.ptr, L.d_metric32.ptr, d_bad);
     NNMG_HIP(hipGetLastError());
 }
 
 // diag_i += sum_q grad_ref(phi_a)(q)^T G_q grad_ref(phi_a)(q), one thread per (cell, local node)
 template <int DIM>
-__global__ void diagonal_kernel(const int32_t* __restrict__ dofmap, const double* __restrict__ m64,
-                                int64_t ncells, int n, int cpb, int wg, GaussTable gt, double* __restrict__ diag) {
+__global__ void diagonal_kernel(const int32_t* __restrict__ dofmap, const int32_t* __restrict__ order,
+                                const double* __restrict__ m64, int64_t npos, int n, int cpb, int wg, GaussTable gt,
+                                double* __restrict__ diag) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int qn = 1;
     for (int a = 0; a < DIM; ++a) qn *= n;
-    if (gid >= ncells * qn) return;
-    const int64_t c = gid / qn;
-    const int a = (int)(gid - c * qn);
+    if (gid >= npos * qn) return;
+    const int64_t pos = gid / qn;
+    const int a = (int)(gid - pos * qn);
+    const int64_t c = order[pos];
+    if (c < 0) return;
     const int dof = dofmap[c * qn + a];
     if (dof < 0) return;
     const int ax = a % n, ay = (a / n) % n, az = DIM == 3 ? a / (n * n) : 0;
@@ -182,20 +189,20 @@ __global__ void diagonal_kernel(const int32_t* __restrict__ dofmap, const double
             const double g0 = gt.DS[qx][ax] * gt.S[qy][ay] * gt.S[qz][az];
             const double g1 = gt.S[qx][ax] * gt.DS[qy][ay] * gt.S[qz][az];
             const double g2 = gt.S[qx][ax] * gt.S[qy][ay] * gt.DS[qz][az];
-            const double G00 = m64[blk_index<3>(c, qx, qy, qz, n, cpb, wg, 0)];
-            const double G11 = m64[blk_index<3>(c, qx, qy, qz, n, cpb, wg, 1)];
-            const double G22 = m64[blk_index<3>(c, qx, qy, qz, n, cpb, wg, 2)];
-            const double G01 = m64[blk_index<3>(c, qx, qy, qz, n, cpb, wg, 3)];
-            const double G02 = m64[blk_index<3>(c, qx, qy, qz, n, cpb, wg, 4)];
-            const double G12 = m64[blk_index<3>(c, qx, qy, qz, n, cpb, wg, 5)];
+            const double G00 = m64[blk_index<3>(pos, qx, qy, qz, n, cpb, wg, 0)];
+            const double G11 = m64[blk_index<3>(pos, qx, qy, qz, n, cpb, wg, 1)];
+            const double G22 = m64[blk_index<3>(pos, qx, qy, qz, n, cpb, wg, 2)];
+            const double G01 = m64[blk_index<3>(pos, qx, qy, qz, n, cpb, wg, 3)];
+            const double G02 = m64[blk_index<3>(pos, qx, qy, qz, n, cpb, wg, 4)];
+            const double G12 = m64[blk_index<3>(pos, qx, qy, qz, n, cpb, wg, 5)];
             sum += G00 * g0 * g0 + G11 * g1 * g1 + G22 * g2 * g2 +
                    2.0 * (G01 * g0 * g1 + G02 * g0 * g2 + G12 * g1 * g2);
         } else {
             const double g0 = gt.DS[qx][ax] * gt.S[qy][ay];
             const double g1 = gt.S[qx][ax] * gt.DS[qy][ay];
-            const double G00 = m64[blk_index<2>(c, qx, qy, 0, n, cpb, wg, 0)];
-            const double G11 = m64[blk_index<2>(c, qx, qy, 0, n, cpb, wg, 1)];
-            const double G01 = m64[blk_index<2>(c, qx, qy, 0, n, cpb, wg, 2)];
+            const double G00 = m64[blk_index<2>(pos, qx, qy, 0, n, cpb, wg, 0)];
+            const double G11 = m64[blk_index<2>(pos, qx, qy, 0, n, cpb, wg, 1)];
+            const double G01 = m64[blk_index<2>(pos, qx, qy, 0, n, cpb, wg, 2)];
             sum += G00 * g0 * g0 + G11 * g1 * g1 + 2.0 * G01 * g0 * g1;
         }
     }
@@ -203,18 +210,19 @@ __global__ void diagonal_kernel(const int32_t* __restrict__ dofmap, const double
 }
 
 void launch_diagonal(const Level& L, double* diag, hipStream_t s) {
-    const int64_t total = L.n_cells * L.q;
+    const int64_t npos = L.nblocks * L.cpb;
+    const int64_t total = npos * L.q;
     if (total == 0) return;
     if (!L.d_metric64.ptr) fail(NNMG_ERR_INVALID_ARG, "diagonal needs the stored metric (level setup only)");
     const int threads = 256;
     const dim3 grid((unsigned)((total + threads - 1) / threads));
     const GaussTable gt = gauss_table(L.basis);
     if (L.dim == 3)
-        hipLaunchKernelGGL(diagonal_kernel<3>, grid, dim3(threads), 0, s, L.d_dofmap.ptr, L.d_metric64.ptr,
-                           L.n_cells, L.n, L.cpb, L.wg, gt, diag);
+        hipLaunchKernelGGL(diagonal_kernel<3>, grid, dim3(threads), 0, s, L.d_dofmap.ptr, L.d_order.ptr,
+                           L.d_metric64.ptr, npos, L.n, L.cpb, L.wg, gt, diag);
     else
-        hipLaunchKernelGGL(diagonal_kernel<2>, grid, dim3(threads), 0, s, L.d_dofmap.ptr, L.d_metric64.ptr,
-                           L.n_cells, L.n, L.cpb, L.wg, gt, diag);
+        hipLaunchKernelGGL(diagonal_kernel<2>, grid, dim3(threads), 0, s, L.d_dofmap.ptr, L.d_order.ptr,
+                           L.d_metric64.ptr, npos, L.n, L.cpb, L.wg, gt, diag);
     NNMG_HIP(hipGetLastError());
 }
 

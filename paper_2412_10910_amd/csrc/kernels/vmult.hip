@@ -16,15 +16,15 @@
 // gradient by collocation (D on the Gauss points; along z in 3D / y in 2D the
 // derivative DS = D S is fused with the interpolation).  At each Gauss point
 // the flux is G grad_ref(u), G = w det(J) J^{-1} J^{-T} the merged metric.
-// Backward: the transposes.  The cell results are not scattered with
-// atomics: every lane stores its N values, coalesced, into a per-level element
-// buffer laid out like the cell-to-DoF map,
+// Backward: the transposes.  The cell results are not added with float
+// atomics: each (cell, node) contribution is written to its own slot of a
+// buffer sorted by DoF,
 //
-//   elem_blk[(blk * N + i) * WG + lane],
+//   contrib[pos_blk[(blk * N + i) * WG + lane]],
 //
-// and the consumers (gather kernels, Chebyshev step, residual, CG update) sum
-// each DoF's contributions through an inverse map built at setup.  The sum
-// order is fixed, so the operator is deterministic.
+// and the consumers (gather, Chebyshev step, residual, CG product) sum every
+// DoF's contiguous run of slots in a fixed order: one launch, no atomics, and
+// a deterministic operator.  (A float-atomic variant is kept for comparison.)
 //
 // Two geometry sources:
 //  * kStoredMetric: G read per Gauss point from
@@ -86,12 +86,18 @@ struct OpShape {
 
 constexpr int kStoredMetric = 0;
 constexpr int kTrilinear = 1;
+constexpr int kSlots = 0;
+constexpr int kAtomic = 1;
 
-template <int DIM, int N, class T, int GEO>
-__global__ __launch_bounds__((OpShape<DIM, N>::WG)) void vmult_kernel(const int32_t* __restrict__ dmap,
+#ifndef NNMG_VMULT_MINWAVES
+#define NNMG_VMULT_MINWAVES 1
+#endif
+template <int DIM, int N, class T, int GEO, int SCATTER>
+__global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vmult_kernel(const int32_t* __restrict__ dmap,
                                                                     const T* __restrict__ geo,
                                                                     const T* __restrict__ src,
-                                                                    T* __restrict__ elem, OpTables<N, T> tb) {
+                                                                    const int32_t* __restrict__ slots,
+                                                                    T* __restrict__ dst, OpTables<N, T> tb) {
     using Sh = OpShape<DIM, N>;
     constexpr int L = Sh::L, WG = Sh::WG, CPB = Sh::CPB, TILE = Sh::TILE;
     constexpr int M = DIM * (DIM + 1) / 2;
@@ -108,34 +114,14 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG)) void vmult_kernel(const int3
     const int t = DIM == 3 ? line / N : line;
     const int row = line * N;  // offset of this lane's x-line in a cell tile
 
-    // geometry constants of this lane's line
-    T c0[DIM], C1[DIM], E1[DIM], D2[DIM], F2[DIM];
+    // the cell's map coefficients go to LDS at once (independent of everything
+    // else); each lane turns them into the constants of its line just before
+    // the geometry step, so they hold no registers during the sweeps
+    __shared__ T lcf[CPB][GEO == kTrilinear ? NC : 1];
     if constexpr (GEO == kTrilinear) {
-        T cf[NC];
-        const T* gc = geo + b * (NC * CPB) + cb;
-#pragma unroll
-        for (int m = 0; m < NC; ++m) cf[m] = gc[m * CPB];
-        if constexpr (DIM == 3) {
-            const T eta = tb.g[j], zeta = tb.g[t];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                // d/dxi = b + e eta + f zeta + h eta zeta          (constant on the line)
-                c0[k] = cf[0 + k] + cf[9 + k] * eta + (cf[12 + k] + cf[18 + k] * eta) * zeta;
-                // d/deta = (c + g zeta) + (e + h zeta) xi
-                C1[k] = cf[3 + k] + cf[15 + k] * zeta;
-                E1[k] = cf[9 + k] + cf[18 + k] * zeta;
-                // d/dzeta = (d + g eta) + (f + h eta) xi
-                D2[k] = cf[6 + k] + cf[15 + k] * eta;
-                F2[k] = cf[12 + k] + cf[18 + k] * eta;
-            }
-        } else {
-            const T eta = tb.g[t];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                c0[k] = cf[0 + k] + cf[4 + k] * eta;  // d/dxi = b + d eta
-                C1[k] = cf[2 + k];                    // d/deta = c + d xi
-                E1[k] = cf[4 + k];
-            }
+        if (act) {
+            const T* gc = geo + b * (NC * CPB) + cb;
+            for (int m = line; m < NC; m += L) lcf[cb][m] = gc[m * CPB];
         }
     }
 
@@ -245,6 +231,30 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG)) void vmult_kernel(const int3
             }
         }
     } else {
+        T c0[DIM], C1[DIM], E1[DIM], D2[DIM], F2[DIM];
+        const T* cf = lcf[cb];
+        if constexpr (DIM == 3) {
+            const T eta = tb.g[j], zeta = tb.g[t];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                // d/dxi = b + e eta + f zeta + h eta zeta          (constant on the line)
+                c0[k] = cf[0 + k] + cf[9 + k] * eta + (cf[12 + k] + cf[18 + k] * eta) * zeta;
+                // d/deta = (c + g zeta) + (e + h zeta) xi
+                C1[k] = cf[3 + k] + cf[15 + k] * zeta;
+                E1[k] = cf[9 + k] + cf[18 + k] * zeta;
+                // d/dzeta = (d + g eta) + (f + h eta) xi
+                D2[k] = cf[6 + k] + cf[15 + k] * eta;
+                F2[k] = cf[12 + k] + cf[18 + k] * eta;
+            }
+        } else {
+            const T eta = tb.g[t];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                c0[k] = cf[0 + k] + cf[4 + k] * eta;  // d/dxi = b + d eta
+                C1[k] = cf[2 + k];                    // d/deta = c + d xi
+                E1[k] = cf[4 + k];
+            }
+        }
         const T wl = DIM == 3 ? tb.w[j] * tb.w[t] : tb.w[t];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -350,9 +360,18 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG)) void vmult_kernel(const int3
         }
     }
     line_apply<N, T, true>(tb.S, u, v);  // x: S^T
-    T* out = elem + b * (N * WG) + lane;
+    if constexpr (SCATTER == kSlots) {
+        const int32_t* ps = slots + b * (N * WG) + lane;
 #pragma unroll
-    for (int i = 0; i < N; ++i) out[i * WG] = v[i];
+        for (int i = 0; i < N; ++i) {
+            const int32_t k = ps[i * WG];
+            if (k >= 0) dst[k] = v[i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (idx[i] >= 0) atomic_add(dst + idx[i], v[i]);
+    }
 }
 
 template <int N, class T>
@@ -370,46 +389,64 @@ static OpTables<N, T> make_tables(const Basis1D& b) {
     return t;
 }
 
-template <int DIM, int N, class T>
-static void vmult_dispatch(const Level& L, const T* geo, int mode, const void* src, void* elem, hipStream_t s) {
-    if (L.nblocks == 0) return;
+template <int DIM, int N, class T, int GEO>
+static void vmult_launches(const Level& L, const T* geo, bool atomic, const void* src, void* dst, hipStream_t s) {
     using Sh = OpShape<DIM, N>;
-    const dim3 grid((unsigned)L.nblocks), block(Sh::WG);
     const OpTables<N, T> tb = make_tables<N, T>(L.basis);
-    if (mode == kTrilinear)
-        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, kTrilinear>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
-                           (const T*)src, (T*)elem, tb);
+    const dim3 grid((unsigned)L.nblocks), block(Sh::WG);
+    if (atomic)
+        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kAtomic>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
+                           (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb);
     else
-        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, kStoredMetric>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
-                           (const T*)src, (T*)elem, tb);
+        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
+                           (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb);
     NNMG_HIP(hipGetLastError());
 }
 
+template <int DIM, int N, class T>
+static void vmult_dispatch(const Level& L, const T* geo, int mode, bool atomic, const void* src, void* dst,
+                           hipStream_t s) {
+    if (L.nblocks == 0) return;
+    if (mode == kTrilinear)
+        vmult_launches<DIM, N, T, kTrilinear>(L, geo, atomic, src, dst, s);
+    else
+        vmult_launches<DIM, N, T, kStoredMetric>(L, geo, atomic, src, dst, s);
+}
+
 template <class T>
-static void vmult_prec(const Level& L, const T* geo, int mode, const void* src, void* elem, hipStream_t s) {
+static void vmult_prec(const Level& L, const T* geo, int mode, bool atomic, const void* src, void* dst,
+                       hipStream_t s) {
 #define NNMG_CASE(D, NN) \
-    if (L.dim == D && L.n == NN) return vmult_dispatch<D, NN, T>(L, geo, mode, src, elem, s);
+    if (L.dim == D && L.n == NN) return vmult_dispatch<D, NN, T>(L, geo, mode, atomic, src, dst, s);
     NNMG_CASE(2, 2) NNMG_CASE(2, 3) NNMG_CASE(2, 4) NNMG_CASE(2, 5)
     NNMG_CASE(3, 2) NNMG_CASE(3, 3) NNMG_CASE(3, 4) NNMG_CASE(3, 5)
 #undef NNMG_CASE
     fail(NNMG_ERR_UNSUPPORTED, "operator degree/dimension");
 }
 
-void launch_vmult_elements(const Level& L, int prec, const void* src, void* elem, hipStream_t s) {
+static void launch_op(const Level& L, int prec, bool atomic, const void* src, void* dst, hipStream_t s) {
     const int mode = L.geometry_mode;
     const void* geo = mode == kTrilinear ? (prec == NNMG_FP64 ? (const void*)L.d_coef64.ptr : (const void*)L.d_coef32.ptr)
                                          : (prec == NNMG_FP64 ? (const void*)L.d_metric64.ptr
                                                               : (const void*)L.d_metric32.ptr);
-    if (L.nblocks > 0 && (!geo || !L.d_dofmap_blk.ptr || !elem)) fail(NNMG_ERR_INVALID_ARG, "operator data missing");
+    if (L.nblocks > 0 && (!geo || !L.d_dofmap_blk.ptr || !dst)) fail(NNMG_ERR_INVALID_ARG, "operator data missing");
     if (prec == NNMG_FP64)
-        vmult_prec<double>(L, (const double*)geo, mode, src, elem, s);
+        vmult_prec<double>(L, (const double*)geo, mode, atomic, src, dst, s);
     else
-        vmult_prec<float>(L, (const float*)geo, mode, src, elem, s);
+        vmult_prec<float>(L, (const float*)geo, mode, atomic, src, dst, s);
+}
+
+void launch_vmult_contrib(const Level& L, int prec, const void* src, void* contrib, hipStream_t s) {
+    launch_op(L, prec, false, src, contrib, s);
 }
 
 void launch_vmult_cells(const Level& L, int prec, const void* src, void* dst, hipStream_t s) {
-    launch_vmult_elements(L, prec, src, L.d_elem.ptr, s);
-    launch_gather(L, prec, L.d_elem.ptr, dst, true, s);
+    if (L.atomic_scatter) {
+        launch_op(L, prec, true, src, dst, s);
+    } else {
+        launch_op(L, prec, false, src, L.d_contrib.ptr, s);
+        launch_gather(L, prec, L.d_contrib.ptr, dst, true, s);
+    }
 }
 
 // block shape of the operator kernel, shared with the layout code of the level setup

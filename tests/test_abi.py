@@ -51,3 +51,16 @@ def test_defaults_without_a_gpu():
     h = C.c_void_p()
     code = lib.nnmg_level_create(None, None, 1, C.byref(h))
     assert code == -1 and lib.nnmg_last_error()
+
+
+def test_library_binds_to_torchs_hip_runtime():
+    """Exactly one HIP runtime in the process: the library reuses torch's."""
+    import subprocess
+    import sys
+    code = ("import paper_2412_10910_amd\n"
+            "maps = open('/proc/self/maps').read()\n"
+            "paths = {l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l}\n"
+            "print(len(paths))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
