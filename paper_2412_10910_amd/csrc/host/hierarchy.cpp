@@ -246,7 +246,6 @@ static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, 
         coarse_solve(H, prec, f, x, s);
         return;
     }
-    Level& L = *H.levels[l];
     WorkVectors& w = H.work[prec][l];
     WorkVectors& wc = H.work[prec][l - 1];
     const Transfer& T = *H.transfers[l - 1];
