@@ -47,11 +47,109 @@ def percentile(xs, p):
 
 
 def vmult_bytes(level, word):
-    """Algorithmic bytes of one operator application: read src, write dst,
-    the int32 cell-to-DoF map and the merged metric (d(d+1)/2 words per Gauss point)."""
+    """Algorithmic bytes of one operator application dst = A src: read src and
+    write dst (N words each), the int32 cell-to-DoF map (q per cell) and the
+    merged metric, d(d+1)/2 words per Gauss point (the stored-geometry form of
+    the operator; the library recomputes the trilinear metric instead, which
+    moves fewer bytes, so this is the method's figure, not a count of ours)."""
     q = (level.degree + 1) ** level.dim
     m = level.dim * (level.dim + 1) // 2
     return 2 * word * level.n_dofs + 4 * level.n_cells * q + word * level.n_cells * q * m
+
+
+def transfer_bytes(coarse, n_points, word, prolong):
+    """Algorithmic bytes of one prolongation (fine += P coarse) or restriction
+    (coarse += P^T fine): per fine point its index (int32), its d reference
+    coordinates and the fine value (read and written for prolongation, read
+    for restriction); per coarse cell the two point-range offsets it reads,
+    its q int32 DoF indices and the q coarse values (read for prolongation,
+    read and written for restriction)."""
+    q = (coarse.degree + 1) ** coarse.dim
+    d = coarse.dim
+    per_point = 4 + d * word + (2 if prolong else 1) * word
+    per_cell = 8 + 4 * q + (1 if prolong else 2) * word * q
+    return n_points * per_point + coarse.n_cells * per_cell
+
+
+KERNEL_SOURCES = ("paper_2412_10910_amd/csrc/kernels/vmult.hip", "paper_2412_10910_amd/csrc/kernels/gather.hip",
+                  "paper_2412_10910_amd/csrc/kernels/transfer.hip", "paper_2412_10910_amd/csrc/internal.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_operator_transfer_cube_q2_64.txt")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary,
+    or {} when it is missing or was taken on kernel sources that have changed."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return {}
+    kv = {}
+    for line in lines:
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256_16") != kernel_source_hash():
+        return {}
+    return {k[len("traffic_bytes."):]: float(v) for k, v in kv.items() if k.startswith("traffic_bytes.")}
+
+
+def time_launches(fn, reps):
+    """Average duration of fn() in ms from HIP events recorded on the current
+    stream (the stream the library launches on), after 5 untimed calls."""
+    import torch
+    for _ in range(5):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def kernel_rooflines(fine, coarse, transfer, reps):
+    """Operator and transfer kernels of the two finest levels, FP64 and FP32."""
+    import torch
+    dev = "cuda:0"
+    npts = transfer.n_points
+    out = {}
+    for dt, word, tag in ((torch.float64, 8, "fp64"), (torch.float32, 4, "fp32")):
+        src = torch.rand(fine.n_dofs, dtype=torch.float64, device=dev).to(dt)
+        dst = torch.zeros_like(src)
+        csrc = torch.rand(coarse.n_dofs, dtype=torch.float64, device=dev).to(dt)
+        cdst = torch.zeros_like(csrc)
+        ms = time_launches(lambda: fine.vmult_add(src, dst), reps)
+        out[f"operator_{tag}"] = dict(ms=ms, bytes=vmult_bytes(fine, word))
+        ms = time_launches(lambda: transfer.prolongate(csrc, dst), reps)
+        out[f"prolongate_{tag}"] = dict(ms=ms, bytes=transfer_bytes(coarse, npts, word, True))
+        ms = time_launches(lambda: transfer.restrict(src, cdst), reps)
+        out[f"restrict_{tag}"] = dict(ms=ms, bytes=transfer_bytes(coarse, npts, word, False))
+    for v in out.values():
+        v["gbs"] = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+        v["frac"] = v["gbs"] / HBM_PEAK_GBS
+    return out
+
+
+def copy_calibration(nbytes=1 << 30):
+    """A plain device copy of known size: its FETCH_SIZE/WRITE_SIZE readings
+    scale the counters of the other kernels to bytes."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return nbytes
 
 
 def cpu_baseline(cells, cfg):
@@ -111,6 +209,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", help="also print the per-component V-cycle times")
     ap.add_argument("--roofline-reps", type=int, default=100)
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the operator/transfer kernel loops of the two finest levels and a copy of "
+                         "known size (the run that rocprofv3 traces and counts)")
     ap.add_argument("--geometry", choices=["trilinear", "metric"], default=None,
                     help="operator geometry source (default: the library's choice)")
     args = ap.parse_args()
@@ -121,7 +222,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2412_10910_amd as nn
@@ -136,6 +236,18 @@ def main():
 
     log("generating meshes")
     meshes = config_levels(cfg, cells=cells)
+
+    if args.roofline_only:
+        fine = nn.Level.from_mesh(ctx, meshes[-1], degree)
+        coarse = nn.Level.from_mesh(ctx, meshes[-2], degree)
+        tr = nn.Transfer(ctx, fine, coarse)
+        nbytes = copy_calibration()
+        k = kernel_rooflines(fine, coarse, tr, args.roofline_reps)
+        print(json.dumps({"roofline_only": True, "copy_bytes": nbytes, "reps": args.roofline_reps,
+                          "kernels": {n: {"ms": round(v["ms"], 5), "bytes": v["bytes"], "GB/s": round(v["gbs"], 1),
+                                          "frac": round(v["frac"], 4)} for n, v in k.items()}}), flush=True)
+        return
+
     t0 = time.perf_counter()
     levels = [nn.Level.from_mesh(ctx, m, degree) for m in meshes]
     t_levels = time.perf_counter() - t0
@@ -175,30 +287,9 @@ def main():
     value = fine.n_dofs * sum(its64) / tot64 / 1e6
     value32 = fine.n_dofs * sum(its32) / tot32 / 1e6
 
-    # operator kernel on the fine level: one launch per call, timed with events
-    log("timing the operator kernel")
-    reps = args.roofline_reps
-    src = torch.rand(fine.n_dofs, dtype=torch.float64, device=dev)
-    dst = torch.zeros_like(src)
-    for _ in range(5):
-        fine.vmult_add(src, dst)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        fine.vmult_add(src, dst)
-    e1.record()
-    torch.cuda.synchronize()
-    k_ms = e0.elapsed_time(e1) / reps
-    bytes64 = vmult_bytes(fine, 8)
-    achieved = bytes64 / (k_ms * 1e-3) / 1e9
-    src32, dst32 = src.float(), dst.float()
-    e0.record()
-    for _ in range(reps):
-        fine.vmult_add(src32, dst32)
-    e1.record()
-    torch.cuda.synchronize()
-    k32_ms = e0.elapsed_time(e1) / reps
-    achieved32 = vmult_bytes(fine, 4) / (k32_ms * 1e-3) / 1e9
+    log("timing the operator and transfer kernels")
+    k = kernel_rooflines(fine, levels[-2], transfers[-1], args.roofline_reps)
+    traffic = recorded_traffic()
 
     profile = None
     if args.profile:
@@ -212,6 +303,13 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline([3, 6, 13, 29], cfg)
+
+    op = k["operator_fp64"]
+
+    def entry(name):
+        v = k[name]
+        return {"ms": round(v["ms"], 5), "bytes": v["bytes"], "achieved": round(v["gbs"], 1),
+                "frac": round(v["frac"], 4), "traffic": traffic.get(name)}
 
     line = {
         "metric": METRIC,
@@ -241,21 +339,22 @@ def main():
             "relres": info32["relres"],
             "latency_ms": {"p50": round(percentile(lat32, 50) * 1e3, 4),
                            "p99": round(percentile(lat32, 99) * 1e3, 4)},
-            "speedup_vs_fp64_mg": round((tot64 / sum(its64) * its64[-1]) / (tot32 / sum(its32) * its32[-1]), 3),
+            "speedup_vs_fp64_mg": round(tot64 / tot32, 3),
         },
         "setup_s": {"levels": round(t_levels, 3), "transfers": round(t_transfers, 3), "hierarchy": round(t_hier, 3)},
         "roofline": {
             "bound": "hbm",
-            "kernel": "vmult3_kernel<3,double> (fine level, 262144 cells)",
-            "achieved": round(achieved, 1),
+            "achieved": round(op["gbs"], 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "bytes_per_launch": bytes64,
-            "kernel_ms": round(k_ms, 5),
-            "fp32": {"kernel_ms": round(k32_ms, 5), "achieved": round(achieved32, 1),
-                     "frac": round(achieved32 / HBM_PEAK_GBS, 4)},
+            "frac": round(op["frac"], 4),
+            "traffic": traffic.get("operator_fp64"),
+            "kernel": "operator application on the 64^3 level, float64: vmult_kernel<3,3,double,1,0> "
+                      "(per-cell sum factorization) + gather_kernel<double> (per-DoF sum of the cell "
+                      "contributions), back to back on one stream",
+            "bytes_per_launch": op["bytes"],
+            "ms_per_launch": round(op["ms"], 5),
+            "kernels": {n: entry(n) for n in k},
         },
         "cpu_baseline": cpu,
     }

@@ -204,6 +204,13 @@ class Transfer:
         except Exception:
             pass
 
+    @property
+    def n_points(self) -> int:
+        """Number of fine support points carried by P (the unconstrained fine DoFs)."""
+        n, npj = C.c_int64(), C.c_int64()
+        check(lib().nnmg_transfer_points(self.handle, C.byref(n), None, None, None, C.byref(npj)))
+        return n.value
+
     def points(self) -> dict:
         n, npj = C.c_int64(), C.c_int64()
         check(lib().nnmg_transfer_points(self.handle, C.byref(n), None, None, None, C.byref(npj)))
