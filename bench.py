@@ -71,6 +71,13 @@ def transfer_bytes(coarse, n_points, word, prolong):
     return n_points * per_point + coarse.n_cells * per_cell
 
 
+# level pairs (fine <- coarse) for --roofline-only: workload, cells per direction, degree
+ROOFLINE_WORKLOADS = {
+    "cube_q2_64": (1, [6, 13, 29, 64], 2),      # 64^3 <- 29^3, 2.1M DoFs
+    "ball_q3_96": (2, [5, 9, 19, 43, 96], 3),   # 96^3 <- 43^3, 24.1M DoFs
+    "ball_q4_75": ("2q4", [5, 7, 15, 34, 75], 4),  # 75^3 <- 34^3, 27.3M DoFs
+}
+
 KERNEL_SOURCES = ("paper_2412_10910_amd/csrc/kernels/vmult.hip", "paper_2412_10910_amd/csrc/kernels/gather.hip",
                   "paper_2412_10910_amd/csrc/kernels/transfer.hip", "paper_2412_10910_amd/csrc/internal.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_operator_transfer_cube_q2_64.txt")
@@ -212,6 +219,8 @@ def main():
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the operator/transfer kernel loops of the two finest levels and a copy of "
                          "known size (the run that rocprofv3 traces and counts)")
+    ap.add_argument("--roofline-workload", choices=sorted(ROOFLINE_WORKLOADS), default="cube_q2_64",
+                    help="level pair of --roofline-only")
     ap.add_argument("--geometry", choices=["trilinear", "metric"], default=None,
                     help="operator geometry source (default: the library's choice)")
     args = ap.parse_args()
@@ -235,15 +244,17 @@ def main():
     ctx = nn.Context(0)
 
     log("generating meshes")
-    meshes = config_levels(cfg, cells=cells)
+    meshes = config_levels(cfg, cells=cells) if not args.roofline_only else None
 
     if args.roofline_only:
-        fine = nn.Level.from_mesh(ctx, meshes[-1], degree)
-        coarse = nn.Level.from_mesh(ctx, meshes[-2], degree)
+        rcfg, rcells, rdeg = ROOFLINE_WORKLOADS[args.roofline_workload]
+        rmeshes = config_levels(rcfg, cells=rcells)
+        fine = nn.Level.from_mesh(ctx, rmeshes[-1], rdeg)
+        coarse = nn.Level.from_mesh(ctx, rmeshes[-2], rdeg)
         tr = nn.Transfer(ctx, fine, coarse)
         nbytes = copy_calibration()
         k = kernel_rooflines(fine, coarse, tr, args.roofline_reps)
-        print(json.dumps({"roofline_only": True, "copy_bytes": nbytes, "reps": args.roofline_reps,
+        print(json.dumps({"roofline_only": True, "workload": args.roofline_workload, "copy_bytes": nbytes, "reps": args.roofline_reps,
                           "kernels": {n: {"ms": round(v["ms"], 5), "bytes": v["bytes"], "GB/s": round(v["gbs"], 1),
                                           "frac": round(v["frac"], 4)} for n, v in k.items()}}), flush=True)
         return

@@ -18,6 +18,10 @@
 
 #include "../internal.hpp"
 
+#ifndef NNMG_RESTRICT_PTS_PER_LANE
+#define NNMG_RESTRICT_PTS_PER_LANE 8
+#endif
+
 namespace nnmg {
 
 Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_transfer_opts& o) {
@@ -152,7 +156,7 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
         std::vector<int32_t> off((size_t)(C + 1), 0);
         for (int64_t i = 0; i < np; ++i) off[(size_t)T->h_point_owner[(size_t)i] + 1]++;
         for (int64_t c = 0; c < C; ++c) off[(size_t)(c + 1)] += off[(size_t)c];
-        std::vector<int32_t> fidx((size_t)np);
+        std::vector<int32_t> fidx((size_t)np), sowner((size_t)np);
         std::vector<double> xi64((size_t)(np * dim));
         std::vector<float> xi32((size_t)(np * dim));
         {
@@ -160,6 +164,7 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
             for (int64_t i = 0; i < np; ++i) {
                 const int32_t p = cur[(size_t)T->h_point_owner[(size_t)i]]++;
                 fidx[(size_t)p] = T->h_point_dof[(size_t)i];
+                sowner[(size_t)p] = T->h_point_owner[(size_t)i];
                 for (int a = 0; a < dim; ++a) {
                     const double x = T->h_point_xi[(size_t)(i * dim + a)];
                     xi64[(size_t)(a * np + p)] = x;
@@ -167,14 +172,24 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
                 }
             }
         }
+        // owner cells of the first and last point of every block of kPointBlock points
+        const int64_t nblk = (np + kPointBlock - 1) / kPointBlock;
+        std::vector<int32_t> bc((size_t)(2 * nblk));
+        for (int64_t b = 0; b < nblk; ++b) {
+            bc[(size_t)(2 * b)] = sowner[(size_t)(b * kPointBlock)];
+            bc[(size_t)(2 * b + 1)] = sowner[(size_t)std::min<int64_t>(np, (b + 1) * kPointBlock) - 1];
+        }
+        T->d_blk_cells.upload(ctx, bc);
         T->d_off.upload(ctx, off);
         T->d_fine.upload(ctx, fidx);
         T->d_xi64.upload(ctx, xi64);
         T->d_xi32.upload(ctx, xi32);
-        // lanes per coarse cell: about half the average number of points, 4..64
+        // lane groups per coarse cell of the restriction: about avg / NNMG_RESTRICT_PTS_PER_LANE, 4..64
+        // (the kernel multiplies by the lanes that share a point)
         const double avg = C ? (double)np / (double)C : 0.0;
+        const double per_lane = coarse->n <= 3 ? NNMG_RESTRICT_PTS_PER_LANE : 2 * NNMG_RESTRICT_PTS_PER_LANE;
         int team = 4;
-        while (team < 64 && 2.0 * (2 * team) <= avg) team *= 2;
+        while (team < 64 && per_lane * (2 * team) <= avg) team *= 2;
         T->team = team;
     } catch (...) {
         level_release(T->fine);

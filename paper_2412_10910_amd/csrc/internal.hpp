@@ -164,7 +164,11 @@ struct Transfer {
     DeviceArray<int32_t> d_fine;         // [n_points] fine DoF, grouped by owner
     DeviceArray<double> d_xi64;          // [dim][n_points], grouped by owner
     DeviceArray<float> d_xi32;
+    DeviceArray<int32_t> d_blk_cells;    // [2][n_points / kPointBlock]: owner of the first and last
+                                         // point of each block of the point-parallel kernels
 };
+
+constexpr int kPointBlock = 256;  // points per block of the point-parallel transfer kernels
 
 void transfer_retain(Transfer* t);
 void transfer_release(Transfer* t);

@@ -9,12 +9,20 @@
 //             §3.2 (eqs. local_evaluation, tensor_product_evaluation).
 // restrict:   coarse += P^T fine (paper §2, eq. residual2).
 //
-// The points are stored grouped by owner coarse cell.  A team of `team` lanes
-// (a power of two dividing 64) handles one coarse cell: for prolongation the
-// team loads the cell's coarse values once and evaluates its points, each
-// fine DoF being written by exactly one lane; for restriction every lane
-// accumulates the cell's local vector over its points, the team reduces by
-// cross-lane shuffles and the sums are scatter-added with float atomics.
+// The points are stored grouped by owner coarse cell.
+//
+// Prolongation is point-parallel: one lane per point, blocks of kPointBlock
+// consecutive points.  The few coarse cells a block's points belong to have
+// their q coarse values staged in LDS once, and each lane evaluates its point
+// against its cell's values and adds the result into its fine DoF (each fine
+// DoF is the target of exactly one point, so there are no write conflicts).
+// All point data are read with coalesced loads.
+//
+// Restriction is cell-parallel: a team of `team` lanes (a power of two
+// dividing 64) handles one coarse cell.  Every lane accumulates the cell's
+// local vector over its points, loading the data of several points before
+// using any of them; the team reduces by cross-lane shuffles and the sums are
+// scatter-added with float atomics.
 #include "../internal.hpp"
 #include "common.hpp"
 
@@ -211,62 +219,113 @@ struct Pow {
     static constexpr int value = DIM == 2 ? N * N : N * N * N;
 };
 
-template <int DIM, int N, class T>
-__global__ __launch_bounds__(256) void prolongate_kernel(const int32_t* __restrict__ off,
-                                                         const int32_t* __restrict__ fine,
-                                                         const T* __restrict__ xi, int64_t npts,
-                                                         const int32_t* __restrict__ cdm,
-                                                         const T* __restrict__ uc, T* __restrict__ uf,
-                                                         int ncells, int team_log2, NodeTable<N, T> nt) {
-    constexpr int Q = Pow<DIM, N>::value;
-    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t K = gid >> team_log2;
-    const int team = 1 << team_log2;
-    const int t = (int)(gid & (team - 1));
-    if (K >= ncells) return;
-    const int p0 = off[K], p1 = off[K + 1];
-    if (p0 == p1) return;
-    T u[Q];
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-        const int g = cdm[K * Q + a];
-        u[a] = g >= 0 ? uc[g] : T(0);
-    }
-    for (int p = p0 + t; p < p1; p += team) {
-        T px[N], py[N];
-        lagrange_eval<N, T>(nt, xi[p], px);
-        lagrange_eval<N, T>(nt, xi[npts + p], py);
-        T val = T(0);
-        if constexpr (DIM == 3) {
-            T pz[N];
-            lagrange_eval<N, T>(nt, xi[2 * npts + p], pz);
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                T s1 = T(0);
-#pragma unroll
-                for (int b = 0; b < N; ++b) {
-                    T s0 = T(0);
-#pragma unroll
-                    for (int a = 0; a < N; ++a) s0 += px[a] * u[(c * N + b) * N + a];
-                    s1 += py[b] * s0;
-                }
-                val += pz[c] * s1;
-            }
-        } else {
+// value at reference point x of the Q_k function with nodal values get(a) on
+// one cell: tensor-product evaluation, x direction innermost
+template <int DIM, int N, class T, class Get>
+__device__ __forceinline__ T eval_point(const NodeTable<N, T>& nt, const T* x, Get get) {
+    T px[N], py[N];
+    lagrange_eval<N, T>(nt, x[0], px);
+    lagrange_eval<N, T>(nt, x[1], py);
+    T val = T(0);
+    if constexpr (DIM == 3) {
+        T pz[N];
+        lagrange_eval<N, T>(nt, x[2], pz);
+        // one z-slice of values in flight at a time for the larger cells
+#pragma unroll(N <= 3 ? N : 1)
+        for (int c = 0; c < N; ++c) {
+            T s1 = T(0);
 #pragma unroll
             for (int b = 0; b < N; ++b) {
                 T s0 = T(0);
 #pragma unroll
-                for (int a = 0; a < N; ++a) s0 += px[a] * u[b * N + a];
-                val += py[b] * s0;
+                for (int a = 0; a < N; ++a) s0 += px[a] * get((c * N + b) * N + a);
+                s1 += py[b] * s0;
             }
+            val += pz[c] * s1;
         }
-        const int f = fine[p];
-        uf[f] += val;
+    } else {
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            T s0 = T(0);
+#pragma unroll
+            for (int a = 0; a < N; ++a) s0 += px[a] * get(b * N + a);
+            val += py[b] * s0;
+        }
     }
+    return val;
 }
 
 template <int DIM, int N, class T>
+__global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
+    const int32_t* __restrict__ off, const int32_t* __restrict__ fine, const T* __restrict__ xi, int64_t npts,
+    const int32_t* __restrict__ blk_cells, const int32_t* __restrict__ cdm, const T* __restrict__ uc,
+    T* __restrict__ uf, NodeTable<N, T> nt) {
+    constexpr int Q = Pow<DIM, N>::value;
+    // LDS for the coarse values of up to NCMAX cells (16 KB in float64)
+    constexpr int NCMAX = (2048 / Q) < kPointBlock ? (2048 / Q) : kPointBlock;
+    __shared__ T su[NCMAX * Q];
+    __shared__ int32_t soff[NCMAX + 1];
+    const int64_t b = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t p = b * kPointBlock + tid;
+    const bool valid = p < npts;
+    // the point's own data first, so that these loads overlap the staging
+    int f = 0;
+    T x[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) x[a] = T(0);
+    if (valid) {
+        f = fine[p];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) x[a] = xi[a * npts + p];
+    }
+    const int c0 = blk_cells[2 * b], c1 = blk_cells[2 * b + 1];
+    const int ns = (c1 - c0 + 1) < NCMAX ? (c1 - c0 + 1) : NCMAX;  // cells staged in LDS
+    for (int i = tid; i <= ns; i += kPointBlock) soff[i] = off[c0 + i];
+    for (int i = tid; i < ns * Q; i += kPointBlock) {
+        const int g = cdm[(int64_t)c0 * Q + i];
+        su[i] = g >= 0 ? uc[g] : T(0);
+    }
+    __syncthreads();
+    if (!valid) return;
+    T val;
+    if (p < soff[ns]) {
+        // largest local cell i with soff[i] <= p (empty cells have equal offsets)
+        int lo = 0, hi = ns;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (soff[mid] <= p) lo = mid; else hi = mid;
+        }
+        const T* u = su + lo * Q;
+        val = eval_point<DIM, N, T>(nt, x, [&](int a) { return u[a]; });
+    } else {
+        // more cells in this block than LDS holds: search the offsets and
+        // read the coarse values from global memory
+        int lo = c0 + ns - 1, hi = c1 + 1;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (off[mid] <= p) lo = mid; else hi = mid;
+        }
+        const int32_t* dm = cdm + (int64_t)lo * Q;
+        val = eval_point<DIM, N, T>(nt, x, [&](int a) {
+            const int g = dm[a];
+            return g >= 0 ? uc[g] : T(0);
+        });
+    }
+    uf[f] += val;
+}
+
+#ifndef NNMG_RESTRICT_UNROLL
+#define NNMG_RESTRICT_UNROLL 4
+#endif
+
+// Restriction, one team of `team` = S * G lanes per coarse cell.  The G lane
+// groups split the cell's points; the S lanes of a group read the same points
+// and split the cell's q outputs by the slowest reference index (z in 3D, y in
+// 2D): lane s owns the NS = ceil(N / S) slices starting at s * NS, so that
+// only q / S accumulators live in registers.  The groups are reduced by
+// cross-lane shuffles and the sums are scatter-added with float atomics.
+template <int DIM, int N, class T, int S>
 __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ fine,
                                                        const T* __restrict__ xi, int64_t npts,
@@ -274,55 +333,96 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
                                                        const T* __restrict__ rf, T* __restrict__ rc,
                                                        int ncells, int team_log2, NodeTable<N, T> nt) {
     constexpr int Q = Pow<DIM, N>::value;
+    constexpr int NS = (N + S - 1) / S;      // slowest-index slices per lane
+    constexpr int SLICE = Q / N;             // outputs per slice
+    constexpr int QL = NS * SLICE;           // outputs per lane
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t K = gid >> team_log2;
     const int team = 1 << team_log2;
     const int t = (int)(gid & (team - 1));
+    const int s = t % S, g = t / S, G = team / S;
     // K and the point range are uniform over a team, so whole teams leave together
     if (K >= ncells) return;
     const int p0 = off[K], p1 = off[K + 1];
     if (p0 == p1) return;
-    T R[Q];
+    T R[QL];
 #pragma unroll
-    for (int a = 0; a < Q; ++a) R[a] = T(0);
-    for (int p = p0 + t; p < p1; p += team) {
-        const T r = rf[fine[p]];
-        T px[N], py[N];
-        lagrange_eval<N, T>(nt, xi[p], px);
-        lagrange_eval<N, T>(nt, xi[npts + p], py);
-        if constexpr (DIM == 3) {
-            T pz[N];
-            lagrange_eval<N, T>(nt, xi[2 * npts + p], pz);
+    for (int a = 0; a < QL; ++a) R[a] = T(0);
+    // U points per group and round: all their loads are issued before any use
+    constexpr int U = NNMG_RESTRICT_UNROLL;
+    for (int base = p0 + g; base < p1; base += U * G) {
+        int fi[U];
+        T xs[U][DIM], r[U];
 #pragma unroll
-            for (int c = 0; c < N; ++c) {
-                const T rz = r * pz[c];
+        for (int u = 0; u < U; ++u) {
+            const int p = base + u * G;
+            const bool ok = p < p1;
+            fi[u] = ok ? fine[p] : -1;
 #pragma unroll
-                for (int b = 0; b < N; ++b) {
-                    const T rzy = rz * py[b];
+            for (int a = 0; a < DIM; ++a) xs[u][a] = ok ? xi[a * npts + p] : T(0);
+        }
 #pragma unroll
-                    for (int a = 0; a < N; ++a) R[(c * N + b) * N + a] += rzy * px[a];
+        for (int u = 0; u < U; ++u) r[u] = fi[u] >= 0 ? rf[fi[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            T ps[N];
+            lagrange_eval<N, T>(nt, xs[u][DIM - 1], ps);
+            // r times the lane's slices of the slowest-index basis values
+            T w[NS];
+#pragma unroll
+            for (int c = 0; c < NS; ++c) {
+                T v = T(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m)
+                    if (m == s * NS + c) v = ps[m];
+                w[c] = r[u] * v;
+            }
+            T px[N];
+            lagrange_eval<N, T>(nt, xs[u][0], px);
+            if constexpr (DIM == 3) {
+                T py[N];
+                lagrange_eval<N, T>(nt, xs[u][1], py);
+#pragma unroll
+                for (int c = 0; c < NS; ++c) {
+#pragma unroll
+                    for (int b = 0; b < N; ++b) {
+                        const T wy = w[c] * py[b];
+#pragma unroll
+                        for (int a = 0; a < N; ++a) R[(c * N + b) * N + a] += wy * px[a];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < NS; ++c) {
+#pragma unroll
+                    for (int a = 0; a < N; ++a) R[c * N + a] += w[c] * px[a];
                 }
             }
-        } else {
-#pragma unroll
-            for (int b = 0; b < N; ++b) {
-                const T ry = r * py[b];
-#pragma unroll
-                for (int a = 0; a < N; ++a) R[b * N + a] += ry * px[a];
-            }
         }
     }
-    for (int o = team >> 1; o > 0; o >>= 1) {
+    for (int o = G >> 1; o > 0; o >>= 1) {
 #pragma unroll
-        for (int a = 0; a < Q; ++a) R[a] += __shfl_xor(R[a], o, team);
+        for (int a = 0; a < QL; ++a) R[a] += __shfl_xor(R[a], o * S, team);
     }
+    // output i of lane s is local node s * QL + i; group g writes every G-th
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-        if ((a & (team - 1)) == t) {
-            const int g = cdm[K * Q + a];
-            if (g >= 0) atomic_add(rc + g, R[a]);
+    for (int i = 0; i < QL; ++i) {
+        const int node = s * QL + i;
+        if ((i % G) == g && node < Q) {
+            const int gdof = cdm[K * Q + node];
+            if (gdof >= 0) atomic_add(rc + gdof, R[i]);
         }
     }
+}
+
+// lanes sharing each point in the restriction: keep the per-lane outputs
+// (q / S accumulators) within the register budget of a few waves per SIMD
+template <int N, class T>
+constexpr int restrict_split() {
+    if constexpr (sizeof(T) == 8)
+        return N <= 3 ? 1 : (N == 4 ? 2 : 4);
+    else
+        return N <= 3 ? 1 : 2;
 }
 
 template <int N, class T>
@@ -346,18 +446,22 @@ static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, con
                               hipStream_t s) {
     const Level& C = *tr.coarse;
     if (tr.n_points == 0 || C.n_cells == 0) return;
-    const int threads = 256;
-    const int64_t total = C.n_cells * (int64_t)tr.team;
-    const dim3 grid((unsigned)((total + threads - 1) / threads));
     const NodeTable<N, T> nt = node_table<N, T>(C.basis);
-    if (prolong)
-        hipLaunchKernelGGL((prolongate_kernel<DIM, N, T>), grid, dim3(threads), 0, s, tr.d_off.ptr, tr.d_fine.ptr,
-                           xi, tr.n_points, C.d_dofmap.ptr, (const T*)in, (T*)out, (int)C.n_cells,
-                           log2i(tr.team), nt);
-    else
-        hipLaunchKernelGGL((restrict_kernel<DIM, N, T>), grid, dim3(threads), 0, s, tr.d_off.ptr, tr.d_fine.ptr,
-                           xi, tr.n_points, C.d_dofmap.ptr, (const T*)in, (T*)out, (int)C.n_cells,
-                           log2i(tr.team), nt);
+    if (prolong) {
+        const dim3 grid((unsigned)((tr.n_points + kPointBlock - 1) / kPointBlock));
+        hipLaunchKernelGGL((prolongate_points_kernel<DIM, N, T>), grid, dim3(kPointBlock), 0, s, tr.d_off.ptr,
+                           tr.d_fine.ptr, xi, tr.n_points, tr.d_blk_cells.ptr, C.d_dofmap.ptr, (const T*)in,
+                           (T*)out, nt);
+        NNMG_HIP(hipGetLastError());
+        return;
+    }
+    constexpr int S = DIM == 3 ? restrict_split<N, T>() : 1;
+    const int team = std::max(tr.team, S);
+    const int threads = 256;
+    const int64_t total = C.n_cells * (int64_t)team;
+    const dim3 grid((unsigned)((total + threads - 1) / threads));
+    hipLaunchKernelGGL((restrict_kernel<DIM, N, T, S>), grid, dim3(threads), 0, s, tr.d_off.ptr, tr.d_fine.ptr, xi,
+                       tr.n_points, C.d_dofmap.ptr, (const T*)in, (T*)out, (int)C.n_cells, log2i(team), nt);
     NNMG_HIP(hipGetLastError());
 }
 
