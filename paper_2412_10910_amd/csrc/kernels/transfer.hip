@@ -231,7 +231,8 @@ __device__ __forceinline__ T eval_point(const NodeTable<N, T>& nt, const T* x, G
         T pz[N];
         lagrange_eval<N, T>(nt, x[2], pz);
         // one z-slice of values in flight at a time for the larger cells
-#pragma unroll(N <= 3 ? N : 1)
+        constexpr int ZU = N <= 3 ? N : 1;
+#pragma unroll ZU
         for (int c = 0; c < N; ++c) {
             T s1 = T(0);
 #pragma unroll

@@ -84,6 +84,22 @@ struct OpShape {
     static constexpr int TILE = DIM == 3 ? N * N * N : N * N;
 };
 
+// LDS hand-off between the lanes of a block.  A block of one wavefront needs
+// no hardware barrier: LDS operations of a wavefront complete in issue order,
+// so it is enough to keep the compiler from moving LDS accesses across this
+// point.  Unlike a workgroup barrier this does not wait for outstanding
+// global loads, which stay in flight across the sweeps.
+template <int WG>
+__device__ __forceinline__ void block_sync() {
+    if constexpr (WG == kWave) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 constexpr int kStoredMetric = 0;
 constexpr int kTrilinear = 1;
 constexpr int kSlots = 0;
@@ -126,10 +142,16 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
     }
 
     const int32_t* dm = dmap + b * (N * WG) + lane;
-    int32_t idx[N];
+    int32_t idx[N], slot[N];
     T u[N], v[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) idx[i] = dm[i * WG];
+    if constexpr (SCATTER == kSlots) {
+        // output slots are needed only at the end; load them with the inputs
+        const int32_t* ps = slots + b * (N * WG) + lane;
+#pragma unroll
+        for (int i = 0; i < N; ++i) slot[i] = ps[i * WG];
+    }
 #pragma unroll
     for (int i = 0; i < N; ++i) u[i] = idx[i] >= 0 ? src[idx[i]] : T(0);
 
@@ -146,7 +168,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
 #pragma unroll
             for (int i = 0; i < N; ++i) A[row + i] = v[i];
         }
-        __syncthreads();
+        block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             T s = tb.S[j][0] * A[(t * N + 0) * N + i];
@@ -159,7 +181,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
 #pragma unroll
             for (int i = 0; i < N; ++i) B[row + i] = u[i];
         }
-        __syncthreads();
+        block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const T w0 = B[(0 * N + j) * N + i];
@@ -178,7 +200,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
 #pragma unroll
             for (int i = 0; i < N; ++i) A[row + i] = v[i];
         }
-        __syncthreads();
+        block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const T w0 = A[0 * N + i];
@@ -201,7 +223,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
 #pragma unroll
             for (int i = 0; i < N; ++i) Cc[row + i] = v[i];
         }
-        __syncthreads();
+        block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             T s = tb.D[j][0] * Cc[(t * N + 0) * N + i];
@@ -303,7 +325,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
 #pragma unroll
             for (int i = 0; i < N; ++i) A[row + i] = gy[i];
         }
-        __syncthreads();
+        block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             T s = u[i];
@@ -319,7 +341,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
                 Cc[row + i] = gz[i];
             }
         }
-        __syncthreads();
+        block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             T s = tb.S[0][t] * B[(0 * N + j) * N + i] + tb.DS[0][t] * Cc[(0 * N + j) * N + i];
@@ -333,7 +355,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
 #pragma unroll
             for (int i = 0; i < N; ++i) A[row + i] = v[i];
         }
-        __syncthreads();
+        block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             T s = tb.S[0][j] * A[(t * N + 0) * N + i];
@@ -350,7 +372,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
                 Cc[row + i] = gz[i];
             }
         }
-        __syncthreads();
+        block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             T s = tb.S[0][t] * B[0 * N + i] + tb.DS[0][t] * Cc[0 * N + i];
@@ -361,12 +383,9 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
     }
     line_apply<N, T, true>(tb.S, u, v);  // x: S^T
     if constexpr (SCATTER == kSlots) {
-        const int32_t* ps = slots + b * (N * WG) + lane;
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const int32_t k = ps[i * WG];
-            if (k >= 0) dst[k] = v[i];
-        }
+        for (int i = 0; i < N; ++i)
+            if (slot[i] >= 0) dst[slot[i]] = v[i];
     } else {
 #pragma unroll
         for (int i = 0; i < N; ++i)
