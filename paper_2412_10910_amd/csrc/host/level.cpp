@@ -282,17 +282,36 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
         }
         L->d_dofmap_blk.upload(ctx, blk);
         // contribution slots: the (cell, node) contributions of DoF i occupy
-        // [off[i], off[i+1]) of a DoF-sorted buffer; pos_blk gives each lane's slots
+        // [off[i], off[i+1]) of a DoF-sorted buffer; pos_blk gives each lane's slots.
+        // Where the first node of a lane's x-line is the same DoF as the last
+        // node of the same line of the previous cell in the block (and both
+        // lanes are in one wavefront), the kernel adds the two in registers:
+        // the first node gets no slot and the last node's slot carries
+        // kMergeNext.
         {
+            std::vector<uint8_t> merged(blk.size(), 0), receives(blk.size(), 0);
+            for (int64_t b = 0; b < L->nblocks; ++b)
+                for (int p = 1; p < L->cpb; ++p)
+                    for (int line = 0; line < Lc; ++line) {
+                        const int lane0 = p * Lc + line, laneL = (p - 1) * Lc + line;
+                        if (lane0 / kWaveLanes != laneL / kWaveLanes) continue;
+                        const size_t k0 = (size_t)((b * n + 0) * WG + lane0);
+                        const size_t kL = (size_t)((b * n + (n - 1)) * WG + laneL);
+                        if (blk[k0] >= 0 && blk[k0] == blk[kL]) {
+                            merged[k0] = 1;
+                            receives[kL] = 1;
+                        }
+                    }
             std::vector<int32_t> off((size_t)L->n_dofs + 1, 0);
             for (size_t k = 0; k < blk.size(); ++k)
-                if (blk[k] >= 0) off[(size_t)blk[k] + 1]++;
+                if (blk[k] >= 0 && !merged[k]) off[(size_t)blk[k] + 1]++;
             for (int64_t i = 0; i < L->n_dofs; ++i) off[(size_t)i + 1] += off[(size_t)i];
-            if ((int64_t)off[(size_t)L->n_dofs] > (int64_t)INT32_MAX) fail(NNMG_ERR_UNSUPPORTED, "too many contributions");
+            if ((int64_t)off[(size_t)L->n_dofs] >= (int64_t)kMergeNext)
+                fail(NNMG_ERR_UNSUPPORTED, "too many contributions");
             std::vector<int32_t> cur(off.begin(), off.end() - 1);
             std::vector<int32_t> pos(blk.size(), -1);
             for (size_t k = 0; k < blk.size(); ++k)
-                if (blk[k] >= 0) pos[k] = cur[(size_t)blk[k]]++;
+                if (blk[k] >= 0 && !merged[k]) pos[k] = cur[(size_t)blk[k]]++ | (receives[k] ? kMergeNext : 0);
             L->d_inv_off.upload(ctx, off);
             L->d_pos_blk.upload(ctx, pos);
             L->contrib_len = (size_t)off[(size_t)L->n_dofs];

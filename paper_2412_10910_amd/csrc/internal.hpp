@@ -134,7 +134,8 @@ struct Level {
     std::vector<int32_t> order;         // [nblocks * cpb] cell at each block position, -1 = padding
     DeviceArray<int32_t> d_order;
     DeviceArray<int32_t> d_inv_off;     // [N+1] contributions of DoF i: contrib[off[i] .. off[i+1])
-    DeviceArray<int32_t> d_pos_blk;     // operator layout: contribution slot of each (lane, node), -1 = none
+    DeviceArray<int32_t> d_pos_blk;     // operator layout: contribution slot of each (lane, node), -1 = none,
+                                        // | kMergeNext: add the next cell's first node of the line first
     size_t contrib_len = 0;             // number of contribution slots
     DeviceArray<char> d_contrib;        // contribution buffer of the level's own operator calls
     bool atomic_scatter = false;        // float atomics into the output instead of contribution slots
@@ -168,7 +169,9 @@ struct Transfer {
                                          // point of each block of the point-parallel kernels
 };
 
-constexpr int kPointBlock = 256;  // points per block of the point-parallel transfer kernels
+constexpr int kPointBlock = 256;
+constexpr int32_t kMergeNext = 1 << 30;  // flag in a contribution slot index (see Level::d_pos_blk)
+constexpr int kWaveLanes = 64;           // CDNA wavefront width  // points per block of the point-parallel transfer kernels
 
 void transfer_retain(Transfer* t);
 void transfer_release(Transfer* t);

@@ -383,9 +383,20 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
     }
     line_apply<N, T, true>(tb.S, u, v);  // x: S^T
     if constexpr (SCATTER == kSlots) {
+        // the next cell's first node of this line, added here where setup found
+        // it to be the same DoF as this line's last node (same wavefront)
+        const T nxt = __shfl_down(v[0], L, kWave);
 #pragma unroll
-        for (int i = 0; i < N; ++i)
-            if (slot[i] >= 0) dst[slot[i]] = v[i];
+        for (int i = 0; i < N; ++i) {
+            int32_t k = slot[i];
+            if (k >= 0) {
+                if (i == N - 1 && (k & kMergeNext)) {
+                    v[i] += nxt;
+                    k &= ~kMergeNext;
+                }
+                dst[k] = v[i];
+            }
+        }
     } else {
 #pragma unroll
         for (int i = 0; i < N; ++i)
