@@ -110,6 +110,11 @@ typedef struct {
     int max_it;             /* iteration limit (default 200) */
     nnmg_prec vcycle_prec;  /* precision of the V-cycle preconditioner (default FP32) */
     double* history;        /* host [max_it + 1] or NULL: ||r_k||_2 / ||b||_2, k = 0.. */
+    int use_graph;          /* 1 (default): the preconditioner V-cycle is captured once per
+                               precision as a HIP graph and replayed every iteration (bitwise
+                               the same arithmetic as launching it kernel by kernel, 0);
+                               the graph is rebuilt after nnmg_set_cheb_bounds, and not used
+                               while profiling is on */
 } nnmg_cg_opts;
 
 typedef struct {

@@ -78,6 +78,7 @@ class CgOpts(C.Structure):
         ("max_it", C.c_int),
         ("vcycle_prec", C.c_int),
         ("history", C.POINTER(C.c_double)),
+        ("use_graph", C.c_int),
     ]
 
 

@@ -308,7 +308,8 @@ class Hierarchy:
         return z
 
     def pcg_solve(self, b: torch.Tensor, x: torch.Tensor | None = None, rtol: float = 1e-8, max_it: int = 200,
-                  vcycle_dtype=torch.float32, history: bool = True, raise_on_failure: bool = True):
+                  vcycle_dtype=torch.float32, history: bool = True, raise_on_failure: bool = True,
+                  use_graph: bool = True):
         n = self.fine.n_dofs
         x = torch.empty_like(b) if x is None else x
         o = _lib.CgOpts()
@@ -316,6 +317,7 @@ class Hierarchy:
         o.rtol = float(rtol)
         o.max_it = int(max_it)
         o.vcycle_prec = _DTYPE_PREC[vcycle_dtype]
+        o.use_graph = int(bool(use_graph))
         hist = np.full(max_it + 1, np.nan) if history else None
         o.history = hist.ctypes.data_as(C.POINTER(C.c_double)) if history else None
         res = _lib.CgResult()

@@ -109,6 +109,7 @@ void nnmg_default_cg_opts(nnmg_cg_opts* o) {
     o->max_it = 200;
     o->vcycle_prec = NNMG_FP32;
     o->history = nullptr;
+    o->use_graph = 1;
 }
 
 int nnmg_ctx_create(int device, const nnmg_allocator* allocator, nnmg_ctx** out) {
@@ -273,7 +274,7 @@ int nnmg_restrict(const nnmg_transfer* t, nnmg_prec prec, const void* fine, void
         if (coarse == fine) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
         if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
         NNMG_HIP(hipSetDevice(t->ctx->device));
-        launch_restrict(*t, prec, fine, coarse, as_stream(stream));
+        launch_restrict(*t, prec, fine, coarse, true, as_stream(stream));
         return NNMG_OK;
     });
 }

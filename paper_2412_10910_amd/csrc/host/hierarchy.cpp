@@ -63,7 +63,22 @@ struct Hierarchy {
     std::vector<double> acc;
     hipStream_t last = nullptr;
 
+    // the CG preconditioner (cast, V-cycle, cast back on the fixed CG vectors)
+    // captured as a HIP graph per V-cycle precision
+    hipStream_t capture = nullptr;
+    hipGraphExec_t precond_graph[2] = {nullptr, nullptr};
+
+    void drop_graphs() {
+        for (auto& g : precond_graph)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    }
+
     ~Hierarchy() {
+        drop_graphs();
+        if (capture) (void)hipStreamDestroy(capture);
         for (auto& rec : records) {
             (void)hipEventDestroy(rec.a);
             (void)hipEventDestroy(rec.b);
@@ -259,8 +274,9 @@ static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, 
     }
     {
         Scope sc(H, l, kRestrict, s);
-        launch_fill(wc.f.ptr, (size_t)H.levels[l - 1]->n_dofs, prec, s);
-        launch_restrict(T, prec, w.r.ptr, wc.f.ptr, s);
+        // every unconstrained coarse DoF has restriction slots; the constrained
+        // entries of f_c are never written and stay zero
+        launch_restrict(T, prec, w.r.ptr, wc.f.ptr, false, s);
     }
     vcycle_level(H, l - 1, prec, wc.f.ptr, wc.x.ptr, s);
     {
@@ -433,6 +449,7 @@ void set_bounds(Hierarchy& H, int l, double lo, double hi) {
     if (!(lo > 0.0) || !(hi > lo)) fail(NNMG_ERR_INVALID_ARG, "bounds must satisfy 0 < lo < hi");
     H.lo[(size_t)l] = lo;
     H.hi[(size_t)l] = hi;
+    H.drop_graphs();  // the captured V-cycles hold the previous coefficients
 }
 
 void vcycle(Hierarchy& H, int prec, const void* r, void* z, hipStream_t s) {
@@ -452,14 +469,41 @@ int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg
     const size_t n = (size_t)L.n_dofs;
     const int prec = o.vcycle_prec;
     WorkVectors& w32 = H.work[NNMG_FP32][top];
-    auto precondition = [&]() {
+    // z = V(r) on the hierarchy's own vectors, so the launches can be captured once
+    auto launches = [&](hipStream_t st) {
         if (prec == NNMG_FP64) {
-            vcycle_level(H, top, NNMG_FP64, H.r.ptr, H.z.ptr, s);
+            vcycle_level(H, top, NNMG_FP64, H.r.ptr, H.z.ptr, st);
         } else {
-            launch_cast_64_to_32(H.r.ptr, (float*)w32.f.ptr, n, s);
-            vcycle_level(H, top, NNMG_FP32, w32.f.ptr, w32.x.ptr, s);
-            launch_cast_32_to_64((const float*)w32.x.ptr, H.z.ptr, n, s);
+            launch_cast_64_to_32(H.r.ptr, (float*)w32.f.ptr, n, st);
+            vcycle_level(H, top, NNMG_FP32, w32.f.ptr, w32.x.ptr, st);
+            launch_cast_32_to_64((const float*)w32.x.ptr, H.z.ptr, n, st);
         }
+    };
+    const bool graph = o.use_graph && !H.profiling;
+    if (graph && !H.precond_graph[prec]) {
+        if (!H.capture) NNMG_HIP(hipStreamCreateWithFlags(&H.capture, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        NNMG_HIP(hipStreamBeginCapture(H.capture, hipStreamCaptureModeThreadLocal));
+        try {
+            launches(H.capture);
+        } catch (...) {
+            (void)hipStreamEndCapture(H.capture, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        NNMG_HIP(hipStreamEndCapture(H.capture, &g));
+        const hipError_t e = hipGraphInstantiate(&H.precond_graph[prec], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            H.precond_graph[prec] = nullptr;
+            fail(NNMG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+    }
+    auto precondition = [&]() {
+        if (graph)
+            NNMG_HIP(hipGraphLaunch(H.precond_graph[prec], s));
+        else
+            launches(s);
     };
     double* sc = H.scal.ptr;
     NNMG_HIP(hipMemcpyAsync(H.r.ptr, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));

@@ -180,6 +180,22 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
             bc[(size_t)(2 * b + 1)] = sowner[(size_t)std::min<int64_t>(np, (b + 1) * kPointBlock) - 1];
         }
         T->d_blk_cells.upload(ctx, bc);
+        // restriction slots: the sum of coarse cell K for node a goes to
+        // rslot[K q + a], the slots of coarse DoF j being [roff[j], roff[j+1])
+        {
+            const std::vector<int32_t>& cdm = coarse->dofmap;
+            std::vector<int32_t> roff((size_t)coarse->n_dofs + 1, 0);
+            for (size_t k = 0; k < cdm.size(); ++k)
+                if (!coarse->constrained[(size_t)cdm[k]]) roff[(size_t)cdm[k] + 1]++;
+            for (int64_t j = 0; j < coarse->n_dofs; ++j) roff[(size_t)j + 1] += roff[(size_t)j];
+            std::vector<int32_t> cur(roff.begin(), roff.end() - 1);
+            std::vector<int32_t> rslot(cdm.size(), -1);
+            for (size_t k = 0; k < cdm.size(); ++k)
+                if (!coarse->constrained[(size_t)cdm[k]]) rslot[k] = cur[(size_t)cdm[k]]++;
+            T->d_rslot.upload(ctx, rslot);
+            T->d_roff.upload(ctx, roff);
+            T->d_rbuf.alloc(ctx, std::max<size_t>((size_t)roff.back(), 1));
+        }
         T->d_off.upload(ctx, off);
         T->d_fine.upload(ctx, fidx);
         T->d_xi64.upload(ctx, xi64);

@@ -167,6 +167,10 @@ struct Transfer {
     DeviceArray<float> d_xi32;
     DeviceArray<int32_t> d_blk_cells;    // [2][n_points / kPointBlock]: owner of the first and last
                                          // point of each block of the point-parallel kernels
+    // restriction sums per (coarse cell, node), in slots sorted by coarse DoF
+    DeviceArray<int32_t> d_rslot;        // [C_coarse][q] slot of each sum, -1 for constrained DoFs
+    DeviceArray<int32_t> d_roff;         // [N_coarse + 1] DoF j sums rbuf[roff[j] .. roff[j+1])
+    DeviceArray<double> d_rbuf;          // slot values (float64 or float32)
 };
 
 constexpr int kPointBlock = 256;
@@ -214,7 +218,11 @@ void launch_locate(int dim, const double* pts, int np, const double* cverts, con
                    const int* gnb, double inside_tol, double newton_tol, int newton_max_it,
                    int32_t* owner, double* xi, int32_t* flags, hipStream_t s);
 void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fine, hipStream_t s);
-void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, hipStream_t s);
+// coarse = P^T fine (accumulate = false) or coarse += P^T fine; constrained coarse entries untouched
+void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s);
+// dst[i] (+)= sum of elem[off[i] .. off[i+1]) for every i with a non-empty run
+void launch_gather_runs(size_t n, const int32_t* off, int prec, const void* elem, void* dst, bool accumulate,
+                        hipStream_t s);
 
 // vector kernels for the smoother and CG
 // x = d = dinv * f * c0   (first step from a zero guess)

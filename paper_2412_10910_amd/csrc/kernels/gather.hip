@@ -34,16 +34,20 @@ __global__ void gather_kernel(size_t n, const int32_t* __restrict__ off,
     }
 }
 
-void launch_gather(const Level& L, int prec, const void* elem, void* dst, bool accumulate, hipStream_t s) {
-    const size_t n = (size_t)L.n_dofs;
+void launch_gather_runs(size_t n, const int32_t* off, int prec, const void* elem, void* dst, bool accumulate,
+                        hipStream_t s) {
     if (n == 0) return;
     if (prec == NNMG_FP64)
-        hipLaunchKernelGGL(gather_kernel<double>, grid_n(n), dim3(256), 0, s, n, L.d_inv_off.ptr,
-                           (const double*)elem, (double*)dst, (int)accumulate);
+        hipLaunchKernelGGL(gather_kernel<double>, grid_n(n), dim3(256), 0, s, n, off, (const double*)elem,
+                           (double*)dst, (int)accumulate);
     else
-        hipLaunchKernelGGL(gather_kernel<float>, grid_n(n), dim3(256), 0, s, n, L.d_inv_off.ptr,
-                           (const float*)elem, (float*)dst, (int)accumulate);
+        hipLaunchKernelGGL(gather_kernel<float>, grid_n(n), dim3(256), 0, s, n, off, (const float*)elem,
+                           (float*)dst, (int)accumulate);
     NNMG_HIP(hipGetLastError());
+}
+
+void launch_gather(const Level& L, int prec, const void* elem, void* dst, bool accumulate, hipStream_t s) {
+    launch_gather_runs((size_t)L.n_dofs, L.d_inv_off.ptr, prec, elem, dst, accumulate, s);
 }
 
 // r = f - A x;  d = c1 d + c2 dinv r;  x += d      (Chebyshev step, Saad Alg. 12.1)

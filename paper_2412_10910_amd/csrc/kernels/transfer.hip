@@ -21,8 +21,10 @@
 // Restriction is cell-parallel: a team of `team` lanes (a power of two
 // dividing 64) handles one coarse cell.  Every lane accumulates the cell's
 // local vector over its points, loading the data of several points before
-// using any of them; the team reduces by cross-lane shuffles and the sums are
-// scatter-added with float atomics.
+// using any of them; the team reduces by cross-lane shuffles and writes the
+// cell's q sums to their slots, which are sorted by coarse DoF; a gather then
+// adds every coarse DoF's slots in a fixed order.  No float atomics, so the
+// restriction (and the V-cycle) is deterministic.
 #include "../internal.hpp"
 #include "common.hpp"
 
@@ -325,13 +327,13 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
 // and split the cell's q outputs by the slowest reference index (z in 3D, y in
 // 2D): lane s owns the NS = ceil(N / S) slices starting at s * NS, so that
 // only q / S accumulators live in registers.  The groups are reduced by
-// cross-lane shuffles and the sums are scatter-added with float atomics.
+// cross-lane shuffles and the sums are stored to their slots.
 template <int DIM, int N, class T, int S>
 __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ fine,
                                                        const T* __restrict__ xi, int64_t npts,
-                                                       const int32_t* __restrict__ cdm,
-                                                       const T* __restrict__ rf, T* __restrict__ rc,
+                                                       const int32_t* __restrict__ rslot,
+                                                       const T* __restrict__ rf, T* __restrict__ rbuf,
                                                        int ncells, int team_log2, NodeTable<N, T> nt) {
     constexpr int Q = Pow<DIM, N>::value;
     constexpr int NS = (N + S - 1) / S;      // slowest-index slices per lane
@@ -345,7 +347,14 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
     // K and the point range are uniform over a team, so whole teams leave together
     if (K >= ncells) return;
     const int p0 = off[K], p1 = off[K + 1];
-    if (p0 == p1) return;
+    if (p0 == p1) {
+        // a cell without points contributes zeros
+        for (int a = t; a < Q; a += team) {
+            const int k = rslot[K * Q + a];
+            if (k >= 0) rbuf[k] = T(0);
+        }
+        return;
+    }
     T R[QL];
 #pragma unroll
     for (int a = 0; a < QL; ++a) R[a] = T(0);
@@ -410,8 +419,8 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
     for (int i = 0; i < QL; ++i) {
         const int node = s * QL + i;
         if ((i % G) == g && node < Q) {
-            const int gdof = cdm[K * Q + node];
-            if (gdof >= 0) atomic_add(rc + gdof, R[i]);
+            const int k = rslot[K * Q + node];
+            if (k >= 0) rbuf[k] = R[i];
         }
     }
 }
@@ -462,7 +471,8 @@ static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, con
     const int64_t total = C.n_cells * (int64_t)team;
     const dim3 grid((unsigned)((total + threads - 1) / threads));
     hipLaunchKernelGGL((restrict_kernel<DIM, N, T, S>), grid, dim3(threads), 0, s, tr.d_off.ptr, tr.d_fine.ptr, xi,
-                       tr.n_points, C.d_dofmap.ptr, (const T*)in, (T*)out, (int)C.n_cells, log2i(team), nt);
+                       tr.n_points, tr.d_rslot.ptr, (const T*)in, (T*)tr.d_rbuf.ptr, (int)C.n_cells,
+                       log2i(team), nt);
     NNMG_HIP(hipGetLastError());
 }
 
@@ -485,11 +495,12 @@ void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fi
         transfer_prec<float>(t, true, t.d_xi32.ptr, coarse, fine, s);
 }
 
-void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, hipStream_t s) {
+void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s) {
     if (prec == NNMG_FP64)
         transfer_prec<double>(t, false, t.d_xi64.ptr, fine, coarse, s);
     else
         transfer_prec<float>(t, false, t.d_xi32.ptr, fine, coarse, s);
+    launch_gather_runs((size_t)t.coarse->n_dofs, t.d_roff.ptr, prec, t.d_rbuf.ptr, coarse, accumulate, s);
 }
 
 }  // namespace nnmg

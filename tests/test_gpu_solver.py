@@ -108,3 +108,33 @@ def test_profile_components(ctx):
     assert ms.shape == (3, 6)
     assert ms[0, 3] > 0 and np.all(ms[1:, [0, 1, 2, 4, 5]] > 0)
     assert np.all(ms[0, [0, 1, 2, 4, 5]] == 0)
+
+
+def test_graph_replays_match_eager_launches(ctx):
+    """The captured preconditioner graph, replayed over several solves with
+    eager work and synchronisations in between, gives bitwise the results of
+    launching the V-cycle kernel by kernel (both precisions), also after the
+    smoother bounds change (which rebuilds the graph)."""
+    import paper_2412_10910_amd as nn
+    meshes = config_levels(1, cells=[3, 6, 13])
+    levels = [nn.Level.from_mesh(ctx, m, 2) for m in meshes]
+    transfers = [nn.Transfer(ctx, levels[i + 1], levels[i]) for i in range(len(levels) - 1)]
+    H = nn.Hierarchy(ctx, levels, transfers)
+    fine = levels[-1]
+    con = torch.tensor(fine.constrained(), device=DEV)
+    for rep in range(4):
+        if rep == 2:
+            lo, hi = H.cheb_bounds(2)
+            H.set_cheb_bounds(2, lo * 1.1, hi * 1.05)
+        b = torch.tensor(random_vector(fine.n_dofs, 200 + rep), device=DEV)
+        b[con] = 0
+        for dt in (torch.float64, torch.float32):
+            xg, ig = H.pcg_solve(b, rtol=1e-10, vcycle_dtype=dt, use_graph=True)
+            y = fine.vmult(b)  # eager work between replays
+            torch.cuda.synchronize()
+            xe, ie = H.pcg_solve(b, rtol=1e-10, vcycle_dtype=dt, use_graph=False)
+            torch.cuda.synchronize()
+            assert ig["iterations"] == ie["iterations"]
+            assert np.array_equal(ig["history"], ie["history"])
+            assert torch.equal(xg, xe)
+            assert torch.isfinite(y).all()
