@@ -130,30 +130,62 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
     const int t = DIM == 3 ? line / N : line;
     const int row = line * N;  // offset of this lane's x-line in a cell tile
 
-    // the cell's map coefficients go to LDS at once (independent of everything
-    // else); each lane turns them into the constants of its line just before
-    // the geometry step, so they hold no registers during the sweeps
-    __shared__ T lcf[CPB][GEO == kTrilinear ? NC : 1];
-    if constexpr (GEO == kTrilinear) {
-        if (act) {
-            const T* gc = geo + b * (NC * CPB) + cb;
-            for (int m = line; m < NC; m += L) lcf[cb][m] = gc[m * CPB];
-        }
-    }
-
+    // Prologue, in issue order: the DoF indices and output slots of the
+    // lane's line, the cell's map coefficients and the 1D tables (both bound
+    // for LDS), then the source gathers, which wait only for the indices; the
+    // LDS stores come last so that no load waits behind them.
     const int32_t* dm = dmap + b * (N * WG) + lane;
     int32_t idx[N], slot[N];
     T u[N], v[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) idx[i] = dm[i * WG];
     if constexpr (SCATTER == kSlots) {
-        // output slots are needed only at the end; load them with the inputs
         const int32_t* ps = slots + b * (N * WG) + lane;
 #pragma unroll
         for (int i = 0; i < N; ++i) slot[i] = ps[i * WG];
     }
+    // the cell's map coefficients: each lane turns them into the constants of
+    // its line just before the geometry step, so they hold no registers
+    // during the sweeps
+    __shared__ T lcf[CPB][GEO == kTrilinear ? NC : 1];
+    constexpr int R = GEO == kTrilinear ? (NC + L - 1) / L : 1;
+    T cv[R];
+    if constexpr (GEO == kTrilinear) {
+        const T* gc = geo + b * (NC * CPB) + cb;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int m = line + r * L;
+            cv[r] = (act && m < NC) ? gc[m * CPB] : T(0);
+        }
+    }
+    // the 1D tables: rows selected by the lane's y/z index are read from LDS
+    // (indexing the by-value argument with a lane-dependent index would be a
+    // global load on the critical path of every sweep)
+    constexpr int NT = 3 * N * N + 2 * N;
+    static_assert(sizeof(OpTables<N, T>) == NT * sizeof(T), "OpTables must be a flat array of T");
+    constexpr int TE = (NT + WG - 1) / WG;  // table entries per lane
+    __shared__ T ltab[NT];
+    T tv[TE];
+#pragma unroll
+    for (int e = 0; e < TE; ++e)
+        tv[e] = lane + e * WG < NT ? reinterpret_cast<const T*>(&tb)[lane + e * WG] : T(0);
 #pragma unroll
     for (int i = 0; i < N; ++i) u[i] = idx[i] >= 0 ? src[idx[i]] : T(0);
+    if constexpr (GEO == kTrilinear) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int m = line + r * L;
+            if (act && m < NC) lcf[cb][m] = cv[r];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < TE; ++e)
+        if (lane + e * WG < NT) ltab[lane + e * WG] = tv[e];
+    const T* lS = ltab;
+    const T* lDS = ltab + N * N;
+    const T* lD = ltab + 2 * N * N;
+    const T* lg = ltab + 3 * N * N;
+    const T* lw = lg + N;
 
     T* A = lds[0][cb];
     T* B = lds[1][cb];
@@ -171,9 +203,9 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
         block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            T s = tb.S[j][0] * A[(t * N + 0) * N + i];
+            T s = lS[j * N + 0] * A[(t * N + 0) * N + i];
 #pragma unroll
-            for (int c = 1; c < N; ++c) s += tb.S[j][c] * A[(t * N + c) * N + i];
+            for (int c = 1; c < N; ++c) s += lS[j * N + c] * A[(t * N + c) * N + i];
             u[i] = s;
         }
         // z: interpolate and differentiate
@@ -185,12 +217,12 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const T w0 = B[(0 * N + j) * N + i];
-            T s0 = tb.S[t][0] * w0, s1 = tb.DS[t][0] * w0;
+            T s0 = lS[t * N + 0] * w0, s1 = lDS[t * N + 0] * w0;
 #pragma unroll
             for (int c = 1; c < N; ++c) {
                 const T w = B[(c * N + j) * N + i];
-                s0 += tb.S[t][c] * w;
-                s1 += tb.DS[t][c] * w;
+                s0 += lS[t * N + c] * w;
+                s1 += lDS[t * N + c] * w;
             }
             v[i] = s0;
             gz[i] = s1;
@@ -204,12 +236,12 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const T w0 = A[0 * N + i];
-            T s0 = tb.S[t][0] * w0, s1 = tb.DS[t][0] * w0;
+            T s0 = lS[t * N + 0] * w0, s1 = lDS[t * N + 0] * w0;
 #pragma unroll
             for (int c = 1; c < N; ++c) {
                 const T w = A[c * N + i];
-                s0 += tb.S[t][c] * w;
-                s1 += tb.DS[t][c] * w;
+                s0 += lS[t * N + c] * w;
+                s1 += lDS[t * N + c] * w;
             }
             v[i] = s0;
             gz[i] = s1;
@@ -226,9 +258,9 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
         block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            T s = tb.D[j][0] * Cc[(t * N + 0) * N + i];
+            T s = lD[j * N + 0] * Cc[(t * N + 0) * N + i];
 #pragma unroll
-            for (int c = 1; c < N; ++c) s += tb.D[j][c] * Cc[(t * N + c) * N + i];
+            for (int c = 1; c < N; ++c) s += lD[j * N + c] * Cc[(t * N + c) * N + i];
             gy[i] = s;
         }
     }
@@ -256,7 +288,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
         T c0[DIM], C1[DIM], E1[DIM], D2[DIM], F2[DIM];
         const T* cf = lcf[cb];
         if constexpr (DIM == 3) {
-            const T eta = tb.g[j], zeta = tb.g[t];
+            const T eta = lg[j], zeta = lg[t];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 // d/dxi = b + e eta + f zeta + h eta zeta          (constant on the line)
@@ -269,7 +301,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
                 F2[k] = cf[12 + k] + cf[18 + k] * eta;
             }
         } else {
-            const T eta = tb.g[t];
+            const T eta = lg[t];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 c0[k] = cf[0 + k] + cf[4 + k] * eta;  // d/dxi = b + d eta
@@ -277,7 +309,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
                 E1[k] = cf[4 + k];
             }
         }
-        const T wl = DIM == 3 ? tb.w[j] * tb.w[t] : tb.w[t];
+        const T wl = DIM == 3 ? lw[j] * lw[t] : lw[t];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const T xi = tb.g[i];
@@ -330,7 +362,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
         for (int i = 0; i < N; ++i) {
             T s = u[i];
 #pragma unroll
-            for (int c = 0; c < N; ++c) s += tb.D[c][j] * A[(t * N + c) * N + i];
+            for (int c = 0; c < N; ++c) s += lD[c * N + j] * A[(t * N + c) * N + i];
             u[i] = s;
         }
         // z: S^T (sum) + DS^T fz
@@ -344,10 +376,10 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
         block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            T s = tb.S[0][t] * B[(0 * N + j) * N + i] + tb.DS[0][t] * Cc[(0 * N + j) * N + i];
+            T s = lS[0 * N + t] * B[(0 * N + j) * N + i] + lDS[0 * N + t] * Cc[(0 * N + j) * N + i];
 #pragma unroll
             for (int q = 1; q < N; ++q)
-                s += tb.S[q][t] * B[(q * N + j) * N + i] + tb.DS[q][t] * Cc[(q * N + j) * N + i];
+                s += lS[q * N + t] * B[(q * N + j) * N + i] + lDS[q * N + t] * Cc[(q * N + j) * N + i];
             v[i] = s;
         }
         // y: S^T
@@ -358,9 +390,9 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
         block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            T s = tb.S[0][j] * A[(t * N + 0) * N + i];
+            T s = lS[0 * N + j] * A[(t * N + 0) * N + i];
 #pragma unroll
-            for (int q = 1; q < N; ++q) s += tb.S[q][j] * A[(t * N + q) * N + i];
+            for (int q = 1; q < N; ++q) s += lS[q * N + j] * A[(t * N + q) * N + i];
             u[i] = s;
         }
     } else {
@@ -375,9 +407,9 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
         block_sync<WG>();
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            T s = tb.S[0][t] * B[0 * N + i] + tb.DS[0][t] * Cc[0 * N + i];
+            T s = lS[0 * N + t] * B[0 * N + i] + lDS[0 * N + t] * Cc[0 * N + i];
 #pragma unroll
-            for (int q = 1; q < N; ++q) s += tb.S[q][t] * B[q * N + i] + tb.DS[q][t] * Cc[q * N + i];
+            for (int q = 1; q < N; ++q) s += lS[q * N + t] * B[q * N + i] + lDS[q * N + t] * Cc[q * N + i];
             u[i] = s;
         }
     }
