@@ -49,7 +49,9 @@ struct Hierarchy {
     // coarse solve
     int64_t m = 0;
     DeviceArray<int32_t> free_idx;
-    DeviceArray<double> inv, bf, xf, yf, cx, cax, cr, cf;
+    DeviceArray<double> inv, amat;  // m x m: A^{-1} and A on the unconstrained block
+    DeviceArray<double> bf, xf;     // [m] work vectors of the solve
+    DeviceArray<double> cx, cax;    // [N] unit vectors and operator columns at setup
 
     WorkVectors work[2][16];  // [prec][level]
 
@@ -157,14 +159,11 @@ static void setup_coarse(Hierarchy& H) {
     const size_t N = (size_t)C.n_dofs, m = (size_t)H.m;
     H.cx.alloc(ctx, N);
     H.cax.alloc(ctx, N);
-    H.cr.alloc(ctx, N);
-    H.cf.alloc(ctx, N);
-    for (auto* a : {&H.cx, &H.cax, &H.cr, &H.cf}) NNMG_HIP(hipMemset(a->ptr, 0, a->bytes()));
+    for (auto* a : {&H.cx, &H.cax}) NNMG_HIP(hipMemset(a->ptr, 0, a->bytes()));
     if (m == 0) return;
     H.free_idx.upload(ctx, idx);
     H.bf.alloc(ctx, m);
     H.xf.alloc(ctx, m);
-    H.yf.alloc(ctx, m);
     H.inv.alloc(ctx, m * m);
     // columns of A on the unconstrained block: A e_j by the operator kernel
     for (size_t j = 0; j < m; ++j) {
@@ -174,6 +173,9 @@ static void setup_coarse(Hierarchy& H) {
         launch_fill(H.cax.ptr, N, NNMG_FP64, nullptr);
         launch_set_unit(H.cx.ptr, N, idx[j], 0.0, nullptr);
     }
+    // keep A (for the refinement step) before inverting in place
+    H.amat.alloc(ctx, m * m);
+    NNMG_HIP(hipMemcpy(H.amat.ptr, H.inv.ptr, m * m * sizeof(double), hipMemcpyDeviceToDevice));
     DeviceArray<double> rowbuf, colbuf;
     rowbuf.alloc(ctx, m);
     colbuf.alloc(ctx, m);
@@ -181,30 +183,21 @@ static void setup_coarse(Hierarchy& H) {
     NNMG_HIP(hipDeviceSynchronize());
 }
 
-// x = A_0^{-1} f (one refinement step), f and x in `prec`
+// x = A_0^{-1} f (one refinement step), f and x in `prec`, the arithmetic in
+// float64 on the unconstrained block:
+//   y = A^{-1} f,  r = f - A y,  x = y + A^{-1} r
+// with the dense A and A^{-1} of the unconstrained block (three row-parallel
+// kernels that gather f and scatter x through the free-DoF list themselves)
 static void coarse_solve(Hierarchy& H, int prec, const void* f, void* x, hipStream_t s) {
     Level& C = *H.levels[0];
     const size_t N = (size_t)C.n_dofs, m = (size_t)H.m;
-    const double* src = (const double*)f;
-    if (prec == NNMG_FP32) {
-        launch_cast_32_to_64((const float*)f, H.cf.ptr, N, s);
-        src = H.cf.ptr;
-    }
-    double* out = prec == NNMG_FP64 ? (double*)x : H.cx.ptr;
-    launch_fill(out, N, NNMG_FP64, s);
-    if (m > 0) {
-        launch_gather_free(H.free_idx.ptr, m, src, H.bf.ptr, s);
-        launch_gemv(H.inv.ptr, m, H.bf.ptr, H.xf.ptr, s);
-        launch_scatter_free(H.free_idx.ptr, m, H.xf.ptr, out, s);
-        // refinement: x += A^{-1} (f - A x)
-        launch_vmult_cells(C, NNMG_FP64, out, H.cax.ptr, s);
-        launch_residual(NNMG_FP64, N, src, H.cax.ptr, H.cr.ptr, s);
-        launch_gather_free(H.free_idx.ptr, m, H.cr.ptr, H.bf.ptr, s);
-        launch_gemv(H.inv.ptr, m, H.bf.ptr, H.yf.ptr, s);
-        launch_add(NNMG_FP64, m, H.yf.ptr, H.xf.ptr, s);
-        launch_scatter_free(H.free_idx.ptr, m, H.xf.ptr, out, s);
-    }
-    if (prec == NNMG_FP32) launch_cast_64_to_32(H.cx.ptr, (float*)x, N, s);
+    launch_fill(x, N, prec, s);  // constrained entries
+    if (m == 0) return;
+    const int32_t* fi = H.free_idx.ptr;
+    launch_coarse_gemv(H.inv.ptr, m, f, prec, fi, nullptr, NNMG_FP64, nullptr, 1.0, H.xf.ptr, NNMG_FP64, nullptr, s);
+    launch_coarse_gemv(H.amat.ptr, m, H.xf.ptr, NNMG_FP64, nullptr, f, prec, fi, -1.0, H.bf.ptr, NNMG_FP64, nullptr,
+                       s);
+    launch_coarse_gemv(H.inv.ptr, m, H.bf.ptr, NNMG_FP64, nullptr, H.xf.ptr, NNMG_FP64, nullptr, 1.0, x, prec, fi, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -206,6 +206,9 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
         const double per_lane = coarse->n <= 3 ? NNMG_RESTRICT_PTS_PER_LANE : 2 * NNMG_RESTRICT_PTS_PER_LANE;
         int team = 4;
         while (team < 64 && per_lane * (2 * team) <= avg) team *= 2;
+        // small coarse levels: more lanes per cell, so that the launch still
+        // has enough wavefronts in flight to hide the memory latency
+        while (team < 64 && (double)C * team < 131072.0 && 2 * team <= avg) team *= 2;
         T->team = team;
     } catch (...) {
         level_release(T->fine);

@@ -234,7 +234,6 @@ void launch_cheb_step(int prec, size_t n, const void* f, void* ax, const void* d
 // r = f - ax; ax = 0
 void launch_residual(int prec, size_t n, const void* f, void* ax, void* r, hipStream_t s);
 // y += x
-void launch_add(int prec, size_t n, const void* x, void* y, hipStream_t s);
 void launch_splitmix_vector(double* v, const uint8_t* mask_free, size_t n, uint64_t seed, hipStream_t s);
 
 // float64 reductions: out = sum_i a_i b_i (two-stage, deterministic)
@@ -250,9 +249,10 @@ void launch_axpy(size_t n, double a_sign, const double* scal_a, int idx, const d
                  hipStream_t s);
 
 // dense coarse solve
-void launch_gather_free(const int32_t* free_idx, size_t m, const double* x, double* xf, hipStream_t s);
-void launch_scatter_free(const int32_t* free_idx, size_t m, const double* xf, double* x, hipStream_t s);
-void launch_gemv(const double* M, size_t m, const double* x, double* y, hipStream_t s);
+// O[oidx ? oidx[i] : i] = base_i + sign * sum_j M_ij V[vidx ? vidx[j] : j], base_i = B[bidx ? bidx[i] : i] or 0
+void launch_coarse_gemv(const double* M, size_t m, const void* V, int vprec, const int32_t* vidx, const void* B,
+                        int bprec, const int32_t* bidx, double sign, void* O, int oprec, const int32_t* oidx,
+                        hipStream_t s);
 void launch_gauss_jordan(double* M, size_t m, double* rowbuf, double* colbuf, hipStream_t s);
 void launch_column_from_unit(const int32_t* free_idx, size_t m, const double* ax, double* M, size_t col,
                              hipStream_t s);

@@ -153,20 +153,6 @@ void launch_residual(int prec, size_t n, const void* f, void* ax, void* r, hipSt
     NNMG_HIP(hipGetLastError());
 }
 
-template <class T>
-__global__ void add_kernel(size_t n, const T* __restrict__ x, T* __restrict__ y) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        y[i] += x[i];
-}
-
-void launch_add(int prec, size_t n, const void* x, void* y, hipStream_t s) {
-    if (n == 0) return;
-    if (prec == NNMG_FP64)
-        hipLaunchKernelGGL(add_kernel<double>, grid_for(n), dim3(256), 0, s, n, (const double*)x, (double*)y);
-    else
-        hipLaunchKernelGGL(add_kernel<float>, grid_for(n), dim3(256), 0, s, n, (const float*)x, (float*)y);
-    NNMG_HIP(hipGetLastError());
-}
 
 __global__ void lincomb_kernel(size_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -339,48 +325,50 @@ void launch_axpy(size_t n, double a_sign, const double* scal_a, int idx, const d
 // ---------------------------------------------------------------------------
 // dense coarse solve: explicit inverse of the unconstrained block
 // ---------------------------------------------------------------------------
-__global__ void gather_free_kernel(const int32_t* __restrict__ idx, size_t m, const double* __restrict__ x,
-                                   double* __restrict__ xf) {
-    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (i < m) xf[i] = x[idx[i]];
-}
-
-void launch_gather_free(const int32_t* free_idx, size_t m, const double* x, double* xf, hipStream_t s) {
-    if (m == 0) return;
-    hipLaunchKernelGGL(gather_free_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, free_idx, m, x, xf);
-    NNMG_HIP(hipGetLastError());
-}
-
-__global__ void scatter_free_kernel(const int32_t* __restrict__ idx, size_t m, const double* __restrict__ xf,
-                                    double* __restrict__ x) {
-    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (i < m) x[idx[i]] = xf[i];
-}
-
-void launch_scatter_free(const int32_t* free_idx, size_t m, const double* xf, double* x, hipStream_t s) {
-    if (m == 0) return;
-    hipLaunchKernelGGL(scatter_free_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, free_idx, m, xf, x);
-    NNMG_HIP(hipGetLastError());
-}
-
-// y = M x, M row-major m x m; one wavefront per row, coalesced row reads
-__global__ __launch_bounds__(256) void gemv_kernel(const double* __restrict__ M, size_t m,
-                                                   const double* __restrict__ x, double* __restrict__ y) {
-    const size_t row = blockIdx.x * (size_t)(blockDim.x / kWave) + threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    if (row >= m) return;
+// Coarse solve step on the unconstrained block, one 256-lane block per row:
+//   y_i = base_i + sign * sum_j M_ij v_j,
+// with v_j = V[vidx[j]] (or V[j]) and base_i = B[bidx[i]] (or B[i], or 0),
+// stored to O[oidx[i]] (or O[i]) in O's precision.  Rows are read coalesced;
+// the row sum is reduced in a fixed order.
+template <class TV, class TB, class TO>
+__global__ __launch_bounds__(256) void coarse_gemv_kernel(const double* __restrict__ M, size_t m,
+                                                          const TV* __restrict__ V, const int32_t* __restrict__ vidx,
+                                                          const TB* __restrict__ B, const int32_t* __restrict__ bidx,
+                                                          double sign, TO* __restrict__ O,
+                                                          const int32_t* __restrict__ oidx) {
+    __shared__ double part[256 / kWave];
+    const size_t row = blockIdx.x;
     const double* a = M + row * m;
     double s = 0.0;
-    for (size_t j = lane; j < m; j += kWave) s += a[j] * x[j];
+    for (size_t j = threadIdx.x; j < m; j += 256) s += a[j] * (double)V[vidx ? vidx[j] : j];
     for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kWave);
-    if (lane == 0) y[row] = s;
+    if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 256 / kWave; ++w) t += part[w];
+        const double b = B ? (double)B[bidx ? bidx[row] : row] : 0.0;
+        O[oidx ? oidx[row] : row] = (TO)(b + sign * t);
+    }
 }
 
-void launch_gemv(const double* M, size_t m, const double* x, double* y, hipStream_t s) {
+template <class TV, class TB, class TO>
+static void coarse_gemv_t(const double* M, size_t m, const void* V, const int32_t* vidx, const void* B,
+                          const int32_t* bidx, double sign, void* O, const int32_t* oidx, hipStream_t s) {
+    hipLaunchKernelGGL((coarse_gemv_kernel<TV, TB, TO>), dim3((unsigned)m), dim3(256), 0, s, M, m, (const TV*)V, vidx,
+                       (const TB*)B, bidx, sign, (TO*)O, oidx);
+}
+
+void launch_coarse_gemv(const double* M, size_t m, const void* V, int vprec, const int32_t* vidx, const void* B,
+                        int bprec, const int32_t* bidx, double sign, void* O, int oprec, const int32_t* oidx,
+                        hipStream_t s) {
     if (m == 0) return;
-    const size_t rows_per_block = 256 / kWave;
-    hipLaunchKernelGGL(gemv_kernel, dim3((unsigned)((m + rows_per_block - 1) / rows_per_block)), dim3(256), 0, s,
-                       M, m, x, y);
+    const bool v64 = vprec == NNMG_FP64, b64 = bprec == NNMG_FP64, o64 = oprec == NNMG_FP64;
+    if (v64 && b64 && o64) coarse_gemv_t<double, double, double>(M, m, V, vidx, B, bidx, sign, O, oidx, s);
+    else if (!v64 && b64 && o64) coarse_gemv_t<float, double, double>(M, m, V, vidx, B, bidx, sign, O, oidx, s);
+    else if (v64 && !b64 && o64) coarse_gemv_t<double, float, double>(M, m, V, vidx, B, bidx, sign, O, oidx, s);
+    else if (v64 && b64 && !o64) coarse_gemv_t<double, double, float>(M, m, V, vidx, B, bidx, sign, O, oidx, s);
+    else fail(NNMG_ERR_INVALID_ARG, "coarse_gemv precision combination");
     NNMG_HIP(hipGetLastError());
 }
 

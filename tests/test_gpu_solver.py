@@ -138,3 +138,30 @@ def test_graph_replays_match_eager_launches(ctx):
             assert np.array_equal(ig["history"], ie["history"])
             assert torch.equal(xg, xe)
             assert torch.isfinite(y).all()
+
+
+@pytest.mark.parametrize("cfg,cells,k", [(0, [9], 1), (1, [6], 2), (2, [3], 3)])
+def test_coarse_solve_alone(ctx, cfg, cells, k):
+    """With one level the V-cycle is the coarse solve: A^{-1} r (float64, one
+    refinement step) against a dense solve of the oracle's reduced system,
+    and the float32 V-cycle (float64 solve, float32 input and output)."""
+    import paper_2412_10910_amd as nn
+    from _parity import Pair
+    (m,) = config_levels(cfg, cells=cells)
+    p = Pair(ctx, m, k)
+    H = nn.Hierarchy(ctx, [p.lib], [])
+    free = p.orc.free
+    r = np.where(free, random_vector(p.orc.n_dofs, 91), 0.0)
+    A = p.A.toarray()
+    expect = np.zeros_like(r)
+    expect[free] = np.linalg.solve(A[np.ix_(free, free)], r[free])
+    z = p.to_orc(H.vcycle(p.to_lib(r)))
+    assert rel_err(z, expect) <= 1e-12
+    assert np.all(z[~free] == 0)
+    # float32 V-cycle: the input is rounded to float32, the solve is float64,
+    # the output is rounded to float32 (one rounding, 6e-8 relative)
+    r32 = r.astype(np.float32).astype(np.float64)
+    expect32 = np.zeros_like(r)
+    expect32[free] = np.linalg.solve(A[np.ix_(free, free)], r32[free])
+    z32 = p.to_orc(H.vcycle(p.to_lib(r, torch.float32)))
+    assert rel_err(z32, expect32) <= 2e-7
