@@ -10,6 +10,8 @@ these inputs; neither side imports the other.
 from .meshes import (  # noqa: F401
     Mesh,
     structured_box,
+    structured_brick,
+    dirichlet_face,
     perturb_interior,
     ball_map,
     scramble,
@@ -22,4 +24,5 @@ from .sources import (  # noqa: F401
     bump_centres_ball,
     config_source,
     random_vector,
+    random_load,
 )

@@ -63,8 +63,37 @@ def structured_box(dim: int, n: int, lo: float = 0.0, hi: float = 1.0) -> Mesh:
     return Mesh(verts.astype(np.float64), cells.astype(np.int32), on_bnd.astype(np.uint8))
 
 
-def perturb_interior(mesh: Mesh, alpha: float, h: float, rng: np.random.Generator) -> Mesh:
-    """Move every coordinate of every non-boundary vertex by U(-alpha*h, alpha*h)."""
+def structured_brick(cells, lo, hi) -> Mesh:
+    """Structured hexahedral mesh of the box [lo, hi] with cells[a] cells along
+    axis a (x fastest, as structured_box); every boundary vertex Dirichlet."""
+    nx, ny, nz = (int(c) for c in cells)
+    if min(nx, ny, nz) < 1:
+        raise ValueError("cells must be >= 1")
+    axes = [np.linspace(lo[a], hi[a], cells[a] + 1) for a in range(3)]
+    n1 = [nx + 1, ny + 1, nz + 1]
+    iv = np.arange(n1[0] * n1[1] * n1[2])
+    ix, iy, iz = iv % n1[0], (iv // n1[0]) % n1[1], iv // (n1[0] * n1[1])
+    verts = np.stack([axes[0][ix], axes[1][iy], axes[2][iz]], axis=1)
+    ic = np.arange(nx * ny * nz)
+    cx, cy, cz = ic % nx, (ic // nx) % ny, ic // (nx * ny)
+    base = cx + n1[0] * (cy + n1[1] * cz)
+    cells_ = np.empty((ic.size, 8), dtype=np.int64)
+    for b in range(8):
+        cells_[:, b] = base + (b & 1) + n1[0] * (((b >> 1) & 1) + n1[1] * ((b >> 2) & 1))
+    on_bnd = (ix == 0) | (ix == nx) | (iy == 0) | (iy == ny) | (iz == 0) | (iz == nz)
+    return Mesh(verts.astype(np.float64), cells_.astype(np.int32), on_bnd.astype(np.uint8))
+
+
+def dirichlet_face(mesh: Mesh, axis: int, value: float) -> Mesh:
+    """The same mesh with only the vertices on the plane x_axis = value Dirichlet."""
+    tol = 1e-12 * max(1.0, float(np.ptp(mesh.vertices)))
+    d = (np.abs(mesh.vertices[:, axis] - value) < tol).astype(np.uint8)
+    return Mesh(mesh.vertices.copy(), mesh.cells.copy(), d)
+
+
+def perturb_interior(mesh: Mesh, alpha: float, h, rng: np.random.Generator) -> Mesh:
+    """Move every coordinate of every non-boundary vertex by U(-alpha*h, alpha*h)
+    (h a number or one cell size per axis)."""
     v = mesh.vertices.copy()
     # the boundary is found geometrically (a vertex on a facet of the bounding
     # box), so the result does not depend on the Dirichlet flags
@@ -73,7 +102,8 @@ def perturb_interior(mesh: Mesh, alpha: float, h: float, rng: np.random.Generato
     tol = 1e-12 * max(1.0, float(np.max(hi - lo)))
     geo_bnd = np.any((np.abs(mesh.vertices - lo) < tol) | (np.abs(mesh.vertices - hi) < tol), axis=1)
     interior = ~geo_bnd
-    delta = rng.uniform(-alpha * h, alpha * h, size=v.shape)
+    hh = np.broadcast_to(np.asarray(h, dtype=np.float64), (v.shape[1],))
+    delta = rng.uniform(-1.0, 1.0, size=v.shape) * (alpha * hh)
     v[interior] += delta[interior]
     return Mesh(v, mesh.cells.copy(), mesh.dirichlet.copy())
 
@@ -154,11 +184,18 @@ CONFIGS = {
     # reduced ball hierarchies that the oracle can solve in seconds
     "2p3": dict(dim=3, degree=3, domain="ball", cells=[4, 7, 15, 32], alpha=0.0, source="bumps_ball"),
     "2p4": dict(dim=3, degree=4, domain="ball", cells=[5, 11, 24], alpha=0.0, source="bumps_ball"),
+    # 3D linear elasticity (vector Q2, lambda = mu = 1) on the beam [0,5] x [0,1]^2
+    # clamped at x = 0, body load (0, 0, -1); cells per level (x, y, z),
+    # interior vertices +-0.1h
+    3: dict(dim=3, degree=2, domain="beam", cells=[(14, 3, 3), (33, 7, 7), (80, 16, 16)], alpha=0.1,
+            source="gravity", operator="elasticity", lam=1.0, mu=1.0),
 }
+
+BEAM_LENGTH = 5.0
 
 
 def _seed_base(cfg) -> int:
-    return {0: 0, 1: 1, 2: 2, "2q4": 2, "2p3": 2, "2p4": 2}.get(cfg, 9)
+    return {0: 0, 1: 1, 2: 2, "2q4": 2, "2p3": 2, "2p4": 2, 3: 3}.get(cfg, 9)
 
 
 def level_mesh(domain: str, dim: int, n: int, alpha: float, seed: int) -> Mesh:
@@ -172,6 +209,14 @@ def level_mesh(domain: str, dim: int, n: int, alpha: float, seed: int) -> Mesh:
         if alpha > 0:
             m = perturb_interior(m, alpha, 2.0 / n, np.random.default_rng(seed))
         return ball_map(m)
+    if domain == "beam":
+        # n = (cells along x, y, z); clamped (Dirichlet) on the face x = 0 only
+        hi = (BEAM_LENGTH, 1.0, 1.0)
+        m = structured_brick(n, (0.0, 0.0, 0.0), hi)
+        if alpha > 0:
+            h = [hi[a] / n[a] for a in range(3)]
+            m = perturb_interior(m, alpha, h, np.random.default_rng(seed))
+        return dirichlet_face(m, 0, 0.0)
     raise ValueError(domain)
 
 

@@ -47,6 +47,14 @@ def config_source(cfg, rhs_id: int = 0):
     kind = c["source"]
     if kind == "one":
         return lambda x: np.ones(np.asarray(x).shape[:-1], dtype=np.float64)
+    if kind == "gravity":
+        # vector body load (0, 0, -1): x [..., 3] -> f [..., 3]
+        def gravity(x):
+            x = np.asarray(x, dtype=np.float64)
+            f = np.zeros(x.shape[:-1] + (3,))
+            f[..., 2] = -1.0
+            return f
+        return gravity
     rng = np.random.default_rng(2000 * _seed_base(cfg) + rhs_id)
     if kind == "bumps":
         cen = bump_centres_cube(c["dim"], rng)
@@ -60,3 +68,22 @@ def config_source(cfg, rhs_id: int = 0):
 def random_vector(n: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
     """Seeded uniform float64 vector (used for operator inputs and Lanczos start vectors)."""
     return np.random.default_rng(seed).uniform(lo, hi, size=n)
+
+
+def random_load(rhs_id: int, count: int = 4, width: float = 0.3):
+    """Smooth random vector body load on the beam: per component a sum of
+    `count` Gaussian bumps of the given width with random centres in the beam
+    and random signed amplitudes, from numpy.random.default_rng(3000 + rhs_id)."""
+    rng = np.random.default_rng(3000 + rhs_id)
+    cen = rng.uniform((0.0, 0.0, 0.0), (5.0, 1.0, 1.0), size=(3, count, 3))
+    amp = rng.uniform(-1.0, 1.0, size=(3, count))
+
+    def load(x):
+        x = np.asarray(x, dtype=np.float64)
+        f = np.zeros(x.shape[:-1] + (3,))
+        for c in range(3):
+            for g in range(count):
+                d2 = np.sum((x - cen[c, g]) ** 2, axis=-1)
+                f[..., c] += amp[c, g] * np.exp(-d2 / (2.0 * width * width))
+        return f
+    return load
