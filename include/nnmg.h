@@ -117,6 +117,20 @@ typedef struct {
                                while profiling is on */
 } nnmg_cg_opts;
 
+/* The operator of a level. */
+typedef enum {
+    NNMG_OP_LAPLACE = 0,    /* -div grad u (paper §2, eq. problem) */
+    NNMG_OP_ELASTICITY = 1  /* linear elasticity, -div sigma(u) (paper §4, Applications to FEA,
+                               eq. linear_elasticity): vector Q_k with dim components, 3D only */
+} nnmg_operator;
+
+/* Settings of nnmg_level_create_ex. */
+typedef struct {
+    nnmg_operator op;  /* default NNMG_OP_LAPLACE */
+    double lambda;     /* Lame coefficients of NNMG_OP_ELASTICITY (default 1, 1); */
+    double mu;         /* sigma = lambda tr(eps) I + 2 mu eps, mu > 0, lambda >= 0 */
+} nnmg_level_opts;
+
 typedef struct {
     int iterations;  /* CG iterations performed */
     double relres;   /* final ||r||_2 / ||b||_2 */
@@ -133,6 +147,7 @@ void nnmg_ctx_destroy(nnmg_ctx* ctx);
 /* Message of the last failing call on this thread ("" if none). */
 const char* nnmg_last_error(void);
 
+void nnmg_default_level_opts(nnmg_level_opts* opts);
 void nnmg_default_transfer_opts(nnmg_transfer_opts* opts);
 void nnmg_default_mg_opts(nnmg_mg_opts* opts);
 void nnmg_default_cg_opts(nnmg_cg_opts* opts);
@@ -148,11 +163,30 @@ void nnmg_default_cg_opts(nnmg_cg_opts* opts);
  * of range, repeated vertex in a cell, non-positive Jacobian at a Gauss
  * point), OOM, HIP. */
 int nnmg_level_create(nnmg_ctx* ctx, const nnmg_mesh* mesh, int degree, nnmg_level** out);
+
+/* As nnmg_level_create, with the operator chosen by opts (NULL: defaults).
+ * For NNMG_OP_ELASTICITY (paper §4, Applications to FEA) a level carries
+ * dim displacement components per Q_k node; every vector of the level has
+ * n_dofs = dim * n_nodes entries interleaved by node (component c of node i
+ * at dim * i + c).  The clamped boundary is the union of the faces whose
+ * vertices all carry the Dirichlet flag (all components fixed at zero there);
+ * every other boundary face is traction free.  Transfers and hierarchies
+ * accept elasticity levels like Laplace levels (P acts on each component).
+ * Errors as nnmg_level_create; UNSUPPORTED for elasticity in 2D; INVALID_ARG
+ * for mu <= 0 or lambda < 0. */
+int nnmg_level_create_ex(nnmg_ctx* ctx, const nnmg_mesh* mesh, int degree, const nnmg_level_opts* opts,
+                         nnmg_level** out);
 void nnmg_level_destroy(nnmg_level* level);
 
+/* n_dofs: entries of the level's vectors (ncomp * nodes); n_free: those not
+ * constrained. */
 int nnmg_level_info(const nnmg_level* level, int64_t* n_dofs, int64_t* n_free, int64_t* n_cells);
 
-/* Support point of every DoF: host [n_dofs][dim] (paper §2, eq. pointwise). */
+/* Components per node: 1 (Laplace) or dim (elasticity). */
+int nnmg_level_components(const nnmg_level* level, int* ncomp);
+
+/* Support point of every DoF: host [n_dofs][dim] (paper §2, eq. pointwise);
+ * the components of one node share its point. */
 int nnmg_level_support_points(const nnmg_level* level, double* host_xyz);
 
 /* Constrained flag of every DoF: host uint8 [n_dofs]. */
@@ -164,8 +198,9 @@ int nnmg_level_quadrature_points(const nnmg_level* level, double* host_xyz);
 
 /* b_i = sum over cells and Gauss points of f_q phi_i(x_q) |det J_q| w_q
  * (paper §2: the load functional b(v) of eq. problem, with the Gauss rule of
- * §4).  f_qp_dev: float64 device [n_cells][(k+1)^dim] values of f at the points
- * of nnmg_level_quadrature_points.  b_dev is overwritten; its constrained
+ * §4).  f_qp_dev: float64 device [n_cells][(k+1)^dim][ncomp] values of f at
+ * the points of nnmg_level_quadrature_points (for elasticity the body force,
+ * b_(i,c) = sum f_c phi_i |det J| w).  b_dev is overwritten; its constrained
  * entries are zero.  Asynchronous on `stream`. */
 int nnmg_level_assemble_rhs(nnmg_level* level, const double* f_qp_dev, double* b_dev, void* stream);
 

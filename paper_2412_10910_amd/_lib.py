@@ -52,6 +52,13 @@ class Allocator(C.Structure):
     _fields_ = [("user", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN)]
 
 
+OP_LAPLACE, OP_ELASTICITY = 0, 1
+
+
+class LevelOpts(C.Structure):
+    _fields_ = [("op", C.c_int), ("lam", C.c_double), ("mu", C.c_double)]
+
+
 class TransferOpts(C.Structure):
     _fields_ = [
         ("bbox_expand", C.c_double),
@@ -93,10 +100,13 @@ SIGNATURES = {
     "nnmg_ctx_create": (C.c_int, [C.c_int, C.POINTER(Allocator), C.POINTER(_vp)]),
     "nnmg_ctx_destroy": (None, [_vp]),
     "nnmg_last_error": (C.c_char_p, []),
+    "nnmg_default_level_opts": (None, [C.POINTER(LevelOpts)]),
     "nnmg_default_transfer_opts": (None, [C.POINTER(TransferOpts)]),
     "nnmg_default_mg_opts": (None, [C.POINTER(MgOpts)]),
     "nnmg_default_cg_opts": (None, [C.POINTER(CgOpts)]),
     "nnmg_level_create": (C.c_int, [_vp, C.POINTER(Mesh), C.c_int, C.POINTER(_vp)]),
+    "nnmg_level_create_ex": (C.c_int, [_vp, C.POINTER(Mesh), C.c_int, C.POINTER(LevelOpts), C.POINTER(_vp)]),
+    "nnmg_level_components": (C.c_int, [_vp, C.POINTER(C.c_int)]),
     "nnmg_level_destroy": (None, [_vp]),
     "nnmg_level_info": (C.c_int, [_vp, _i64p, _i64p, _i64p]),
     "nnmg_level_support_points": (C.c_int, [_vp, C.POINTER(C.c_double)]),

@@ -84,8 +84,15 @@ class Context:
 class Level:
     """One mesh level and its Q_k space (nnmg_level_create)."""
 
-    def __init__(self, ctx: Context, vertices, cells, dirichlet=None, degree: int = 1):
+    OPERATORS = {"laplace": _lib.OP_LAPLACE, "elasticity": _lib.OP_ELASTICITY}
+
+    def __init__(self, ctx: Context, vertices, cells, dirichlet=None, degree: int = 1, operator: str = "laplace",
+                 lam: float = 1.0, mu: float = 1.0):
+        """operator: "laplace" (scalar) or "elasticity" (vector Q_k, dim components
+        interleaved by node; lam, mu are the Lame coefficients)."""
         self.ctx = ctx
+        if operator not in self.OPERATORS:
+            raise ValueError(f"operator must be one of {sorted(self.OPERATORS)}")
         v = np.ascontiguousarray(vertices, dtype=np.float64)
         c = np.ascontiguousarray(cells, dtype=np.int32)
         d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
@@ -98,18 +105,27 @@ class Level:
             c.ctypes.data_as(C.POINTER(C.c_int32)),
             d.ctypes.data_as(C.POINTER(C.c_uint8)) if d is not None else None)
         h = C.c_void_p()
+        opts = _lib.LevelOpts()
+        lib().nnmg_default_level_opts(C.byref(opts))
+        opts.op = self.OPERATORS[operator]
+        opts.lam, opts.mu = float(lam), float(mu)
         with torch.cuda.device(ctx.device):
-            check(lib().nnmg_level_create(ctx.handle, C.byref(mesh), int(degree), C.byref(h)))
+            check(lib().nnmg_level_create_ex(ctx.handle, C.byref(mesh), int(degree), C.byref(opts), C.byref(h)))
         self.handle = h
         self.dim = int(v.shape[1])
         self.degree = int(degree)
+        self.operator = operator
+        nco = C.c_int()
+        check(lib().nnmg_level_components(h, C.byref(nco)))
+        self.ncomp = nco.value
         nd, nf, nc = C.c_int64(), C.c_int64(), C.c_int64()
         check(lib().nnmg_level_info(h, C.byref(nd), C.byref(nf), C.byref(nc)))
         self.n_dofs, self.n_free, self.n_cells = nd.value, nf.value, nc.value
 
     @classmethod
-    def from_mesh(cls, ctx: Context, mesh, degree: int):
-        return cls(ctx, mesh.vertices, mesh.cells, mesh.dirichlet, degree)
+    def from_mesh(cls, ctx: Context, mesh, degree: int, operator: str = "laplace", lam: float = 1.0,
+                  mu: float = 1.0):
+        return cls(ctx, mesh.vertices, mesh.cells, mesh.dirichlet, degree, operator, lam, mu)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -144,8 +160,9 @@ class Level:
         return torch.zeros(self.n_dofs, dtype=dtype, device=f"cuda:{self.ctx.device}")
 
     def assemble_rhs(self, f_qp: torch.Tensor, b: torch.Tensor | None = None) -> torch.Tensor:
+        """f_qp: [n_cells][(k+1)^dim][ncomp] source values at quadrature_points()."""
         q = (self.degree + 1) ** self.dim
-        fq = _vec(f_qp, self.n_cells * q, self.ctx.device, torch.float64, "f_qp")
+        fq = _vec(f_qp, self.n_cells * q * self.ncomp, self.ctx.device, torch.float64, "f_qp")
         b = self.empty(torch.float64) if b is None else b
         check(lib().nnmg_level_assemble_rhs(self.handle, fq, _vec(b, self.n_dofs, self.ctx.device,
                                                                    torch.float64, "b"), _stream()))

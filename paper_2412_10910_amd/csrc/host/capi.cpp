@@ -7,7 +7,7 @@
 
 namespace nnmg {
 
-Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree);
+Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree, const nnmg_level_opts& opts);
 void level_diagonal(const Level& L, int prec, void* out, hipStream_t s);
 void level_quadrature_points(const Level& L, double* out);
 Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_transfer_opts& o);
@@ -103,6 +103,13 @@ void nnmg_default_mg_opts(nnmg_mg_opts* o) {
     o->eig_start = nullptr;
 }
 
+void nnmg_default_level_opts(nnmg_level_opts* o) {
+    if (!o) return;
+    o->op = NNMG_OP_LAPLACE;
+    o->lambda = 1.0;
+    o->mu = 1.0;
+}
+
 void nnmg_default_cg_opts(nnmg_cg_opts* o) {
     if (!o) return;
     o->rtol = 1e-8;
@@ -134,11 +141,27 @@ int nnmg_ctx_create(int device, const nnmg_allocator* allocator, nnmg_ctx** out)
 
 void nnmg_ctx_destroy(nnmg_ctx* ctx) { delete ctx; }
 
-int nnmg_level_create(nnmg_ctx* ctx, const nnmg_mesh* mesh, int degree, nnmg_level** out) {
+int nnmg_level_create_ex(nnmg_ctx* ctx, const nnmg_mesh* mesh, int degree, const nnmg_level_opts* opts,
+                         nnmg_level** out) {
     return guarded([&] {
         if (!ctx || !out) fail(NNMG_ERR_INVALID_ARG, "ctx or out is NULL");
         NNMG_HIP(hipSetDevice(ctx->device));
-        *out = static_cast<nnmg_level*>(level_create(ctx, mesh, degree));
+        nnmg_level_opts o;
+        nnmg_default_level_opts(&o);
+        if (opts) o = *opts;
+        *out = static_cast<nnmg_level*>(level_create(ctx, mesh, degree, o));
+        return NNMG_OK;
+    });
+}
+
+int nnmg_level_create(nnmg_ctx* ctx, const nnmg_mesh* mesh, int degree, nnmg_level** out) {
+    return nnmg_level_create_ex(ctx, mesh, degree, nullptr, out);
+}
+
+int nnmg_level_components(const nnmg_level* l, int* ncomp) {
+    return guarded([&] {
+        if (!l || !ncomp) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        *ncomp = l->ncomp;
         return NNMG_OK;
     });
 }
@@ -160,7 +183,10 @@ int nnmg_level_info(const nnmg_level* l, int64_t* n_dofs, int64_t* n_free, int64
 int nnmg_level_support_points(const nnmg_level* l, double* xyz) {
     return guarded([&] {
         if (!l || !xyz) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
-        std::memcpy(xyz, l->support.data(), l->support.size() * sizeof(double));
+        const int d = l->dim, nc = l->ncomp;
+        for (int64_t i = 0; i < l->n_nodes; ++i)
+            for (int c = 0; c < nc; ++c)
+                std::memcpy(xyz + (i * nc + c) * d, l->support.data() + i * d, (size_t)d * sizeof(double));
         return NNMG_OK;
     });
 }
@@ -168,7 +194,8 @@ int nnmg_level_support_points(const nnmg_level* l, double* xyz) {
 int nnmg_level_constrained(const nnmg_level* l, uint8_t* mask) {
     return guarded([&] {
         if (!l || !mask) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
-        std::memcpy(mask, l->constrained.data(), l->constrained.size());
+        for (int64_t i = 0; i < l->n_nodes; ++i)
+            for (int c = 0; c < l->ncomp; ++c) mask[i * l->ncomp + c] = l->constrained[(size_t)i];
         return NNMG_OK;
     });
 }

@@ -111,7 +111,7 @@ static void alloc_work(Hierarchy& H, int prec) {
         w.r.alloc(H.ctx, b);
         w.ax.alloc(H.ctx, b);
         for (auto* a : {&w.f, &w.x, &w.d, &w.r, &w.ax}) NNMG_HIP(hipMemset(a->ptr, 0, b));
-        w.contrib.alloc(H.ctx, std::max<size_t>(H.levels[l]->contrib_len, 1) * wsize(prec));
+        w.contrib.alloc(H.ctx, std::max<size_t>(H.levels[l]->contrib_len * H.levels[l]->ncomp, 1) * wsize(prec));
     }
 }
 
@@ -154,7 +154,7 @@ static void setup_coarse(Hierarchy& H) {
     Ctx* ctx = H.ctx;
     std::vector<int32_t> idx;
     for (int64_t i = 0; i < C.n_dofs; ++i)
-        if (!C.constrained[(size_t)i]) idx.push_back((int32_t)i);
+        if (!C.constrained[(size_t)(i / C.ncomp)]) idx.push_back((int32_t)i);
     H.m = (int64_t)idx.size();
     const size_t N = (size_t)C.n_dofs, m = (size_t)H.m;
     H.cx.alloc(ctx, N);
@@ -377,8 +377,11 @@ Hierarchy* hierarchy_create(Ctx* ctx, nnmg_level* const* levels, int nl, nnmg_tr
     if (nl > 1 && !transfers) fail(NNMG_ERR_INVALID_ARG, "transfers is NULL");
     if (o.cheb_degree < 1 || !(o.smoothing_range > 1.0) || !(o.eig_safety > 0.0) || o.eig_iters < 1)
         fail(NNMG_ERR_INVALID_ARG, "multigrid options");
-    for (int i = 0; i < nl; ++i)
+    for (int i = 0; i < nl; ++i) {
         if (!levels[i]) fail(NNMG_ERR_INVALID_ARG, "level is NULL");
+        if (levels[i]->op != levels[0]->op || levels[i]->lam != levels[0]->lam || levels[i]->mu != levels[0]->mu)
+            fail(NNMG_ERR_INVALID_ARG, "all levels must carry the same operator");
+    }
     for (int i = 0; i + 1 < nl; ++i) {
         const Transfer* t = transfers[i];
         if (!t || t->fine != levels[i + 1] || t->coarse != levels[i])

@@ -154,13 +154,13 @@ static void number_dofs(Level& L) {
         }
     }
     if (next > INT32_MAX) fail(NNMG_ERR_UNSUPPORTED, "more than 2^31 DoFs");
-    L.n_dofs = next;
+    L.n_nodes = next;
 }
 
 static void find_constraints(Level& L, const uint8_t* dirichlet) {
     const int dim = L.dim, k = L.degree, n = L.n, q = L.q, nv = 1 << dim;
     const int64_t C = L.n_cells;
-    L.constrained.assign((size_t)L.n_dofs, 0);
+    L.constrained.assign((size_t)L.n_nodes, 0);
     if (!dirichlet) return;
     const int fv = 1 << (dim - 1);
     std::unordered_map<std::array<int32_t, 4>, int, Key4Hash> count;
@@ -193,8 +193,8 @@ static void find_constraints(Level& L, const uint8_t* dirichlet) {
 
 static void compute_support_points(Level& L) {
     const int dim = L.dim, n = L.n, q = L.q, nv = 1 << dim;
-    L.support.assign((size_t)(L.n_dofs * dim), 0.0);
-    std::vector<char> done((size_t)L.n_dofs, 0);
+    L.support.assign((size_t)(L.n_nodes * dim), 0.0);
+    std::vector<char> done((size_t)L.n_nodes, 0);
     for (int64_t c = 0; c < L.n_cells; ++c) {
         const int32_t* cv = &L.cells[(size_t)(c * nv)];
         for (int a = 0; a < q; ++a) {
@@ -215,8 +215,14 @@ static void compute_support_points(Level& L) {
     }
 }
 
-Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
+Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree, const nnmg_level_opts& opts) {
     if (!mesh) fail(NNMG_ERR_INVALID_ARG, "mesh is NULL");
+    if (opts.op != NNMG_OP_LAPLACE && opts.op != NNMG_OP_ELASTICITY) fail(NNMG_ERR_INVALID_ARG, "operator");
+    if (opts.op == NNMG_OP_ELASTICITY) {
+        if (mesh->dim != 3) fail(NNMG_ERR_UNSUPPORTED, "the elasticity operator is three-dimensional");
+        if (!(opts.mu > 0.0) || !(opts.lambda >= 0.0) || !std::isfinite(opts.lambda) || !std::isfinite(opts.mu))
+            fail(NNMG_ERR_INVALID_ARG, "Lame coefficients must satisfy mu > 0, lambda >= 0");
+    }
     if (mesh->dim != 2 && mesh->dim != 3) fail(NNMG_ERR_UNSUPPORTED, "dim must be 2 or 3");
     if (degree < 1 || degree > 4) fail(NNMG_ERR_UNSUPPORTED, "degree must be in 1..4");
     if (mesh->n_vertices <= 0 || mesh->n_cells <= 0 || !mesh->vertices || !mesh->cells)
@@ -248,11 +254,18 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
         L->vertices.assign(mesh->vertices, mesh->vertices + mesh->n_vertices * dim);
         L->cells.assign(mesh->cells, mesh->cells + mesh->n_cells * nv);
 
+        L->op = opts.op;
+        L->ncomp = opts.op == NNMG_OP_ELASTICITY ? dim : 1;
+        L->lam = opts.lambda;
+        L->mu = opts.mu;
         number_dofs(*L);
         find_constraints(*L, mesh->dirichlet_vertex);
         compute_support_points(*L);
-        for (int64_t i = 0; i < L->n_dofs; ++i)
-            if (L->constrained[(size_t)i]) L->constrained_idx.push_back((int32_t)i);
+        if (L->n_nodes * L->ncomp > INT32_MAX) fail(NNMG_ERR_UNSUPPORTED, "more than 2^31 DoFs");
+        L->n_dofs = L->n_nodes * L->ncomp;
+        for (int64_t i = 0; i < L->n_nodes; ++i)
+            if (L->constrained[(size_t)i])
+                for (int c = 0; c < L->ncomp; ++c) L->constrained_idx.push_back((int32_t)(i * L->ncomp + c));
         L->n_free = L->n_dofs - (int64_t)L->constrained_idx.size();
 
         NNMG_HIP(hipSetDevice(ctx->device));
@@ -302,11 +315,11 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
                             receives[kL] = 1;
                         }
                     }
-            std::vector<int32_t> off((size_t)L->n_dofs + 1, 0);
+            std::vector<int32_t> off((size_t)L->n_nodes + 1, 0);
             for (size_t k = 0; k < blk.size(); ++k)
                 if (blk[k] >= 0 && !merged[k]) off[(size_t)blk[k] + 1]++;
-            for (int64_t i = 0; i < L->n_dofs; ++i) off[(size_t)i + 1] += off[(size_t)i];
-            if ((int64_t)off[(size_t)L->n_dofs] >= (int64_t)kMergeNext)
+            for (int64_t i = 0; i < L->n_nodes; ++i) off[(size_t)i + 1] += off[(size_t)i];
+            if ((int64_t)off[(size_t)L->n_nodes] * L->ncomp >= (int64_t)kMergeNext)
                 fail(NNMG_ERR_UNSUPPORTED, "too many contributions");
             std::vector<int32_t> cur(off.begin(), off.end() - 1);
             std::vector<int32_t> pos(blk.size(), -1);
@@ -314,8 +327,9 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
                 if (blk[k] >= 0 && !merged[k]) pos[k] = cur[(size_t)blk[k]]++ | (receives[k] ? kMergeNext : 0);
             L->d_inv_off.upload(ctx, off);
             L->d_pos_blk.upload(ctx, pos);
-            L->contrib_len = (size_t)off[(size_t)L->n_dofs];
-            L->d_contrib.alloc(ctx, std::max<size_t>(L->contrib_len, 1) * sizeof(double));
+            L->contrib_len = (size_t)off[(size_t)L->n_nodes];
+            // ncomp values per slot: component c of slot k at ncomp * k + c
+            L->d_contrib.alloc(ctx, std::max<size_t>(L->contrib_len * L->ncomp, 1) * sizeof(double));
         }
         L->d_constrained.upload(ctx, L->constrained_idx);
         std::vector<double> cv((size_t)(L->n_cells * nv * dim));
@@ -388,9 +402,10 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree) {
         std::vector<float> coef32(coef.begin(), coef.end());
         L->d_coef32.upload(ctx, coef32);
         const char* mode = std::getenv("NNMG_GEOMETRY");
-        L->geometry_mode = (mode && std::string(mode) == "metric") ? 0 : 1;
+        // the elasticity operator rebuilds J from the map coefficients
+        L->geometry_mode = (mode && std::string(mode) == "metric" && L->op == NNMG_OP_LAPLACE) ? 0 : 1;
         const char* scatter = std::getenv("NNMG_SCATTER");
-        L->atomic_scatter = scatter && std::string(scatter) == "atomic";
+        L->atomic_scatter = scatter && std::string(scatter) == "atomic" && L->op == NNMG_OP_LAPLACE;
         if (L->geometry_mode == 1) {
             NNMG_HIP(hipDeviceSynchronize());
             L->d_metric64.reset();

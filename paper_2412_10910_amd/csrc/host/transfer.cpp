@@ -27,6 +27,7 @@ namespace nnmg {
 Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_transfer_opts& o) {
     if (!fine || !coarse) fail(NNMG_ERR_INVALID_ARG, "level is NULL");
     if (fine->dim != coarse->dim) fail(NNMG_ERR_INVALID_ARG, "levels of different dimension");
+    if (fine->ncomp != coarse->ncomp) fail(NNMG_ERR_INVALID_ARG, "levels with different numbers of components");
     if (fine->ctx->device != ctx->device || coarse->ctx->device != ctx->device)
         fail(NNMG_ERR_INVALID_ARG, "levels on another device");
     if (!(o.bbox_expand >= 0.0) || !(o.inside_tol >= 0.0) || !(o.newton_tol > 0.0) || o.newton_max_it < 1)
@@ -42,9 +43,9 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
         level_retain(fine);
         level_retain(coarse);
 
-        // query points
+        // query points: the unconstrained fine nodes (P acts on every component alike)
         std::vector<double> pts;
-        for (int64_t i = 0; i < fine->n_dofs; ++i) {
+        for (int64_t i = 0; i < fine->n_nodes; ++i) {
             if (fine->constrained[(size_t)i]) continue;
             T->h_point_dof.push_back((int32_t)i);
             for (int a = 0; a < dim; ++a) pts.push_back(fine->support[(size_t)(i * dim + a)]);
@@ -184,17 +185,18 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
         // rslot[K q + a], the slots of coarse DoF j being [roff[j], roff[j+1])
         {
             const std::vector<int32_t>& cdm = coarse->dofmap;
-            std::vector<int32_t> roff((size_t)coarse->n_dofs + 1, 0);
+            std::vector<int32_t> roff((size_t)coarse->n_nodes + 1, 0);
             for (size_t k = 0; k < cdm.size(); ++k)
                 if (!coarse->constrained[(size_t)cdm[k]]) roff[(size_t)cdm[k] + 1]++;
-            for (int64_t j = 0; j < coarse->n_dofs; ++j) roff[(size_t)j + 1] += roff[(size_t)j];
+            for (int64_t j = 0; j < coarse->n_nodes; ++j) roff[(size_t)j + 1] += roff[(size_t)j];
             std::vector<int32_t> cur(roff.begin(), roff.end() - 1);
             std::vector<int32_t> rslot(cdm.size(), -1);
             for (size_t k = 0; k < cdm.size(); ++k)
                 if (!coarse->constrained[(size_t)cdm[k]]) rslot[k] = cur[(size_t)cdm[k]]++;
             T->d_rslot.upload(ctx, rslot);
             T->d_roff.upload(ctx, roff);
-            T->d_rbuf.alloc(ctx, std::max<size_t>((size_t)roff.back(), 1));
+            // ncomp values per slot: component c of slot k at ncomp * k + c
+            T->d_rbuf.alloc(ctx, std::max<size_t>((size_t)roff.back() * coarse->ncomp, 1));
         }
         T->d_off.upload(ctx, off);
         T->d_fine.upload(ctx, fidx);
@@ -207,8 +209,9 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
         int team = 4;
         while (team < 64 && per_lane * (2 * team) <= avg) team *= 2;
         // small coarse levels: more lanes per cell, so that the launch still
-        // has enough wavefronts in flight to hide the memory latency
-        while (team < 64 && (double)C * team < 131072.0 && 2 * team <= avg) team *= 2;
+        // has enough wavefronts in flight to hide the memory latency (about
+        // 1k; larger teams cost more in the cross-lane reduction)
+        while (team < 64 && (double)C * team < 65536.0 && 2 * team <= avg) team *= 2;
         T->team = team;
     } catch (...) {
         level_release(T->fine);

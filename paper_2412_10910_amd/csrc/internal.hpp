@@ -112,15 +112,19 @@ struct Level {
     int wg = 64;        // lanes per block of the operator kernel
     int cpb = 0;        // cells per block of the operator kernel
     int64_t nblocks = 0;
-    int64_t n_cells = 0, n_dofs = 0, n_free = 0;
+    int64_t n_cells = 0, n_dofs = 0, n_free = 0;  // n_dofs = ncomp * n_nodes (vector DoFs interleaved by node)
+    int64_t n_nodes = 0;     // scalar Q_k nodes
+    int ncomp = 1;           // 1: Laplace; dim: linear elasticity
+    int op = 0;              // NNMG_OP_LAPLACE or NNMG_OP_ELASTICITY
+    double lam = 1.0, mu = 1.0;  // Lame coefficients of the elasticity operator
     Basis1D basis;
 
     std::vector<double> vertices;    // [V][dim]
     std::vector<int32_t> cells;      // [C][2^dim]
     std::vector<double> support;     // [N][dim]
     std::vector<int32_t> dofmap;     // [C][q] global DoF of every local node
-    std::vector<uint8_t> constrained;  // [N]
-    std::vector<int32_t> constrained_idx;
+    std::vector<uint8_t> constrained;  // [n_nodes] node mask (every component of a constrained node is fixed)
+    std::vector<int32_t> constrained_idx;  // constrained vector DoFs
 
     DeviceArray<int32_t> d_dofmap;      // [C][q], -1 for constrained DoFs
     DeviceArray<int32_t> d_dofmap_blk;  // operator layout [blk][n][wg], -1 for constrained / padding
@@ -221,8 +225,8 @@ void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fi
 // coarse = P^T fine (accumulate = false) or coarse += P^T fine; constrained coarse entries untouched
 void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s);
 // dst[i] (+)= sum of elem[off[i] .. off[i+1]) for every i with a non-empty run
-void launch_gather_runs(size_t n, const int32_t* off, int prec, const void* elem, void* dst, bool accumulate,
-                        hipStream_t s);
+void launch_gather_runs(size_t n, int ncomp, const int32_t* off, int prec, const void* elem, void* dst,
+                        bool accumulate, hipStream_t s);
 
 // vector kernels for the smoother and CG
 // x = d = dinv * f * c0   (first step from a zero guess)

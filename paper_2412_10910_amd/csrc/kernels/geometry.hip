@@ -209,7 +209,50 @@ __global__ void diagonal_kernel(const int32_t* __restrict__ dofmap, const int32_
     atomicAdd(diag + dof, sum);
 }
 
+// Diagonal of the elasticity operator (paper §4, eq. linear_elasticity), one
+// thread per (cell, local node a):
+//   diag_(a,c) += sum_q w det J [ (lam + mu) (d_c phi_a)^2 + mu |grad phi_a|^2 ]
+// with the physical gradient grad phi_a = J^{-T} grad_ref phi_a.
+__global__ void elasticity_diagonal_kernel(const int32_t* __restrict__ dofmap, const double* __restrict__ cverts,
+                                           int64_t ncells, int n, GaussTable gt, double lam, double mu,
+                                           double* __restrict__ diag) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int qn = n * n * n;
+    if (gid >= ncells * qn) return;
+    const int64_t c = gid / qn;
+    const int a = (int)(gid - c * qn);
+    const int dof = dofmap[c * qn + a];
+    if (dof < 0) return;
+    const int ax = a % n, ay = (a / n) % n, az = a / (n * n);
+    double sum[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < qn; ++q) {
+        const int qx = q % n, qy = (q / n) % n, qz = q / (n * n);
+        const double xi[3] = {gt.g[qx], gt.g[qy], gt.g[qz]};
+        const double w = gt.w[qx] * gt.w[qy] * gt.w[qz];
+        const double gr[3] = {gt.DS[qx][ax] * gt.S[qy][ay] * gt.S[qz][az], gt.S[qx][ax] * gt.DS[qy][ay] * gt.S[qz][az],
+                              gt.S[qx][ax] * gt.S[qy][ay] * gt.DS[qz][az]};
+        double J[3][3], Ji[3][3];
+        q1_jacobian<3>(cverts + c * 8 * 3, xi, J);
+        const double det = det_inv<3>(J, Ji);
+        double g[3];  // g_i = sum_k Ji[k][i] gr_k
+        for (int i = 0; i < 3; ++i) g[i] = Ji[0][i] * gr[0] + Ji[1][i] * gr[1] + Ji[2][i] * gr[2];
+        const double s = w * det, g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        for (int i = 0; i < 3; ++i) sum[i] += s * ((lam + mu) * g[i] * g[i] + mu * g2);
+    }
+    for (int i = 0; i < 3; ++i) atomicAdd(diag + (int64_t)dof * 3 + i, sum[i]);
+}
+
 void launch_diagonal(const Level& L, double* diag, hipStream_t s) {
+    if (L.op == NNMG_OP_ELASTICITY) {
+        const int64_t total = L.n_cells * L.q;
+        if (total == 0) return;
+        const int threads = 256;
+        hipLaunchKernelGGL(elasticity_diagonal_kernel, dim3((unsigned)((total + threads - 1) / threads)),
+                           dim3(threads), 0, s, L.d_dofmap.ptr, L.d_cellverts.ptr, L.n_cells, L.n,
+                           gauss_table(L.basis), L.lam, L.mu, diag);
+        NNMG_HIP(hipGetLastError());
+        return;
+    }
     const int64_t npos = L.nblocks * L.cpb;
     const int64_t total = npos * L.q;
     if (total == 0) return;
@@ -245,10 +288,11 @@ void launch_invert_diagonal(const Level& L, const double* diag, hipStream_t s) {
     NNMG_HIP(hipGetLastError());
 }
 
-// b_i += sum_q f_q |det J_q| w_q phi_a(x_q), one thread per (cell, local node)
+// b_(i,c) += sum_q f_(q,c) |det J_q| w_q phi_a(x_q), one thread per (cell, local
+// node); nc components per node (vector DoF nc i + c, f given as [cell][q][nc])
 template <int DIM>
 __global__ void rhs_kernel(const int32_t* __restrict__ dofmap, const double* __restrict__ cverts,
-                           const double* __restrict__ fq, int64_t ncells, int n, GaussTable gt,
+                           const double* __restrict__ fq, int64_t ncells, int n, int nc, GaussTable gt,
                            double* __restrict__ b) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int qn = 1;
@@ -259,7 +303,7 @@ __global__ void rhs_kernel(const int32_t* __restrict__ dofmap, const double* __r
     const int dof = dofmap[c * qn + a];
     if (dof < 0) return;
     const int ax = a % n, ay = (a / n) % n, az = DIM == 3 ? a / (n * n) : 0;
-    double sum = 0.0;
+    double sum[3] = {0.0, 0.0, 0.0};
     for (int q = 0; q < qn; ++q) {
         const int qx = q % n, qy = (q / n) % n, qz = DIM == 3 ? q / (n * n) : 0;
         double xi[DIM];
@@ -275,9 +319,10 @@ __global__ void rhs_kernel(const int32_t* __restrict__ dofmap, const double* __r
         double J[DIM][DIM], Ji[DIM][DIM];
         q1_jacobian<DIM>(cverts + c * (1 << DIM) * DIM, xi, J);
         const double det = det_inv<DIM>(J, Ji);
-        sum += fq[c * qn + q] * fabs(det) * w * phi;
+        const double s = fabs(det) * w * phi;
+        for (int k = 0; k < nc; ++k) sum[k] += fq[(c * qn + q) * nc + k] * s;
     }
-    atomicAdd(b + dof, sum);
+    for (int k = 0; k < nc; ++k) atomicAdd(b + (int64_t)dof * nc + k, sum[k]);
 }
 
 void launch_assemble_rhs(const Level& L, const double* fq, double* b, hipStream_t s) {
@@ -288,10 +333,10 @@ void launch_assemble_rhs(const Level& L, const double* fq, double* b, hipStream_
     const GaussTable gt = gauss_table(L.basis);
     if (L.dim == 3)
         hipLaunchKernelGGL(rhs_kernel<3>, grid, dim3(threads), 0, s, L.d_dofmap.ptr, L.d_cellverts.ptr, fq,
-                           L.n_cells, L.n, gt, b);
+                           L.n_cells, L.n, L.ncomp, gt, b);
     else
         hipLaunchKernelGGL(rhs_kernel<2>, grid, dim3(threads), 0, s, L.d_dofmap.ptr, L.d_cellverts.ptr, fq,
-                           L.n_cells, L.n, gt, b);
+                           L.n_cells, L.n, L.ncomp, gt, b);
     NNMG_HIP(hipGetLastError());
 }
 

@@ -258,15 +258,18 @@ __device__ __forceinline__ T eval_point(const NodeTable<N, T>& nt, const T* x, G
     return val;
 }
 
-template <int DIM, int N, class T>
+// NC components per node (vector DoF NC g + c): the staged values of a cell
+// are [node][component], and each point is evaluated once per component
+template <int DIM, int N, int NC, class T>
 __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
     const int32_t* __restrict__ off, const int32_t* __restrict__ fine, const T* __restrict__ xi, int64_t npts,
     const int32_t* __restrict__ blk_cells, const int32_t* __restrict__ cdm, const T* __restrict__ uc,
     T* __restrict__ uf, NodeTable<N, T> nt) {
     constexpr int Q = Pow<DIM, N>::value;
+    constexpr int QC = Q * NC;  // staged values per cell
     // LDS for the coarse values of up to NCMAX cells (16 KB in float64)
-    constexpr int NCMAX = (2048 / Q) < kPointBlock ? (2048 / Q) : kPointBlock;
-    __shared__ T su[NCMAX * Q];
+    constexpr int NCMAX = (2048 / QC) < kPointBlock ? (2048 / QC) : kPointBlock;
+    __shared__ T su[NCMAX * QC];
     __shared__ int32_t soff[NCMAX + 1];
     const int64_t b = blockIdx.x;
     const int tid = threadIdx.x;
@@ -285,13 +288,12 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
     const int c0 = blk_cells[2 * b], c1 = blk_cells[2 * b + 1];
     const int ns = (c1 - c0 + 1) < NCMAX ? (c1 - c0 + 1) : NCMAX;  // cells staged in LDS
     for (int i = tid; i <= ns; i += kPointBlock) soff[i] = off[c0 + i];
-    for (int i = tid; i < ns * Q; i += kPointBlock) {
-        const int g = cdm[(int64_t)c0 * Q + i];
-        su[i] = g >= 0 ? uc[g] : T(0);
+    for (int i = tid; i < ns * QC; i += kPointBlock) {
+        const int g = cdm[(int64_t)c0 * Q + i / NC];
+        su[i] = g >= 0 ? uc[(int64_t)g * NC + i % NC] : T(0);
     }
     __syncthreads();
     if (!valid) return;
-    T val;
     if (p < soff[ns]) {
         // largest local cell i with soff[i] <= p (empty cells have equal offsets)
         int lo = 0, hi = ns;
@@ -299,8 +301,10 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
             const int mid = (lo + hi) >> 1;
             if (soff[mid] <= p) lo = mid; else hi = mid;
         }
-        const T* u = su + lo * Q;
-        val = eval_point<DIM, N, T>(nt, x, [&](int a) { return u[a]; });
+        const T* u = su + lo * QC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            uf[(int64_t)f * NC + c] += eval_point<DIM, N, T>(nt, x, [&](int a) { return u[a * NC + c]; });
     } else {
         // more cells in this block than LDS holds: search the offsets and
         // read the coarse values from global memory
@@ -310,12 +314,13 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
             if (off[mid] <= p) lo = mid; else hi = mid;
         }
         const int32_t* dm = cdm + (int64_t)lo * Q;
-        val = eval_point<DIM, N, T>(nt, x, [&](int a) {
-            const int g = dm[a];
-            return g >= 0 ? uc[g] : T(0);
-        });
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            uf[(int64_t)f * NC + c] += eval_point<DIM, N, T>(nt, x, [&](int a) {
+                const int g = dm[a];
+                return g >= 0 ? uc[(int64_t)g * NC + c] : T(0);
+            });
     }
-    uf[f] += val;
 }
 
 #ifndef NNMG_RESTRICT_UNROLL
@@ -328,7 +333,9 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
 // 2D): lane s owns the NS = ceil(N / S) slices starting at s * NS, so that
 // only q / S accumulators live in registers.  The groups are reduced by
 // cross-lane shuffles and the sums are stored to their slots.
-template <int DIM, int N, class T, int S>
+// With NC components per node the cell is processed once per component
+// (vector DoF NC i + c); the sums of slot k go to rbuf[NC k + c].
+template <int DIM, int N, int NC, class T, int S>
 __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ fine,
                                                        const T* __restrict__ xi, int64_t npts,
@@ -351,10 +358,12 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
         // a cell without points contributes zeros
         for (int a = t; a < Q; a += team) {
             const int k = rslot[K * Q + a];
-            if (k >= 0) rbuf[k] = T(0);
+            if (k >= 0)
+                for (int c = 0; c < NC; ++c) rbuf[(int64_t)k * NC + c] = T(0);
         }
         return;
     }
+    for (int comp = 0; comp < NC; ++comp) {
     T R[QL];
 #pragma unroll
     for (int a = 0; a < QL; ++a) R[a] = T(0);
@@ -372,7 +381,7 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
             for (int a = 0; a < DIM; ++a) xs[u][a] = ok ? xi[a * npts + p] : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) r[u] = fi[u] >= 0 ? rf[fi[u]] : T(0);
+        for (int u = 0; u < U; ++u) r[u] = fi[u] >= 0 ? rf[(int64_t)fi[u] * NC + comp] : T(0);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             T ps[N];
@@ -420,8 +429,9 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
         const int node = s * QL + i;
         if ((i % G) == g && node < Q) {
             const int k = rslot[K * Q + node];
-            if (k >= 0) rbuf[k] = R[i];
+            if (k >= 0) rbuf[(int64_t)k * NC + comp] = R[i];
         }
+    }
     }
 }
 
@@ -451,7 +461,7 @@ static int log2i(int v) {
     return l;
 }
 
-template <int DIM, int N, class T>
+template <int DIM, int N, int NC, class T>
 static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, const void* in, void* out,
                               hipStream_t s) {
     const Level& C = *tr.coarse;
@@ -459,7 +469,7 @@ static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, con
     const NodeTable<N, T> nt = node_table<N, T>(C.basis);
     if (prolong) {
         const dim3 grid((unsigned)((tr.n_points + kPointBlock - 1) / kPointBlock));
-        hipLaunchKernelGGL((prolongate_points_kernel<DIM, N, T>), grid, dim3(kPointBlock), 0, s, tr.d_off.ptr,
+        hipLaunchKernelGGL((prolongate_points_kernel<DIM, N, NC, T>), grid, dim3(kPointBlock), 0, s, tr.d_off.ptr,
                            tr.d_fine.ptr, xi, tr.n_points, tr.d_blk_cells.ptr, C.d_dofmap.ptr, (const T*)in,
                            (T*)out, nt);
         NNMG_HIP(hipGetLastError());
@@ -470,7 +480,7 @@ static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, con
     const int threads = 256;
     const int64_t total = C.n_cells * (int64_t)team;
     const dim3 grid((unsigned)((total + threads - 1) / threads));
-    hipLaunchKernelGGL((restrict_kernel<DIM, N, T, S>), grid, dim3(threads), 0, s, tr.d_off.ptr, tr.d_fine.ptr, xi,
+    hipLaunchKernelGGL((restrict_kernel<DIM, N, NC, T, S>), grid, dim3(threads), 0, s, tr.d_off.ptr, tr.d_fine.ptr, xi,
                        tr.n_points, tr.d_rslot.ptr, (const T*)in, (T*)tr.d_rbuf.ptr, (int)C.n_cells,
                        log2i(team), nt);
     NNMG_HIP(hipGetLastError());
@@ -479,11 +489,12 @@ static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, con
 template <class T>
 static void transfer_prec(const Transfer& tr, bool prolong, const T* xi, const void* in, void* out,
                           hipStream_t s) {
-    const int d = tr.coarse->dim, n = tr.coarse->n;
-#define NNMG_CASE(D, NN) \
-    if (d == D && n == NN) return transfer_dispatch<D, NN, T>(tr, prolong, xi, in, out, s);
-    NNMG_CASE(2, 2) NNMG_CASE(2, 3) NNMG_CASE(2, 4) NNMG_CASE(2, 5)
-    NNMG_CASE(3, 2) NNMG_CASE(3, 3) NNMG_CASE(3, 4) NNMG_CASE(3, 5)
+    const int d = tr.coarse->dim, n = tr.coarse->n, nc = tr.coarse->ncomp;
+#define NNMG_CASE(D, NN, NCC) \
+    if (d == D && n == NN && nc == NCC) return transfer_dispatch<D, NN, NCC, T>(tr, prolong, xi, in, out, s);
+    NNMG_CASE(2, 2, 1) NNMG_CASE(2, 3, 1) NNMG_CASE(2, 4, 1) NNMG_CASE(2, 5, 1)
+    NNMG_CASE(3, 2, 1) NNMG_CASE(3, 3, 1) NNMG_CASE(3, 4, 1) NNMG_CASE(3, 5, 1)
+    NNMG_CASE(3, 2, 3) NNMG_CASE(3, 3, 3) NNMG_CASE(3, 4, 3) NNMG_CASE(3, 5, 3)
 #undef NNMG_CASE
     fail(NNMG_ERR_UNSUPPORTED, "transfer degree/dimension");
 }
@@ -500,7 +511,8 @@ void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse
         transfer_prec<double>(t, false, t.d_xi64.ptr, fine, coarse, s);
     else
         transfer_prec<float>(t, false, t.d_xi32.ptr, fine, coarse, s);
-    launch_gather_runs((size_t)t.coarse->n_dofs, t.d_roff.ptr, prec, t.d_rbuf.ptr, coarse, accumulate, s);
+    launch_gather_runs((size_t)t.coarse->n_dofs, t.coarse->ncomp, t.d_roff.ptr, prec, t.d_rbuf.ptr, coarse,
+                       accumulate, s);
 }
 
 }  // namespace nnmg

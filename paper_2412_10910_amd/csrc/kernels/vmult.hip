@@ -436,6 +436,268 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
     }
 }
 
+// ---------------------------------------------------------------------------
+// Linear elasticity (paper §4, Applications to FEA, eq. linear_elasticity):
+// a(u, v) = (sigma(u), grad v), sigma = lam tr(grad u) I + mu (grad u + grad u^T),
+// for dim = 3 displacement components interleaved by node (vector DoF 3 i + c).
+//
+// Same block shape, lane layout, geometry rebuild and contribution slots as
+// the Laplace kernel; each lane keeps one x-line of a cell for all three
+// components.  The forward sweeps run once per component and leave the
+// reference gradient ghat_c,k = d u_c / d xi_k at the lane's Gauss points in
+// lane-private LDS.  At each point, with R the rows of det(J) J^{-1} (cross
+// products of the columns of J),
+//   grad u = ghat R / det J,  sigma as above,  F = w sigma R^T,
+// and F_c,k is integrated against d phi / d xi_k by the backward sweeps, one
+// component at a time; component c of slot k is contrib[3 k + c].
+// ---------------------------------------------------------------------------
+template <int N, class T>
+__global__ __launch_bounds__((OpShape<3, N>::WG)) void elasticity_kernel(const int32_t* __restrict__ dmap,
+                                                                         const T* __restrict__ geo,
+                                                                         const T* __restrict__ src,
+                                                                         const int32_t* __restrict__ slots,
+                                                                         T* __restrict__ dst, OpTables<N, T> tb,
+                                                                         T lam, T mu) {
+    using Sh = OpShape<3, N>;
+    constexpr int L = Sh::L, WG = Sh::WG, CPB = Sh::CPB, TILE = Sh::TILE;
+    constexpr int NC = 21;
+    __shared__ T lds[3][CPB][TILE];
+    __shared__ T lg9[9 * N][WG];  // lane-private: ghat (then F) of [component][direction][point]
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x;
+    const int cell = lane / L;
+    const int line = lane - cell * L;
+    const bool act = cell < CPB;
+    const int cb = act ? cell : 0;
+    const int j = line % N, t = line / N;
+    const int row = line * N;
+
+    const int32_t* dm = dmap + b * (N * WG) + lane;
+    int32_t idx[N], slot[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) idx[i] = dm[i * WG];
+    const int32_t* ps = slots + b * (N * WG) + lane;
+#pragma unroll
+    for (int i = 0; i < N; ++i) slot[i] = ps[i * WG];
+    __shared__ T lcf[CPB][NC];
+    constexpr int R = (NC + L - 1) / L;
+    T cv[R];
+    {
+        const T* gc = geo + b * (NC * CPB) + cb;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int m = line + r * L;
+            cv[r] = (act && m < NC) ? gc[m * CPB] : T(0);
+        }
+    }
+    constexpr int NT = 3 * N * N + 2 * N;
+    static_assert(sizeof(OpTables<N, T>) == NT * sizeof(T), "OpTables must be a flat array of T");
+    constexpr int TE = (NT + WG - 1) / WG;
+    __shared__ T ltab[NT];
+    T tv[TE];
+#pragma unroll
+    for (int e = 0; e < TE; ++e)
+        tv[e] = lane + e * WG < NT ? reinterpret_cast<const T*>(&tb)[lane + e * WG] : T(0);
+    T uc[3][N];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < N; ++i) uc[c][i] = idx[i] >= 0 ? src[(int64_t)idx[i] * 3 + c] : T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int m = line + r * L;
+        if (act && m < NC) lcf[cb][m] = cv[r];
+    }
+#pragma unroll
+    for (int e = 0; e < TE; ++e)
+        if (lane + e * WG < NT) ltab[lane + e * WG] = tv[e];
+    const T* lS = ltab;
+    const T* lDS = ltab + N * N;
+    const T* lD = ltab + 2 * N * N;
+    const T* lg = ltab + 3 * N * N;
+    const T* lw = lg + N;
+    T* A = lds[0][cb];
+    T* B = lds[1][cb];
+    T* Cc = lds[2][cb];
+    auto G = [&](int c, int k, int i) -> T& { return lg9[(c * 3 + k) * N + i][lane]; };
+
+    // ---- forward, one component at a time ---------------------------------
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        T u[N], v[N], gz[N], gx[N], gy[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) u[i] = uc[c][i];
+        line_apply<N, T, false>(tb.S, u, v);
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) A[row + i] = v[i];
+        }
+        block_sync<WG>();
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = lS[j * N + 0] * A[(t * N + 0) * N + i];
+#pragma unroll
+            for (int q = 1; q < N; ++q) s += lS[j * N + q] * A[(t * N + q) * N + i];
+            u[i] = s;
+        }
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) B[row + i] = u[i];
+        }
+        block_sync<WG>();
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const T w0 = B[(0 * N + j) * N + i];
+            T s0 = lS[t * N + 0] * w0, s1 = lDS[t * N + 0] * w0;
+#pragma unroll
+            for (int q = 1; q < N; ++q) {
+                const T w = B[(q * N + j) * N + i];
+                s0 += lS[t * N + q] * w;
+                s1 += lDS[t * N + q] * w;
+            }
+            v[i] = s0;
+            gz[i] = s1;
+        }
+        line_apply<N, T, false>(tb.D, v, gx);
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) Cc[row + i] = v[i];
+        }
+        block_sync<WG>();
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = lD[j * N + 0] * Cc[(t * N + 0) * N + i];
+#pragma unroll
+            for (int q = 1; q < N; ++q) s += lD[j * N + q] * Cc[(t * N + q) * N + i];
+            gy[i] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            G(c, 0, i) = gx[i];
+            G(c, 1, i) = gy[i];
+            G(c, 2, i) = gz[i];
+        }
+        // the tiles are rewritten by the next component
+        block_sync<WG>();
+    }
+
+    // ---- stress at the Gauss points of the line ---------------------------
+    {
+        T c0[3], C1[3], E1[3], D2[3], F2[3];
+        const T* cf = lcf[cb];
+        const T eta = lg[j], zeta = lg[t];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            c0[k] = cf[0 + k] + cf[9 + k] * eta + (cf[12 + k] + cf[18 + k] * eta) * zeta;
+            C1[k] = cf[3 + k] + cf[15 + k] * zeta;
+            E1[k] = cf[9 + k] + cf[18 + k] * zeta;
+            D2[k] = cf[6 + k] + cf[15 + k] * eta;
+            F2[k] = cf[12 + k] + cf[18 + k] * eta;
+        }
+        const T wl = lw[j] * lw[t];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const T xi = tb.g[i];
+            T c1[3], c2[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                c1[k] = C1[k] + E1[k] * xi;
+                c2[k] = D2[k] + F2[k] * xi;
+            }
+            // rows of det(J) J^{-1}
+            const T Rm[3][3] = {{c1[1] * c2[2] - c1[2] * c2[1], c1[2] * c2[0] - c1[0] * c2[2], c1[0] * c2[1] - c1[1] * c2[0]},
+                                {c2[1] * c0[2] - c2[2] * c0[1], c2[2] * c0[0] - c2[0] * c0[2], c2[0] * c0[1] - c2[1] * c0[0]},
+                                {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2], c0[0] * c1[1] - c0[1] * c1[0]}};
+            const T det = c0[0] * Rm[0][0] + c0[1] * Rm[0][1] + c0[2] * Rm[0][2];
+            const T rdet = recip(det);
+            T gp[3][3];  // physical gradient: gp[c][m] = d u_c / d x_m
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T h0 = G(c, 0, i), h1 = G(c, 1, i), h2 = G(c, 2, i);
+#pragma unroll
+                for (int m = 0; m < 3; ++m) gp[c][m] = (h0 * Rm[0][m] + h1 * Rm[1][m] + h2 * Rm[2][m]) * rdet;
+            }
+            const T tr = gp[0][0] + gp[1][1] + gp[2][2];
+            const T w = tb.w[i] * wl;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T sg[3];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) sg[m] = mu * (gp[c][m] + gp[m][c]) + (m == c ? lam * tr : T(0));
+#pragma unroll
+                for (int k = 0; k < 3; ++k) G(c, k, i) = w * (sg[0] * Rm[k][0] + sg[1] * Rm[k][1] + sg[2] * Rm[k][2]);
+            }
+        }
+    }
+
+    // ---- backward, one component at a time --------------------------------
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        T u[N], v[N], gx[N], gy[N], gz[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            gx[i] = G(c, 0, i);
+            gy[i] = G(c, 1, i);
+            gz[i] = G(c, 2, i);
+        }
+        line_apply<N, T, true>(tb.D, gx, u);
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) A[row + i] = gy[i];
+        }
+        block_sync<WG>();
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = u[i];
+#pragma unroll
+            for (int q = 0; q < N; ++q) s += lD[q * N + j] * A[(t * N + q) * N + i];
+            u[i] = s;
+        }
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                B[row + i] = u[i];
+                Cc[row + i] = gz[i];
+            }
+        }
+        block_sync<WG>();
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = lS[0 * N + t] * B[(0 * N + j) * N + i] + lDS[0 * N + t] * Cc[(0 * N + j) * N + i];
+#pragma unroll
+            for (int q = 1; q < N; ++q)
+                s += lS[q * N + t] * B[(q * N + j) * N + i] + lDS[q * N + t] * Cc[(q * N + j) * N + i];
+            v[i] = s;
+        }
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) A[row + i] = v[i];
+        }
+        block_sync<WG>();
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = lS[0 * N + j] * A[(t * N + 0) * N + i];
+#pragma unroll
+            for (int q = 1; q < N; ++q) s += lS[q * N + j] * A[(t * N + q) * N + i];
+            u[i] = s;
+        }
+        line_apply<N, T, true>(tb.S, u, v);
+        const T nxt = __shfl_down(v[0], L, kWave);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            int32_t k = slot[i];
+            if (k >= 0) {
+                if (i == N - 1 && (k & kMergeNext)) {
+                    v[i] += nxt;
+                    k &= ~kMergeNext;
+                }
+                dst[(int64_t)k * 3 + c] = v[i];
+            }
+        }
+        block_sync<WG>();
+    }
+}
+
 template <int N, class T>
 static OpTables<N, T> make_tables(const Basis1D& b) {
     OpTables<N, T> t;
@@ -469,6 +731,17 @@ template <int DIM, int N, class T>
 static void vmult_dispatch(const Level& L, const T* geo, int mode, bool atomic, const void* src, void* dst,
                            hipStream_t s) {
     if (L.nblocks == 0) return;
+    if constexpr (DIM == 3) {
+        if (L.op == NNMG_OP_ELASTICITY) {
+            // contribution slots only (no atomic variant), trilinear geometry
+            const OpTables<N, T> tb = make_tables<N, T>(L.basis);
+            hipLaunchKernelGGL((elasticity_kernel<N, T>), dim3((unsigned)L.nblocks), dim3(OpShape<3, N>::WG), 0, s,
+                               L.d_dofmap_blk.ptr, geo, (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, (T)L.lam,
+                               (T)L.mu);
+            NNMG_HIP(hipGetLastError());
+            return;
+        }
+    }
     if (mode == kTrilinear)
         vmult_launches<DIM, N, T, kTrilinear>(L, geo, atomic, src, dst, s);
     else
@@ -503,7 +776,7 @@ void launch_vmult_contrib(const Level& L, int prec, const void* src, void* contr
 }
 
 void launch_vmult_cells(const Level& L, int prec, const void* src, void* dst, hipStream_t s) {
-    if (L.atomic_scatter) {
+    if (L.atomic_scatter && L.op == NNMG_OP_LAPLACE) {
         launch_op(L, prec, true, src, dst, s);
     } else {
         launch_op(L, prec, false, src, L.d_contrib.ptr, s);

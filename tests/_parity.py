@@ -28,30 +28,39 @@ def match_dofs(lib_points: np.ndarray, orc_points: np.ndarray) -> np.ndarray:
 
 
 class Pair:
-    """One mesh level on both sides."""
+    """One mesh level on both sides (Laplace, or linear elasticity with
+    lam = mu = 1 and DoF 3 i + c for component c of node i on both sides)."""
 
-    def __init__(self, ctx, mesh, degree):
+    def __init__(self, ctx, mesh, degree, operator="laplace", lam=1.0, mu=1.0):
         import paper_2412_10910_amd as nn
         self.mesh = mesh
         self.k = degree
+        self.operator, self.lam, self.mu = operator, lam, mu
         self.orc = space.Space(mesh, degree)
-        self.lib = nn.Level.from_mesh(ctx, mesh, degree)
-        assert self.lib.n_dofs == self.orc.n_dofs
-        self.perm = match_dofs(self.lib.support_points(), self.orc.support_points)
-        assert np.array_equal(self.lib.constrained(), self.orc.constrained[self.perm])
+        self.lib = nn.Level.from_mesh(ctx, mesh, degree, operator, lam, mu)
+        self.nc = self.lib.ncomp
+        assert self.lib.n_dofs == self.orc.n_dofs * self.nc
+        node_perm = match_dofs(self.lib.support_points()[:: self.nc], self.orc.support_points)
+        self.perm = (self.nc * node_perm[:, None] + np.arange(self.nc)[None, :]).reshape(-1)
+        self.free = np.repeat(self.orc.free, self.nc)  # oracle order
+        assert np.array_equal(self.lib.constrained(), ~self.free[self.perm])
         self._A = None
 
     @property
     def A(self):
         if self._A is None:
-            self._A = assemble.stiffness(self.orc)
+            if self.operator == "elasticity":
+                from oracle import elasticity
+                self._A = elasticity.stiffness(self.orc, self.lam, self.mu)
+            else:
+                self._A = assemble.stiffness(self.orc)
         return self._A
 
     def to_lib(self, v_orc: np.ndarray, dtype=torch.float64) -> torch.Tensor:
         return torch.tensor(v_orc[self.perm], dtype=dtype, device=DEV)
 
     def to_orc(self, t: torch.Tensor) -> np.ndarray:
-        out = np.empty(self.orc.n_dofs)
+        out = np.empty(self.orc.n_dofs * self.nc)
         out[self.perm] = t.double().cpu().numpy()
         return out
 
@@ -62,15 +71,23 @@ def rel_err(a: np.ndarray, b: np.ndarray) -> float:
     return float(np.abs(a - b).max()) / (den if den > 0 else 1.0)
 
 
-def build_pairs(ctx, meshes, degree):
-    return [Pair(ctx, m, degree) for m in meshes]
+def build_pairs(ctx, meshes, degree, operator="laplace"):
+    return [Pair(ctx, m, degree, operator) for m in meshes]
+
+
+def oracle_prolongation(fine, coarse):
+    P = transfer.prolongation(fine.orc, coarse.orc)[0]
+    if fine.nc > 1:
+        from oracle import elasticity
+        P = elasticity.vector_prolongation(P, fine.nc)
+    return P
 
 
 def oracle_hierarchy(pairs, eig_start_orc, dtype=np.float64, bounds=None):
-    Ps = [transfer.prolongation(pairs[i + 1].orc, pairs[i].orc)[0] for i in range(len(pairs) - 1)]
-    return multigrid.Hierarchy([p.A for p in pairs], [p.orc.free for p in pairs], Ps, eig_start=eig_start_orc,
+    Ps = [oracle_prolongation(pairs[i + 1], pairs[i]) for i in range(len(pairs) - 1)]
+    return multigrid.Hierarchy([p.A for p in pairs], [p.free for p in pairs], Ps, eig_start=eig_start_orc,
                                bounds=bounds, dtype=dtype)
 
 
 def eig_starts(pairs, seed=100):
-    return [random_vector(p.orc.n_dofs, seed + i) for i, p in enumerate(pairs)]
+    return [random_vector(p.orc.n_dofs * p.nc, seed + i) for i, p in enumerate(pairs)]

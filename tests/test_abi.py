@@ -43,6 +43,9 @@ def test_defaults_without_a_gpu():
     m = _lib.MgOpts()
     lib.nnmg_default_mg_opts(C.byref(m))
     assert (m.cheb_degree, m.smoothing_range, m.eig_safety, m.eig_iters) == (3, 20.0, 1.2, 12)
+    lo = _lib.LevelOpts()
+    lib.nnmg_default_level_opts(C.byref(lo))
+    assert (lo.op, lo.lam, lo.mu) == (_lib.OP_LAPLACE, 1.0, 1.0)
     t = _lib.TransferOpts()
     lib.nnmg_default_transfer_opts(C.byref(t))
     assert (t.bbox_expand, t.inside_tol, t.newton_tol, t.newton_max_it, t.allow_projection) == \
