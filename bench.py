@@ -48,34 +48,50 @@ def percentile(xs, p):
 
 def vmult_bytes(level, word):
     """Algorithmic bytes of one operator application dst = A src: read src and
-    write dst (N words each), the int32 cell-to-DoF map (q per cell) and the
-    merged metric, d(d+1)/2 words per Gauss point (the stored-geometry form of
-    the operator; the library recomputes the trilinear metric instead, which
-    moves fewer bytes, so this is the method's figure, not a count of ours)."""
+    write dst (N words each), the int32 cell-to-node map (q per cell) and the
+    stored geometry per Gauss point: the merged metric, d(d+1)/2 words, for the
+    Laplacian; J^{-1} and w det J, d^2 + 1 words, for elasticity (the
+    stored-geometry form of the operator; the library rebuilds the geometry
+    from the trilinear map instead, which moves fewer bytes, so this is the
+    method's figure, not a count of ours)."""
     q = (level.degree + 1) ** level.dim
-    m = level.dim * (level.dim + 1) // 2
+    m = level.dim * (level.dim + 1) // 2 if level.ncomp == 1 else level.dim * level.dim + 1
     return 2 * word * level.n_dofs + 4 * level.n_cells * q + word * level.n_cells * q * m
 
 
 def transfer_bytes(coarse, n_points, word, prolong):
     """Algorithmic bytes of one prolongation (fine += P coarse) or restriction
     (coarse += P^T fine): per fine point its index (int32), its d reference
-    coordinates and the fine value (read and written for prolongation, read
-    for restriction); per coarse cell the two point-range offsets it reads,
-    its q int32 DoF indices and the q coarse values (read for prolongation,
-    read and written for restriction)."""
+    coordinates and the fine values of its nc components (read and written for
+    prolongation, read for restriction); per coarse cell the two point-range
+    offsets it reads, its q int32 node indices and the nc q coarse values (read
+    for prolongation, read and written for restriction)."""
     q = (coarse.degree + 1) ** coarse.dim
-    d = coarse.dim
-    per_point = 4 + d * word + (2 if prolong else 1) * word
-    per_cell = 8 + 4 * q + (1 if prolong else 2) * word * q
+    d, nc = coarse.dim, coarse.ncomp
+    per_point = 4 + d * word + (2 if prolong else 1) * nc * word
+    per_cell = 8 + 4 * q + (1 if prolong else 2) * nc * word * q
     return n_points * per_point + coarse.n_cells * per_cell
 
 
+# main-run workloads: config, cells per direction (coarse -> fine), degree,
+# operator, the oracle sample of the CPU baseline, and a description
+WORKLOADS = {
+    "cube_q2": dict(cfg=1, cells=[6, 13, 29, 64], degree=2, operator="laplace", cpu_cells=[3, 6, 13, 29],
+                    text="3D Poisson Q2 on the unit cube, non-nested perturbed hex levels 64^3/29^3/13^3/6^3 "
+                         "(+-0.15h), 8 Gaussian bumps, float64 V-cycle in float64 PCG to 1e-8"),
+    "beam_q2": dict(cfg=3, cells=[(14, 3, 3), (33, 7, 7), (80, 16, 16)], degree=2, operator="elasticity",
+                    cpu_cells=[(10, 2, 2), (22, 5, 5), (50, 10, 10)],
+                    text="3D linear elasticity, vector Q2, lambda = mu = 1, beam [0,5]x[0,1]^2 clamped at x = 0, "
+                         "body load (0,0,-1), non-nested perturbed hex levels 80x16x16/33x7x7/14x3x3 (+-0.1h), "
+                         "float64 V-cycle in float64 PCG to 1e-8"),
+}
+
 # level pairs (fine <- coarse) for --roofline-only: workload, cells per direction, degree
 ROOFLINE_WORKLOADS = {
-    "cube_q2_64": (1, [6, 13, 29, 64], 2),      # 64^3 <- 29^3, 2.1M DoFs
-    "ball_q3_96": (2, [5, 9, 19, 43, 96], 3),   # 96^3 <- 43^3, 24.1M DoFs
-    "ball_q4_75": ("2q4", [5, 7, 15, 34, 75], 4),  # 75^3 <- 34^3, 27.3M DoFs
+    "cube_q2_64": (1, [6, 13, 29, 64], 2, "laplace"),      # 64^3 <- 29^3, 2.1M DoFs
+    "ball_q3_96": (2, [5, 9, 19, 43, 96], 3, "laplace"),   # 96^3 <- 43^3, 24.1M DoFs
+    "ball_q4_75": ("2q4", [5, 7, 15, 34, 75], 4, "laplace"),  # 75^3 <- 34^3, 27.3M DoFs
+    "beam_q2": (3, [(14, 3, 3), (33, 7, 7), (80, 16, 16)], 2, "elasticity"),  # 525,987 DoFs
 }
 
 KERNEL_SOURCES = ("paper_2412_10910_amd/csrc/kernels/vmult.hip", "paper_2412_10910_amd/csrc/kernels/gather.hip",
@@ -159,7 +175,7 @@ def copy_calibration(nbytes=1 << 30):
     return nbytes
 
 
-def cpu_baseline(cells, cfg):
+def cpu_baseline(cells, cfg, operator="laplace"):
     """Oracle PCG on a reduced instance of the same workload recipe, 1 thread."""
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -168,20 +184,28 @@ def cpu_baseline(cells, cfg):
 import json, time, sys
 sys.path.insert(0, {ROOT!r})
 import numpy as np
-from oracle import assemble, multigrid, space, transfer
+from oracle import assemble, elasticity, multigrid, space, transfer
 from workloads import config_levels, config_source, random_vector
 meshes = config_levels({cfg!r}, cells={cells!r})
-k = {2}
+k = 2
 sps = [space.Space(m, k) for m in meshes]
-As = [assemble.stiffness(s) for s in sps]
-Ps = [transfer.prolongation(sps[i + 1], sps[i])[0] for i in range(len(sps) - 1)]
-H = multigrid.Hierarchy(As, [s.free for s in sps], Ps,
-                        eig_start=[random_vector(s.n_dofs, 100 + i) for i, s in enumerate(sps)])
-b = assemble.load_vector(sps[-1], config_source({cfg!r}))
+if {operator!r} == "elasticity":
+    nc = 3
+    As = [elasticity.stiffness(s, 1.0, 1.0) for s in sps]
+    Ps = [elasticity.vector_prolongation(transfer.prolongation(sps[i + 1], sps[i])[0], 3) for i in range(len(sps) - 1)]
+    frees = [elasticity.vector_free(s) for s in sps]
+    b = elasticity.load_vector(sps[-1], config_source({cfg!r}))
+else:
+    nc = 1
+    As = [assemble.stiffness(s) for s in sps]
+    Ps = [transfer.prolongation(sps[i + 1], sps[i])[0] for i in range(len(sps) - 1)]
+    frees = [s.free for s in sps]
+    b = assemble.load_vector(sps[-1], config_source({cfg!r}))
+H = multigrid.Hierarchy(As, frees, Ps, eig_start=[random_vector(s.n_dofs * nc, 100 + i) for i, s in enumerate(sps)])
 t0 = time.perf_counter()
 x, it, hist = H.pcg(b, rtol=1e-8)
 t = time.perf_counter() - t0
-print(json.dumps(dict(n=sps[-1].n_dofs, it=it, t=t)))
+print(json.dumps(dict(n=sps[-1].n_dofs * nc, it=it, t=t)))
 """
     t0 = time.perf_counter()
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
@@ -192,7 +216,7 @@ print(json.dumps(dict(n=sps[-1].n_dofs, it=it, t=t)))
     r = json.loads(out.stdout.strip().splitlines()[-1])
     return dict(value=round(r["n"] * r["it"] / r["t"] / 1e6, 4), unit=UNIT, cores=1, kind="oracle",
                 sample=(f"oracle float64 PCG + float64 V-cycle (scipy CSR) on the same recipe at "
-                        f"{'/'.join(str(c) for c in cells[::-1])} cells per direction "
+                        f"{' / '.join(str(c) for c in cells[::-1])} cells "
                         f"({r['n']} fine DoFs), {r['it']} iterations in {r['t']:.2f} s; "
                         f"setup excluded; {wall:.1f} s wall including setup"),
                 cpu=_cpu_model(), host_cpus=os.cpu_count())
@@ -219,6 +243,8 @@ def main():
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the operator/transfer kernel loops of the two finest levels and a copy of "
                          "known size (the run that rocprofv3 traces and counts)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="cube_q2",
+                    help="the PCG workload (default: the 3D Poisson cube the metric is quoted on)")
     ap.add_argument("--roofline-workload", choices=sorted(ROOFLINE_WORKLOADS), default="cube_q2_64",
                     help="level pair of --roofline-only")
     ap.add_argument("--geometry", choices=["trilinear", "metric"], default=None,
@@ -236,9 +262,8 @@ def main():
     import paper_2412_10910_amd as nn
     from workloads import config_levels, config_source
 
-    cfg = 1
-    cells = [6, 13, 29, 64]
-    degree = 2
+    wl = WORKLOADS[args.workload]
+    cfg, cells, degree, operator = wl["cfg"], wl["cells"], wl["degree"], wl["operator"]
     dev = "cuda:0"
     torch.cuda.init()
     ctx = nn.Context(0)
@@ -247,10 +272,10 @@ def main():
     meshes = config_levels(cfg, cells=cells) if not args.roofline_only else None
 
     if args.roofline_only:
-        rcfg, rcells, rdeg = ROOFLINE_WORKLOADS[args.roofline_workload]
+        rcfg, rcells, rdeg, rop = ROOFLINE_WORKLOADS[args.roofline_workload]
         rmeshes = config_levels(rcfg, cells=rcells)
-        fine = nn.Level.from_mesh(ctx, rmeshes[-1], rdeg)
-        coarse = nn.Level.from_mesh(ctx, rmeshes[-2], rdeg)
+        fine = nn.Level.from_mesh(ctx, rmeshes[-1], rdeg, rop)
+        coarse = nn.Level.from_mesh(ctx, rmeshes[-2], rdeg, rop)
         tr = nn.Transfer(ctx, fine, coarse)
         nbytes = copy_calibration()
         k = kernel_rooflines(fine, coarse, tr, args.roofline_reps)
@@ -260,7 +285,7 @@ def main():
         return
 
     t0 = time.perf_counter()
-    levels = [nn.Level.from_mesh(ctx, m, degree) for m in meshes]
+    levels = [nn.Level.from_mesh(ctx, m, degree, operator) for m in meshes]
     t_levels = time.perf_counter() - t0
     t0 = time.perf_counter()
     transfers = [nn.Transfer(ctx, levels[i + 1], levels[i]) for i in range(len(levels) - 1)]
@@ -300,7 +325,7 @@ def main():
 
     log("timing the operator and transfer kernels")
     k = kernel_rooflines(fine, levels[-2], transfers[-1], args.roofline_reps)
-    traffic = recorded_traffic()
+    traffic = recorded_traffic() if args.workload == "cube_q2" else {}
 
     profile = None
     if args.profile:
@@ -313,7 +338,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline([3, 6, 13, 29], cfg)
+        cpu = cpu_baseline(wl["cpu_cells"], cfg, operator)
 
     op = k["operator_fp64"]
 
@@ -336,8 +361,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "3D Poisson Q2 on the unit cube, non-nested perturbed hex levels "
-                        "64^3/29^3/13^3/6^3 (+-0.15h), 8 Gaussian bumps, float64 V-cycle in float64 PCG to 1e-8",
+            "workload": wl["text"],
             "fine_dofs": fine.n_dofs,
             "level_dofs": [lv.n_dofs for lv in levels],
             "iterations": its64[-1],
@@ -360,9 +384,10 @@ def main():
             "unit": "GB/s",
             "frac": round(op["frac"], 4),
             "traffic": traffic.get("operator_fp64"),
-            "kernel": "operator application on the 64^3 level, float64: vmult_kernel<3,3,double,1,0> "
-                      "(per-cell sum factorization) + gather_kernel<double> (per-DoF sum of the cell "
-                      "contributions), back to back on one stream",
+            "kernel": (f"operator application on the finest level ({fine.n_dofs} DoFs), float64: "
+                       + ("vmult_kernel<3,3,double,1,0>" if operator == "laplace" else "elasticity_kernel<3,double>")
+                       + " (per-cell sum factorization) + gather_kernel (per-DoF sum of the cell "
+                         "contributions), back to back on one stream"),
             "bytes_per_launch": op["bytes"],
             "ms_per_launch": round(op["ms"], 5),
             "kernels": {n: entry(n) for n in k},

@@ -273,9 +273,10 @@ int nnmg_set_cheb_bounds(nnmg_hierarchy* h, int level, double lo, double hi);
 
 /* z = V(r): one V-cycle on the finest level with a zero initial guess
  * (Algorithm V_cycle): Chebyshev-Jacobi pre-smoothing, residual, restriction,
- * recursion, exact float64 coarse solve plus one refinement step,
- * prolongation, post-smoothing from the current iterate.  r and z are vectors
- * of the finest level in `prec`.  Asynchronous. */
+ * recursion, exact float64 coarse solve (dense inverse of the unconstrained
+ * block; in a float64 cycle plus one refinement step whose residual uses the
+ * level's operator), prolongation, post-smoothing from the current iterate.
+ * r and z are vectors of the finest level in `prec`.  Asynchronous. */
 int nnmg_vcycle(nnmg_hierarchy* h, nnmg_prec prec, const void* r_dev, void* z_dev, void* stream);
 
 /* Float64 CG from x0 = 0 preconditioned by one V-cycle in opts->vcycle_prec

@@ -49,9 +49,8 @@ struct Hierarchy {
     // coarse solve
     int64_t m = 0;
     DeviceArray<int32_t> free_idx;
-    DeviceArray<double> inv, amat;  // m x m: A^{-1} and A on the unconstrained block
-    DeviceArray<double> bf, xf;     // [m] work vectors of the solve
-    DeviceArray<double> cx, cax;    // [N] unit vectors and operator columns at setup
+    DeviceArray<double> inv;        // m x m: A^{-1} on the unconstrained block
+    DeviceArray<double> cx, cax;    // [N] unit vectors and operator columns at setup; y and r of the solve
 
     WorkVectors work[2][16];  // [prec][level]
 
@@ -162,8 +161,6 @@ static void setup_coarse(Hierarchy& H) {
     for (auto* a : {&H.cx, &H.cax}) NNMG_HIP(hipMemset(a->ptr, 0, a->bytes()));
     if (m == 0) return;
     H.free_idx.upload(ctx, idx);
-    H.bf.alloc(ctx, m);
-    H.xf.alloc(ctx, m);
     H.inv.alloc(ctx, m * m);
     // columns of A on the unconstrained block: A e_j by the operator kernel
     for (size_t j = 0; j < m; ++j) {
@@ -173,9 +170,6 @@ static void setup_coarse(Hierarchy& H) {
         launch_fill(H.cax.ptr, N, NNMG_FP64, nullptr);
         launch_set_unit(H.cx.ptr, N, idx[j], 0.0, nullptr);
     }
-    // keep A (for the refinement step) before inverting in place
-    H.amat.alloc(ctx, m * m);
-    NNMG_HIP(hipMemcpy(H.amat.ptr, H.inv.ptr, m * m * sizeof(double), hipMemcpyDeviceToDevice));
     DeviceArray<double> rowbuf, colbuf;
     rowbuf.alloc(ctx, m);
     colbuf.alloc(ctx, m);
@@ -183,21 +177,28 @@ static void setup_coarse(Hierarchy& H) {
     NNMG_HIP(hipDeviceSynchronize());
 }
 
-// x = A_0^{-1} f (one refinement step), f and x in `prec`, the arithmetic in
-// float64 on the unconstrained block:
-//   y = A^{-1} f,  r = f - A y,  x = y + A^{-1} r
-// with the dense A and A^{-1} of the unconstrained block (three row-parallel
-// kernels that gather f and scatter x through the free-DoF list themselves)
+static void op_residual(Hierarchy& H, int l, int prec, const void* f, const void* x, void* r, hipStream_t s);
+
+// x = A_0^{-1} f on the unconstrained block with the dense float64 inverse
+// (row-parallel kernels that gather f and scatter x through the free-DoF list
+// themselves).  In float64, one refinement step:
+//   y = A^{-1} f,  r = f - A y (the level's own operator),  x = y + A^{-1} r.
+// In float32 the single product suffices: its error, cond(A) times the
+// float64 rounding, lies far below the float32 rounding of x.
 static void coarse_solve(Hierarchy& H, int prec, const void* f, void* x, hipStream_t s) {
     Level& C = *H.levels[0];
     const size_t N = (size_t)C.n_dofs, m = (size_t)H.m;
     launch_fill(x, N, prec, s);  // constrained entries
     if (m == 0) return;
     const int32_t* fi = H.free_idx.ptr;
-    launch_coarse_gemv(H.inv.ptr, m, f, prec, fi, nullptr, NNMG_FP64, nullptr, 1.0, H.xf.ptr, NNMG_FP64, nullptr, s);
-    launch_coarse_gemv(H.amat.ptr, m, H.xf.ptr, NNMG_FP64, nullptr, f, prec, fi, -1.0, H.bf.ptr, NNMG_FP64, nullptr,
-                       s);
-    launch_coarse_gemv(H.inv.ptr, m, H.bf.ptr, NNMG_FP64, nullptr, H.xf.ptr, NNMG_FP64, nullptr, 1.0, x, prec, fi, s);
+    if (prec == NNMG_FP32) {
+        launch_coarse_gemv(H.inv.ptr, m, f, prec, fi, nullptr, NNMG_FP64, nullptr, 1.0, x, prec, fi, s);
+        return;
+    }
+    // y into the unconstrained entries of cx, whose constrained entries stay zero
+    launch_coarse_gemv(H.inv.ptr, m, f, prec, fi, nullptr, NNMG_FP64, nullptr, 1.0, H.cx.ptr, NNMG_FP64, fi, s);
+    op_residual(H, 0, NNMG_FP64, f, H.cx.ptr, H.cax.ptr, s);
+    launch_coarse_gemv(H.inv.ptr, m, H.cax.ptr, NNMG_FP64, fi, H.cx.ptr, NNMG_FP64, fi, 1.0, x, prec, fi, s);
 }
 
 // ---------------------------------------------------------------------------

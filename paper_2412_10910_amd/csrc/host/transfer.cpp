@@ -19,7 +19,7 @@
 #include "../internal.hpp"
 
 #ifndef NNMG_RESTRICT_PTS_PER_LANE
-#define NNMG_RESTRICT_PTS_PER_LANE 8
+#define NNMG_RESTRICT_PTS_PER_LANE 4
 #endif
 
 namespace nnmg {
@@ -202,8 +202,9 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
         T->d_fine.upload(ctx, fidx);
         T->d_xi64.upload(ctx, xi64);
         T->d_xi32.upload(ctx, xi32);
-        // lane groups per coarse cell of the restriction: about avg / NNMG_RESTRICT_PTS_PER_LANE, 4..64
-        // (the kernel multiplies by the lanes that share a point)
+        // lanes per coarse cell and component of the restriction: about
+        // avg / NNMG_RESTRICT_PTS_PER_LANE, 4..64 (the kernel multiplies by the
+        // lanes that share a point)
         const double avg = C ? (double)np / (double)C : 0.0;
         const double per_lane = coarse->n <= 3 ? NNMG_RESTRICT_PTS_PER_LANE : 2 * NNMG_RESTRICT_PTS_PER_LANE;
         int team = 4;
@@ -211,7 +212,8 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
         // small coarse levels: more lanes per cell, so that the launch still
         // has enough wavefronts in flight to hide the memory latency (about
         // 1k; larger teams cost more in the cross-lane reduction)
-        while (team < 64 && (double)C * team < 65536.0 && 2 * team <= avg) team *= 2;
+        const double teams = (double)C * coarse->ncomp;
+        while (team < 64 && teams * team < 65536.0 && 2 * team <= avg) team *= 2;
         T->team = team;
     } catch (...) {
         level_release(T->fine);

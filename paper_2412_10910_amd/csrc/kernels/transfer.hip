@@ -327,14 +327,45 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
 #define NNMG_RESTRICT_UNROLL 4
 #endif
 
-// Restriction, one team of `team` = S * G lanes per coarse cell.  The G lane
+constexpr int next_pow2(int v) { return v <= 1 ? 1 : 2 * next_pow2((v + 1) / 2); }
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// Butterfly reduce-scatter of QP partial sums over the 2^levels lanes of a
+// lane group (lane bit j at distance S << j): at level j each lane keeps half
+// of the values it still holds, the upper half if its bit j is set, and adds
+// its partner's copy of that half, so the shuffles total about QP instead of
+// QP * levels.  After level j < log2(QP) a lane holds QP >> (j + 1) values;
+// value i then stands for output i + sum_j bit_j * (QP >> (j + 1)).  Levels
+// beyond log2(QP) sum the single value left.
+template <int QP, int J, int JMAX, class T>
+__device__ __forceinline__ void butterfly_reduce(T (&R)[QP], int g, int S, int levels, int width) {
+    if constexpr (J < JMAX) {
+        if (J < levels) {
+            constexpr int H = QP >> (J + 1);
+            const int o = S << J;
+            if constexpr (H >= 1) {
+                const bool hi = (g >> J) & 1;
+#pragma unroll
+                for (int i = 0; i < H; ++i) {
+                    const T send = hi ? R[i] : R[i + H];
+                    const T keep = hi ? R[i + H] : R[i];
+                    R[i] = keep + __shfl_xor(send, o, width);
+                }
+            } else {
+                R[0] += __shfl_xor(R[0], o, width);
+            }
+            butterfly_reduce<QP, J + 1, JMAX, T>(R, g, S, levels, width);
+        }
+    }
+}
+
+// Restriction, one team of `team` = S * G lanes per coarse cell and
+// component (vector DoF NC i + c; NC = 1 for the Laplacian).  The G lane
 // groups split the cell's points; the S lanes of a group read the same points
 // and split the cell's q outputs by the slowest reference index (z in 3D, y in
 // 2D): lane s owns the NS = ceil(N / S) slices starting at s * NS, so that
-// only q / S accumulators live in registers.  The groups are reduced by
-// cross-lane shuffles and the sums are stored to their slots.
-// With NC components per node the cell is processed once per component
-// (vector DoF NC i + c); the sums of slot k go to rbuf[NC k + c].
+// only q / S accumulators live in registers.  The groups are reduced by the
+// butterfly above and the sums of slot k go to rbuf[NC k + c].
 template <int DIM, int N, int NC, class T, int S>
 __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ fine,
@@ -346,27 +377,31 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
     constexpr int NS = (N + S - 1) / S;      // slowest-index slices per lane
     constexpr int SLICE = Q / N;             // outputs per slice
     constexpr int QL = NS * SLICE;           // outputs per lane
+    constexpr int QP = next_pow2(QL);        // padded for the butterfly
+    constexpr int LQ = ilog2(QP);
+    constexpr int JMAX = ilog2(64 / S);      // group levels of a 64-lane team
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t K = gid >> team_log2;
+    const int64_t KC = gid >> team_log2;     // (cell, component) pair
     const int team = 1 << team_log2;
     const int t = (int)(gid & (team - 1));
     const int s = t % S, g = t / S, G = team / S;
-    // K and the point range are uniform over a team, so whole teams leave together
-    if (K >= ncells) return;
+    const int levels = team_log2 - ilog2(S);
+    // KC and the point range are uniform over a team, so whole teams leave together
+    if (KC >= (int64_t)ncells * NC) return;
+    const int64_t K = NC == 1 ? KC : KC / NC;
+    const int comp = NC == 1 ? 0 : (int)(KC - K * NC);
     const int p0 = off[K], p1 = off[K + 1];
     if (p0 == p1) {
         // a cell without points contributes zeros
         for (int a = t; a < Q; a += team) {
             const int k = rslot[K * Q + a];
-            if (k >= 0)
-                for (int c = 0; c < NC; ++c) rbuf[(int64_t)k * NC + c] = T(0);
+            if (k >= 0) rbuf[(int64_t)k * NC + comp] = T(0);
         }
         return;
     }
-    for (int comp = 0; comp < NC; ++comp) {
-    T R[QL];
+    T R[QP];
 #pragma unroll
-    for (int a = 0; a < QL; ++a) R[a] = T(0);
+    for (int a = 0; a < QP; ++a) R[a] = T(0);
     // U points per group and round: all their loads are issued before any use
     constexpr int U = NNMG_RESTRICT_UNROLL;
     for (int base = p0 + g; base < p1; base += U * G) {
@@ -419,19 +454,23 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
             }
         }
     }
-    for (int o = G >> 1; o > 0; o >>= 1) {
+    butterfly_reduce<QP, 0, JMAX, T>(R, g, S, levels, team);
+    // the values this lane holds and the output they stand for
+    const int held = levels < LQ ? (QP >> levels) : 1;
+    int first = 0;
 #pragma unroll
-        for (int a = 0; a < QL; ++a) R[a] += __shfl_xor(R[a], o * S, team);
-    }
-    // output i of lane s is local node s * QL + i; group g writes every G-th
+    for (int j = 0; j < LQ; ++j)
+        if (j < levels && ((g >> j) & 1)) first += QP >> (j + 1);
+    // past log2(QP) levels the lanes that differ in the higher bits hold copies
+    if (levels > LQ && (g >> LQ) != 0) return;
 #pragma unroll
-    for (int i = 0; i < QL; ++i) {
-        const int node = s * QL + i;
-        if ((i % G) == g && node < Q) {
+    for (int i = 0; i < QP; ++i) {
+        const int o = first + i;
+        const int node = s * QL + o;
+        if (i < held && o < QL && node < Q) {
             const int k = rslot[K * Q + node];
             if (k >= 0) rbuf[(int64_t)k * NC + comp] = R[i];
         }
-    }
     }
 }
 
@@ -478,7 +517,7 @@ static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, con
     constexpr int S = DIM == 3 ? restrict_split<N, T>() : 1;
     const int team = std::max(tr.team, S);
     const int threads = 256;
-    const int64_t total = C.n_cells * (int64_t)team;
+    const int64_t total = C.n_cells * (int64_t)NC * team;
     const dim3 grid((unsigned)((total + threads - 1) / threads));
     hipLaunchKernelGGL((restrict_kernel<DIM, N, NC, T, S>), grid, dim3(threads), 0, s, tr.d_off.ptr, tr.d_fine.ptr, xi,
                        tr.n_points, tr.d_rslot.ptr, (const T*)in, (T*)tr.d_rbuf.ptr, (int)C.n_cells,

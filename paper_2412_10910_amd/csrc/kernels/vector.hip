@@ -368,6 +368,8 @@ void launch_coarse_gemv(const double* M, size_t m, const void* V, int vprec, con
     else if (!v64 && b64 && o64) coarse_gemv_t<float, double, double>(M, m, V, vidx, B, bidx, sign, O, oidx, s);
     else if (v64 && !b64 && o64) coarse_gemv_t<double, float, double>(M, m, V, vidx, B, bidx, sign, O, oidx, s);
     else if (v64 && b64 && !o64) coarse_gemv_t<double, double, float>(M, m, V, vidx, B, bidx, sign, O, oidx, s);
+    else if (!v64 && !o64 && B == nullptr)
+        coarse_gemv_t<float, double, float>(M, m, V, vidx, nullptr, nullptr, sign, O, oidx, s);
     else fail(NNMG_ERR_INVALID_ARG, "coarse_gemv precision combination");
     NNMG_HIP(hipGetLastError());
 }

@@ -144,7 +144,8 @@ def test_graph_replays_match_eager_launches(ctx):
 def test_coarse_solve_alone(ctx, cfg, cells, k):
     """With one level the V-cycle is the coarse solve: A^{-1} r (float64, one
     refinement step) against a dense solve of the oracle's reduced system,
-    and the float32 V-cycle (float64 solve, float32 input and output)."""
+    and the float32 V-cycle (float64 inverse applied once, float32 input and
+    output)."""
     import paper_2412_10910_amd as nn
     from _parity import Pair
     (m,) = config_levels(cfg, cells=cells)
