@@ -46,28 +46,30 @@ def percentile(xs, p):
     return s[min(k, len(s)) - 1]
 
 
-def vmult_bytes(level, word):
+def vmult_bytes(level, word, nr=1):
     """Algorithmic bytes of one operator application dst = A src: read src and
     write dst (N words each), the int32 cell-to-node map (q per cell) and the
     stored geometry per Gauss point: the merged metric, d(d+1)/2 words, for the
     Laplacian; J^{-1} and w det J, d^2 + 1 words, for elasticity (the
     stored-geometry form of the operator; the library rebuilds the geometry
     from the trilinear map instead, which moves fewer bytes, so this is the
-    method's figure, not a count of ours)."""
+    method's figure, not a count of ours).  With nr fused right-hand sides the
+    vectors count nr times, the map and the geometry once."""
     q = (level.degree + 1) ** level.dim
     m = level.dim * (level.dim + 1) // 2 if level.ncomp == 1 else level.dim * level.dim + 1
-    return 2 * word * level.n_dofs + 4 * level.n_cells * q + word * level.n_cells * q * m
+    return 2 * word * level.n_dofs * nr + 4 * level.n_cells * q + word * level.n_cells * q * m
 
 
-def transfer_bytes(coarse, n_points, word, prolong):
+def transfer_bytes(coarse, n_points, word, prolong, nr=1):
     """Algorithmic bytes of one prolongation (fine += P coarse) or restriction
     (coarse += P^T fine): per fine point its index (int32), its d reference
     coordinates and the fine values of its nc components (read and written for
     prolongation, read for restriction); per coarse cell the two point-range
     offsets it reads, its q int32 node indices and the nc q coarse values (read
-    for prolongation, read and written for restriction)."""
+    for prolongation, read and written for restriction); values nr times with
+    nr fused right-hand sides."""
     q = (coarse.degree + 1) ** coarse.dim
-    d, nc = coarse.dim, coarse.ncomp
+    d, nc = coarse.dim, coarse.ncomp * nr
     per_point = 4 + d * word + (2 if prolong else 1) * nc * word
     per_cell = 8 + 4 * q + (1 if prolong else 2) * nc * word * q
     return n_points * per_point + coarse.n_cells * per_cell
@@ -79,10 +81,11 @@ WORKLOADS = {
     "cube_q2": dict(cfg=1, cells=[6, 13, 29, 64], degree=2, operator="laplace", cpu_cells=[3, 6, 13, 29],
                     text="3D Poisson Q2 on the unit cube, non-nested perturbed hex levels 64^3/29^3/13^3/6^3 "
                          "(+-0.15h), 8 Gaussian bumps, float64 V-cycle in float64 PCG to 1e-8"),
-    "beam_q2": dict(cfg=3, cells=[(14, 3, 3), (33, 7, 7), (80, 16, 16)], degree=2, operator="elasticity",
+    "beam_q2": dict(cfg=3, cells=[(14, 3, 3), (33, 7, 7), (80, 16, 16)], degree=2, operator="elasticity", rhs=4,
                     cpu_cells=[(10, 2, 2), (22, 5, 5), (50, 10, 10)],
                     text="3D linear elasticity, vector Q2, lambda = mu = 1, beam [0,5]x[0,1]^2 clamped at x = 0, "
-                         "body load (0,0,-1), non-nested perturbed hex levels 80x16x16/33x7x7/14x3x3 (+-0.1h), "
+                         "body load (0,0,-1) and three random smooth loads fused as 4 right-hand sides, "
+                         "non-nested perturbed hex levels 80x16x16/33x7x7/14x3x3 (+-0.1h), "
                          "float64 V-cycle in float64 PCG to 1e-8"),
 }
 
@@ -140,23 +143,28 @@ def time_launches(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def kernel_rooflines(fine, coarse, transfer, reps):
-    """Operator and transfer kernels of the two finest levels, FP64 and FP32."""
+def kernel_rooflines(fine, coarse, transfer, reps, nr=1):
+    """Operator and transfer kernels of the two finest levels, FP64 and FP32;
+    with nr > 1 also the launches that carry nr right-hand sides (suffix _x<nr>)."""
     import torch
     dev = "cuda:0"
     npts = transfer.n_points
     out = {}
     for dt, word, tag in ((torch.float64, 8, "fp64"), (torch.float32, 4, "fp32")):
-        src = torch.rand(fine.n_dofs, dtype=torch.float64, device=dev).to(dt)
-        dst = torch.zeros_like(src)
-        csrc = torch.rand(coarse.n_dofs, dtype=torch.float64, device=dev).to(dt)
-        cdst = torch.zeros_like(csrc)
-        ms = time_launches(lambda: fine.vmult_add(src, dst), reps)
-        out[f"operator_{tag}"] = dict(ms=ms, bytes=vmult_bytes(fine, word))
-        ms = time_launches(lambda: transfer.prolongate(csrc, dst), reps)
-        out[f"prolongate_{tag}"] = dict(ms=ms, bytes=transfer_bytes(coarse, npts, word, True))
-        ms = time_launches(lambda: transfer.restrict(src, cdst), reps)
-        out[f"restrict_{tag}"] = dict(ms=ms, bytes=transfer_bytes(coarse, npts, word, False))
+        for r in sorted({1, nr}):
+            sfx = "" if r == 1 else f"_x{r}"
+            shape_f = (fine.n_dofs,) if r == 1 else (fine.n_dofs, r)
+            shape_c = (coarse.n_dofs,) if r == 1 else (coarse.n_dofs, r)
+            src = torch.rand(shape_f, dtype=torch.float64, device=dev).to(dt)
+            dst = torch.zeros_like(src)
+            csrc = torch.rand(shape_c, dtype=torch.float64, device=dev).to(dt)
+            cdst = torch.zeros_like(csrc)
+            ms = time_launches(lambda: fine.vmult_add(src, dst), reps)
+            out[f"operator_{tag}{sfx}"] = dict(ms=ms, bytes=vmult_bytes(fine, word, r))
+            ms = time_launches(lambda: transfer.prolongate(csrc, dst), reps)
+            out[f"prolongate_{tag}{sfx}"] = dict(ms=ms, bytes=transfer_bytes(coarse, npts, word, True, r))
+            ms = time_launches(lambda: transfer.restrict(src, cdst), reps)
+            out[f"restrict_{tag}{sfx}"] = dict(ms=ms, bytes=transfer_bytes(coarse, npts, word, False, r))
     for v in out.values():
         v["gbs"] = v["bytes"] / (v["ms"] * 1e-3) / 1e9
         v["frac"] = v["gbs"] / HBM_PEAK_GBS
@@ -245,6 +253,8 @@ def main():
                          "known size (the run that rocprofv3 traces and counts)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="cube_q2",
                     help="the PCG workload (default: the 3D Poisson cube the metric is quoted on)")
+    ap.add_argument("--rhs", type=int, default=None,
+                    help="right-hand sides fused per solve (default: the workload's, 1 for the cube, 4 for the beam)")
     ap.add_argument("--roofline-workload", choices=sorted(ROOFLINE_WORKLOADS), default="cube_q2_64",
                     help="level pair of --roofline-only")
     ap.add_argument("--geometry", choices=["trilinear", "metric"], default=None,
@@ -260,7 +270,7 @@ def main():
     import torch
 
     import paper_2412_10910_amd as nn
-    from workloads import config_levels, config_source
+    from workloads import config_levels, config_source, random_load
 
     wl = WORKLOADS[args.workload]
     cfg, cells, degree, operator = wl["cfg"], wl["cells"], wl["degree"], wl["operator"]
@@ -294,8 +304,14 @@ def main():
     H = nn.Hierarchy(ctx, levels, transfers)
     t_hier = time.perf_counter() - t0
     fine = levels[-1]
-    f = config_source(cfg)
-    b = fine.assemble_rhs(torch.tensor(f(fine.quadrature_points()).reshape(-1), dtype=torch.float64, device=dev))
+    nr = args.rhs if args.rhs is not None else wl.get("rhs", 1)
+    if operator == "elasticity":
+        srcs = [config_source(cfg)] + [random_load(i) for i in range(1, nr)]
+    else:
+        srcs = [config_source(cfg, i) for i in range(nr)]
+    qp = fine.quadrature_points()
+    cols = [fine.assemble_rhs(torch.tensor(f(qp).reshape(-1), dtype=torch.float64, device=dev)) for f in srcs]
+    b = cols[0] if nr == 1 else torch.stack(cols, dim=1).contiguous()
     x = torch.empty_like(b)
     torch.cuda.synchronize()
     log(f"setup: levels {t_levels:.2f} s, transfers {t_transfers:.2f} s, hierarchy {t_hier:.2f} s; "
@@ -311,7 +327,10 @@ def main():
             t1 = time.perf_counter()
             _, info = H.pcg_solve(b, x, rtol=1e-8, vcycle_dtype=dtype, history=False)
             lat.append(time.perf_counter() - t1)
-            its.append(info["iterations"])
+            infos = info if isinstance(info, list) else [info]
+            its.append(sum(i["iterations"] for i in infos))
+            info = dict(iterations=[i["iterations"] for i in infos] if nr > 1 else infos[0]["iterations"],
+                        relres=max(i["relres"] for i in infos))
         torch.cuda.synchronize()
         total = time.perf_counter() - t_start
         return total, lat, its, info
@@ -324,7 +343,7 @@ def main():
     value32 = fine.n_dofs * sum(its32) / tot32 / 1e6
 
     log("timing the operator and transfer kernels")
-    k = kernel_rooflines(fine, levels[-2], transfers[-1], args.roofline_reps)
+    k = kernel_rooflines(fine, levels[-2], transfers[-1], args.roofline_reps, nr)
     traffic = recorded_traffic() if args.workload == "cube_q2" else {}
 
     profile = None
@@ -340,7 +359,8 @@ def main():
         log("timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(wl["cpu_cells"], cfg, operator)
 
-    op = k["operator_fp64"]
+    op_key = "operator_fp64" if nr == 1 else f"operator_fp64_x{nr}"
+    op = k[op_key]
 
     def entry(name):
         v = k[name]
@@ -364,13 +384,14 @@ def main():
             "workload": wl["text"],
             "fine_dofs": fine.n_dofs,
             "level_dofs": [lv.n_dofs for lv in levels],
-            "iterations": its64[-1],
+            "rhs": nr,
+            "iterations": info64["iterations"],
         },
         "latency_ms": {"p50": round(percentile(lat64, 50) * 1e3, 4), "p99": round(percentile(lat64, 99) * 1e3, 4)},
         "fp32_mg": {
             "value": round(value32, 2),
             "ms_per_step": round(tot32 / args.steps * 1e3, 4),
-            "iterations": its32[-1],
+            "iterations": info32["iterations"],
             "relres": info32["relres"],
             "latency_ms": {"p50": round(percentile(lat32, 50) * 1e3, 4),
                            "p99": round(percentile(lat32, 99) * 1e3, 4)},
@@ -383,9 +404,11 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(op["frac"], 4),
-            "traffic": traffic.get("operator_fp64"),
-            "kernel": (f"operator application on the finest level ({fine.n_dofs} DoFs), float64: "
-                       + ("vmult_kernel<3,3,double,1,0>" if operator == "laplace" else "elasticity_kernel<3,double>")
+            "traffic": traffic.get(op_key),
+            "kernel": (f"operator application on the finest level ({fine.n_dofs} DoFs"
+                       + (f", {nr} fused right-hand sides" if nr > 1 else "") + "), float64: "
+                       + (f"vmult_kernel<3,3,double,1,0,{1 if nr == 1 else 0}>" if operator == "laplace"
+                          else f"elasticity_kernel<3,double,{1 if nr == 1 else 0}>")
                        + " (per-cell sum factorization) + gather_kernel (per-DoF sum of the cell "
                          "contributions), back to back on one stream"),
             "bytes_per_launch": op["bytes"],

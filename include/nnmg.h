@@ -217,6 +217,20 @@ int nnmg_vmult(const nnmg_level* level, nnmg_prec prec, const void* src_dev, voi
  * not alias.  Asynchronous. */
 int nnmg_vmult_add(const nnmg_level* level, nnmg_prec prec, const void* src_dev, void* dst_dev, void* stream);
 
+/* Several right-hand sides.  The _multi calls apply the operation of their
+ * single-vector counterpart to nrhs vectors (1 <= nrhs <= 8) at once, in one
+ * set of launches that reads the level's indices and geometry once for all of
+ * them.  Vectors are interleaved: entry i of right-hand side r is element
+ * i * nrhs + r of a [n_dofs][nrhs] array (n_dofs * nrhs entries).  Each
+ * right-hand side gets exactly the arithmetic of a single-vector call.  The
+ * first call with a larger nrhs than before grows the object's internal
+ * buffers and synchronizes the device.  Errors: INVALID_ARG for nrhs out of
+ * range, as the single-vector calls otherwise. */
+int nnmg_vmult_multi(const nnmg_level* level, nnmg_prec prec, int nrhs, const void* src_dev, void* dst_dev,
+                     void* stream);
+int nnmg_vmult_add_multi(const nnmg_level* level, nnmg_prec prec, int nrhs, const void* src_dev, void* dst_dev,
+                         void* stream);
+
 /* Diagonal of A_l (1 on constrained rows) into diag_dev.  Asynchronous. */
 int nnmg_level_diagonal(const nnmg_level* level, nnmg_prec prec, void* diag_dev, void* stream);
 
@@ -249,10 +263,20 @@ int nnmg_transfer_points(const nnmg_transfer* transfer, int64_t* n_points, int32
 int nnmg_prolongate(const nnmg_transfer* transfer, nnmg_prec prec, const void* coarse_dev,
                     void* fine_dev_add, void* stream);
 
-/* coarse += P^T fine (paper §2, eq. residual2), an atomic scatter-add.  Only
- * unconstrained coarse entries change.  Asynchronous. */
+/* coarse += P^T fine (paper §2, eq. residual2): per coarse cell the sums over
+ * its points go to slots sorted by coarse DoF, which are then added in a fixed
+ * order (deterministic, no float atomics).  Only unconstrained coarse entries
+ * change.  Uses the transfer's own slot buffer: calls on one transfer must not
+ * overlap.  Asynchronous. */
 int nnmg_restrict(const nnmg_transfer* transfer, nnmg_prec prec, const void* fine_dev,
                   void* coarse_dev_add, void* stream);
+
+/* nnmg_prolongate / nnmg_restrict for nrhs interleaved right-hand sides (see
+ * nnmg_vmult_multi for the layout and the limits). */
+int nnmg_prolongate_multi(const nnmg_transfer* transfer, nnmg_prec prec, int nrhs, const void* coarse_dev,
+                          void* fine_dev_add, void* stream);
+int nnmg_restrict_multi(const nnmg_transfer* transfer, nnmg_prec prec, int nrhs, const void* fine_dev,
+                        void* coarse_dev_add, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Hierarchy, V-cycle and PCG (paper §2 Algorithm V_cycle; §4 recipe)          */
@@ -279,6 +303,10 @@ int nnmg_set_cheb_bounds(nnmg_hierarchy* h, int level, double lo, double hi);
  * r and z are vectors of the finest level in `prec`.  Asynchronous. */
 int nnmg_vcycle(nnmg_hierarchy* h, nnmg_prec prec, const void* r_dev, void* z_dev, void* stream);
 
+/* nnmg_vcycle for nrhs interleaved right-hand sides (layout and limits as for
+ * nnmg_vmult_multi): one V-cycle whose every launch carries all of them. */
+int nnmg_vcycle_multi(nnmg_hierarchy* h, nnmg_prec prec, int nrhs, const void* r_dev, void* z_dev, void* stream);
+
 /* Float64 CG from x0 = 0 preconditioned by one V-cycle in opts->vcycle_prec
  * (paper §4: V-cycle in single, CG in double precision).  b_dev and x_dev are
  * float64 vectors of the finest level.  Synchronous.  Returns NNMG_OK,
@@ -286,6 +314,18 @@ int nnmg_vcycle(nnmg_hierarchy* h, nnmg_prec prec, const void* r_dev, void* z_de
  * x_dev then holds the last iterate). */
 int nnmg_pcg_solve(nnmg_hierarchy* h, const double* b_dev, double* x_dev, const nnmg_cg_opts* opts,
                    nnmg_cg_result* res, void* stream);
+
+/* nrhs independent CG solves run in lockstep, one preconditioner V-cycle and
+ * one operator product for all of them per iteration (b_dev, x_dev
+ * interleaved as for nnmg_vmult_multi).  Each right-hand side keeps its own
+ * scalars and stopping test; once it has converged (or broken down) it is
+ * frozen, so its x and iteration count are those of nnmg_pcg_solve on it
+ * alone, while the others go on.  res: host [nrhs]; opts->history, if set:
+ * host [nrhs][max_it + 1].  Returns NNMG_ERR_BREAKDOWN if any right-hand side
+ * broke down, else NNMG_ERR_NOT_CONVERGED if any did not converge, else
+ * NNMG_OK.  Synchronous. */
+int nnmg_pcg_solve_multi(nnmg_hierarchy* h, int nrhs, const double* b_dev, double* x_dev,
+                         const nnmg_cg_opts* opts, nnmg_cg_result* res, void* stream);
 
 /* Per-component times: when enabled, every V-cycle records HIP events around
  * its components.  nnmg_hierarchy_profile writes the accumulated milliseconds

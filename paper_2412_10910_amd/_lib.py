@@ -115,6 +115,8 @@ SIGNATURES = {
     "nnmg_level_assemble_rhs": (C.c_int, [_vp, _vp, _vp, _vp]),
     "nnmg_vmult": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "nnmg_vmult_add": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "nnmg_vmult_multi": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp]),
+    "nnmg_vmult_add_multi": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp]),
     "nnmg_level_diagonal": (C.c_int, [_vp, C.c_int, _vp, _vp]),
     "nnmg_transfer_create": (C.c_int, [_vp, _vp, _vp, C.POINTER(TransferOpts), C.POINTER(_vp)]),
     "nnmg_transfer_destroy": (None, [_vp]),
@@ -122,13 +124,17 @@ SIGNATURES = {
                                        C.POINTER(C.c_double), _i64p]),
     "nnmg_prolongate": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "nnmg_restrict": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "nnmg_prolongate_multi": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp]),
+    "nnmg_restrict_multi": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp]),
     "nnmg_hierarchy_create": (C.c_int, [_vp, C.POINTER(_vp), C.c_int, C.POINTER(_vp), C.POINTER(MgOpts),
                                         C.POINTER(_vp)]),
     "nnmg_hierarchy_destroy": (None, [_vp]),
     "nnmg_get_cheb_bounds": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "nnmg_set_cheb_bounds": (C.c_int, [_vp, C.c_int, C.c_double, C.c_double]),
     "nnmg_vcycle": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "nnmg_vcycle_multi": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp]),
     "nnmg_pcg_solve": (C.c_int, [_vp, _vp, _vp, C.POINTER(CgOpts), C.POINTER(CgResult), _vp]),
+    "nnmg_pcg_solve_multi": (C.c_int, [_vp, C.c_int, _vp, _vp, C.POINTER(CgOpts), C.POINTER(CgResult), _vp]),
     "nnmg_hierarchy_set_profiling": (C.c_int, [_vp, C.c_int]),
     "nnmg_hierarchy_profile": (C.c_int, [_vp, C.POINTER(C.c_double)]),
 }

@@ -38,6 +38,18 @@ def _vec(t: torch.Tensor, n: int, device: int, dtype=None, name="vector") -> C.c
     return C.c_void_p(t.data_ptr())
 
 
+def _nrhs(t: torch.Tensor, n: int, name="vector") -> int:
+    """Right-hand sides of a vector argument: 1 for shape [n], r for [n, r]
+    (a contiguous [n][r] tensor is the library's interleaved layout)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dim() == 1:
+        return 1
+    if t.dim() == 2 and t.shape[0] == n:
+        return int(t.shape[1])
+    raise ValueError(f"{name} must have shape [{n}] or [{n}, nrhs], got {tuple(t.shape)}")
+
+
 class Context:
     """Binds the library to one GPU.
 
@@ -169,21 +181,30 @@ class Level:
         return b
 
     def vmult(self, src: torch.Tensor, dst: torch.Tensor | None = None) -> torch.Tensor:
+        """dst = A src; src of shape [n_dofs] or [n_dofs, nrhs] (several right-hand sides)."""
         dst = torch.empty_like(src) if dst is None else dst
-        if dst.dtype != src.dtype:
-            raise ValueError("src and dst must have the same dtype")
-        s = _vec(src, self.n_dofs, self.ctx.device, name="src")
-        d = _vec(dst, self.n_dofs, self.ctx.device, name="dst")
-        check(lib().nnmg_vmult(self.handle, _DTYPE_PREC[src.dtype], s, d, _stream()))
+        if dst.dtype != src.dtype or dst.shape != src.shape:
+            raise ValueError("src and dst must have the same dtype and shape")
+        nr = _nrhs(src, self.n_dofs, "src")
+        s = _vec(src, self.n_dofs * nr, self.ctx.device, name="src")
+        d = _vec(dst, self.n_dofs * nr, self.ctx.device, name="dst")
+        if src.dim() == 1:
+            check(lib().nnmg_vmult(self.handle, _DTYPE_PREC[src.dtype], s, d, _stream()))
+        else:
+            check(lib().nnmg_vmult_multi(self.handle, _DTYPE_PREC[src.dtype], nr, s, d, _stream()))
         return dst
 
     def vmult_add(self, src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:
         """dst += A src over the unconstrained rows and columns (one kernel launch)."""
-        if dst.dtype != src.dtype:
-            raise ValueError("src and dst must have the same dtype")
-        s = _vec(src, self.n_dofs, self.ctx.device, name="src")
-        d = _vec(dst, self.n_dofs, self.ctx.device, name="dst")
-        check(lib().nnmg_vmult_add(self.handle, _DTYPE_PREC[src.dtype], s, d, _stream()))
+        if dst.dtype != src.dtype or dst.shape != src.shape:
+            raise ValueError("src and dst must have the same dtype and shape")
+        nr = _nrhs(src, self.n_dofs, "src")
+        s = _vec(src, self.n_dofs * nr, self.ctx.device, name="src")
+        d = _vec(dst, self.n_dofs * nr, self.ctx.device, name="dst")
+        if src.dim() == 1:
+            check(lib().nnmg_vmult_add(self.handle, _DTYPE_PREC[src.dtype], s, d, _stream()))
+        else:
+            check(lib().nnmg_vmult_add_multi(self.handle, _DTYPE_PREC[src.dtype], nr, s, d, _stream()))
         return dst
 
     def diagonal(self, dtype=torch.float64) -> torch.Tensor:
@@ -239,22 +260,34 @@ class Transfer:
                                          xi.ctypes.data_as(C.POINTER(C.c_double)), None))
         return dict(fine_dof=dof, owner=own, xi=xi, n_projected=npj.value)
 
-    def prolongate(self, coarse_vec: torch.Tensor, fine_vec: torch.Tensor) -> torch.Tensor:
-        """fine_vec += P coarse_vec."""
+    def _pair(self, coarse_vec, fine_vec):
         if coarse_vec.dtype != fine_vec.dtype:
             raise ValueError("dtype mismatch")
-        check(lib().nnmg_prolongate(self.handle, _DTYPE_PREC[coarse_vec.dtype],
-                                    _vec(coarse_vec, self.coarse.n_dofs, self.ctx.device, name="coarse"),
-                                    _vec(fine_vec, self.fine.n_dofs, self.ctx.device, name="fine"), _stream()))
+        nr = _nrhs(coarse_vec, self.coarse.n_dofs, "coarse")
+        if _nrhs(fine_vec, self.fine.n_dofs, "fine") != nr or coarse_vec.dim() != fine_vec.dim():
+            raise ValueError("coarse and fine carry different numbers of right-hand sides")
+        c = _vec(coarse_vec, self.coarse.n_dofs * nr, self.ctx.device, name="coarse")
+        f = _vec(fine_vec, self.fine.n_dofs * nr, self.ctx.device, name="fine")
+        return nr, c, f
+
+    def prolongate(self, coarse_vec: torch.Tensor, fine_vec: torch.Tensor) -> torch.Tensor:
+        """fine_vec += P coarse_vec (shapes [n] or [n, nrhs])."""
+        nr, c, f = self._pair(coarse_vec, fine_vec)
+        prec = _DTYPE_PREC[coarse_vec.dtype]
+        if coarse_vec.dim() == 1:
+            check(lib().nnmg_prolongate(self.handle, prec, c, f, _stream()))
+        else:
+            check(lib().nnmg_prolongate_multi(self.handle, prec, nr, c, f, _stream()))
         return fine_vec
 
     def restrict(self, fine_vec: torch.Tensor, coarse_vec: torch.Tensor) -> torch.Tensor:
-        """coarse_vec += P^T fine_vec."""
-        if coarse_vec.dtype != fine_vec.dtype:
-            raise ValueError("dtype mismatch")
-        check(lib().nnmg_restrict(self.handle, _DTYPE_PREC[fine_vec.dtype],
-                                  _vec(fine_vec, self.fine.n_dofs, self.ctx.device, name="fine"),
-                                  _vec(coarse_vec, self.coarse.n_dofs, self.ctx.device, name="coarse"), _stream()))
+        """coarse_vec += P^T fine_vec (shapes [n] or [n, nrhs])."""
+        nr, c, f = self._pair(coarse_vec, fine_vec)
+        prec = _DTYPE_PREC[fine_vec.dtype]
+        if fine_vec.dim() == 1:
+            check(lib().nnmg_restrict(self.handle, prec, f, c, _stream()))
+        else:
+            check(lib().nnmg_restrict_multi(self.handle, prec, nr, f, c, _stream()))
         return coarse_vec
 
 
@@ -316,38 +349,56 @@ class Hierarchy:
         check(lib().nnmg_set_cheb_bounds(self.handle, int(level), float(lo), float(hi)))
 
     def vcycle(self, r: torch.Tensor, z: torch.Tensor | None = None) -> torch.Tensor:
+        """z = V(r); r of shape [n_dofs] or [n_dofs, nrhs]."""
         z = torch.empty_like(r) if z is None else z
-        if z.dtype != r.dtype:
-            raise ValueError("dtype mismatch")
+        if z.dtype != r.dtype or z.shape != r.shape:
+            raise ValueError("r and z must have the same dtype and shape")
         n = self.fine.n_dofs
-        check(lib().nnmg_vcycle(self.handle, _DTYPE_PREC[r.dtype], _vec(r, n, self.ctx.device, name="r"),
-                                _vec(z, n, self.ctx.device, name="z"), _stream()))
+        nr = _nrhs(r, n, "r")
+        rp = _vec(r, n * nr, self.ctx.device, name="r")
+        zp = _vec(z, n * nr, self.ctx.device, name="z")
+        if r.dim() == 1:
+            check(lib().nnmg_vcycle(self.handle, _DTYPE_PREC[r.dtype], rp, zp, _stream()))
+        else:
+            check(lib().nnmg_vcycle_multi(self.handle, _DTYPE_PREC[r.dtype], nr, rp, zp, _stream()))
         return z
 
     def pcg_solve(self, b: torch.Tensor, x: torch.Tensor | None = None, rtol: float = 1e-8, max_it: int = 200,
                   vcycle_dtype=torch.float32, history: bool = True, raise_on_failure: bool = True,
                   use_graph: bool = True):
+        """Float64 PCG preconditioned by one V-cycle in vcycle_dtype.  b of shape
+        [n_dofs] gives info as a dict; b of shape [n_dofs, nrhs] runs the nrhs
+        solves in lockstep (nnmg_pcg_solve_multi) and gives a list of dicts."""
         n = self.fine.n_dofs
+        nr = _nrhs(b, n, "b")
         x = torch.empty_like(b) if x is None else x
+        if x.shape != b.shape:
+            raise ValueError("b and x must have the same shape")
         o = _lib.CgOpts()
         lib().nnmg_default_cg_opts(C.byref(o))
         o.rtol = float(rtol)
         o.max_it = int(max_it)
         o.vcycle_prec = _DTYPE_PREC[vcycle_dtype]
         o.use_graph = int(bool(use_graph))
-        hist = np.full(max_it + 1, np.nan) if history else None
+        hist = np.full((nr, max_it + 1), np.nan) if history else None
         o.history = hist.ctypes.data_as(C.POINTER(C.c_double)) if history else None
-        res = _lib.CgResult()
-        code = lib().nnmg_pcg_solve(self.handle, _vec(b, n, self.ctx.device, torch.float64, "b"),
-                                    _vec(x, n, self.ctx.device, torch.float64, "x"), C.byref(o), C.byref(res),
-                                    _stream())
-        info = dict(iterations=res.iterations, relres=res.relres, status=_lib.ERRORS.get(res.status, "OK")
-                    if res.status else "OK")
-        if history:
-            info["history"] = hist[: res.iterations + 1].copy()
+        res = (_lib.CgResult * nr)()
+        bp = _vec(b, n * nr, self.ctx.device, torch.float64, "b")
+        xp = _vec(x, n * nr, self.ctx.device, torch.float64, "x")
+        if b.dim() == 1:
+            code = lib().nnmg_pcg_solve(self.handle, bp, xp, C.byref(o), res, _stream())
+        else:
+            code = lib().nnmg_pcg_solve_multi(self.handle, nr, bp, xp, C.byref(o), res, _stream())
+        infos = []
+        for k in range(nr):
+            info = dict(iterations=res[k].iterations, relres=res[k].relres,
+                        status=_lib.ERRORS.get(res[k].status, "OK") if res[k].status else "OK")
+            if history:
+                info["history"] = hist[k, : res[k].iterations + 1].copy()
+            infos.append(info)
         if code != 0 and raise_on_failure:
             check(code)
-        return x, info
+        return x, (infos[0] if b.dim() == 1 else infos)
 
     def set_profiling(self, enabled: bool):
         check(lib().nnmg_hierarchy_set_profiling(self.handle, int(bool(enabled))))

@@ -17,8 +17,9 @@ Hierarchy* hierarchy_create(Ctx* ctx, nnmg_level* const* levels, int nl, nnmg_tr
 void hierarchy_destroy(Hierarchy* h);
 void get_bounds(const Hierarchy& H, int l, double* lo, double* hi);
 void set_bounds(Hierarchy& H, int l, double lo, double hi);
-void vcycle(Hierarchy& H, int prec, const void* r, void* z, hipStream_t s);
-int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg_result* res, hipStream_t s);
+void vcycle(Hierarchy& H, int prec, const void* r, void* z, int nr, hipStream_t s);
+int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg_result* res, int nr,
+        hipStream_t s);
 void set_profiling(Hierarchy& H, bool on);
 void profile(Hierarchy& H, double* ms);
 
@@ -218,27 +219,50 @@ int nnmg_level_assemble_rhs(nnmg_level* l, const double* fq, double* b, void* st
     });
 }
 
+static void check_rhs(int nrhs) {
+    if (nrhs < 1 || nrhs > kMaxRhs) fail(NNMG_ERR_INVALID_ARG, "nrhs must be in 1..8");
+}
+
+static void vmult_impl(const nnmg_level* l, int prec, int nr, const void* src, void* dst, bool add, void* stream) {
+    if (!l || !src || !dst) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+    if (src == dst) fail(NNMG_ERR_INVALID_ARG, "src and dst alias");
+    if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+    check_rhs(nr);
+    NNMG_HIP(hipSetDevice(l->ctx->device));
+    Level& L = const_cast<nnmg_level&>(*l);
+    level_reserve_rhs(L, nr);
+    const hipStream_t s = as_stream(stream);
+    if (!add) launch_fill(dst, (size_t)L.n_dofs * (size_t)nr, prec, s);
+    launch_vmult_cells(L, prec, src, dst, s, nr, L.d_contrib.ptr);
+    if (!add)
+        launch_copy_constrained(L.d_constrained.ptr, L.constrained_idx.size(), src, dst, prec, s, nr);
+}
+
 int nnmg_vmult(const nnmg_level* l, nnmg_prec prec, const void* src, void* dst, void* stream) {
     return guarded([&] {
-        if (!l || !src || !dst) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
-        if (src == dst) fail(NNMG_ERR_INVALID_ARG, "src and dst alias");
-        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
-        NNMG_HIP(hipSetDevice(l->ctx->device));
-        const hipStream_t s = as_stream(stream);
-        launch_fill(dst, (size_t)l->n_dofs, prec, s);
-        launch_vmult_cells(*l, prec, src, dst, s);
-        launch_copy_constrained(l->d_constrained.ptr, l->constrained_idx.size(), src, dst, prec, s);
+        vmult_impl(l, prec, 1, src, dst, false, stream);
         return NNMG_OK;
     });
 }
 
 int nnmg_vmult_add(const nnmg_level* l, nnmg_prec prec, const void* src, void* dst, void* stream) {
     return guarded([&] {
-        if (!l || !src || !dst) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
-        if (src == dst) fail(NNMG_ERR_INVALID_ARG, "src and dst alias");
-        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
-        NNMG_HIP(hipSetDevice(l->ctx->device));
-        launch_vmult_cells(*l, prec, src, dst, as_stream(stream));
+        vmult_impl(l, prec, 1, src, dst, true, stream);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_vmult_multi(const nnmg_level* l, nnmg_prec prec, int nrhs, const void* src, void* dst, void* stream) {
+    return guarded([&] {
+        vmult_impl(l, prec, nrhs, src, dst, false, stream);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_vmult_add_multi(const nnmg_level* l, nnmg_prec prec, int nrhs, const void* src, void* dst,
+                         void* stream) {
+    return guarded([&] {
+        vmult_impl(l, prec, nrhs, src, dst, true, stream);
         return NNMG_OK;
     });
 }
@@ -284,24 +308,48 @@ int nnmg_transfer_points(const nnmg_transfer* t, int64_t* n_points, int32_t* fin
     });
 }
 
+static void transfer_impl(const nnmg_transfer* t, int prec, int nr, const void* in, void* out, bool prolong,
+                          void* stream) {
+    if (!t || !in || !out) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+    if (in == out) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
+    if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+    check_rhs(nr);
+    NNMG_HIP(hipSetDevice(t->ctx->device));
+    Transfer& T = const_cast<nnmg_transfer&>(*t);
+    if (prolong) {
+        launch_prolongate(T, prec, in, out, as_stream(stream), nr);
+    } else {
+        transfer_reserve_rhs(T, nr);
+        launch_restrict(T, prec, in, out, true, as_stream(stream), nr);
+    }
+}
+
 int nnmg_prolongate(const nnmg_transfer* t, nnmg_prec prec, const void* coarse, void* fine, void* stream) {
     return guarded([&] {
-        if (!t || !coarse || !fine) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
-        if (coarse == fine) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
-        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
-        NNMG_HIP(hipSetDevice(t->ctx->device));
-        launch_prolongate(*t, prec, coarse, fine, as_stream(stream));
+        transfer_impl(t, prec, 1, coarse, fine, true, stream);
         return NNMG_OK;
     });
 }
 
 int nnmg_restrict(const nnmg_transfer* t, nnmg_prec prec, const void* fine, void* coarse, void* stream) {
     return guarded([&] {
-        if (!t || !coarse || !fine) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
-        if (coarse == fine) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
-        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
-        NNMG_HIP(hipSetDevice(t->ctx->device));
-        launch_restrict(*t, prec, fine, coarse, true, as_stream(stream));
+        transfer_impl(t, prec, 1, fine, coarse, false, stream);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_prolongate_multi(const nnmg_transfer* t, nnmg_prec prec, int nrhs, const void* coarse, void* fine,
+                          void* stream) {
+    return guarded([&] {
+        transfer_impl(t, prec, nrhs, coarse, fine, true, stream);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_restrict_multi(const nnmg_transfer* t, nnmg_prec prec, int nrhs, const void* fine, void* coarse,
+                        void* stream) {
+    return guarded([&] {
+        transfer_impl(t, prec, nrhs, fine, coarse, false, stream);
         return NNMG_OK;
     });
 }
@@ -339,29 +387,50 @@ int nnmg_set_cheb_bounds(nnmg_hierarchy* h, int level, double lo, double hi) {
     });
 }
 
+static void vcycle_impl(nnmg_hierarchy* h, int prec, int nr, const void* r, void* z, void* stream) {
+    if (!h || !r || !z) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+    if (r == z) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
+    if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+    check_rhs(nr);
+    vcycle(*reinterpret_cast<Hierarchy*>(h), prec, r, z, nr, as_stream(stream));
+}
+
 int nnmg_vcycle(nnmg_hierarchy* h, nnmg_prec prec, const void* r, void* z, void* stream) {
     return guarded([&] {
-        if (!h || !r || !z) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
-        if (r == z) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
-        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
-        vcycle(*reinterpret_cast<Hierarchy*>(h), prec, r, z, as_stream(stream));
+        vcycle_impl(h, prec, 1, r, z, stream);
         return NNMG_OK;
     });
 }
 
+int nnmg_vcycle_multi(nnmg_hierarchy* h, nnmg_prec prec, int nrhs, const void* r, void* z, void* stream) {
+    return guarded([&] {
+        vcycle_impl(h, prec, nrhs, r, z, stream);
+        return NNMG_OK;
+    });
+}
+
+static int pcg_impl(nnmg_hierarchy* h, int nr, const double* b, double* x, const nnmg_cg_opts* opts,
+                    nnmg_cg_result* res, void* stream) {
+    if (!h || !b || !x || !res) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+    if (b == x) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
+    check_rhs(nr);
+    nnmg_cg_opts o;
+    nnmg_default_cg_opts(&o);
+    if (opts) o = *opts;
+    const int st = pcg(*reinterpret_cast<Hierarchy*>(h), b, x, o, res, nr, as_stream(stream));
+    if (st == NNMG_ERR_NOT_CONVERGED) report(st, "CG reached max_it before the tolerance");
+    if (st == NNMG_ERR_BREAKDOWN) report(st, "CG breakdown (non-positive curvature or NaN)");
+    return st;
+}
+
 int nnmg_pcg_solve(nnmg_hierarchy* h, const double* b, double* x, const nnmg_cg_opts* opts, nnmg_cg_result* res,
                    void* stream) {
-    return guarded([&] {
-        if (!h || !b || !x || !res) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
-        if (b == x) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
-        nnmg_cg_opts o;
-        nnmg_default_cg_opts(&o);
-        if (opts) o = *opts;
-        const int st = pcg(*reinterpret_cast<Hierarchy*>(h), b, x, o, res, as_stream(stream));
-        if (st == NNMG_ERR_NOT_CONVERGED) report(st, "CG reached max_it before the tolerance");
-        if (st == NNMG_ERR_BREAKDOWN) report(st, "CG breakdown (non-positive curvature or NaN)");
-        return st;
-    });
+    return guarded([&] { return pcg_impl(h, 1, b, x, opts, res, stream); });
+}
+
+int nnmg_pcg_solve_multi(nnmg_hierarchy* h, int nrhs, const double* b, double* x, const nnmg_cg_opts* opts,
+                         nnmg_cg_result* res, void* stream) {
+    return guarded([&] { return pcg_impl(h, nrhs, b, x, opts, res, stream); });
 }
 
 int nnmg_hierarchy_set_profiling(nnmg_hierarchy* h, int enabled) {

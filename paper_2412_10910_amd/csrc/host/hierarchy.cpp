@@ -14,6 +14,10 @@
 // the coarse problem is solved with the explicit inverse of the unconstrained
 // block plus one step of iterative refinement, always in float64.
 //
+// Several right-hand sides (nr <= kMaxRhs, vectors interleaved as [DoF][nr])
+// run through one V-cycle or one CG together: every launch carries all of
+// them, and each is computed exactly as it would be on its own.
+//
 // The Chebyshev sweep is the three-term recurrence on D^{-1} A over
 // [lambda_max / range, lambda_max] (Saad, Alg. 12.1), with the residual
 // recomputed as f - A x at every step; lambda_max is eig_safety times the
@@ -50,11 +54,12 @@ struct Hierarchy {
     int64_t m = 0;
     DeviceArray<int32_t> free_idx;
     DeviceArray<double> inv;        // m x m: A^{-1} on the unconstrained block
-    DeviceArray<double> cx, cax;    // [N] unit vectors and operator columns at setup; y and r of the solve
+    DeviceArray<double> cx, cax;    // [N] unit vectors and operator columns at setup; [N][nr] y and r of the solve
 
-    WorkVectors work[2][16];  // [prec][level]
+    WorkVectors work[2][16];  // [prec][level], vectors of rhs_cap right-hand sides
+    int rhs_cap = 0;          // right-hand sides the work and CG vectors hold
 
-    // CG
+    // CG: vectors [N][rhs_cap]; scalars kScal per right-hand side, then a scratch word
     DeviceArray<double> r, p, qv, z, partial, scal;
     double* hscal = nullptr;  // pinned
 
@@ -66,15 +71,17 @@ struct Hierarchy {
 
     // the CG preconditioner (cast, V-cycle, cast back on the fixed CG vectors)
     // captured as a HIP graph per V-cycle precision
+    // and number of right-hand sides
     hipStream_t capture = nullptr;
-    hipGraphExec_t precond_graph[2] = {nullptr, nullptr};
+    hipGraphExec_t precond_graph[2][kMaxRhs + 1] = {};
 
     void drop_graphs() {
-        for (auto& g : precond_graph)
-            if (g) {
-                (void)hipGraphExecDestroy(g);
-                g = nullptr;
-            }
+        for (auto& row : precond_graph)
+            for (auto& g : row)
+                if (g) {
+                    (void)hipGraphExecDestroy(g);
+                    g = nullptr;
+                }
     }
 
     ~Hierarchy() {
@@ -99,19 +106,35 @@ namespace nnmg {
 
 static size_t wsize(int prec) { return prec == NNMG_FP64 ? 8 : 4; }
 
-static void alloc_work(Hierarchy& H, int prec) {
-    for (size_t l = 0; l < H.levels.size(); ++l) {
-        WorkVectors& w = H.work[prec][l];
-        if (w.f.ptr || H.levels[l]->n_dofs == 0) continue;
-        const size_t b = (size_t)H.levels[l]->n_dofs * wsize(prec);
-        w.f.alloc(H.ctx, b);
-        w.x.alloc(H.ctx, b);
-        w.d.alloc(H.ctx, b);
-        w.r.alloc(H.ctx, b);
-        w.ax.alloc(H.ctx, b);
-        for (auto* a : {&w.f, &w.x, &w.d, &w.r, &w.ax}) NNMG_HIP(hipMemset(a->ptr, 0, b));
-        w.contrib.alloc(H.ctx, std::max<size_t>(H.levels[l]->contrib_len * H.levels[l]->ncomp, 1) * wsize(prec));
+// (re)allocate the work vectors of both precisions, the CG vectors and the
+// coarse-solve vectors for nr right-hand sides, and grow the transfers'
+// restriction buffers; drops the captured preconditioners, which hold the
+// previous addresses
+static void ensure_rhs(Hierarchy& H, int nr) {
+    if (nr < 1 || nr > kMaxRhs) fail(NNMG_ERR_INVALID_ARG, "number of right-hand sides must be in 1..8");
+    if (nr <= H.rhs_cap) return;
+    NNMG_HIP(hipDeviceSynchronize());  // earlier launches may still use the vectors
+    H.drop_graphs();
+    for (int prec : {NNMG_FP64, NNMG_FP32})
+        for (size_t l = 0; l < H.levels.size(); ++l) {
+            WorkVectors& w = H.work[prec][l];
+            const Level& L = *H.levels[l];
+            const size_t b = std::max<size_t>((size_t)L.n_dofs * (size_t)nr, 1) * wsize(prec);
+            for (auto* a : {&w.f, &w.x, &w.d, &w.r, &w.ax}) {
+                a->alloc(H.ctx, b);
+                NNMG_HIP(hipMemset(a->ptr, 0, b));
+            }
+            w.contrib.alloc(H.ctx, std::max<size_t>(L.contrib_len * L.ncomp * (size_t)nr, 1) * wsize(prec));
+        }
+    const size_t n = std::max<size_t>((size_t)H.levels.back()->n_dofs * (size_t)nr, 1);
+    for (auto* a : {&H.r, &H.p, &H.qv, &H.z}) a->alloc(H.ctx, n);
+    const size_t nc = std::max<size_t>((size_t)H.levels[0]->n_dofs * (size_t)nr, 1);
+    for (auto* a : {&H.cx, &H.cax}) {
+        a->alloc(H.ctx, nc);
+        NNMG_HIP(hipMemset(a->ptr, 0, a->bytes()));
     }
+    for (auto* t : H.transfers) transfer_reserve_rhs(*t, nr);
+    H.rhs_cap = nr;
 }
 
 static hipEvent_t take_event(Hierarchy& H) {
@@ -177,7 +200,7 @@ static void setup_coarse(Hierarchy& H) {
     NNMG_HIP(hipDeviceSynchronize());
 }
 
-static void op_residual(Hierarchy& H, int l, int prec, const void* f, const void* x, void* r, hipStream_t s);
+static void op_residual(Hierarchy& H, int l, int prec, const void* f, const void* x, void* r, int nr, hipStream_t s);
 
 // x = A_0^{-1} f on the unconstrained block with the dense float64 inverse
 // (row-parallel kernels that gather f and scatter x through the free-DoF list
@@ -185,20 +208,20 @@ static void op_residual(Hierarchy& H, int l, int prec, const void* f, const void
 //   y = A^{-1} f,  r = f - A y (the level's own operator),  x = y + A^{-1} r.
 // In float32 the single product suffices: its error, cond(A) times the
 // float64 rounding, lies far below the float32 rounding of x.
-static void coarse_solve(Hierarchy& H, int prec, const void* f, void* x, hipStream_t s) {
+static void coarse_solve(Hierarchy& H, int prec, const void* f, void* x, int nr, hipStream_t s) {
     Level& C = *H.levels[0];
     const size_t N = (size_t)C.n_dofs, m = (size_t)H.m;
-    launch_fill(x, N, prec, s);  // constrained entries
+    launch_fill(x, N * (size_t)nr, prec, s);  // constrained entries
     if (m == 0) return;
     const int32_t* fi = H.free_idx.ptr;
     if (prec == NNMG_FP32) {
-        launch_coarse_gemv(H.inv.ptr, m, f, prec, fi, nullptr, NNMG_FP64, nullptr, 1.0, x, prec, fi, s);
+        launch_coarse_gemv(H.inv.ptr, m, f, prec, fi, nullptr, NNMG_FP64, nullptr, 1.0, x, prec, fi, s, nr);
         return;
     }
     // y into the unconstrained entries of cx, whose constrained entries stay zero
-    launch_coarse_gemv(H.inv.ptr, m, f, prec, fi, nullptr, NNMG_FP64, nullptr, 1.0, H.cx.ptr, NNMG_FP64, fi, s);
-    op_residual(H, 0, NNMG_FP64, f, H.cx.ptr, H.cax.ptr, s);
-    launch_coarse_gemv(H.inv.ptr, m, H.cax.ptr, NNMG_FP64, fi, H.cx.ptr, NNMG_FP64, fi, 1.0, x, prec, fi, s);
+    launch_coarse_gemv(H.inv.ptr, m, f, prec, fi, nullptr, NNMG_FP64, nullptr, 1.0, H.cx.ptr, NNMG_FP64, fi, s, nr);
+    op_residual(H, 0, NNMG_FP64, f, H.cx.ptr, H.cax.ptr, nr, s);
+    launch_coarse_gemv(H.inv.ptr, m, H.cax.ptr, NNMG_FP64, fi, H.cx.ptr, NNMG_FP64, fi, 1.0, x, prec, fi, s, nr);
 }
 
 // ---------------------------------------------------------------------------
@@ -206,32 +229,33 @@ static void coarse_solve(Hierarchy& H, int prec, const void* f, void* x, hipStre
 // ---------------------------------------------------------------------------
 // x <- x + d with d <- c1 d + c2 D^{-1} (f - A x)   (c1 unused when first)
 static void op_cheb_step(Hierarchy& H, int l, int prec, const void* f, const void* dinv, void* x, double c1,
-                         double c2, bool first, hipStream_t s) {
+                         double c2, bool first, int nr, hipStream_t s) {
     Level& L = *H.levels[l];
     WorkVectors& w = H.work[prec][l];
     if (L.atomic_scatter) {
-        launch_vmult_cells(L, prec, x, w.ax.ptr, s);
-        launch_cheb_step(prec, (size_t)L.n_dofs, f, w.ax.ptr, dinv, x, w.d.ptr, first ? 0.0 : c1, c2, s);
+        launch_vmult_cells(L, prec, x, w.ax.ptr, s, nr, w.contrib.ptr);
+        launch_cheb_step(prec, (size_t)L.n_dofs, f, w.ax.ptr, dinv, x, w.d.ptr, first ? 0.0 : c1, c2, s, nr);
     } else {
-        launch_vmult_contrib(L, prec, x, w.contrib.ptr, s);
-        launch_cheb_step_gather(L, prec, w.contrib.ptr, f, dinv, x, w.d.ptr, c1, c2, first, s);
+        launch_vmult_contrib(L, prec, x, w.contrib.ptr, s, nr);
+        launch_cheb_step_gather(L, prec, w.contrib.ptr, f, dinv, x, w.d.ptr, c1, c2, first, s, nr);
     }
 }
 
 // r = f - A x
-static void op_residual(Hierarchy& H, int l, int prec, const void* f, const void* x, void* r, hipStream_t s) {
+static void op_residual(Hierarchy& H, int l, int prec, const void* f, const void* x, void* r, int nr, hipStream_t s) {
     Level& L = *H.levels[l];
     WorkVectors& w = H.work[prec][l];
     if (L.atomic_scatter) {
-        launch_vmult_cells(L, prec, x, w.ax.ptr, s);
-        launch_residual(prec, (size_t)L.n_dofs, f, w.ax.ptr, r, s);
+        launch_vmult_cells(L, prec, x, w.ax.ptr, s, nr, w.contrib.ptr);
+        launch_residual(prec, (size_t)L.n_dofs * (size_t)nr, f, w.ax.ptr, r, s);
     } else {
-        launch_vmult_contrib(L, prec, x, w.contrib.ptr, s);
-        launch_residual_gather(L, prec, w.contrib.ptr, f, r, s);
+        launch_vmult_contrib(L, prec, x, w.contrib.ptr, s, nr);
+        launch_residual_gather(L, prec, w.contrib.ptr, f, r, s, nr);
     }
 }
 
-static void chebyshev(Hierarchy& H, int l, int prec, const void* f, void* x, bool zero_start, hipStream_t s) {
+static void chebyshev(Hierarchy& H, int l, int prec, const void* f, void* x, bool zero_start, int nr,
+                      hipStream_t s) {
     Level& L = *H.levels[l];
     WorkVectors& w = H.work[prec][l];
     const void* dinv = prec == NNMG_FP64 ? (const void*)L.d_dinv64.ptr : (const void*)L.d_dinv32.ptr;
@@ -239,20 +263,20 @@ static void chebyshev(Hierarchy& H, int l, int prec, const void* f, void* x, boo
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
     if (zero_start)
-        launch_cheb_first_zero(prec, (size_t)L.n_dofs, f, dinv, x, w.d.ptr, 1.0 / theta, s);
+        launch_cheb_first_zero(prec, (size_t)L.n_dofs, f, dinv, x, w.d.ptr, 1.0 / theta, s, nr);
     else
-        op_cheb_step(H, l, prec, f, dinv, x, 0.0, 1.0 / theta, true, s);
+        op_cheb_step(H, l, prec, f, dinv, x, 0.0, 1.0 / theta, true, nr, s);
     for (int j = 1; j < H.opts.cheb_degree; ++j) {
         const double rho_new = 1.0 / (2.0 * sigma - rho);
-        op_cheb_step(H, l, prec, f, dinv, x, rho_new * rho, 2.0 * rho_new / delta, false, s);
+        op_cheb_step(H, l, prec, f, dinv, x, rho_new * rho, 2.0 * rho_new / delta, false, nr, s);
         rho = rho_new;
     }
 }
 
-static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, hipStream_t s) {
+static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, int nr, hipStream_t s) {
     if (l == 0) {
         Scope sc(H, 0, kCoarse, s);
-        coarse_solve(H, prec, f, x, s);
+        coarse_solve(H, prec, f, x, nr, s);
         return;
     }
     WorkVectors& w = H.work[prec][l];
@@ -260,26 +284,26 @@ static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, 
     const Transfer& T = *H.transfers[l - 1];
     {
         Scope sc(H, l, kPre, s);
-        chebyshev(H, l, prec, f, x, true, s);
+        chebyshev(H, l, prec, f, x, true, nr, s);
     }
     {
         Scope sc(H, l, kRes, s);
-        op_residual(H, l, prec, f, x, w.r.ptr, s);
+        op_residual(H, l, prec, f, x, w.r.ptr, nr, s);
     }
     {
         Scope sc(H, l, kRestrict, s);
         // every unconstrained coarse DoF has restriction slots; the constrained
         // entries of f_c are never written and stay zero
-        launch_restrict(T, prec, w.r.ptr, wc.f.ptr, false, s);
+        launch_restrict(T, prec, w.r.ptr, wc.f.ptr, false, s, nr);
     }
-    vcycle_level(H, l - 1, prec, wc.f.ptr, wc.x.ptr, s);
+    vcycle_level(H, l - 1, prec, wc.f.ptr, wc.x.ptr, nr, s);
     {
         Scope sc(H, l, kProlong, s);
-        launch_prolongate(T, prec, wc.x.ptr, x, s);
+        launch_prolongate(T, prec, wc.x.ptr, x, s, nr);
     }
     {
         Scope sc(H, l, kPost, s);
-        chebyshev(H, l, prec, f, x, false, s);
+        chebyshev(H, l, prec, f, x, false, nr, s);
     }
 }
 
@@ -319,9 +343,10 @@ static double tridiagonal_max_eig(const std::vector<double>& d, const std::vecto
 }
 
 static double host_dot(Hierarchy& H, const double* a, const double* b, size_t n) {
-    launch_dot(a, b, n, H.partial.ptr, H.scal.ptr + 7, nullptr);
+    double* scratch = H.scal.ptr + kScal * kMaxRhs;
+    launch_dot(a, b, n, H.partial.ptr, scratch, nullptr);
     double v = 0.0;
-    NNMG_HIP(hipMemcpy(&v, H.scal.ptr + 7, sizeof(double), hipMemcpyDeviceToHost));
+    NNMG_HIP(hipMemcpy(&v, scratch, sizeof(double), hipMemcpyDeviceToHost));
     return v;
 }
 
@@ -403,10 +428,10 @@ Hierarchy* hierarchy_create(Ctx* ctx, nnmg_level* const* levels, int nl, nnmg_tr
         }
         H->opts.eig_start = nullptr;
         const size_t nmax = (size_t)H->levels.back()->n_dofs;
-        H->partial.alloc(ctx, dot_partials(nmax > 0 ? nmax : 1) + 8);
-        H->scal.alloc(ctx, 8);
-        NNMG_HIP(hipMemset(H->scal.ptr, 0, 8 * sizeof(double)));
-        NNMG_HIP(hipHostMalloc((void**)&H->hscal, 8 * sizeof(double), hipHostMallocDefault));
+        H->partial.alloc(ctx, dot_partials(nmax > 0 ? nmax : 1) * kMaxRhs + 8);
+        H->scal.alloc(ctx, kScal * kMaxRhs + 8);
+        NNMG_HIP(hipMemset(H->scal.ptr, 0, H->scal.bytes()));
+        NNMG_HIP(hipHostMalloc((void**)&H->hscal, (kScal * kMaxRhs + 8) * sizeof(double), hipHostMallocDefault));
         H->lo.assign((size_t)nl, 0.0);
         H->hi.assign((size_t)nl, 0.0);
         H->opts.eig_start = o.eig_start;
@@ -417,13 +442,7 @@ Hierarchy* hierarchy_create(Ctx* ctx, nnmg_level* const* levels, int nl, nnmg_tr
         }
         H->opts.eig_start = nullptr;  // the caller's vectors are not kept
         setup_coarse(*H);
-        alloc_work(*H, NNMG_FP64);
-        alloc_work(*H, NNMG_FP32);
-        const size_t n = (size_t)H->levels.back()->n_dofs;
-        H->r.alloc(ctx, n);
-        H->p.alloc(ctx, n);
-        H->qv.alloc(ctx, n);
-        H->z.alloc(ctx, n);
+        ensure_rhs(*H, 1);
         H->acc.assign((size_t)nl * kComponents, 0.0);
         NNMG_HIP(hipDeviceSynchronize());
     } catch (...) {
@@ -449,35 +468,43 @@ void set_bounds(Hierarchy& H, int l, double lo, double hi) {
     H.drop_graphs();  // the captured V-cycles hold the previous coefficients
 }
 
-void vcycle(Hierarchy& H, int prec, const void* r, void* z, hipStream_t s) {
+void vcycle(Hierarchy& H, int prec, const void* r, void* z, int nr, hipStream_t s) {
+    ensure_rhs(H, nr);
     H.last = s;
-    vcycle_level(H, (int)H.levels.size() - 1, prec, r, z, s);
+    vcycle_level(H, (int)H.levels.size() - 1, prec, r, z, nr, s);
 }
 
 // ---------------------------------------------------------------------------
-// PCG (float64), Saad Alg. 9.1 with x0 = 0
+// PCG (float64), Saad Alg. 9.1 with x0 = 0, for nr right-hand sides at once
 // ---------------------------------------------------------------------------
-int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg_result* res, hipStream_t s) {
+// Each right-hand side has its own scalars (scal + r * kScal) and its own
+// stopping test.  One that has converged (or broken down) is frozen: its
+// active flag is cleared, so alpha = beta = 0 from then on and its iterate and
+// residual stay exactly as they were, while the others go on.
+int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg_result* res, int nr,
+        hipStream_t s) {
     if (o.max_it < 0 || !(o.rtol >= 0.0)) fail(NNMG_ERR_INVALID_ARG, "CG options");
     if (o.vcycle_prec != NNMG_FP64 && o.vcycle_prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "vcycle_prec");
+    ensure_rhs(H, nr);
     H.last = s;
     Level& L = *H.levels.back();
     const int top = (int)H.levels.size() - 1;
-    const size_t n = (size_t)L.n_dofs;
+    const size_t n = (size_t)L.n_dofs, nv = n * (size_t)nr;
     const int prec = o.vcycle_prec;
     WorkVectors& w32 = H.work[NNMG_FP32][top];
     // z = V(r) on the hierarchy's own vectors, so the launches can be captured once
     auto launches = [&](hipStream_t st) {
         if (prec == NNMG_FP64) {
-            vcycle_level(H, top, NNMG_FP64, H.r.ptr, H.z.ptr, st);
+            vcycle_level(H, top, NNMG_FP64, H.r.ptr, H.z.ptr, nr, st);
         } else {
-            launch_cast_64_to_32(H.r.ptr, (float*)w32.f.ptr, n, st);
-            vcycle_level(H, top, NNMG_FP32, w32.f.ptr, w32.x.ptr, st);
-            launch_cast_32_to_64((const float*)w32.x.ptr, H.z.ptr, n, st);
+            launch_cast_64_to_32(H.r.ptr, (float*)w32.f.ptr, nv, st);
+            vcycle_level(H, top, NNMG_FP32, w32.f.ptr, w32.x.ptr, nr, st);
+            launch_cast_32_to_64((const float*)w32.x.ptr, H.z.ptr, nv, st);
         }
     };
     const bool graph = o.use_graph && !H.profiling;
-    if (graph && !H.precond_graph[prec]) {
+    hipGraphExec_t& exec = H.precond_graph[prec][nr];
+    if (graph && !exec) {
         if (!H.capture) NNMG_HIP(hipStreamCreateWithFlags(&H.capture, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
         NNMG_HIP(hipStreamBeginCapture(H.capture, hipStreamCaptureModeThreadLocal));
@@ -489,77 +516,110 @@ int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg
             throw;
         }
         NNMG_HIP(hipStreamEndCapture(H.capture, &g));
-        const hipError_t e = hipGraphInstantiate(&H.precond_graph[prec], g, nullptr, nullptr, 0);
+        const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
-            H.precond_graph[prec] = nullptr;
+            exec = nullptr;
             fail(NNMG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
         }
     }
     auto precondition = [&]() {
         if (graph)
-            NNMG_HIP(hipGraphLaunch(H.precond_graph[prec], s));
+            NNMG_HIP(hipGraphLaunch(exec, s));
         else
             launches(s);
     };
     double* sc = H.scal.ptr;
-    NNMG_HIP(hipMemcpyAsync(H.r.ptr, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    launch_fill(x, n, NNMG_FP64, s);
-    launch_dot(b, b, n, H.partial.ptr, sc + 6, s);
-    NNMG_HIP(hipMemcpyAsync(H.hscal + 6, sc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
-    NNMG_HIP(hipStreamSynchronize(s));
-    const double bnorm = std::sqrt(H.hscal[6]);
-    if (o.history) o.history[0] = 1.0;
-    res->iterations = 0;
-    res->relres = bnorm > 0 ? 1.0 : 0.0;
-    res->status = NNMG_OK;
-    if (!(bnorm > 0.0)) {
-        if (std::isnan(bnorm)) {
-            res->status = NNMG_ERR_BREAKDOWN;
-            return NNMG_ERR_BREAKDOWN;
+    double* hs = H.hscal;
+    const size_t nsc = (size_t)kScal * (size_t)nr;
+    auto fetch = [&]() {
+        NNMG_HIP(hipMemcpyAsync(hs, sc, nsc * sizeof(double), hipMemcpyDeviceToHost, s));
+        NNMG_HIP(hipStreamSynchronize(s));
+    };
+    // the host copy is current (fetched with nothing launched since), so it can go back whole
+    auto push_flags = [&]() { NNMG_HIP(hipMemcpyAsync(sc, hs, nsc * sizeof(double), hipMemcpyHostToDevice, s)); };
+    const size_t hlen = (size_t)o.max_it + 1;
+    NNMG_HIP(hipMemcpyAsync(H.r.ptr, b, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_fill(x, nv, NNMG_FP64, s);
+    launch_dot(b, b, n, H.partial.ptr, sc + 6, s, nr, kScal);
+    fetch();
+    std::vector<double> bnorm((size_t)nr);
+    std::vector<char> active((size_t)nr, 0);
+    int n_active = 0;
+    for (int k = 0; k < nr; ++k) {
+        const double bn = std::sqrt(hs[k * kScal + 6]);
+        bnorm[(size_t)k] = bn;
+        if (o.history) o.history[(size_t)k * hlen] = 1.0;
+        res[k].iterations = 0;
+        res[k].relres = bn > 0 ? 1.0 : 0.0;
+        res[k].status = NNMG_OK;
+        if (std::isnan(bn)) {
+            res[k].status = NNMG_ERR_BREAKDOWN;
+        } else if (bn > 0.0) {
+            res[k].status = NNMG_ERR_NOT_CONVERGED;
+            active[(size_t)k] = 1;
+            ++n_active;
         }
-        res->relres = 0.0;
-        return NNMG_OK;
+        hs[k * kScal + 7] = active[(size_t)k] ? 1.0 : 0.0;
     }
+    auto overall = [&]() {
+        int st = NNMG_OK;
+        for (int k = 0; k < nr; ++k)
+            if (res[k].status == NNMG_ERR_BREAKDOWN) st = NNMG_ERR_BREAKDOWN;
+            else if (res[k].status != NNMG_OK && st == NNMG_OK) st = res[k].status;
+        return st;
+    };
+    if (n_active == 0) return overall();
+    push_flags();
     precondition();
-    launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 0, s);
-    NNMG_HIP(hipMemcpyAsync(H.p.ptr, H.z.ptr, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    int status = NNMG_ERR_NOT_CONVERGED;
+    launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 0, s, nr, kScal);
+    NNMG_HIP(hipMemcpyAsync(H.p.ptr, H.z.ptr, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
     for (int it = 1; it <= o.max_it; ++it) {
         if (L.atomic_scatter) {
-            launch_fill(H.qv.ptr, n, NNMG_FP64, s);
-            launch_vmult_cells(L, NNMG_FP64, H.p.ptr, H.qv.ptr, s);
-            launch_dot(H.p.ptr, H.qv.ptr, n, H.partial.ptr, sc + 1, s);
+            launch_fill(H.qv.ptr, nv, NNMG_FP64, s);
+            launch_vmult_cells(L, NNMG_FP64, H.p.ptr, H.qv.ptr, s, nr, H.work[NNMG_FP64][top].contrib.ptr);
+            launch_dot(H.p.ptr, H.qv.ptr, n, H.partial.ptr, sc + 1, s, nr, kScal);
         } else {
             double* cb = (double*)H.work[NNMG_FP64][top].contrib.ptr;
-            launch_vmult_contrib(L, NNMG_FP64, H.p.ptr, cb, s);
-            launch_gather_dot(L, cb, H.p.ptr, H.qv.ptr, H.partial.ptr, sc + 1, s);
+            launch_vmult_contrib(L, NNMG_FP64, H.p.ptr, cb, s, nr);
+            launch_gather_dot(L, cb, H.p.ptr, H.qv.ptr, H.partial.ptr, sc + 1, s, nr);
         }
-        launch_scalar_op(sc, 0, s);
-        launch_cg_update(n, x, H.r.ptr, H.p.ptr, H.qv.ptr, sc, H.partial.ptr, sc + 3, s);
-        NNMG_HIP(hipMemcpyAsync(H.hscal, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-        NNMG_HIP(hipStreamSynchronize(s));
-        const double pq = H.hscal[1], rr = H.hscal[3];
-        res->iterations = it;
-        if (!(pq > 0.0) || !std::isfinite(rr)) {
-            status = NNMG_ERR_BREAKDOWN;
-            break;
+        launch_scalar_op(sc, 0, s, nr);
+        launch_cg_update(n, x, H.r.ptr, H.p.ptr, H.qv.ptr, sc, H.partial.ptr, sc + 3, s, nr);
+        fetch();
+        bool changed = false;
+        for (int k = 0; k < nr; ++k) {
+            if (!active[(size_t)k]) continue;
+            const double pq = hs[k * kScal + 1], rr = hs[k * kScal + 3];
+            res[k].iterations = it;
+            bool stop = false;
+            if (!(pq > 0.0) || !std::isfinite(rr)) {
+                res[k].status = NNMG_ERR_BREAKDOWN;
+                stop = true;
+            } else {
+                const double rel = std::sqrt(rr) / bnorm[(size_t)k];
+                res[k].relres = rel;
+                if (o.history) o.history[(size_t)k * hlen + (size_t)it] = rel;
+                if (rel <= o.rtol) {
+                    res[k].status = NNMG_OK;
+                    stop = true;
+                }
+            }
+            if (stop) {
+                active[(size_t)k] = 0;
+                hs[k * kScal + 7] = 0.0;
+                --n_active;
+                changed = true;
+            }
         }
-        const double rel = std::sqrt(rr) / bnorm;
-        res->relres = rel;
-        if (o.history) o.history[it] = rel;
-        if (rel <= o.rtol) {
-            status = NNMG_OK;
-            break;
-        }
-        if (it == o.max_it) break;
+        if (n_active == 0 || it == o.max_it) break;
+        if (changed) push_flags();
         precondition();
-        launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 4, s);
-        launch_scalar_op(sc, 1, s);
-        launch_cg_direction(n, H.z.ptr, H.p.ptr, sc, s);
+        launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 4, s, nr, kScal);
+        launch_scalar_op(sc, 1, s, nr);
+        launch_cg_direction(n, H.z.ptr, H.p.ptr, sc, s, nr);
     }
-    res->status = status;
-    return status;
+    return overall();
 }
 
 // ---------------------------------------------------------------------------

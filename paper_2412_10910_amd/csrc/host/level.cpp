@@ -46,6 +46,15 @@ inline uint64_t edge_key(int32_t a, int32_t b) {
 
 void level_retain(Level* l) { l->refs.fetch_add(1); }
 
+void level_reserve_rhs(Level& l, int nr) {
+    if (nr < 1 || nr > kMaxRhs) fail(NNMG_ERR_INVALID_ARG, "number of right-hand sides must be in 1..8");
+    if (nr <= l.contrib_rhs) return;
+    NNMG_HIP(hipSetDevice(l.ctx->device));
+    NNMG_HIP(hipDeviceSynchronize());  // earlier launches may still use the buffer
+    l.d_contrib.alloc(l.ctx, std::max<size_t>(l.contrib_len * l.ncomp * (size_t)nr, 1) * sizeof(double));
+    l.contrib_rhs = nr;
+}
+
 void level_release(Level* l) {
     if (l && l->refs.fetch_sub(1) == 1) delete static_cast<nnmg_level*>(l);
 }

@@ -196,7 +196,8 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
             T->d_rslot.upload(ctx, rslot);
             T->d_roff.upload(ctx, roff);
             // ncomp values per slot: component c of slot k at ncomp * k + c
-            T->d_rbuf.alloc(ctx, std::max<size_t>((size_t)roff.back() * coarse->ncomp, 1));
+            T->n_rslots = (size_t)roff.back();
+            T->d_rbuf.alloc(ctx, std::max<size_t>(T->n_rslots * coarse->ncomp, 1));
         }
         T->d_off.upload(ctx, off);
         T->d_fine.upload(ctx, fidx);
@@ -225,6 +226,15 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
 }
 
 void transfer_retain(Transfer* t) { t->refs.fetch_add(1); }
+
+void transfer_reserve_rhs(Transfer& t, int nr) {
+    if (nr < 1 || nr > kMaxRhs) fail(NNMG_ERR_INVALID_ARG, "number of right-hand sides must be in 1..8");
+    if (nr <= t.rbuf_rhs) return;
+    NNMG_HIP(hipSetDevice(t.ctx->device));
+    NNMG_HIP(hipDeviceSynchronize());  // earlier launches may still use the buffer
+    t.d_rbuf.alloc(t.ctx, std::max<size_t>(t.n_rslots * t.coarse->ncomp * (size_t)nr, 1));
+    t.rbuf_rhs = nr;
+}
 
 void transfer_release(Transfer* t) {
     if (!t || t->refs.fetch_sub(1) != 1) return;

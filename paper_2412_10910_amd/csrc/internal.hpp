@@ -142,6 +142,7 @@ struct Level {
                                         // | kMergeNext: add the next cell's first node of the line first
     size_t contrib_len = 0;             // number of contribution slots
     DeviceArray<char> d_contrib;        // contribution buffer of the level's own operator calls
+    int contrib_rhs = 1;                // right-hand sides d_contrib holds (grown on demand)
     bool atomic_scatter = false;        // float atomics into the output instead of contribution slots
     DeviceArray<double> d_diag64;       // operator diagonal, 1 on constrained
     DeviceArray<double> d_dinv64;       // inverse diagonal, 0 on constrained
@@ -174,10 +175,19 @@ struct Transfer {
     // restriction sums per (coarse cell, node), in slots sorted by coarse DoF
     DeviceArray<int32_t> d_rslot;        // [C_coarse][q] slot of each sum, -1 for constrained DoFs
     DeviceArray<int32_t> d_roff;         // [N_coarse + 1] DoF j sums rbuf[roff[j] .. roff[j+1])
+    size_t n_rslots = 0;                 // restriction slots
     DeviceArray<double> d_rbuf;          // slot values (float64 or float32)
+    int rbuf_rhs = 1;                    // right-hand sides d_rbuf holds (grown on demand)
 };
 
 constexpr int kPointBlock = 256;
+constexpr int kMaxRhs = 8;               // right-hand sides one launch can carry (interleaved [DoF][nr])
+constexpr int kScal = 8;                 // CG scalars per right-hand side
+
+// grow the level's contribution buffer / the transfer's restriction buffer to
+// nr right-hand sides (synchronizes the device when it reallocates)
+void level_reserve_rhs(Level& l, int nr);
+void transfer_reserve_rhs(Transfer& t, int nr);
 constexpr int32_t kMergeNext = 1 << 30;  // flag in a contribution slot index (see Level::d_pos_blk)
 constexpr int kWaveLanes = 64;           // CDNA wavefront width  // points per block of the point-parallel transfer kernels
 
@@ -193,23 +203,31 @@ void launch_cast_32_to_64(const float* a, double* b, size_t n, hipStream_t s);
 void launch_set_constrained(const int32_t* idx, size_t n, double v, void* dst, int prec, hipStream_t s);
 void launch_lincomb(size_t n, double a, const double* x, double b, double* y, hipStream_t s);  // y = a x + b y
 void launch_copy_constrained(const int32_t* idx, size_t n, const void* src, void* dst, int prec,
-                             hipStream_t s);
+                             hipStream_t s, int nr = 1);
 
 // operator apply: dst += A src over the cells (constrained rows untouched)
 void vmult_shape(int dim, int n, int* wg, int* cells_per_block);
 // contrib = the (cell, node) contributions of A src, in DoF-sorted slots
-void launch_vmult_contrib(const Level& L, int prec, const void* src, void* contrib, hipStream_t s);
+void launch_vmult_contrib(const Level& L, int prec, const void* src, void* contrib, hipStream_t s, int nr = 1);
 // consumers of a contribution buffer (kernels/gather.hip); constrained rows are not written
-void launch_gather(const Level& L, int prec, const void* contrib, void* dst, bool accumulate, hipStream_t s);
+// (nr interleaved right-hand sides; the vectors hold n_dofs * nr values)
+void launch_gather(const Level& L, int prec, const void* contrib, void* dst, bool accumulate, hipStream_t s,
+                   int nr = 1);
 void launch_cheb_step_gather(const Level& L, int prec, const void* contrib, const void* f, const void* dinv,
-                             void* x, void* d, double c1, double c2, bool first, hipStream_t s);
-void launch_residual_gather(const Level& L, int prec, const void* contrib, const void* f, void* r, hipStream_t s);
+                             void* x, void* d, double c1, double c2, bool first, hipStream_t s, int nr = 1);
+void launch_residual_gather(const Level& L, int prec, const void* contrib, const void* f, void* r, hipStream_t s,
+                            int nr = 1);
+// out[r * kScal] = p_r . q_r
 void launch_gather_dot(const Level& L, const double* contrib, const double* p, double* q, double* partial,
-                       double* out, hipStream_t s);
-void launch_sum_partials(const double* partial, size_t m, double* out, hipStream_t s);
+                       double* out, hipStream_t s, int nr = 1);
+// out[r * ostride] = sum of partial[block][r] over m blocks
+void launch_sum_partials(const double* partial, size_t m, double* out, hipStream_t s, int nr = 1,
+                         size_t ostride = 1);
 // dst += A src on the unconstrained rows and columns (constrained entries untouched);
-// uses the level's own contribution buffer: not for concurrent calls on one level
-void launch_vmult_cells(const Level& L, int prec, const void* src, void* dst, hipStream_t s);
+// uses `contrib`, else the level's own contribution buffer (one right-hand
+// side; not for concurrent calls on one level)
+void launch_vmult_cells(const Level& L, int prec, const void* src, void* dst, hipStream_t s, int nr = 1,
+                        void* contrib = nullptr);
 // geometry, diagonal, right-hand side (setup kernels)
 void launch_geometry(Level& L, int* d_bad, hipStream_t s);
 void launch_diagonal(const Level& L, double* diag, hipStream_t s);
@@ -221,42 +239,50 @@ void launch_locate(int dim, const double* pts, int np, const double* cverts, con
                    const int32_t* boff, const int32_t* bcells, const double* glo, const double* gstep,
                    const int* gnb, double inside_tol, double newton_tol, int newton_max_it,
                    int32_t* owner, double* xi, int32_t* flags, hipStream_t s);
-void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fine, hipStream_t s);
+void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fine, hipStream_t s, int nr = 1);
 // coarse = P^T fine (accumulate = false) or coarse += P^T fine; constrained coarse entries untouched
-void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s);
-// dst[i] (+)= sum of elem[off[i] .. off[i+1]) for every i with a non-empty run
-void launch_gather_runs(size_t n, int ncomp, const int32_t* off, int prec, const void* elem, void* dst,
-                        bool accumulate, hipStream_t s);
+void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s,
+                     int nr = 1);
+// dst[v] (+)= sum of the run of v's node, for every value v of n * nr (n vector DoFs of ncomp
+// components) whose node has one; elem holds one plane of `plane` entries per right-hand side,
+// component c of slot k at k * ncomp + c
+void launch_gather_runs(size_t n, int ncomp, const int32_t* off, int prec, const void* elem, size_t plane,
+                        void* dst, bool accumulate, hipStream_t s, int nr = 1);
+// entries of one right-hand side's plane of a level's contribution buffer
+size_t contrib_plane(const Level& L);
 
 // vector kernels for the smoother and CG
 // x = d = dinv * f * c0   (first step from a zero guess)
 void launch_cheb_first_zero(int prec, size_t n, const void* f, const void* dinv, void* x, void* d,
-                            double c0, hipStream_t s);
+                            double c0, hipStream_t s, int nr = 1);
 // r = f - ax; ax = 0; d = c1 d + c2 dinv r (c1 = 0 for a first step); x += d
 void launch_cheb_step(int prec, size_t n, const void* f, void* ax, const void* dinv, void* x, void* d,
-                      double c1, double c2, hipStream_t s);
+                      double c1, double c2, hipStream_t s, int nr = 1);
 // r = f - ax; ax = 0
 void launch_residual(int prec, size_t n, const void* f, void* ax, void* r, hipStream_t s);
 // y += x
 void launch_splitmix_vector(double* v, const uint8_t* mask_free, size_t n, uint64_t seed, hipStream_t s);
 
 // float64 reductions: out = sum_i a_i b_i (two-stage, deterministic)
-void launch_dot(const double* a, const double* b, size_t n, double* partial, double* out, hipStream_t s);
+void launch_dot(const double* a, const double* b, size_t n, double* partial, double* out, hipStream_t s,
+                int nr = 1, size_t ostride = 1);
 size_t dot_partials(size_t n);
 // CG kernels; scal layout documented in hierarchy.cpp
+// (n vector DoFs, nr interleaved right-hand sides, scalars of r at scal + r * kScal)
 void launch_cg_update(size_t n, double* x, double* r, const double* p, const double* q, const double* scal,
-                      double* partial, double* rr_out, hipStream_t s);
-void launch_cg_direction(size_t n, const double* z, double* p, const double* scal, hipStream_t s);
-void launch_scalar_op(double* scal, int op, hipStream_t s);
+                      double* partial, double* rr_out, hipStream_t s, int nr = 1);
+void launch_cg_direction(size_t n, const double* z, double* p, const double* scal, hipStream_t s, int nr = 1);
+void launch_scalar_op(double* scal, int op, hipStream_t s, int nr = 1);
 void launch_jacobi(size_t n, const double* dinv, const double* r, double* z, hipStream_t s);
 void launch_axpy(size_t n, double a_sign, const double* scal_a, int idx, const double* x, double* y,
                  hipStream_t s);
 
 // dense coarse solve
 // O[oidx ? oidx[i] : i] = base_i + sign * sum_j M_ij V[vidx ? vidx[j] : j], base_i = B[bidx ? bidx[i] : i] or 0
+// (nr interleaved right-hand sides: index i stands for values i nr .. i nr + nr - 1)
 void launch_coarse_gemv(const double* M, size_t m, const void* V, int vprec, const int32_t* vidx, const void* B,
                         int bprec, const int32_t* bidx, double sign, void* O, int oprec, const int32_t* oidx,
-                        hipStream_t s);
+                        hipStream_t s, int nr = 1);
 void launch_gauss_jordan(double* M, size_t m, double* rowbuf, double* colbuf, hipStream_t s);
 void launch_column_from_unit(const int32_t* free_idx, size_t m, const double* ax, double* M, size_t col,
                              hipStream_t s);

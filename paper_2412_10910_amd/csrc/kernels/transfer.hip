@@ -221,17 +221,13 @@ struct Pow {
     static constexpr int value = DIM == 2 ? N * N : N * N * N;
 };
 
-// value at reference point x of the Q_k function with nodal values get(a) on
-// one cell: tensor-product evaluation, x direction innermost
+// value at a reference point of the Q_k function with nodal values get(a) on
+// one cell, from the 1D basis values px, py (, pz) at the point's
+// coordinates: tensor-product evaluation, x direction innermost
 template <int DIM, int N, class T, class Get>
-__device__ __forceinline__ T eval_point(const NodeTable<N, T>& nt, const T* x, Get get) {
-    T px[N], py[N];
-    lagrange_eval<N, T>(nt, x[0], px);
-    lagrange_eval<N, T>(nt, x[1], py);
+__device__ __forceinline__ T contract_point(const T* px, const T* py, const T* pz, Get get) {
     T val = T(0);
     if constexpr (DIM == 3) {
-        T pz[N];
-        lagrange_eval<N, T>(nt, x[2], pz);
         // one z-slice of values in flight at a time for the larger cells
         constexpr int ZU = N <= 3 ? N : 1;
 #pragma unroll ZU
@@ -247,6 +243,7 @@ __device__ __forceinline__ T eval_point(const NodeTable<N, T>& nt, const T* x, G
             val += pz[c] * s1;
         }
     } else {
+        (void)pz;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
             T s0 = T(0);
@@ -258,19 +255,23 @@ __device__ __forceinline__ T eval_point(const NodeTable<N, T>& nt, const T* x, G
     return val;
 }
 
-// NC components per node (vector DoF NC g + c): the staged values of a cell
-// are [node][component], and each point is evaluated once per component
-template <int DIM, int N, int NC, class T>
+// nv values per coarse node (nc components times nr interleaved right-hand
+// sides, value c of node g at g nv + c): the staged values of a cell are
+// [node][value], and the basis at a point is evaluated once for all values.
+// NVT > 0 fixes nv at compile time; NVT = 0 takes nv_in.
+template <int DIM, int N, class T, int NVT>
 __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
     const int32_t* __restrict__ off, const int32_t* __restrict__ fine, const T* __restrict__ xi, int64_t npts,
     const int32_t* __restrict__ blk_cells, const int32_t* __restrict__ cdm, const T* __restrict__ uc,
-    T* __restrict__ uf, NodeTable<N, T> nt) {
+    T* __restrict__ uf, NodeTable<N, T> nt, int nv_in) {
+    const int nv = NVT > 0 ? NVT : nv_in;
     constexpr int Q = Pow<DIM, N>::value;
-    constexpr int QC = Q * NC;  // staged values per cell
-    // LDS for the coarse values of up to NCMAX cells (16 KB in float64)
-    constexpr int NCMAX = (2048 / QC) < kPointBlock ? (2048 / QC) : kPointBlock;
-    __shared__ T su[NCMAX * QC];
-    __shared__ int32_t soff[NCMAX + 1];
+    // LDS for the coarse values of the block's first cells (16 KB in float64)
+    constexpr int kStage = 2048;
+    __shared__ T su[kStage];
+    __shared__ int32_t soff[kPointBlock + 1];
+    const int QC = Q * nv;  // staged values per cell
+    const int ncap = kStage / QC < kPointBlock ? kStage / QC : kPointBlock;
     const int64_t b = blockIdx.x;
     const int tid = threadIdx.x;
     const int64_t p = b * kPointBlock + tid;
@@ -286,14 +287,20 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
         for (int a = 0; a < DIM; ++a) x[a] = xi[a * npts + p];
     }
     const int c0 = blk_cells[2 * b], c1 = blk_cells[2 * b + 1];
-    const int ns = (c1 - c0 + 1) < NCMAX ? (c1 - c0 + 1) : NCMAX;  // cells staged in LDS
+    const int ns = (c1 - c0 + 1) < ncap ? (c1 - c0 + 1) : ncap;  // cells staged in LDS
     for (int i = tid; i <= ns; i += kPointBlock) soff[i] = off[c0 + i];
     for (int i = tid; i < ns * QC; i += kPointBlock) {
-        const int g = cdm[(int64_t)c0 * Q + i / NC];
-        su[i] = g >= 0 ? uc[(int64_t)g * NC + i % NC] : T(0);
+        const int a = nv == 1 ? i : i / nv;
+        const int g = cdm[(int64_t)c0 * Q + a];
+        su[i] = g >= 0 ? uc[(int64_t)g * nv + (i - a * nv)] : T(0);
     }
     __syncthreads();
     if (!valid) return;
+    T px[N], py[N], pz[N];
+    lagrange_eval<N, T>(nt, x[0], px);
+    lagrange_eval<N, T>(nt, x[1], py);
+    if constexpr (DIM == 3) lagrange_eval<N, T>(nt, x[2], pz);
+    T* out = uf + (int64_t)f * nv;
     if (p < soff[ns]) {
         // largest local cell i with soff[i] <= p (empty cells have equal offsets)
         int lo = 0, hi = ns;
@@ -302,9 +309,11 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
             if (soff[mid] <= p) lo = mid; else hi = mid;
         }
         const T* u = su + lo * QC;
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            uf[(int64_t)f * NC + c] += eval_point<DIM, N, T>(nt, x, [&](int a) { return u[a * NC + c]; });
+        if (nv == 1)  // constant LDS offsets
+            out[0] += contract_point<DIM, N, T>(px, py, pz, [&](int a) { return u[a]; });
+        else
+            for (int c = 0; c < nv; ++c)
+                out[c] += contract_point<DIM, N, T>(px, py, pz, [&](int a) { return u[a * nv + c]; });
     } else {
         // more cells in this block than LDS holds: search the offsets and
         // read the coarse values from global memory
@@ -314,11 +323,10 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
             if (off[mid] <= p) lo = mid; else hi = mid;
         }
         const int32_t* dm = cdm + (int64_t)lo * Q;
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            uf[(int64_t)f * NC + c] += eval_point<DIM, N, T>(nt, x, [&](int a) {
+        for (int c = 0; c < nv; ++c)
+            out[c] += contract_point<DIM, N, T>(px, py, pz, [&](int a) {
                 const int g = dm[a];
-                return g >= 0 ? uc[(int64_t)g * NC + c] : T(0);
+                return g >= 0 ? uc[(int64_t)g * nv + c] : T(0);
             });
     }
 }
@@ -359,20 +367,24 @@ __device__ __forceinline__ void butterfly_reduce(T (&R)[QP], int g, int S, int l
     }
 }
 
-// Restriction, one team of `team` = S * G lanes per coarse cell and
-// component (vector DoF NC i + c; NC = 1 for the Laplacian).  The G lane
+// Restriction, one team of `team` = S * G lanes per coarse cell and value
+// (nv = nc nr values per coarse node: nc components times nr interleaved
+// right-hand sides, value c nr + r of node i at nv i + c nr + r).  The G lane
 // groups split the cell's points; the S lanes of a group read the same points
 // and split the cell's q outputs by the slowest reference index (z in 3D, y in
 // 2D): lane s owns the NS = ceil(N / S) slices starting at s * NS, so that
 // only q / S accumulators live in registers.  The groups are reduced by the
-// butterfly above and the sums of slot k go to rbuf[NC k + c].
-template <int DIM, int N, int NC, class T, int S>
+// butterfly above; the sums of slot k for component c of right-hand side r go
+// to rbuf[r plane + nc k + c], the layout of the operator's contributions.
+template <int DIM, int N, class T, int S>
 __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ fine,
                                                        const T* __restrict__ xi, int64_t npts,
                                                        const int32_t* __restrict__ rslot,
                                                        const T* __restrict__ rf, T* __restrict__ rbuf,
-                                                       int ncells, int team_log2, NodeTable<N, T> nt) {
+                                                       int ncells, int team_log2, NodeTable<N, T> nt, int nc,
+                                                       int nr, int64_t plane) {
+    const int nv = nc * nr;
     constexpr int Q = Pow<DIM, N>::value;
     constexpr int NS = (N + S - 1) / S;      // slowest-index slices per lane
     constexpr int SLICE = Q / N;             // outputs per slice
@@ -381,21 +393,23 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
     constexpr int LQ = ilog2(QP);
     constexpr int JMAX = ilog2(64 / S);      // group levels of a 64-lane team
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t KC = gid >> team_log2;     // (cell, component) pair
+    const int64_t KC = gid >> team_log2;     // (cell, value) pair
     const int team = 1 << team_log2;
     const int t = (int)(gid & (team - 1));
     const int s = t % S, g = t / S, G = team / S;
     const int levels = team_log2 - ilog2(S);
     // KC and the point range are uniform over a team, so whole teams leave together
-    if (KC >= (int64_t)ncells * NC) return;
-    const int64_t K = NC == 1 ? KC : KC / NC;
-    const int comp = NC == 1 ? 0 : (int)(KC - K * NC);
+    if (KC >= (int64_t)ncells * nv) return;
+    const int64_t K = nv == 1 ? KC : KC / nv;
+    const int comp = (int)(KC - K * nv);
+    const int cc = nr == 1 ? comp : comp / nr, rr = comp - cc * nr;
+    T* __restrict__ out = rbuf + rr * plane + cc;  // slot k at out[nc k]
     const int p0 = off[K], p1 = off[K + 1];
     if (p0 == p1) {
         // a cell without points contributes zeros
         for (int a = t; a < Q; a += team) {
             const int k = rslot[K * Q + a];
-            if (k >= 0) rbuf[(int64_t)k * NC + comp] = T(0);
+            if (k >= 0) out[(int64_t)k * nc] = T(0);
         }
         return;
     }
@@ -416,7 +430,7 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
             for (int a = 0; a < DIM; ++a) xs[u][a] = ok ? xi[a * npts + p] : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) r[u] = fi[u] >= 0 ? rf[(int64_t)fi[u] * NC + comp] : T(0);
+        for (int u = 0; u < U; ++u) r[u] = fi[u] >= 0 ? rf[(int64_t)fi[u] * nv + comp] : T(0);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             T ps[N];
@@ -469,7 +483,7 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
         const int node = s * QL + o;
         if (i < held && o < QL && node < Q) {
             const int k = rslot[K * Q + node];
-            if (k >= 0) rbuf[(int64_t)k * NC + comp] = R[i];
+            if (k >= 0) out[(int64_t)k * nc] = R[i];
         }
     }
 }
@@ -500,58 +514,70 @@ static int log2i(int v) {
     return l;
 }
 
-template <int DIM, int N, int NC, class T>
-static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, const void* in, void* out,
+template <int DIM, int N, class T>
+static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, const void* in, void* out, int nv,
                               hipStream_t s) {
     const Level& C = *tr.coarse;
     if (tr.n_points == 0 || C.n_cells == 0) return;
     const NodeTable<N, T> nt = node_table<N, T>(C.basis);
     if (prolong) {
         const dim3 grid((unsigned)((tr.n_points + kPointBlock - 1) / kPointBlock));
-        hipLaunchKernelGGL((prolongate_points_kernel<DIM, N, NC, T>), grid, dim3(kPointBlock), 0, s, tr.d_off.ptr,
-                           tr.d_fine.ptr, xi, tr.n_points, tr.d_blk_cells.ptr, C.d_dofmap.ptr, (const T*)in,
-                           (T*)out, nt);
+#define NNMG_PROLONG(NVT)                                                                                   \
+    hipLaunchKernelGGL((prolongate_points_kernel<DIM, N, T, NVT>), grid, dim3(kPointBlock), 0, s, tr.d_off.ptr, \
+                       tr.d_fine.ptr, xi, tr.n_points, tr.d_blk_cells.ptr, C.d_dofmap.ptr, (const T*)in, (T*)out, \
+                       nt, nv)
+        if (nv == 1)
+            NNMG_PROLONG(1);
+        else if (nv == 3)
+            NNMG_PROLONG(3);
+        else
+            NNMG_PROLONG(0);
+#undef NNMG_PROLONG
         NNMG_HIP(hipGetLastError());
         return;
     }
     constexpr int S = DIM == 3 ? restrict_split<N, T>() : 1;
     const int team = std::max(tr.team, S);
     const int threads = 256;
-    const int64_t total = C.n_cells * (int64_t)NC * team;
+    const int64_t total = C.n_cells * (int64_t)nv * team;
     const dim3 grid((unsigned)((total + threads - 1) / threads));
-    hipLaunchKernelGGL((restrict_kernel<DIM, N, NC, T, S>), grid, dim3(threads), 0, s, tr.d_off.ptr, tr.d_fine.ptr, xi,
+    hipLaunchKernelGGL((restrict_kernel<DIM, N, T, S>), grid, dim3(threads), 0, s, tr.d_off.ptr, tr.d_fine.ptr, xi,
                        tr.n_points, tr.d_rslot.ptr, (const T*)in, (T*)tr.d_rbuf.ptr, (int)C.n_cells,
-                       log2i(team), nt);
+                       log2i(team), nt, C.ncomp, nv / C.ncomp, (int64_t)(tr.n_rslots * C.ncomp));
     NNMG_HIP(hipGetLastError());
 }
 
 template <class T>
-static void transfer_prec(const Transfer& tr, bool prolong, const T* xi, const void* in, void* out,
+static void transfer_prec(const Transfer& tr, bool prolong, const T* xi, const void* in, void* out, int nr,
                           hipStream_t s) {
-    const int d = tr.coarse->dim, n = tr.coarse->n, nc = tr.coarse->ncomp;
-#define NNMG_CASE(D, NN, NCC) \
-    if (d == D && n == NN && nc == NCC) return transfer_dispatch<D, NN, NCC, T>(tr, prolong, xi, in, out, s);
-    NNMG_CASE(2, 2, 1) NNMG_CASE(2, 3, 1) NNMG_CASE(2, 4, 1) NNMG_CASE(2, 5, 1)
-    NNMG_CASE(3, 2, 1) NNMG_CASE(3, 3, 1) NNMG_CASE(3, 4, 1) NNMG_CASE(3, 5, 1)
-    NNMG_CASE(3, 2, 3) NNMG_CASE(3, 3, 3) NNMG_CASE(3, 4, 3) NNMG_CASE(3, 5, 3)
+    const int d = tr.coarse->dim, n = tr.coarse->n;
+    if (nr < 1 || nr > kMaxRhs) fail(NNMG_ERR_INVALID_ARG, "number of right-hand sides");
+    const int nv = tr.coarse->ncomp * nr;
+#define NNMG_CASE(D, NN) \
+    if (d == D && n == NN) return transfer_dispatch<D, NN, T>(tr, prolong, xi, in, out, nv, s);
+    NNMG_CASE(2, 2) NNMG_CASE(2, 3) NNMG_CASE(2, 4) NNMG_CASE(2, 5)
+    NNMG_CASE(3, 2) NNMG_CASE(3, 3) NNMG_CASE(3, 4) NNMG_CASE(3, 5)
 #undef NNMG_CASE
     fail(NNMG_ERR_UNSUPPORTED, "transfer degree/dimension");
 }
 
-void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fine, hipStream_t s) {
+void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fine, hipStream_t s, int nr) {
     if (prec == NNMG_FP64)
-        transfer_prec<double>(t, true, t.d_xi64.ptr, coarse, fine, s);
+        transfer_prec<double>(t, true, t.d_xi64.ptr, coarse, fine, nr, s);
     else
-        transfer_prec<float>(t, true, t.d_xi32.ptr, coarse, fine, s);
+        transfer_prec<float>(t, true, t.d_xi32.ptr, coarse, fine, nr, s);
 }
 
-void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s) {
+// rbuf must hold nr values per slot: Transfer::rbuf_rhs right-hand sides
+void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s,
+                     int nr) {
+    if (nr > t.rbuf_rhs) fail(NNMG_ERR_INVALID_ARG, "restriction buffer holds fewer right-hand sides");
     if (prec == NNMG_FP64)
-        transfer_prec<double>(t, false, t.d_xi64.ptr, fine, coarse, s);
+        transfer_prec<double>(t, false, t.d_xi64.ptr, fine, coarse, nr, s);
     else
-        transfer_prec<float>(t, false, t.d_xi32.ptr, fine, coarse, s);
-    launch_gather_runs((size_t)t.coarse->n_dofs, t.coarse->ncomp, t.d_roff.ptr, prec, t.d_rbuf.ptr, coarse,
-                       accumulate, s);
+        transfer_prec<float>(t, false, t.d_xi32.ptr, fine, coarse, nr, s);
+    launch_gather_runs((size_t)t.coarse->n_dofs, t.coarse->ncomp, t.d_roff.ptr, prec, t.d_rbuf.ptr,
+                       t.n_rslots * (size_t)t.coarse->ncomp, coarse, accumulate, s, nr);
 }
 
 }  // namespace nnmg

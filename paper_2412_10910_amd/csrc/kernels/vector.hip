@@ -19,6 +19,19 @@ static dim3 grid_for(size_t n, int threads = 256, size_t cap = 1 << 20) {
     return dim3((unsigned)g);
 }
 
+#define NNMG_NR_DISPATCH(nr, ...)                                    \
+    switch (nr) {                                                    \
+        case 1: { constexpr int NR = 1; __VA_ARGS__; } break;               \
+        case 2: { constexpr int NR = 2; __VA_ARGS__; } break;               \
+        case 3: { constexpr int NR = 3; __VA_ARGS__; } break;               \
+        case 4: { constexpr int NR = 4; __VA_ARGS__; } break;               \
+        case 5: { constexpr int NR = 5; __VA_ARGS__; } break;               \
+        case 6: { constexpr int NR = 6; __VA_ARGS__; } break;               \
+        case 7: { constexpr int NR = 7; __VA_ARGS__; } break;               \
+        case 8: { constexpr int NR = 8; __VA_ARGS__; } break;               \
+        default: fail(NNMG_ERR_INVALID_ARG, "number of right-hand sides"); \
+    }
+
 template <class T>
 __global__ void fill_kernel(T* __restrict__ x, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -52,20 +65,26 @@ void launch_cast_32_to_64(const float* a, double* b, size_t n, hipStream_t s) {
     NNMG_HIP(hipGetLastError());
 }
 
+// dst = src on the listed vector DoFs, for nr interleaved right-hand sides
 template <class T>
-__global__ void copy_idx_kernel(const int32_t* __restrict__ idx, size_t n, const T* __restrict__ src,
+__global__ void copy_idx_kernel(const int32_t* __restrict__ idx, size_t n, int nr, const T* __restrict__ src,
                                 T* __restrict__ dst) {
     const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (i < n) dst[idx[i]] = src[idx[i]];
+    if (i < n * (size_t)nr) {
+        const size_t v = (size_t)idx[i / nr] * nr + i % nr;
+        dst[v] = src[v];
+    }
 }
 
-void launch_copy_constrained(const int32_t* idx, size_t n, const void* src, void* dst, int prec, hipStream_t s) {
+void launch_copy_constrained(const int32_t* idx, size_t n, const void* src, void* dst, int prec, hipStream_t s,
+                             int nr) {
     if (n == 0) return;
-    const dim3 g((unsigned)((n + 255) / 256));
+    const dim3 g((unsigned)((n * (size_t)nr + 255) / 256));
     if (prec == NNMG_FP64)
-        hipLaunchKernelGGL(copy_idx_kernel<double>, g, dim3(256), 0, s, idx, n, (const double*)src, (double*)dst);
+        hipLaunchKernelGGL(copy_idx_kernel<double>, g, dim3(256), 0, s, idx, n, nr, (const double*)src,
+                           (double*)dst);
     else
-        hipLaunchKernelGGL(copy_idx_kernel<float>, g, dim3(256), 0, s, idx, n, (const float*)src, (float*)dst);
+        hipLaunchKernelGGL(copy_idx_kernel<float>, g, dim3(256), 0, s, idx, n, nr, (const float*)src, (float*)dst);
     NNMG_HIP(hipGetLastError());
 }
 
@@ -88,49 +107,56 @@ void launch_set_constrained(const int32_t* idx, size_t n, double v, void* dst, i
 // ---------------------------------------------------------------------------
 // Chebyshev smoother steps
 // ---------------------------------------------------------------------------
-template <class T>
+// n values; dinv is per vector DoF, shared by the NR interleaved right-hand sides
+template <int NR, class T>
 __global__ void cheb_first_zero_kernel(size_t n, const T* __restrict__ f, const T* __restrict__ dinv,
                                        T* __restrict__ x, T* __restrict__ d, T c0) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const T v = dinv[i] * f[i] * c0;
+        const T v = dinv[NR == 1 ? i : i / NR] * f[i] * c0;
         d[i] = v;
         x[i] = v;
     }
 }
 
 void launch_cheb_first_zero(int prec, size_t n, const void* f, const void* dinv, void* x, void* d, double c0,
-                            hipStream_t s) {
+                            hipStream_t s, int nr) {
     if (n == 0) return;
-    if (prec == NNMG_FP64)
-        hipLaunchKernelGGL(cheb_first_zero_kernel<double>, grid_for(n), dim3(256), 0, s, n, (const double*)f,
-                           (const double*)dinv, (double*)x, (double*)d, c0);
-    else
-        hipLaunchKernelGGL(cheb_first_zero_kernel<float>, grid_for(n), dim3(256), 0, s, n, (const float*)f,
-                           (const float*)dinv, (float*)x, (float*)d, (float)c0);
+    const size_t nv = n * (size_t)nr;
+    NNMG_NR_DISPATCH(nr, {
+        if (prec == NNMG_FP64)
+            hipLaunchKernelGGL((cheb_first_zero_kernel<NR, double>), grid_for(nv), dim3(256), 0, s, nv,
+                               (const double*)f, (const double*)dinv, (double*)x, (double*)d, c0);
+        else
+            hipLaunchKernelGGL((cheb_first_zero_kernel<NR, float>), grid_for(nv), dim3(256), 0, s, nv,
+                               (const float*)f, (const float*)dinv, (float*)x, (float*)d, (float)c0);
+    });
     NNMG_HIP(hipGetLastError());
 }
 
-template <class T>
+template <int NR, class T>
 __global__ void cheb_step_kernel(size_t n, const T* __restrict__ f, T* __restrict__ ax, const T* __restrict__ dinv,
                                  T* __restrict__ x, T* __restrict__ d, T c1, T c2) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const T r = f[i] - ax[i];
         ax[i] = T(0);
-        const T dn = c1 * d[i] + c2 * (dinv[i] * r);
+        const T dn = c1 * d[i] + c2 * (dinv[NR == 1 ? i : i / NR] * r);
         d[i] = dn;
         x[i] += dn;
     }
 }
 
 void launch_cheb_step(int prec, size_t n, const void* f, void* ax, const void* dinv, void* x, void* d, double c1,
-                      double c2, hipStream_t s) {
+                      double c2, hipStream_t s, int nr) {
     if (n == 0) return;
-    if (prec == NNMG_FP64)
-        hipLaunchKernelGGL(cheb_step_kernel<double>, grid_for(n), dim3(256), 0, s, n, (const double*)f,
-                           (double*)ax, (const double*)dinv, (double*)x, (double*)d, c1, c2);
-    else
-        hipLaunchKernelGGL(cheb_step_kernel<float>, grid_for(n), dim3(256), 0, s, n, (const float*)f, (float*)ax,
-                           (const float*)dinv, (float*)x, (float*)d, (float)c1, (float)c2);
+    const size_t nv = n * (size_t)nr;
+    NNMG_NR_DISPATCH(nr, {
+        if (prec == NNMG_FP64)
+            hipLaunchKernelGGL((cheb_step_kernel<NR, double>), grid_for(nv), dim3(256), 0, s, nv, (const double*)f,
+                               (double*)ax, (const double*)dinv, (double*)x, (double*)d, c1, c2);
+        else
+            hipLaunchKernelGGL((cheb_step_kernel<NR, float>), grid_for(nv), dim3(256), 0, s, nv, (const float*)f,
+                               (float*)ax, (const float*)dinv, (float*)x, (float*)d, (float)c1, (float)c2);
+    });
     NNMG_HIP(hipGetLastError());
 }
 
@@ -187,7 +213,11 @@ void launch_splitmix_vector(double* v, const uint8_t* unused, size_t n, uint64_t
 }
 
 // ---------------------------------------------------------------------------
-// float64 reductions, two stages with a fixed partition: deterministic
+// float64 reductions, two stages with a fixed partition: deterministic.
+// With NR interleaved right-hand sides the lanes stride over the rows (vector
+// DoFs) exactly as for one right-hand side and keep NR sums, so that each
+// right-hand side is reduced in the order it would be on its own; the first
+// stage writes partial[block][NR], the second reduces each column.
 // ---------------------------------------------------------------------------
 constexpr int kRedThreads = 256;
 constexpr size_t kRedMaxBlocks = 1024;
@@ -199,99 +229,135 @@ size_t dot_partials(size_t n) {
     return g;
 }
 
-__device__ inline double block_sum(double v) {
-    __shared__ double sh[kRedThreads / kWave];
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+// block sums of v[0..NR), written by thread r < NR to out[r * ostride]
+template <int NR>
+__device__ inline void block_sums(const double (&v)[NR], double* out, size_t ostride) {
+    __shared__ double sh[NR][kRedThreads / kWave];
     const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
-    if (l == 0) sh[w] = v;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        double a = v[r];
+        for (int o = kWave / 2; o > 0; o >>= 1) a += __shfl_down(a, o, kWave);
+        if (l == 0) sh[r][w] = a;
+    }
     __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kRedThreads / kWave; ++i) s += sh[i];
-    return s;  // valid in thread 0
+    if (threadIdx.x < NR) {
+        double s = 0.0;
+        for (int i = 0; i < kRedThreads / kWave; ++i) s += sh[threadIdx.x][i];
+        out[threadIdx.x * ostride] = s;
+    }
 }
 
+template <int NR>
 __global__ __launch_bounds__(kRedThreads) void dot_stage1(const double* __restrict__ a, const double* __restrict__ b,
                                                           size_t n, double* __restrict__ partial) {
-    double s = 0.0;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        s += a[i] * b[i];
-    s = block_sum(s);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    double s[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) s[r] = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s[r] += a[i * NR + r] * b[i * NR + r];
+    }
+    block_sums<NR>(s, partial + blockIdx.x * NR, 1);
 }
 
-__global__ __launch_bounds__(kRedThreads) void sum_stage2(const double* __restrict__ partial, size_t m,
-                                                          double* __restrict__ out) {
-    double s = 0.0;
-    for (size_t i = threadIdx.x; i < m; i += blockDim.x) s += partial[i];
-    s = block_sum(s);
-    if (threadIdx.x == 0) *out = s;
+// out[r] = sum over the m blocks of partial[block][r]; one block per column
+__global__ __launch_bounds__(kRedThreads) void sum_stage2(const double* __restrict__ partial, size_t m, int nr,
+                                                          double* __restrict__ out, size_t ostride) {
+    const int r = blockIdx.x;
+    double s[1] = {0.0};
+    for (size_t i = threadIdx.x; i < m; i += blockDim.x) s[0] += partial[i * nr + r];
+    block_sums<1>(s, out + r * ostride, 1);
 }
 
-void launch_sum_partials(const double* partial, size_t m, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(kRedThreads), 0, s, partial, m, out);
+void launch_sum_partials(const double* partial, size_t m, double* out, hipStream_t s, int nr, size_t ostride) {
+    hipLaunchKernelGGL(sum_stage2, dim3((unsigned)nr), dim3(kRedThreads), 0, s, partial, m, nr, out, ostride);
     NNMG_HIP(hipGetLastError());
 }
 
-void launch_dot(const double* a, const double* b, size_t n, double* partial, double* out, hipStream_t s) {
+void launch_dot(const double* a, const double* b, size_t n, double* partial, double* out, hipStream_t s, int nr,
+                size_t ostride) {
     const size_t g = dot_partials(n);
-    hipLaunchKernelGGL(dot_stage1, dim3((unsigned)g), dim3(kRedThreads), 0, s, a, b, n, partial);
-    hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(kRedThreads), 0, s, partial, g, out);
-    NNMG_HIP(hipGetLastError());
+    NNMG_NR_DISPATCH(nr, {
+        hipLaunchKernelGGL((dot_stage1<NR>), dim3((unsigned)g), dim3(kRedThreads), 0, s, a, b, n, partial);
+    });
+    launch_sum_partials(partial, g, out, s, nr, ostride);
 }
 
-// scal: [0] rz, [1] pq, [2] alpha, [3] rr, [4] rz_new, [5] beta
+// CG scalars of right-hand side r at scal + r * kScal:
+// [0] rz, [1] pq, [2] alpha, [3] rr, [4] rz_new, [5] beta, [6] b.b, [7] active (1 or 0)
+template <int NR>
 __global__ __launch_bounds__(kRedThreads) void cg_update_stage1(size_t n, double* __restrict__ x,
                                                                 double* __restrict__ r, const double* __restrict__ p,
                                                                 const double* __restrict__ q,
                                                                 const double* __restrict__ scal,
                                                                 double* __restrict__ partial) {
-    const double alpha = scal[2];
-    double s = 0.0;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        x[i] += alpha * p[i];
-        const double rn = r[i] - alpha * q[i];
-        r[i] = rn;
-        s += rn * rn;
+    double alpha[NR], s[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        alpha[k] = scal[k * kScal + 2];
+        s[k] = 0.0;
     }
-    s = block_sum(s);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const size_t v = i * NR + k;
+            x[v] += alpha[k] * p[v];
+            const double rn = r[v] - alpha[k] * q[v];
+            r[v] = rn;
+            s[k] += rn * rn;
+        }
+    }
+    block_sums<NR>(s, partial + blockIdx.x * NR, 1);
 }
 
 void launch_cg_update(size_t n, double* x, double* r, const double* p, const double* q, const double* scal,
-                      double* partial, double* rr_out, hipStream_t s) {
+                      double* partial, double* rr_out, hipStream_t s, int nr) {
     const size_t g = dot_partials(n);
-    hipLaunchKernelGGL(cg_update_stage1, dim3((unsigned)g), dim3(kRedThreads), 0, s, n, x, r, p, q, scal, partial);
-    hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(kRedThreads), 0, s, partial, g, rr_out);
-    NNMG_HIP(hipGetLastError());
+    NNMG_NR_DISPATCH(nr, {
+        hipLaunchKernelGGL((cg_update_stage1<NR>), dim3((unsigned)g), dim3(kRedThreads), 0, s, n, x, r, p, q, scal,
+                           partial);
+    });
+    launch_sum_partials(partial, g, rr_out, s, nr, kScal);
 }
 
+template <int NR>
 __global__ void cg_direction_kernel(size_t n, const double* __restrict__ z, double* __restrict__ p,
                                     const double* __restrict__ scal) {
-    const double beta = scal[5];
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = z[i] + beta * p[i];
-}
-
-void launch_cg_direction(size_t n, const double* z, double* p, const double* scal, hipStream_t s) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(cg_direction_kernel, grid_for(n), dim3(256), 0, s, n, z, p, scal);
-    NNMG_HIP(hipGetLastError());
-}
-
-// op 0: alpha = rz / pq;  op 1: beta = rz_new / rz, rz = rz_new
-__global__ void scalar_kernel(double* scal, int op) {
-    if (threadIdx.x != 0) return;
-    if (op == 0) {
-        scal[2] = scal[0] / scal[1];
-    } else {
-        scal[5] = scal[4] / scal[0];
-        scal[0] = scal[4];
+    double beta[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) beta[k] = scal[k * kScal + 5];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) p[i * NR + k] = z[i * NR + k] + beta[k] * p[i * NR + k];
     }
 }
 
-void launch_scalar_op(double* scal, int op, hipStream_t s) {
-    hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(1), 0, s, scal, op);
+void launch_cg_direction(size_t n, const double* z, double* p, const double* scal, hipStream_t s, int nr) {
+    if (n == 0) return;
+    NNMG_NR_DISPATCH(nr, {
+        hipLaunchKernelGGL((cg_direction_kernel<NR>), grid_for(n), dim3(256), 0, s, n, z, p, scal);
+    });
+    NNMG_HIP(hipGetLastError());
+}
+
+// op 0: alpha = rz / pq;  op 1: beta = rz_new / rz, rz = rz_new.  A right-hand
+// side that is no longer active gets alpha = beta = 0 and keeps its iterate.
+__global__ void scalar_kernel(double* scal, int op, int nr) {
+    const int k = threadIdx.x;
+    if (k >= nr) return;
+    double* c = scal + k * kScal;
+    const bool on = c[7] != 0.0;
+    if (op == 0) {
+        c[2] = on ? c[0] / c[1] : 0.0;
+    } else {
+        c[5] = on ? c[4] / c[0] : 0.0;
+        c[0] = c[4];
+    }
+}
+
+void launch_scalar_op(double* scal, int op, hipStream_t s, int nr) {
+    hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(64), 0, s, scal, op, nr);
     NNMG_HIP(hipGetLastError());
 }
 
@@ -325,51 +391,67 @@ void launch_axpy(size_t n, double a_sign, const double* scal_a, int idx, const d
 // ---------------------------------------------------------------------------
 // dense coarse solve: explicit inverse of the unconstrained block
 // ---------------------------------------------------------------------------
-// Coarse solve step on the unconstrained block, one 256-lane block per row:
-//   y_i = base_i + sign * sum_j M_ij v_j,
-// with v_j = V[vidx[j]] (or V[j]) and base_i = B[bidx[i]] (or B[i], or 0),
-// stored to O[oidx[i]] (or O[i]) in O's precision.  Rows are read coalesced;
-// the row sum is reduced in a fixed order.
-template <class TV, class TB, class TO>
+// Coarse solve step on the unconstrained block, one 256-lane block per row,
+// for NR interleaved right-hand sides at once (the row is read once):
+//   y_i,r = base_i,r + sign * sum_j M_ij v_j,r,
+// with v_j,r = V[vidx[j] NR + r] (or V[j NR + r]) and base_i,r = B[bidx[i] NR + r]
+// (or B[i NR + r], or 0), stored to O[oidx[i] NR + r] (or O[i NR + r]) in O's
+// precision.  Rows are read coalesced; each row sum is reduced in a fixed
+// order, the same for every NR.
+template <int NR, class TV, class TB, class TO>
 __global__ __launch_bounds__(256) void coarse_gemv_kernel(const double* __restrict__ M, size_t m,
                                                           const TV* __restrict__ V, const int32_t* __restrict__ vidx,
                                                           const TB* __restrict__ B, const int32_t* __restrict__ bidx,
                                                           double sign, TO* __restrict__ O,
                                                           const int32_t* __restrict__ oidx) {
-    __shared__ double part[256 / kWave];
+    __shared__ double part[NR][256 / kWave];
     const size_t row = blockIdx.x;
     const double* a = M + row * m;
-    double s = 0.0;
-    for (size_t j = threadIdx.x; j < m; j += 256) s += a[j] * (double)V[vidx ? vidx[j] : j];
-    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kWave);
-    if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = s;
+    double s[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) s[r] = 0.0;
+    for (size_t j = threadIdx.x; j < m; j += 256) {
+        const double mj = a[j];
+        const size_t vj = (vidx ? (size_t)vidx[j] : j) * NR;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s[r] += mj * (double)V[vj + r];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        double v = s[r];
+        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+        if (threadIdx.x % kWave == 0) part[r][threadIdx.x / kWave] = v;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < NR) {
+        const int r = threadIdx.x;
         double t = 0.0;
-        for (int w = 0; w < 256 / kWave; ++w) t += part[w];
-        const double b = B ? (double)B[bidx ? bidx[row] : row] : 0.0;
-        O[oidx ? oidx[row] : row] = (TO)(b + sign * t);
+        for (int w = 0; w < 256 / kWave; ++w) t += part[r][w];
+        const double b = B ? (double)B[(bidx ? (size_t)bidx[row] : row) * NR + r] : 0.0;
+        O[(oidx ? (size_t)oidx[row] : row) * NR + r] = (TO)(b + sign * t);
     }
 }
 
 template <class TV, class TB, class TO>
 static void coarse_gemv_t(const double* M, size_t m, const void* V, const int32_t* vidx, const void* B,
-                          const int32_t* bidx, double sign, void* O, const int32_t* oidx, hipStream_t s) {
-    hipLaunchKernelGGL((coarse_gemv_kernel<TV, TB, TO>), dim3((unsigned)m), dim3(256), 0, s, M, m, (const TV*)V, vidx,
-                       (const TB*)B, bidx, sign, (TO*)O, oidx);
+                          const int32_t* bidx, double sign, void* O, const int32_t* oidx, int nr, hipStream_t s) {
+    NNMG_NR_DISPATCH(nr, {
+        hipLaunchKernelGGL((coarse_gemv_kernel<NR, TV, TB, TO>), dim3((unsigned)m), dim3(256), 0, s, M, m,
+                           (const TV*)V, vidx, (const TB*)B, bidx, sign, (TO*)O, oidx);
+    });
 }
 
 void launch_coarse_gemv(const double* M, size_t m, const void* V, int vprec, const int32_t* vidx, const void* B,
                         int bprec, const int32_t* bidx, double sign, void* O, int oprec, const int32_t* oidx,
-                        hipStream_t s) {
+                        hipStream_t s, int nr) {
     if (m == 0) return;
     const bool v64 = vprec == NNMG_FP64, b64 = bprec == NNMG_FP64, o64 = oprec == NNMG_FP64;
-    if (v64 && b64 && o64) coarse_gemv_t<double, double, double>(M, m, V, vidx, B, bidx, sign, O, oidx, s);
-    else if (!v64 && b64 && o64) coarse_gemv_t<float, double, double>(M, m, V, vidx, B, bidx, sign, O, oidx, s);
-    else if (v64 && !b64 && o64) coarse_gemv_t<double, float, double>(M, m, V, vidx, B, bidx, sign, O, oidx, s);
-    else if (v64 && b64 && !o64) coarse_gemv_t<double, double, float>(M, m, V, vidx, B, bidx, sign, O, oidx, s);
+    if (v64 && b64 && o64) coarse_gemv_t<double, double, double>(M, m, V, vidx, B, bidx, sign, O, oidx, nr, s);
+    else if (!v64 && b64 && o64) coarse_gemv_t<float, double, double>(M, m, V, vidx, B, bidx, sign, O, oidx, nr, s);
+    else if (v64 && !b64 && o64) coarse_gemv_t<double, float, double>(M, m, V, vidx, B, bidx, sign, O, oidx, nr, s);
+    else if (v64 && b64 && !o64) coarse_gemv_t<double, double, float>(M, m, V, vidx, B, bidx, sign, O, oidx, nr, s);
     else if (!v64 && !o64 && B == nullptr)
-        coarse_gemv_t<float, double, float>(M, m, V, vidx, nullptr, nullptr, sign, O, oidx, s);
+        coarse_gemv_t<float, double, float>(M, m, V, vidx, nullptr, nullptr, sign, O, oidx, nr, s);
     else fail(NNMG_ERR_INVALID_ARG, "coarse_gemv precision combination");
     NNMG_HIP(hipGetLastError());
 }

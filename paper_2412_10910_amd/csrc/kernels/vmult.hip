@@ -108,12 +108,22 @@ constexpr int kAtomic = 1;
 #ifndef NNMG_VMULT_MINWAVES
 #define NNMG_VMULT_MINWAVES 1
 #endif
-template <int DIM, int N, class T, int GEO, int SCATTER>
+// nr right-hand sides (vectors interleaved as [DoF][nr]) are applied one
+// after the other by each block: the indices, slots, map coefficients and
+// tables are loaded once per cell for all of them.  The contributions of
+// right-hand side r go to their own plane, dst + r * plane, so that each
+// pass stores exactly what a single-vector call stores (interleaved stores
+// would write partial cache lines); the atomic variant adds into the
+// interleaved output vector.  NRT = 1 fixes nr = 1 at
+// compile time (the loop disappears); NRT = 0 takes nr_in.
+template <int DIM, int N, class T, int GEO, int SCATTER, int NRT>
 __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vmult_kernel(const int32_t* __restrict__ dmap,
                                                                     const T* __restrict__ geo,
                                                                     const T* __restrict__ src,
                                                                     const int32_t* __restrict__ slots,
-                                                                    T* __restrict__ dst, OpTables<N, T> tb) {
+                                                                    T* __restrict__ dst, OpTables<N, T> tb,
+                                                                    int nr_in, int64_t plane) {
+    const int nr = NRT > 0 ? NRT : nr_in;
     using Sh = OpShape<DIM, N>;
     constexpr int L = Sh::L, WG = Sh::WG, CPB = Sh::CPB, TILE = Sh::TILE;
     constexpr int M = DIM * (DIM + 1) / 2;
@@ -170,7 +180,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
     for (int e = 0; e < TE; ++e)
         tv[e] = lane + e * WG < NT ? reinterpret_cast<const T*>(&tb)[lane + e * WG] : T(0);
 #pragma unroll
-    for (int i = 0; i < N; ++i) u[i] = idx[i] >= 0 ? src[idx[i]] : T(0);
+    for (int i = 0; i < N; ++i) u[i] = idx[i] >= 0 ? src[(int64_t)idx[i] * nr] : T(0);
     if constexpr (GEO == kTrilinear) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -191,6 +201,13 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
     T* B = lds[1][cb];
     T* Cc = lds[2][cb];
 
+    for (int rhs = 0;;) {
+    // the next right-hand side's values are loaded while this one is swept
+    T un[N];
+    if (NRT != 1 && rhs + 1 < nr) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) un[i] = idx[i] >= 0 ? src[(int64_t)idx[i] * nr + rhs + 1] : T(0);
+    }
     // ---- forward --------------------------------------------------------
     line_apply<N, T, false>(tb.S, u, v);  // x: nodes -> Gauss points
     T gz[N];                              // derivative along the last direction
@@ -426,13 +443,19 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
                     v[i] += nxt;
                     k &= ~kMergeNext;
                 }
-                dst[k] = v[i];
+                dst[(int64_t)rhs * plane + k] = v[i];
             }
         }
     } else {
 #pragma unroll
         for (int i = 0; i < N; ++i)
-            if (idx[i] >= 0) atomic_add(dst + idx[i], v[i]);
+            if (idx[i] >= 0) atomic_add(dst + (int64_t)idx[i] * nr + rhs, v[i]);
+    }
+    if (++rhs >= nr) break;
+    // the tiles are rewritten by the next right-hand side
+    block_sync<WG>();
+#pragma unroll
+    for (int i = 0; i < N; ++i) u[i] = un[i];
     }
 }
 
@@ -449,15 +472,17 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
 // products of the columns of J),
 //   grad u = ghat R / det J,  sigma as above,  F = w sigma R^T,
 // and F_c,k is integrated against d phi / d xi_k by the backward sweeps, one
-// component at a time; component c of slot k is contrib[3 k + c].
+// component at a time; component c of slot k is contrib[3 k + c] in the
+// plane of its right-hand side.
 // ---------------------------------------------------------------------------
-template <int N, class T>
+template <int N, class T, int NRT>
 __global__ __launch_bounds__((OpShape<3, N>::WG)) void elasticity_kernel(const int32_t* __restrict__ dmap,
                                                                          const T* __restrict__ geo,
                                                                          const T* __restrict__ src,
                                                                          const int32_t* __restrict__ slots,
                                                                          T* __restrict__ dst, OpTables<N, T> tb,
-                                                                         T lam, T mu) {
+                                                                         T lam, T mu, int nr_in, int64_t plane) {
+    const int nr = NRT > 0 ? NRT : nr_in;  // as in vmult_kernel
     using Sh = OpShape<3, N>;
     constexpr int L = Sh::L, WG = Sh::WG, CPB = Sh::CPB, TILE = Sh::TILE;
     constexpr int NC = 21;
@@ -502,7 +527,7 @@ __global__ __launch_bounds__((OpShape<3, N>::WG)) void elasticity_kernel(const i
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int i = 0; i < N; ++i) uc[c][i] = idx[i] >= 0 ? src[(int64_t)idx[i] * 3 + c] : T(0);
+        for (int i = 0; i < N; ++i) uc[c][i] = idx[i] >= 0 ? src[((int64_t)idx[i] * 3 + c) * nr] : T(0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int m = line + r * L;
@@ -521,6 +546,16 @@ __global__ __launch_bounds__((OpShape<3, N>::WG)) void elasticity_kernel(const i
     T* Cc = lds[2][cb];
     auto G = [&](int c, int k, int i) -> T& { return lg9[(c * 3 + k) * N + i][lane]; };
 
+    for (int rhs = 0;;) {
+    // the next right-hand side's values are loaded while this one is swept
+    T ucn[3][N];
+    if (NRT != 1 && rhs + 1 < nr) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+                ucn[c][i] = idx[i] >= 0 ? src[((int64_t)idx[i] * 3 + c) * nr + rhs + 1] : T(0);
+    }
     // ---- forward, one component at a time ---------------------------------
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
@@ -691,10 +726,16 @@ __global__ __launch_bounds__((OpShape<3, N>::WG)) void elasticity_kernel(const i
                     v[i] += nxt;
                     k &= ~kMergeNext;
                 }
-                dst[(int64_t)k * 3 + c] = v[i];
+                dst[(int64_t)rhs * plane + (int64_t)k * 3 + c] = v[i];
             }
         }
         block_sync<WG>();
+    }
+    if (++rhs >= nr) break;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < N; ++i) uc[c][i] = ucn[c][i];
     }
 }
 
@@ -714,73 +755,94 @@ static OpTables<N, T> make_tables(const Basis1D& b) {
 }
 
 template <int DIM, int N, class T, int GEO>
-static void vmult_launches(const Level& L, const T* geo, bool atomic, const void* src, void* dst, hipStream_t s) {
+static void vmult_launches(const Level& L, const T* geo, bool atomic, const void* src, void* dst, int nr,
+                           hipStream_t s) {
     using Sh = OpShape<DIM, N>;
     const OpTables<N, T> tb = make_tables<N, T>(L.basis);
     const dim3 grid((unsigned)L.nblocks), block(Sh::WG);
-    if (atomic)
-        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kAtomic>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
-                           (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb);
-    else
-        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
-                           (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb);
+    const int64_t plane = (int64_t)contrib_plane(L);
+    if (atomic) {
+        if (nr == 1)
+            hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kAtomic, 1>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
+                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane);
+        else
+            hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kAtomic, 0>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
+                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane);
+    } else {
+        if (nr == 1)
+            hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 1>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
+                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane);
+        else
+            hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 0>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
+                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane);
+    }
     NNMG_HIP(hipGetLastError());
 }
 
 template <int DIM, int N, class T>
-static void vmult_dispatch(const Level& L, const T* geo, int mode, bool atomic, const void* src, void* dst,
+static void vmult_dispatch(const Level& L, const T* geo, int mode, bool atomic, const void* src, void* dst, int nr,
                            hipStream_t s) {
     if (L.nblocks == 0) return;
     if constexpr (DIM == 3) {
         if (L.op == NNMG_OP_ELASTICITY) {
             // contribution slots only (no atomic variant), trilinear geometry
             const OpTables<N, T> tb = make_tables<N, T>(L.basis);
-            hipLaunchKernelGGL((elasticity_kernel<N, T>), dim3((unsigned)L.nblocks), dim3(OpShape<3, N>::WG), 0, s,
-                               L.d_dofmap_blk.ptr, geo, (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, (T)L.lam,
-                               (T)L.mu);
+            const int64_t plane = (int64_t)contrib_plane(L);
+            if (nr == 1)
+                hipLaunchKernelGGL((elasticity_kernel<N, T, 1>), dim3((unsigned)L.nblocks), dim3(OpShape<3, N>::WG), 0,
+                                   s, L.d_dofmap_blk.ptr, geo, (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, (T)L.lam,
+                                   (T)L.mu, nr, plane);
+            else
+                hipLaunchKernelGGL((elasticity_kernel<N, T, 0>), dim3((unsigned)L.nblocks), dim3(OpShape<3, N>::WG), 0,
+                                   s, L.d_dofmap_blk.ptr, geo, (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, (T)L.lam,
+                                   (T)L.mu, nr, plane);
             NNMG_HIP(hipGetLastError());
             return;
         }
     }
     if (mode == kTrilinear)
-        vmult_launches<DIM, N, T, kTrilinear>(L, geo, atomic, src, dst, s);
+        vmult_launches<DIM, N, T, kTrilinear>(L, geo, atomic, src, dst, nr, s);
     else
-        vmult_launches<DIM, N, T, kStoredMetric>(L, geo, atomic, src, dst, s);
+        vmult_launches<DIM, N, T, kStoredMetric>(L, geo, atomic, src, dst, nr, s);
 }
 
 template <class T>
-static void vmult_prec(const Level& L, const T* geo, int mode, bool atomic, const void* src, void* dst,
+static void vmult_prec(const Level& L, const T* geo, int mode, bool atomic, const void* src, void* dst, int nr,
                        hipStream_t s) {
 #define NNMG_CASE(D, NN) \
-    if (L.dim == D && L.n == NN) return vmult_dispatch<D, NN, T>(L, geo, mode, atomic, src, dst, s);
+    if (L.dim == D && L.n == NN) return vmult_dispatch<D, NN, T>(L, geo, mode, atomic, src, dst, nr, s);
     NNMG_CASE(2, 2) NNMG_CASE(2, 3) NNMG_CASE(2, 4) NNMG_CASE(2, 5)
     NNMG_CASE(3, 2) NNMG_CASE(3, 3) NNMG_CASE(3, 4) NNMG_CASE(3, 5)
 #undef NNMG_CASE
     fail(NNMG_ERR_UNSUPPORTED, "operator degree/dimension");
 }
 
-static void launch_op(const Level& L, int prec, bool atomic, const void* src, void* dst, hipStream_t s) {
+static void launch_op(const Level& L, int prec, bool atomic, const void* src, void* dst, int nr, hipStream_t s) {
     const int mode = L.geometry_mode;
     const void* geo = mode == kTrilinear ? (prec == NNMG_FP64 ? (const void*)L.d_coef64.ptr : (const void*)L.d_coef32.ptr)
                                          : (prec == NNMG_FP64 ? (const void*)L.d_metric64.ptr
                                                               : (const void*)L.d_metric32.ptr);
     if (L.nblocks > 0 && (!geo || !L.d_dofmap_blk.ptr || !dst)) fail(NNMG_ERR_INVALID_ARG, "operator data missing");
+    if (nr < 1 || nr > kMaxRhs) fail(NNMG_ERR_INVALID_ARG, "number of right-hand sides");
     if (prec == NNMG_FP64)
-        vmult_prec<double>(L, (const double*)geo, mode, atomic, src, dst, s);
+        vmult_prec<double>(L, (const double*)geo, mode, atomic, src, dst, nr, s);
     else
-        vmult_prec<float>(L, (const float*)geo, mode, atomic, src, dst, s);
+        vmult_prec<float>(L, (const float*)geo, mode, atomic, src, dst, nr, s);
 }
 
-void launch_vmult_contrib(const Level& L, int prec, const void* src, void* contrib, hipStream_t s) {
-    launch_op(L, prec, false, src, contrib, s);
+void launch_vmult_contrib(const Level& L, int prec, const void* src, void* contrib, hipStream_t s, int nr) {
+    launch_op(L, prec, false, src, contrib, nr, s);
 }
 
-void launch_vmult_cells(const Level& L, int prec, const void* src, void* dst, hipStream_t s) {
+void launch_vmult_cells(const Level& L, int prec, const void* src, void* dst, hipStream_t s, int nr,
+                        void* contrib) {
     if (L.atomic_scatter && L.op == NNMG_OP_LAPLACE) {
-        launch_op(L, prec, true, src, dst, s);
+        launch_op(L, prec, true, src, dst, nr, s);
     } else {
-        launch_op(L, prec, false, src, L.d_contrib.ptr, s);
-        launch_gather(L, prec, L.d_contrib.ptr, dst, true, s);
+        void* cb = contrib ? contrib : (void*)L.d_contrib.ptr;
+        if (!contrib && nr != 1) fail(NNMG_ERR_INVALID_ARG, "a contribution buffer is needed for several right-hand sides");
+        launch_op(L, prec, false, src, cb, nr, s);
+        launch_gather(L, prec, cb, dst, true, s, nr);
     }
 }
 
