@@ -279,6 +279,42 @@ int nnmg_restrict_multi(const nnmg_transfer* transfer, nnmg_prec prec, int nrhs,
                         void* coarse_dev_add, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Autotuner: kernel variants timed on the GPU at hand                          */
+/* ------------------------------------------------------------------------ */
+
+/* Timings of the variants of an operation and the one kept. */
+typedef struct {
+    int n_variants;  /* entries of ms that were timed */
+    double ms[8];    /* average milliseconds per call of each variant, -1 where not timed */
+    int chosen;      /* index of the variant now in use */
+} nnmg_tune_result;
+
+/* Times the variants of the level's operator application as the V-cycle uses
+ * it (product and the residual that consumes it, reps calls each after two
+ * warm-up calls, on a private stream, in `prec`) and keeps the fastest:
+ *   0 geometry rebuilt from the trilinear map, contributions in slots
+ *   1 geometry rebuilt from the trilinear map, float atomics
+ *   2 stored merged metric per Gauss point,    contributions in slots
+ *   3 stored merged metric per Gauss point,    float atomics
+ * (the elasticity operator has variant 0 only).  The variants differ only
+ * in the order of floating-point sums (atomics: an order that varies between
+ * runs), the operator being the one of paper §3.2 throughout.  The stored
+ * metric is computed when needed and freed when not kept.  Synchronizes the
+ * device; hierarchies holding the level re-capture their V-cycle graphs.
+ * nnmg_level_set_variant forces a variant, nnmg_level_variant reads it. */
+int nnmg_level_tune(nnmg_level* level, nnmg_prec prec, int reps, nnmg_tune_result* res);
+int nnmg_level_set_variant(nnmg_level* level, int variant);
+int nnmg_level_variant(const nnmg_level* level, int* variant);
+
+/* Times the restriction (paper §2, eq. residual2) with 4 << v lanes per
+ * coarse cell, v = 0..4, and keeps the fastest (same contract as
+ * nnmg_level_tune).  nnmg_transfer_set_team forces a team of 4, 8, 16, 32 or
+ * 64 lanes; nnmg_transfer_team reads it. */
+int nnmg_transfer_tune(nnmg_transfer* transfer, nnmg_prec prec, int reps, nnmg_tune_result* res);
+int nnmg_transfer_set_team(nnmg_transfer* transfer, int team);
+int nnmg_transfer_team(const nnmg_transfer* transfer, int* team);
+
+/* ------------------------------------------------------------------------ */
 /* Hierarchy, V-cycle and PCG (paper §2 Algorithm V_cycle; §4 recipe)          */
 /* ------------------------------------------------------------------------ */
 

@@ -93,6 +93,10 @@ class CgResult(C.Structure):
     _fields_ = [("iterations", C.c_int), ("relres", C.c_double), ("status", C.c_int)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("n_variants", C.c_int), ("ms", C.c_double * 8), ("chosen", C.c_int)]
+
+
 # every symbol declared in include/nnmg.h, with its ctypes signature
 _vp = C.c_void_p
 _i64p = C.POINTER(C.c_int64)
@@ -136,6 +140,12 @@ SIGNATURES = {
     "nnmg_pcg_solve": (C.c_int, [_vp, _vp, _vp, C.POINTER(CgOpts), C.POINTER(CgResult), _vp]),
     "nnmg_pcg_solve_multi": (C.c_int, [_vp, C.c_int, _vp, _vp, C.POINTER(CgOpts), C.POINTER(CgResult), _vp]),
     "nnmg_hierarchy_set_profiling": (C.c_int, [_vp, C.c_int]),
+    "nnmg_level_tune": (C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(TuneResult)]),
+    "nnmg_level_set_variant": (C.c_int, [_vp, C.c_int]),
+    "nnmg_level_variant": (C.c_int, [_vp, C.POINTER(C.c_int)]),
+    "nnmg_transfer_tune": (C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(TuneResult)]),
+    "nnmg_transfer_set_team": (C.c_int, [_vp, C.c_int]),
+    "nnmg_transfer_team": (C.c_int, [_vp, C.POINTER(C.c_int)]),
     "nnmg_hierarchy_profile": (C.c_int, [_vp, C.POINTER(C.c_double)]),
 }
 

@@ -207,6 +207,24 @@ class Level:
             check(lib().nnmg_vmult_add_multi(self.handle, _DTYPE_PREC[src.dtype], nr, s, d, _stream()))
         return dst
 
+    VARIANTS = ("trilinear+slots", "trilinear+atomic", "metric+slots", "metric+atomic")
+
+    def tune(self, dtype=torch.float32, reps: int = 10) -> dict:
+        """Time the operator variants on this GPU and keep the fastest (nnmg_level_tune)."""
+        res = _lib.TuneResult()
+        check(lib().nnmg_level_tune(self.handle, _DTYPE_PREC[dtype], int(reps), C.byref(res)))
+        return dict(ms={self.VARIANTS[v]: res.ms[v] for v in range(res.n_variants)},
+                    chosen=self.VARIANTS[res.chosen])
+
+    @property
+    def variant(self) -> int:
+        v = C.c_int()
+        check(lib().nnmg_level_variant(self.handle, C.byref(v)))
+        return v.value
+
+    def set_variant(self, variant: int):
+        check(lib().nnmg_level_set_variant(self.handle, int(variant)))
+
     def diagonal(self, dtype=torch.float64) -> torch.Tensor:
         out = self.empty(dtype)
         check(lib().nnmg_level_diagonal(self.handle, _DTYPE_PREC[dtype], _vec(out, self.n_dofs, self.ctx.device),
@@ -248,6 +266,21 @@ class Transfer:
         n, npj = C.c_int64(), C.c_int64()
         check(lib().nnmg_transfer_points(self.handle, C.byref(n), None, None, None, C.byref(npj)))
         return n.value
+
+    def tune(self, dtype=torch.float32, reps: int = 10) -> dict:
+        """Time the restriction with 4..64 lanes per coarse cell and keep the fastest."""
+        res = _lib.TuneResult()
+        check(lib().nnmg_transfer_tune(self.handle, _DTYPE_PREC[dtype], int(reps), C.byref(res)))
+        return dict(ms={4 << v: res.ms[v] for v in range(res.n_variants)}, chosen=4 << res.chosen)
+
+    @property
+    def team(self) -> int:
+        v = C.c_int()
+        check(lib().nnmg_transfer_team(self.handle, C.byref(v)))
+        return v.value
+
+    def set_team(self, team: int):
+        check(lib().nnmg_transfer_set_team(self.handle, int(team)))
 
     def points(self) -> dict:
         n, npj = C.c_int64(), C.c_int64()
@@ -399,6 +432,12 @@ class Hierarchy:
         if code != 0 and raise_on_failure:
             check(code)
         return x, (infos[0] if b.dim() == 1 else infos)
+
+    def tune(self, dtype=torch.float32, reps: int = 10) -> dict:
+        """Tune every level's operator and every transfer's restriction (the
+        V-cycle's precision is the one to tune for)."""
+        return dict(levels=[lv.tune(dtype, reps) for lv in self.levels],
+                    transfers=[tr.tune(dtype, reps) for tr in self.transfers])
 
     def set_profiling(self, enabled: bool):
         check(lib().nnmg_hierarchy_set_profiling(self.handle, int(bool(enabled))))

@@ -28,6 +28,7 @@ SOURCES = [
     "host/transfer.cpp",
     "host/hierarchy.cpp",
     "host/capi.cpp",
+    "host/tune.cpp",
     "kernels/vmult.hip",
     "kernels/geometry.hip",
     "kernels/transfer.hip",

@@ -433,6 +433,56 @@ int nnmg_pcg_solve_multi(nnmg_hierarchy* h, int nrhs, const double* b, double* x
     return guarded([&] { return pcg_impl(h, nrhs, b, x, opts, res, stream); });
 }
 
+int nnmg_level_tune(nnmg_level* level, nnmg_prec prec, int reps, nnmg_tune_result* res) {
+    return guarded([&] {
+        if (!level || !res) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        level_tune(*level, prec, reps, res);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_level_set_variant(nnmg_level* level, int variant) {
+    return guarded([&] {
+        if (!level) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        level_set_variant(*level, variant);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_level_variant(const nnmg_level* level, int* variant) {
+    return guarded([&] {
+        if (!level || !variant) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        *variant = level_variant(*level);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_transfer_tune(nnmg_transfer* transfer, nnmg_prec prec, int reps, nnmg_tune_result* res) {
+    return guarded([&] {
+        if (!transfer || !res) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        transfer_tune(*transfer, prec, reps, res);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_transfer_set_team(nnmg_transfer* transfer, int team) {
+    return guarded([&] {
+        if (!transfer) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        transfer_set_team(*transfer, team);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_transfer_team(const nnmg_transfer* transfer, int* team) {
+    return guarded([&] {
+        if (!transfer || !team) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        *team = transfer->team;
+        return NNMG_OK;
+    });
+}
+
 int nnmg_hierarchy_set_profiling(nnmg_hierarchy* h, int enabled) {
     return guarded([&] {
         if (!h) fail(NNMG_ERR_INVALID_ARG, "hierarchy is NULL");

@@ -74,6 +74,15 @@ struct Hierarchy {
     // and number of right-hand sides
     hipStream_t capture = nullptr;
     hipGraphExec_t precond_graph[2][kMaxRhs + 1] = {};
+    long graph_sig = 0;  // config_sig() when the graphs were captured
+
+    // changes whenever the autotuner switches a kernel variant of a level or transfer
+    long config_sig() const {
+        long v = 0;
+        for (auto* l : levels) v += l->config_version;
+        for (auto* t : transfers) v += t->config_version;
+        return v;
+    }
 
     void drop_graphs() {
         for (auto& row : precond_graph)
@@ -503,6 +512,10 @@ int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg
         }
     };
     const bool graph = o.use_graph && !H.profiling;
+    if (H.graph_sig != H.config_sig()) {  // captured with other kernel variants
+        H.drop_graphs();
+        H.graph_sig = H.config_sig();
+    }
     hipGraphExec_t& exec = H.precond_graph[prec][nr];
     if (graph && !exec) {
         if (!H.capture) NNMG_HIP(hipStreamCreateWithFlags(&H.capture, hipStreamNonBlocking));

@@ -1,0 +1,177 @@
+// Autotuner: times the variants of a level's operator application and of a
+// transfer's restriction on the GPU at hand and keeps the fastest.
+//
+// Level variants (the operator as the V-cycle uses it, product plus the
+// residual that consumes it):
+//   0  geometry rebuilt from the trilinear map, contributions in slots + gather
+//   1  geometry rebuilt from the trilinear map, float atomics into the output
+//   2  stored merged metric per Gauss point,    contributions in slots + gather
+//   3  stored merged metric per Gauss point,    float atomics into the output
+// The elasticity operator has variant 0 only.  Transfer variants: the lanes
+// per coarse cell of the restriction, 4 << v for v = 0..4.
+//
+// Every choice changes only the order in which floating-point sums are formed
+// (atomics: an order that varies from run to run), never what is summed.
+#include <algorithm>
+#include <functional>
+
+#include "../internal.hpp"
+
+namespace nnmg {
+
+namespace {
+
+double time_ms(const std::function<void(hipStream_t)>& fn, int reps, hipStream_t s) {
+    for (int i = 0; i < 2; ++i) fn(s);
+    hipEvent_t a, b;
+    NNMG_HIP(hipEventCreate(&a));
+    NNMG_HIP(hipEventCreate(&b));
+    NNMG_HIP(hipEventRecord(a, s));
+    for (int i = 0; i < reps; ++i) fn(s);
+    NNMG_HIP(hipEventRecord(b, s));
+    NNMG_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    NNMG_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return (double)ms / reps;
+}
+
+// a scratch vector of n values with entries in [-1, 1) in `prec`
+DeviceArray<char> scratch_vector(Ctx* ctx, size_t n, int prec, uint64_t seed, hipStream_t s) {
+    DeviceArray<double> v64;
+    v64.alloc(ctx, std::max<size_t>(n, 1));
+    launch_splitmix_vector(v64.ptr, nullptr, n, seed, s);
+    DeviceArray<char> out;
+    out.alloc(ctx, std::max<size_t>(n, 1) * (prec == NNMG_FP64 ? 8 : 4));
+    if (prec == NNMG_FP64)
+        NNMG_HIP(hipMemcpyAsync(out.ptr, v64.ptr, n * 8, hipMemcpyDeviceToDevice, s));
+    else
+        launch_cast_64_to_32(v64.ptr, (float*)out.ptr, n, s);
+    NNMG_HIP(hipStreamSynchronize(s));
+    return out;
+}
+
+void ensure_metric(Level& L) {
+    if (L.d_metric64.ptr) return;
+    const int M = L.dim * (L.dim + 1) / 2;
+    const size_t mlen = (size_t)(L.nblocks * M * L.n * L.wg);
+    L.d_metric64.alloc(L.ctx, mlen);
+    L.d_metric32.alloc(L.ctx, mlen);
+    NNMG_HIP(hipMemset(L.d_metric64.ptr, 0, L.d_metric64.bytes()));
+    NNMG_HIP(hipMemset(L.d_metric32.ptr, 0, L.d_metric32.bytes()));
+    DeviceArray<int> bad;
+    bad.alloc(L.ctx, 1);
+    NNMG_HIP(hipMemset(bad.ptr, 0, sizeof(int)));
+    launch_geometry(L, bad.ptr, nullptr);
+    NNMG_HIP(hipDeviceSynchronize());
+}
+
+void apply_variant(Level& L, int v) {
+    if (L.op != NNMG_OP_LAPLACE && v != 0) fail(NNMG_ERR_UNSUPPORTED, "the elasticity operator has variant 0 only");
+    if (v < 0 || v > 3) fail(NNMG_ERR_INVALID_ARG, "operator variant must be in 0..3");
+    NNMG_HIP(hipDeviceSynchronize());  // launches of the previous variant may be in flight
+    if (v >= 2) ensure_metric(L);
+    L.geometry_mode = v >= 2 ? 0 : 1;
+    L.atomic_scatter = (v & 1) != 0;
+    if (L.geometry_mode == 1) {
+        L.d_metric64.reset();
+        L.d_metric32.reset();
+    }
+    ++L.config_version;
+}
+
+}  // namespace
+
+int level_variant(const Level& L) { return (L.geometry_mode == 0 ? 2 : 0) + (L.atomic_scatter ? 1 : 0); }
+
+void level_set_variant(Level& L, int v) {
+    NNMG_HIP(hipSetDevice(L.ctx->device));
+    apply_variant(L, v);
+}
+
+void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res) {
+    if (reps < 1) fail(NNMG_ERR_INVALID_ARG, "reps must be positive");
+    NNMG_HIP(hipSetDevice(L.ctx->device));
+    const size_t n = (size_t)L.n_dofs;
+    const int nvar = L.op == NNMG_OP_LAPLACE ? 4 : 1;
+    hipStream_t s;
+    NNMG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    try {
+        DeviceArray<char> x = scratch_vector(L.ctx, n, prec, 0x7E57ull, s);
+        DeviceArray<char> f = scratch_vector(L.ctx, n, prec, 0x7E58ull, s);
+        DeviceArray<char> r, ax;
+        const size_t bytes = std::max<size_t>(n, 1) * (prec == NNMG_FP64 ? 8 : 4);
+        r.alloc(L.ctx, bytes / sizeof(char));
+        ax.alloc(L.ctx, bytes / sizeof(char));
+        NNMG_HIP(hipMemset(ax.ptr, 0, bytes));
+        level_reserve_rhs(L, 1);
+        res->n_variants = nvar;
+        for (double& t : res->ms) t = -1.0;
+        int best = 0;
+        for (int v = 0; v < nvar; ++v) {
+            apply_variant(L, v);
+            res->ms[v] = time_ms(
+                [&](hipStream_t st) {
+                    if (L.atomic_scatter) {
+                        launch_vmult_cells(L, prec, x.ptr, ax.ptr, st);
+                        launch_residual(prec, n, f.ptr, ax.ptr, r.ptr, st);
+                    } else {
+                        launch_vmult_contrib(L, prec, x.ptr, L.d_contrib.ptr, st);
+                        launch_residual_gather(L, prec, L.d_contrib.ptr, f.ptr, r.ptr, st);
+                    }
+                },
+                reps, s);
+            if (res->ms[v] < res->ms[best]) best = v;
+        }
+        apply_variant(L, best);
+        res->chosen = best;
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+        throw;
+    }
+    NNMG_HIP(hipStreamSynchronize(s));
+    NNMG_HIP(hipStreamDestroy(s));
+}
+
+void transfer_set_team(Transfer& T, int team) {
+    if (team != 4 && team != 8 && team != 16 && team != 32 && team != 64)
+        fail(NNMG_ERR_INVALID_ARG, "restriction team must be 4, 8, 16, 32 or 64 lanes");
+    NNMG_HIP(hipSetDevice(T.ctx->device));
+    NNMG_HIP(hipDeviceSynchronize());
+    T.team = team;
+    ++T.config_version;
+}
+
+void transfer_tune(Transfer& T, int prec, int reps, nnmg_tune_result* res) {
+    if (reps < 1) fail(NNMG_ERR_INVALID_ARG, "reps must be positive");
+    NNMG_HIP(hipSetDevice(T.ctx->device));
+    hipStream_t s;
+    NNMG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    try {
+        DeviceArray<char> fine = scratch_vector(T.ctx, (size_t)T.fine->n_dofs, prec, 0x7E59ull, s);
+        DeviceArray<char> coarse;
+        coarse.alloc(T.ctx, std::max<size_t>((size_t)T.coarse->n_dofs, 1) * (prec == NNMG_FP64 ? 8 : 4));
+        NNMG_HIP(hipMemset(coarse.ptr, 0, coarse.bytes()));
+        res->n_variants = 5;
+        for (double& t : res->ms) t = -1.0;
+        int best = 0;
+        for (int v = 0; v < 5; ++v) {
+            transfer_set_team(T, 4 << v);
+            res->ms[v] = time_ms([&](hipStream_t st) { launch_restrict(T, prec, fine.ptr, coarse.ptr, false, st); },
+                                 reps, s);
+            if (res->ms[v] < res->ms[best]) best = v;
+        }
+        transfer_set_team(T, 4 << best);
+        res->chosen = best;
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+        throw;
+    }
+    NNMG_HIP(hipStreamSynchronize(s));
+    NNMG_HIP(hipStreamDestroy(s));
+}
+
+}  // namespace nnmg

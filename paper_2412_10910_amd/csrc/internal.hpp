@@ -143,6 +143,7 @@ struct Level {
     size_t contrib_len = 0;             // number of contribution slots
     DeviceArray<char> d_contrib;        // contribution buffer of the level's own operator calls
     int contrib_rhs = 1;                // right-hand sides d_contrib holds (grown on demand)
+    int config_version = 0;             // bumped when the autotuner changes the kernel variant
     bool atomic_scatter = false;        // float atomics into the output instead of contribution slots
     DeviceArray<double> d_diag64;       // operator diagonal, 1 on constrained
     DeviceArray<double> d_dinv64;       // inverse diagonal, 0 on constrained
@@ -178,6 +179,7 @@ struct Transfer {
     size_t n_rslots = 0;                 // restriction slots
     DeviceArray<double> d_rbuf;          // slot values (float64 or float32)
     int rbuf_rhs = 1;                    // right-hand sides d_rbuf holds (grown on demand)
+    int config_version = 0;              // bumped when the autotuner changes the team size
 };
 
 constexpr int kPointBlock = 256;
@@ -188,6 +190,13 @@ constexpr int kScal = 8;                 // CG scalars per right-hand side
 // nr right-hand sides (synchronizes the device when it reallocates)
 void level_reserve_rhs(Level& l, int nr);
 void transfer_reserve_rhs(Transfer& t, int nr);
+
+// autotuner (host/tune.cpp)
+int level_variant(const Level& L);
+void level_set_variant(Level& L, int v);
+void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res);
+void transfer_set_team(Transfer& T, int team);
+void transfer_tune(Transfer& T, int prec, int reps, nnmg_tune_result* res);
 constexpr int32_t kMergeNext = 1 << 30;  // flag in a contribution slot index (see Level::d_pos_blk)
 constexpr int kWaveLanes = 64;           // CDNA wavefront width  // points per block of the point-parallel transfer kernels
 

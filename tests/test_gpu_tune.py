@@ -1,0 +1,111 @@
+"""The autotuner: every operator variant and every restriction team size must
+give the oracle's result (float64 within 1e-12, float32 within 2e-5 of the
+largest entry; the variants only reorder floating-point sums), tuning must
+keep the fastest variant it timed, and a hierarchy must re-capture its V-cycle
+graph when a variant under it changes.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import config_levels, config_source, random_vector
+
+from _parity import DEV, Pair, oracle_prolongation, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 2e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2412_10910_amd as nn
+    return nn.Context(0)
+
+
+@pytest.mark.parametrize("cfg,cells,k", [(0, [13], 1), (1, [5], 2), (2, [4], 3), (2, [3], 4)])
+def test_operator_variants_match_oracle(ctx, cfg, cells, k):
+    (m,) = config_levels(cfg, cells=cells)
+    p = Pair(ctx, m, k)
+    x = random_vector(p.orc.n_dofs, 5)
+    ref = p.A @ x
+    for v in range(4):
+        p.lib.set_variant(v)
+        assert p.lib.variant == v
+        for dt, tol in ((torch.float64, TOL64), (torch.float32, TOL32)):
+            assert rel_err(p.to_orc(p.lib.vmult(p.to_lib(x, dt))), ref) <= tol, (v, dt)
+
+
+@pytest.mark.parametrize("cfg,cells,k", [(1, [3, 7], 2), (2, [3, 6], 3), (3, [(3, 1, 1), (7, 2, 2)], 2)])
+def test_restriction_teams_match_oracle(ctx, cfg, cells, k):
+    import paper_2412_10910_amd as nn
+    op = "elasticity" if cfg == 3 else "laplace"
+    cm, fm = config_levels(cfg, cells=cells)
+    f, c = Pair(ctx, fm, k, op), Pair(ctx, cm, k, op)
+    tr = nn.Transfer(ctx, f.lib, c.lib)
+    P = oracle_prolongation(f, c)
+    rf = np.where(f.free, random_vector(f.orc.n_dofs * f.nc, 6), 0.0)
+    ref = P.T @ rf
+    for team in (4, 8, 16, 32, 64):
+        tr.set_team(team)
+        assert tr.team == team
+        for dt, tol in ((torch.float64, TOL64), (torch.float32, TOL32)):
+            out = c.to_orc(tr.restrict(f.to_lib(rf, dt), torch.zeros(c.lib.n_dofs, dtype=dt, device=DEV)))
+            assert rel_err(out, ref) <= tol, (team, dt)
+
+
+def test_tune_keeps_the_fastest_and_the_solver_still_converges(ctx):
+    import paper_2412_10910_amd as nn
+    meshes = config_levels(1, cells=[3, 6, 13, 29])
+    levels = [nn.Level.from_mesh(ctx, m, 2) for m in meshes]
+    transfers = [nn.Transfer(ctx, levels[i + 1], levels[i]) for i in range(len(levels) - 1)]
+    H = nn.Hierarchy(ctx, levels, transfers)
+    fine = levels[-1]
+    b = fine.assemble_rhs(torch.tensor(config_source(1)(fine.quadrature_points()), device=DEV).reshape(-1))
+    _, before = H.pcg_solve(b, rtol=1e-8, vcycle_dtype=torch.float32)
+    report = H.tune(torch.float32, reps=5)
+    for lv, r in zip(levels, report["levels"]):
+        ms = r["ms"]
+        assert len(ms) == 4 and all(t > 0 for t in ms.values())
+        assert r["chosen"] == min(ms, key=ms.get)
+        assert lv.VARIANTS[lv.variant] == r["chosen"]
+    for tr, r in zip(transfers, report["transfers"]):
+        assert r["chosen"] == min(r["ms"], key=r["ms"].get) and tr.team == r["chosen"]
+    for dt in (torch.float32, torch.float64):
+        x, info = H.pcg_solve(b, rtol=1e-8, vcycle_dtype=dt)
+        assert info["status"] == "OK" and abs(info["iterations"] - before["iterations"]) <= 1
+        true = float((b - fine.vmult(x)).norm() / b.norm())
+        assert true <= 1.01e-8
+
+
+def test_graph_recaptured_after_a_variant_change(ctx):
+    """The captured preconditioner bakes in the kernels and buffers of the
+    variant in use; after a change the next solve must use the new variant:
+    graph and kernel-by-kernel solves agree bitwise (slot variants are
+    deterministic)."""
+    import paper_2412_10910_amd as nn
+    meshes = config_levels(1, cells=[3, 6, 13])
+    levels = [nn.Level.from_mesh(ctx, m, 2) for m in meshes]
+    transfers = [nn.Transfer(ctx, levels[i + 1], levels[i]) for i in range(len(levels) - 1)]
+    H = nn.Hierarchy(ctx, levels, transfers)
+    fine = levels[-1]
+    b = fine.assemble_rhs(torch.tensor(config_source(1)(fine.quadrature_points()), device=DEV).reshape(-1))
+    H.pcg_solve(b, rtol=1e-8, vcycle_dtype=torch.float32)  # captures the graph with variant 0
+    for v, team in ((2, 8), (0, 32), (2, 4)):
+        fine.set_variant(v)
+        transfers[-1].set_team(team)
+        xg, ig = H.pcg_solve(b, rtol=1e-8, vcycle_dtype=torch.float32, use_graph=True)
+        xe, ie = H.pcg_solve(b, rtol=1e-8, vcycle_dtype=torch.float32, use_graph=False)
+        assert ig["iterations"] == ie["iterations"]
+        assert torch.equal(xg, xe), v
+
+
+def test_elasticity_has_one_variant(ctx):
+    import paper_2412_10910_amd as nn
+    (m,) = config_levels(3, cells=[(3, 1, 1)])
+    lv = nn.Level.from_mesh(ctx, m, 2, "elasticity")
+    with pytest.raises(nn.NNMGError):
+        lv.set_variant(1)
+    r = lv.tune(torch.float64, reps=3)
+    assert list(r["ms"]) == ["trilinear+slots"] and lv.variant == 0
