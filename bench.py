@@ -26,6 +26,8 @@ import subprocess
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -88,6 +90,148 @@ WORKLOADS = {
                          "non-nested perturbed hex levels 80x16x16/33x7x7/14x3x3 (+-0.1h), "
                          "float64 V-cycle in float64 PCG to 1e-8"),
 }
+
+def run_serving(args, ctx, nn, torch, log):
+    """The serving stream: requests with Poisson arrivals on a pool of resident
+    hierarchies (0.1M..8M DoFs, 3-5 levels), 1..8 bump right-hand sides each,
+    float32-MG in float64 PCG to 1e-8.  The same arrival trace is replayed
+    with one request at a time and with continuous batching."""
+    from workloads import SERVING_POOL, config_levels, config_source
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    pool = []
+    for cfg, cells, k in SERVING_POOL:
+        meshes = config_levels(cfg, cells=cells)
+        levels = [nn.Level.from_mesh(ctx, m, k) for m in meshes]
+        trs = [nn.Transfer(ctx, levels[i + 1], levels[i]) for i in range(len(levels) - 1)]
+        H = nn.Hierarchy(ctx, levels, trs)
+        if not args.no_tune:
+            H.tune(torch.float32, reps=5)
+        # replicas over the same levels and transfers, so a mesh can serve several requests at a time
+        reps = [H] + [nn.Hierarchy(ctx, levels, trs) for _ in range(args.serving_replicas - 1)]
+        fine = levels[-1]
+        qp = fine.quadrature_points()
+        cols = [fine.assemble_rhs(torch.tensor(config_source(cfg, 50 + r)(qp), dtype=torch.float64,
+                                               device=dev).reshape(-1)) for r in range(8)]
+        bank = {r: (cols[0] if r == 1 else torch.stack(cols[:r], dim=1).contiguous()) for r in range(1, 9)}
+        pool.append(dict(H=H, reps=reps, levels=levels, trs=trs, n=fine.n_dofs, bank=bank, cfg=cfg, cells=cells,
+                         k=k))
+        log(f"pool: cfg {cfg} Q{k} {cells} -> {fine.n_dofs} DoFs")
+    t_setup = time.perf_counter() - t0
+    # warm-up (grows the buffers to 8 right-hand sides and captures every graph), then
+    # the one-at-a-time service time of each hierarchy, averaged over 1..8 right-hand sides
+    service = []
+    for P in pool:
+        for Hr in P["reps"]:
+            for r in range(1, 9):
+                Hr.pcg_solve(P["bank"][r], rtol=1e-8, vcycle_dtype=torch.float32, history=False)
+        torch.cuda.synchronize()
+        ts = []
+        for r in (1, 4, 8):
+            t1 = time.perf_counter()
+            P["H"].pcg_solve(P["bank"][r], rtol=1e-8, vcycle_dtype=torch.float32, history=False)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        service.append(sum(ts) / len(ts))
+    mean_service = sum(service) / len(service)
+    rate = args.serving_load / mean_service
+    rng = np.random.default_rng(4000)
+    n_req = args.serving_requests
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    which = rng.integers(len(pool), size=n_req)
+    nrs = rng.integers(1, 9, size=n_req)
+    log(f"serving: {n_req} requests at {rate:.1f}/s (offered load {args.serving_load} of one-at-a-time capacity)")
+
+    def replay(max_active):
+        srv = nn.Server(ctx, max_active=max_active)
+        torch.cuda.synchronize()
+        tickets = []
+        t_start = time.perf_counter()
+        for a, h, r in zip(arrivals, which, nrs):
+            now = time.perf_counter() - t_start
+            if a > now:
+                time.sleep(a - now)
+            P = pool[int(h)]
+            tickets.append((int(h), int(r), time.perf_counter() - t_start,
+                            srv.submit(P["reps"], P["bank"][int(r)], vcycle_dtype=torch.float32)))
+        lat, ends, work, its_all, queued = [], [], 0, [], []
+        for h, r, ts, t in tickets:
+            _, info, tm = t.wait()
+            infos = info if isinstance(info, list) else [info]
+            assert all(i["status"] == "OK" for i in infos)
+            its = sum(i["iterations"] for i in infos)
+            work += pool[h]["n"] * its
+            its_all.append(its / r)
+            lat.append(tm["total_ms"])
+            queued.append(tm["queued_ms"])
+            ends.append(ts + tm["total_ms"] * 1e-3)
+        st = srv.stats()
+        srv.close()
+        makespan = max(ends)
+        return dict(value=work / makespan / 1e6, makespan_s=round(makespan, 4),
+                    latency_ms={"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3)},
+                    mean_queued_ms=round(sum(queued) / len(queued), 3), max_running=st["max_running"],
+                    mean_iterations=round(sum(its_all) / len(its_all), 2))
+
+    log("replay: one request at a time")
+    serial = replay(1)
+    log(f"replay: continuous batching, {args.serving_slots} slots")
+    batched = replay(args.serving_slots)
+    big = pool[-1]
+    log("timing the operator and transfer kernels of the largest hierarchy")
+    k = kernel_rooflines(big["levels"][-1], big["levels"][-2], big["trs"][-1], args.roofline_reps)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline([3, 6, 13, 29], 1, "laplace")
+    op = k["operator_fp32"]
+
+    def entry(name):
+        v = k[name]
+        return {"ms": round(v["ms"], 5), "bytes": v["bytes"], "achieved": round(v["gbs"], 1),
+                "frac": round(v["frac"], 4), "traffic": None}
+
+    line = {
+        "metric": METRIC,
+        "value": round(batched["value"], 2),
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": n_req,
+        "warmup": 8 * len(pool),
+        "ms_per_step": round(batched["makespan_s"] / n_req * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": ("serving stream: Poisson Q2 (perturbed cubes) and Q3 (balls) solves, 0.1M-8M fine DoFs "
+                         "log-uniform over 6 resident meshes with 3-5 non-nested levels, Poisson arrivals, "
+                         "1-8 Gaussian-bump right-hand sides per request, float32-MG in float64 PCG to 1e-8"),
+            "pool_dofs": [P["n"] for P in pool],
+            "requests": n_req,
+            "arrival_rate_per_s": round(rate, 3),
+            "offered_load": args.serving_load,
+            "slots": args.serving_slots,
+            "replicas_per_mesh": args.serving_replicas,
+        },
+        "latency_ms": batched["latency_ms"],
+        "serving": {"continuous_batching": batched, "one_at_a_time": serial,
+                    "speedup": round(batched["value"] / serial["value"], 3),
+                    "service_ms_alone": [round(t * 1e3, 3) for t in service]},
+        "setup_s": {"pool": round(t_setup, 3)},
+        "roofline": {
+            "bound": "hbm", "achieved": round(op["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(op["frac"], 4), "traffic": None,
+            "kernel": (f"operator application on the largest resident level ({big['n']} DoFs), float32 (the "
+                       "V-cycle precision): vmult_kernel + gather_kernel"),
+            "bytes_per_launch": op["bytes"], "ms_per_launch": round(op["ms"], 5),
+            "kernels": {n: entry(n) for n in k},
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
 
 # level pairs (fine <- coarse) for --roofline-only: workload, cells per direction, degree
 ROOFLINE_WORKLOADS = {
@@ -251,8 +395,15 @@ def main():
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the operator/transfer kernel loops of the two finest levels and a copy of "
                          "known size (the run that rocprofv3 traces and counts)")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="cube_q2",
+    ap.add_argument("--serving-requests", type=int, default=120)
+    ap.add_argument("--serving-load", type=float, default=1.0,
+                    help="arrival rate as a fraction of the one-request-at-a-time service rate")
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-replicas", type=int, default=2, help="hierarchies per resident mesh")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["serving"], default="cube_q2",
                     help="the PCG workload (default: the 3D Poisson cube the metric is quoted on)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (operator variant per level, restriction team per transfer)")
     ap.add_argument("--rhs", type=int, default=None,
                     help="right-hand sides fused per solve (default: the workload's, 1 for the cube, 4 for the beam)")
     ap.add_argument("--roofline-workload", choices=sorted(ROOFLINE_WORKLOADS), default="cube_q2_64",
@@ -272,11 +423,13 @@ def main():
     import paper_2412_10910_amd as nn
     from workloads import config_levels, config_source, random_load
 
-    wl = WORKLOADS[args.workload]
-    cfg, cells, degree, operator = wl["cfg"], wl["cells"], wl["degree"], wl["operator"]
     dev = "cuda:0"
     torch.cuda.init()
     ctx = nn.Context(0)
+    if args.workload == "serving" and not args.roofline_only:
+        return run_serving(args, ctx, nn, torch, log)
+    wl = WORKLOADS[args.workload]
+    cfg, cells, degree, operator = wl["cfg"], wl["cells"], wl["degree"], wl["operator"]
 
     log("generating meshes")
     meshes = config_levels(cfg, cells=cells) if not args.roofline_only else None
@@ -303,6 +456,13 @@ def main():
     t0 = time.perf_counter()
     H = nn.Hierarchy(ctx, levels, transfers)
     t_hier = time.perf_counter() - t0
+    tuned = None
+    t_tune = 0.0
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        rep = H.tune(torch.float64, reps=10)
+        t_tune = time.perf_counter() - t0
+        tuned = dict(levels=[r["chosen"] for r in rep["levels"]], restriction_teams=[r["chosen"] for r in rep["transfers"]])
     fine = levels[-1]
     nr = args.rhs if args.rhs is not None else wl.get("rhs", 1)
     if operator == "elasticity":
@@ -397,7 +557,9 @@ def main():
                            "p99": round(percentile(lat32, 99) * 1e3, 4)},
             "speedup_vs_fp64_mg": round(tot64 / tot32, 3),
         },
-        "setup_s": {"levels": round(t_levels, 3), "transfers": round(t_transfers, 3), "hierarchy": round(t_hier, 3)},
+        "setup_s": {"levels": round(t_levels, 3), "transfers": round(t_transfers, 3), "hierarchy": round(t_hier, 3),
+                    "tune": round(t_tune, 3)},
+        "tuned": tuned,
         "roofline": {
             "bound": "hbm",
             "achieved": round(op["gbs"], 1),

@@ -371,6 +371,76 @@ int nnmg_pcg_solve_multi(nnmg_hierarchy* h, int nrhs, const double* b_dev, doubl
 int nnmg_hierarchy_set_profiling(nnmg_hierarchy* h, int enabled);
 int nnmg_hierarchy_profile(nnmg_hierarchy* h, double* ms);
 
+/* Device memory a solve of nrhs right-hand sides needs beyond the
+ * hierarchy's fixed data (work vectors of both precisions, CG vectors,
+ * contribution and restriction buffers); the serving loop admits requests
+ * by it. */
+int nnmg_hierarchy_footprint(const nnmg_hierarchy* h, int nrhs, size_t* bytes);
+
+/* ------------------------------------------------------------------------ */
+/* Serving loop with continuous batching                                       */
+/* ------------------------------------------------------------------------ */
+/* A server owns one loop thread and max_active streams.  Requests name a
+ * resident hierarchy and nrhs right-hand sides (the solve of
+ * nnmg_pcg_solve_multi, paper §4 recipe).  The loop admits queued requests,
+ * in arrival order but without letting one that does not fit hold back later
+ * ones, whenever a slot is free, the request's footprint fits the memory
+ * budget beside the running ones (a request alone is always admitted), and
+ * its hierarchy serves no other request.  Running requests advance one CG
+ * stage at a time on their own streams, so their kernels overlap on the
+ * device.  Each request makes exactly the launches of nnmg_pcg_solve_multi:
+ * its result is the same alone and in the mix.  A hierarchy must not be used
+ * by other calls while a request on it runs. */
+typedef struct nnmg_server nnmg_server;
+
+typedef struct {
+    int max_active;        /* requests running at once (default 4, 1..64) */
+    size_t memory_budget;  /* bytes of footprint the running requests may hold together (default 64 GiB) */
+} nnmg_server_opts;
+
+typedef struct {
+    double queued_ms;  /* submit -> admitted */
+    double run_ms;     /* admitted -> finished */
+    double total_ms;   /* submit -> finished */
+} nnmg_request_times;
+
+typedef struct {
+    int64_t submitted, completed;
+    int running, pending;    /* now */
+    int max_running;         /* most requests running at once so far */
+    size_t reserved;         /* footprint held by the running requests now */
+    size_t max_reserved;     /* most footprint held at once so far */
+} nnmg_server_stats;
+
+void nnmg_default_server_opts(nnmg_server_opts* opts);
+int nnmg_server_create(nnmg_ctx* ctx, const nnmg_server_opts* opts, nnmg_server** out);
+/* Finishes every queued request, then stops the loop.  NULL is a no-op. */
+void nnmg_server_destroy(nnmg_server* server);
+
+/* Queues a request and returns at once with its ticket.  b_dev (float64
+ * [n_dofs][nrhs], complete on the device: synchronize the stream that wrote
+ * it first) and x_dev must stay valid, and b_dev unchanged, until
+ * nnmg_server_wait returns; opts may be NULL (defaults), opts->history (host
+ * [nrhs][max_it + 1]) likewise.  Errors: INVALID_ARG (arguments, nrhs out of
+ * 1..8, server shutting down). */
+int nnmg_server_submit(nnmg_server* server, nnmg_hierarchy* h, int nrhs, const double* b_dev, double* x_dev,
+                       const nnmg_cg_opts* opts, int64_t* ticket);
+/* nnmg_server_submit for a set of n_replicas equivalent hierarchies (built
+ * over the same levels and transfers with the same options, so any of them
+ * gives the same result): the request runs on whichever is idle first.  A hot
+ * mesh can so serve several requests at a time, each replica holding its own
+ * work buffers (nnmg_hierarchy_footprint) beside the shared levels and
+ * transfers. */
+int nnmg_server_submit_any(nnmg_server* server, nnmg_hierarchy* const* replicas, int n_replicas, int nrhs,
+                           const double* b_dev, double* x_dev, const nnmg_cg_opts* opts, int64_t* ticket);
+/* *done = 1 once the request has finished. */
+int nnmg_server_poll(nnmg_server* server, int64_t ticket, int* done);
+/* Blocks until the request has finished, writes res (host [nrhs]) and times
+ * (may be NULL), and retires the ticket.  Returns the request's status, as
+ * nnmg_pcg_solve_multi would. */
+int nnmg_server_wait(nnmg_server* server, int64_t ticket, nnmg_cg_result* res, nnmg_request_times* times);
+int nnmg_server_get_stats(nnmg_server* server, nnmg_server_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -97,6 +97,19 @@ class TuneResult(C.Structure):
     _fields_ = [("n_variants", C.c_int), ("ms", C.c_double * 8), ("chosen", C.c_int)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("max_active", C.c_int), ("memory_budget", C.c_size_t)]
+
+
+class RequestTimes(C.Structure):
+    _fields_ = [("queued_ms", C.c_double), ("run_ms", C.c_double), ("total_ms", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("running", C.c_int), ("pending", C.c_int),
+                ("max_running", C.c_int), ("reserved", C.c_size_t), ("max_reserved", C.c_size_t)]
+
+
 # every symbol declared in include/nnmg.h, with its ctypes signature
 _vp = C.c_void_p
 _i64p = C.POINTER(C.c_int64)
@@ -140,6 +153,16 @@ SIGNATURES = {
     "nnmg_pcg_solve": (C.c_int, [_vp, _vp, _vp, C.POINTER(CgOpts), C.POINTER(CgResult), _vp]),
     "nnmg_pcg_solve_multi": (C.c_int, [_vp, C.c_int, _vp, _vp, C.POINTER(CgOpts), C.POINTER(CgResult), _vp]),
     "nnmg_hierarchy_set_profiling": (C.c_int, [_vp, C.c_int]),
+    "nnmg_hierarchy_footprint": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_size_t)]),
+    "nnmg_default_server_opts": (None, [C.POINTER(ServerOpts)]),
+    "nnmg_server_create": (C.c_int, [_vp, C.POINTER(ServerOpts), C.POINTER(_vp)]),
+    "nnmg_server_destroy": (None, [_vp]),
+    "nnmg_server_submit": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp, C.POINTER(CgOpts), C.POINTER(C.c_int64)]),
+    "nnmg_server_submit_any": (C.c_int, [_vp, C.POINTER(_vp), C.c_int, C.c_int, _vp, _vp, C.POINTER(CgOpts),
+                                         C.POINTER(C.c_int64)]),
+    "nnmg_server_poll": (C.c_int, [_vp, C.c_int64, C.POINTER(C.c_int)]),
+    "nnmg_server_wait": (C.c_int, [_vp, C.c_int64, C.POINTER(CgResult), C.POINTER(RequestTimes)]),
+    "nnmg_server_get_stats": (C.c_int, [_vp, C.POINTER(ServerStats)]),
     "nnmg_level_tune": (C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(TuneResult)]),
     "nnmg_level_set_variant": (C.c_int, [_vp, C.c_int]),
     "nnmg_level_variant": (C.c_int, [_vp, C.POINTER(C.c_int)]),

@@ -439,6 +439,12 @@ class Hierarchy:
         return dict(levels=[lv.tune(dtype, reps) for lv in self.levels],
                     transfers=[tr.tune(dtype, reps) for tr in self.transfers])
 
+    def footprint(self, nrhs: int = 1) -> int:
+        """Device bytes a solve of nrhs right-hand sides needs beyond the hierarchy's fixed data."""
+        v = C.c_size_t()
+        check(lib().nnmg_hierarchy_footprint(self.handle, int(nrhs), C.byref(v)))
+        return v.value
+
     def set_profiling(self, enabled: bool):
         check(lib().nnmg_hierarchy_set_profiling(self.handle, int(bool(enabled))))
 
@@ -446,3 +452,93 @@ class Hierarchy:
         out = np.zeros((len(self.levels), 6), dtype=np.float64)
         check(lib().nnmg_hierarchy_profile(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
+
+
+class Ticket:
+    """A queued serving request; keeps its vectors alive until waited for."""
+
+    def __init__(self, server, ident, b, x, nr, hist, multi):
+        self.server, self.id, self.b, self.x, self.nr, self.hist, self.multi = server, ident, b, x, nr, hist, multi
+
+    def done(self) -> bool:
+        flag = C.c_int()
+        check(lib().nnmg_server_poll(self.server.handle, C.c_int64(self.id), C.byref(flag)))
+        return bool(flag.value)
+
+    def wait(self, raise_on_failure: bool = True):
+        """Block until the request has finished: (x, info or list of infos, times dict)."""
+        res = (_lib.CgResult * self.nr)()
+        times = _lib.RequestTimes()
+        code = lib().nnmg_server_wait(self.server.handle, C.c_int64(self.id), res, C.byref(times))
+        infos = []
+        for k in range(self.nr):
+            info = dict(iterations=res[k].iterations, relres=res[k].relres,
+                        status=_lib.ERRORS.get(res[k].status, "OK") if res[k].status else "OK")
+            if self.hist is not None:
+                info["history"] = self.hist[k, : res[k].iterations + 1].copy()
+            infos.append(info)
+        if code != 0 and raise_on_failure:
+            check(code)
+        t = dict(queued_ms=times.queued_ms, run_ms=times.run_ms, total_ms=times.total_ms)
+        return self.x, (infos if self.multi else infos[0]), t
+
+
+class Server:
+    """Serving loop with continuous batching (nnmg_server_*): requests on
+    resident hierarchies are admitted as slots and memory free up and run
+    overlapped on their own streams."""
+
+    def __init__(self, ctx: Context, max_active: int = 4, memory_budget: int = 64 << 30):
+        self.ctx = ctx
+        o = _lib.ServerOpts()
+        lib().nnmg_default_server_opts(C.byref(o))
+        o.max_active = int(max_active)
+        o.memory_budget = int(memory_budget)
+        h = C.c_void_p()
+        check(lib().nnmg_server_create(ctx.handle, C.byref(o), C.byref(h)))
+        self.handle = h
+
+    def submit(self, hierarchy, b: torch.Tensor, x: torch.Tensor | None = None, rtol: float = 1e-8,
+               max_it: int = 200, vcycle_dtype=torch.float32, history: bool = False, use_graph: bool = True) -> Ticket:
+        """Queue a solve on `hierarchy`, or on whichever of a list of equivalent
+        replicas is idle first (nnmg_server_submit_any)."""
+        replicas = list(hierarchy) if isinstance(hierarchy, (list, tuple)) else [hierarchy]
+        n = replicas[0].fine.n_dofs
+        nr = _nrhs(b, n, "b")
+        x = torch.empty_like(b) if x is None else x
+        if x.shape != b.shape:
+            raise ValueError("b and x must have the same shape")
+        bp = _vec(b, n * nr, self.ctx.device, torch.float64, "b")
+        xp = _vec(x, n * nr, self.ctx.device, torch.float64, "x")
+        o = _lib.CgOpts()
+        lib().nnmg_default_cg_opts(C.byref(o))
+        o.rtol, o.max_it = float(rtol), int(max_it)
+        o.vcycle_prec = _DTYPE_PREC[vcycle_dtype]
+        o.use_graph = int(bool(use_graph))
+        hist = np.full((nr, max_it + 1), np.nan) if history else None
+        o.history = hist.ctypes.data_as(C.POINTER(C.c_double)) if history else None
+        torch.cuda.current_stream().synchronize()  # b complete before the server's streams read it
+        t = C.c_int64()
+        hs = (C.c_void_p * len(replicas))(*[h.handle.value for h in replicas])
+        check(lib().nnmg_server_submit_any(self.handle, hs, len(replicas), nr, bp, xp, C.byref(o), C.byref(t)))
+        return Ticket(self, t.value, b, x, nr, hist, b.dim() == 2)
+
+    def stats(self) -> dict:
+        st = _lib.ServerStats()
+        check(lib().nnmg_server_get_stats(self.handle, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nnmg_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def footprint(self, hierarchy: "Hierarchy", nrhs: int) -> int:
+        return hierarchy.footprint(nrhs)
+

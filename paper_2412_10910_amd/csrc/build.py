@@ -29,6 +29,7 @@ SOURCES = [
     "host/hierarchy.cpp",
     "host/capi.cpp",
     "host/tune.cpp",
+    "host/server.cpp",
     "kernels/vmult.hip",
     "kernels/geometry.hip",
     "kernels/transfer.hip",

@@ -21,6 +21,15 @@ void vcycle(Hierarchy& H, int prec, const void* r, void* z, int nr, hipStream_t 
 int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg_result* res, int nr,
         hipStream_t s);
 void set_profiling(Hierarchy& H, bool on);
+size_t hierarchy_footprint(const Hierarchy& H, int nr);
+struct Server;
+Server* server_create(Ctx* ctx, const nnmg_server_opts& o);
+void server_destroy(Server* S);
+int64_t server_submit(Server* S, Hierarchy* const* replicas, int n_replicas, int nr, const double* b, double* x,
+                      const nnmg_cg_opts& o);
+int server_wait(Server* S, int64_t id, nnmg_cg_result* res, nnmg_request_times* times, std::string* err);
+bool server_poll(Server* S, int64_t id);
+void server_stats(Server* S, nnmg_server_stats* out);
 void profile(Hierarchy& H, double* ms);
 
 namespace {
@@ -479,6 +488,88 @@ int nnmg_transfer_team(const nnmg_transfer* transfer, int* team) {
     return guarded([&] {
         if (!transfer || !team) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
         *team = transfer->team;
+        return NNMG_OK;
+    });
+}
+
+int nnmg_hierarchy_footprint(const nnmg_hierarchy* h, int nrhs, size_t* bytes) {
+    return guarded([&] {
+        if (!h || !bytes) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        check_rhs(nrhs);
+        *bytes = hierarchy_footprint(*reinterpret_cast<const Hierarchy*>(h), nrhs);
+        return NNMG_OK;
+    });
+}
+
+void nnmg_default_server_opts(nnmg_server_opts* o) {
+    if (!o) return;
+    o->max_active = 4;
+    o->memory_budget = (size_t)64 << 30;
+}
+
+int nnmg_server_create(nnmg_ctx* ctx, const nnmg_server_opts* opts, nnmg_server** out) {
+    return guarded([&] {
+        if (!ctx || !out) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        nnmg_server_opts o;
+        nnmg_default_server_opts(&o);
+        if (opts) o = *opts;
+        *out = reinterpret_cast<nnmg_server*>(server_create(ctx, o));
+        return NNMG_OK;
+    });
+}
+
+void nnmg_server_destroy(nnmg_server* server) {
+    try {
+        server_destroy(reinterpret_cast<Server*>(server));
+    } catch (...) {
+    }
+}
+
+int nnmg_server_submit_any(nnmg_server* server, nnmg_hierarchy* const* replicas, int n_replicas, int nrhs,
+                           const double* b, double* x, const nnmg_cg_opts* opts, int64_t* ticket) {
+    return guarded([&] {
+        if (!server || !replicas || !b || !x || !ticket) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (b == x) fail(NNMG_ERR_INVALID_ARG, "vectors alias");
+        check_rhs(nrhs);
+        nnmg_cg_opts o;
+        nnmg_default_cg_opts(&o);
+        if (opts) o = *opts;
+        *ticket = server_submit(reinterpret_cast<Server*>(server), reinterpret_cast<Hierarchy* const*>(replicas),
+                                n_replicas, nrhs, b, x, o);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_server_submit(nnmg_server* server, nnmg_hierarchy* h, int nrhs, const double* b, double* x,
+                       const nnmg_cg_opts* opts, int64_t* ticket) {
+    return nnmg_server_submit_any(server, &h, 1, nrhs, b, x, opts, ticket);
+}
+
+int nnmg_server_poll(nnmg_server* server, int64_t ticket, int* done) {
+    return guarded([&] {
+        if (!server || !done) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        *done = server_poll(reinterpret_cast<Server*>(server), ticket) ? 1 : 0;
+        return NNMG_OK;
+    });
+}
+
+int nnmg_server_wait(nnmg_server* server, int64_t ticket, nnmg_cg_result* res, nnmg_request_times* times) {
+    return guarded([&] {
+        if (!server) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        std::string err;
+        const int st = server_wait(reinterpret_cast<Server*>(server), ticket, res, times, &err);
+        if (st != NNMG_OK)
+            report(st, err.empty() ? (st == NNMG_ERR_NOT_CONVERGED ? "CG reached max_it before the tolerance"
+                                                                     : "request failed")
+                                   : err);
+        return st;
+    });
+}
+
+int nnmg_server_get_stats(nnmg_server* server, nnmg_server_stats* stats) {
+    return guarded([&] {
+        if (!server || !stats) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        server_stats(reinterpret_cast<Server*>(server), stats);
         return NNMG_OK;
     });
 }

@@ -36,6 +36,8 @@ enum { kPre = 0, kRes = 1, kRestrict = 2, kCoarse = 3, kProlong = 4, kPost = 5, 
 struct WorkVectors {
     DeviceArray<char> f, x, d, ax, r;  // ax: operator output of atomic-scatter levels, kept zero between uses
     DeviceArray<char> contrib;         // operator contribution slots of this level
+    DeviceArray<char> rbuf;            // restriction sums into this level (its transfer's slots): the
+                                       // hierarchy's own, so hierarchies sharing a transfer can run at once
 };
 
 struct ProfileRecord {
@@ -75,6 +77,8 @@ struct Hierarchy {
     hipStream_t capture = nullptr;
     hipGraphExec_t precond_graph[2][kMaxRhs + 1] = {};
     long graph_sig = 0;  // config_sig() when the graphs were captured
+
+    std::atomic<bool> in_use{false};  // held by a serving request
 
     // changes whenever the autotuner switches a kernel variant of a level or transfer
     long config_sig() const {
@@ -134,6 +138,7 @@ static void ensure_rhs(Hierarchy& H, int nr) {
                 NNMG_HIP(hipMemset(a->ptr, 0, b));
             }
             w.contrib.alloc(H.ctx, std::max<size_t>(L.contrib_len * L.ncomp * (size_t)nr, 1) * wsize(prec));
+            if (l + 1 < H.levels.size()) w.rbuf.alloc(H.ctx, restriction_scratch_bytes(*H.transfers[l], nr));
         }
     const size_t n = std::max<size_t>((size_t)H.levels.back()->n_dofs * (size_t)nr, 1);
     for (auto* a : {&H.r, &H.p, &H.qv, &H.z}) a->alloc(H.ctx, n);
@@ -142,7 +147,6 @@ static void ensure_rhs(Hierarchy& H, int nr) {
         a->alloc(H.ctx, nc);
         NNMG_HIP(hipMemset(a->ptr, 0, a->bytes()));
     }
-    for (auto* t : H.transfers) transfer_reserve_rhs(*t, nr);
     H.rhs_cap = nr;
 }
 
@@ -303,7 +307,7 @@ static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, 
         Scope sc(H, l, kRestrict, s);
         // every unconstrained coarse DoF has restriction slots; the constrained
         // entries of f_c are never written and stay zero
-        launch_restrict(T, prec, w.r.ptr, wc.f.ptr, false, s, nr);
+        launch_restrict(T, prec, w.r.ptr, wc.f.ptr, false, s, nr, wc.rbuf.ptr);
     }
     vcycle_level(H, l - 1, prec, wc.f.ptr, wc.x.ptr, nr, s);
     {
@@ -490,116 +494,176 @@ void vcycle(Hierarchy& H, int prec, const void* r, void* z, int nr, hipStream_t 
 // stopping test.  One that has converged (or broken down) is frozen: its
 // active flag is cleared, so alpha = beta = 0 from then on and its iterate and
 // residual stay exactly as they were, while the others go on.
-int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg_result* res, int nr,
-        hipStream_t s) {
-    if (o.max_it < 0 || !(o.rtol >= 0.0)) fail(NNMG_ERR_INVALID_ARG, "CG options");
-    if (o.vcycle_prec != NNMG_FP64 && o.vcycle_prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "vcycle_prec");
-    ensure_rhs(H, nr);
-    H.last = s;
-    Level& L = *H.levels.back();
-    const int top = (int)H.levels.size() - 1;
-    const size_t n = (size_t)L.n_dofs, nv = n * (size_t)nr;
-    const int prec = o.vcycle_prec;
-    WorkVectors& w32 = H.work[NNMG_FP32][top];
+//
+// The solve is a resumable task: every stage ends with an asynchronous copy
+// of the scalars to pinned host memory and an event; step() runs when that
+// event has completed, takes the decisions the scalars call for and launches
+// the next stage.  The blocking solve waits for each event in turn; the
+// serving loop (host/server.cpp) advances many tasks on their own streams.
+struct PcgTask {
+    Hierarchy& H;
+    const double* b;
+    double* x;
+    nnmg_cg_opts o;
+    nnmg_cg_result* res;
+    int nr;
+    hipStream_t s;
+    hipEvent_t ev = nullptr;
+    int it = 0;
+    bool started = false;  // the b.b stage is done once started
+    bool done = false;
+    std::vector<double> bnorm;
+    std::vector<char> active;
+    int n_active = 0;
+    bool graph = false;
+    int prec = NNMG_FP64;
+    size_t n = 0, nv = 0, nsc = 0, hlen = 0;
+
+    PcgTask(Hierarchy& h, const double* b_, double* x_, const nnmg_cg_opts& o_, nnmg_cg_result* r_, int nr_,
+            hipStream_t s_)
+        : H(h), b(b_), x(x_), o(o_), res(r_), nr(nr_), s(s_) {}
+    ~PcgTask() {
+        if (ev) (void)hipEventDestroy(ev);
+    }
+
+    Level& L() { return *H.levels.back(); }
+    int top() const { return (int)H.levels.size() - 1; }
+
     // z = V(r) on the hierarchy's own vectors, so the launches can be captured once
-    auto launches = [&](hipStream_t st) {
+    void launches(hipStream_t st) {
+        WorkVectors& w32 = H.work[NNMG_FP32][top()];
         if (prec == NNMG_FP64) {
-            vcycle_level(H, top, NNMG_FP64, H.r.ptr, H.z.ptr, nr, st);
+            vcycle_level(H, top(), NNMG_FP64, H.r.ptr, H.z.ptr, nr, st);
         } else {
             launch_cast_64_to_32(H.r.ptr, (float*)w32.f.ptr, nv, st);
-            vcycle_level(H, top, NNMG_FP32, w32.f.ptr, w32.x.ptr, nr, st);
+            vcycle_level(H, top(), NNMG_FP32, w32.f.ptr, w32.x.ptr, nr, st);
             launch_cast_32_to_64((const float*)w32.x.ptr, H.z.ptr, nv, st);
         }
-    };
-    const bool graph = o.use_graph && !H.profiling;
-    if (H.graph_sig != H.config_sig()) {  // captured with other kernel variants
-        H.drop_graphs();
-        H.graph_sig = H.config_sig();
     }
-    hipGraphExec_t& exec = H.precond_graph[prec][nr];
-    if (graph && !exec) {
-        if (!H.capture) NNMG_HIP(hipStreamCreateWithFlags(&H.capture, hipStreamNonBlocking));
-        hipGraph_t g = nullptr;
-        NNMG_HIP(hipStreamBeginCapture(H.capture, hipStreamCaptureModeThreadLocal));
-        try {
-            launches(H.capture);
-        } catch (...) {
-            (void)hipStreamEndCapture(H.capture, &g);
-            if (g) (void)hipGraphDestroy(g);
-            throw;
-        }
-        NNMG_HIP(hipStreamEndCapture(H.capture, &g));
-        const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            exec = nullptr;
-            fail(NNMG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-        }
-    }
-    auto precondition = [&]() {
+
+    void precondition() {
         if (graph)
-            NNMG_HIP(hipGraphLaunch(exec, s));
+            NNMG_HIP(hipGraphLaunch(H.precond_graph[prec][nr], s));
         else
             launches(s);
-    };
-    double* sc = H.scal.ptr;
-    double* hs = H.hscal;
-    const size_t nsc = (size_t)kScal * (size_t)nr;
-    auto fetch = [&]() {
-        NNMG_HIP(hipMemcpyAsync(hs, sc, nsc * sizeof(double), hipMemcpyDeviceToHost, s));
-        NNMG_HIP(hipStreamSynchronize(s));
-    };
-    // the host copy is current (fetched with nothing launched since), so it can go back whole
-    auto push_flags = [&]() { NNMG_HIP(hipMemcpyAsync(sc, hs, nsc * sizeof(double), hipMemcpyHostToDevice, s)); };
-    const size_t hlen = (size_t)o.max_it + 1;
-    NNMG_HIP(hipMemcpyAsync(H.r.ptr, b, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
-    launch_fill(x, nv, NNMG_FP64, s);
-    launch_dot(b, b, n, H.partial.ptr, sc + 6, s, nr, kScal);
-    fetch();
-    std::vector<double> bnorm((size_t)nr);
-    std::vector<char> active((size_t)nr, 0);
-    int n_active = 0;
-    for (int k = 0; k < nr; ++k) {
-        const double bn = std::sqrt(hs[k * kScal + 6]);
-        bnorm[(size_t)k] = bn;
-        if (o.history) o.history[(size_t)k * hlen] = 1.0;
-        res[k].iterations = 0;
-        res[k].relres = bn > 0 ? 1.0 : 0.0;
-        res[k].status = NNMG_OK;
-        if (std::isnan(bn)) {
-            res[k].status = NNMG_ERR_BREAKDOWN;
-        } else if (bn > 0.0) {
-            res[k].status = NNMG_ERR_NOT_CONVERGED;
-            active[(size_t)k] = 1;
-            ++n_active;
-        }
-        hs[k * kScal + 7] = active[(size_t)k] ? 1.0 : 0.0;
     }
-    auto overall = [&]() {
+
+    // scalars to the host, then the event step() waits for
+    void fetch_async() {
+        NNMG_HIP(hipMemcpyAsync(H.hscal, H.scal.ptr, nsc * sizeof(double), hipMemcpyDeviceToHost, s));
+        NNMG_HIP(hipEventRecord(ev, s));
+    }
+
+    // the host copy is current (fetched with nothing launched since), so it can go back whole
+    void push_flags() {
+        NNMG_HIP(hipMemcpyAsync(H.scal.ptr, H.hscal, nsc * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+
+    // operator product, alpha, update of x and r, and the fetch of the new scalars
+    void iteration_body() {
+        double* sc = H.scal.ptr;
+        Level& lv = L();
+        if (lv.atomic_scatter) {
+            launch_fill(H.qv.ptr, nv, NNMG_FP64, s);
+            launch_vmult_cells(lv, NNMG_FP64, H.p.ptr, H.qv.ptr, s, nr, H.work[NNMG_FP64][top()].contrib.ptr);
+            launch_dot(H.p.ptr, H.qv.ptr, n, H.partial.ptr, sc + 1, s, nr, kScal);
+        } else {
+            double* cb = (double*)H.work[NNMG_FP64][top()].contrib.ptr;
+            launch_vmult_contrib(lv, NNMG_FP64, H.p.ptr, cb, s, nr);
+            launch_gather_dot(lv, cb, H.p.ptr, H.qv.ptr, H.partial.ptr, sc + 1, s, nr);
+        }
+        launch_scalar_op(sc, 0, s, nr);
+        launch_cg_update(n, x, H.r.ptr, H.p.ptr, H.qv.ptr, sc, H.partial.ptr, sc + 3, s, nr);
+        fetch_async();
+    }
+
+    // first stage: r = b, x = 0, b.b
+    void start() {
+        if (o.max_it < 0 || !(o.rtol >= 0.0)) fail(NNMG_ERR_INVALID_ARG, "CG options");
+        if (o.vcycle_prec != NNMG_FP64 && o.vcycle_prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "vcycle_prec");
+        ensure_rhs(H, nr);
+        H.last = s;
+        n = (size_t)L().n_dofs;
+        nv = n * (size_t)nr;
+        nsc = (size_t)kScal * (size_t)nr;
+        hlen = (size_t)o.max_it + 1;
+        prec = o.vcycle_prec;
+        graph = o.use_graph && !H.profiling;
+        if (H.graph_sig != H.config_sig()) {  // captured with other kernel variants
+            H.drop_graphs();
+            H.graph_sig = H.config_sig();
+        }
+        hipGraphExec_t& exec = H.precond_graph[prec][nr];
+        if (graph && !exec) {
+            if (!H.capture) NNMG_HIP(hipStreamCreateWithFlags(&H.capture, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            NNMG_HIP(hipStreamBeginCapture(H.capture, hipStreamCaptureModeThreadLocal));
+            try {
+                launches(H.capture);
+            } catch (...) {
+                (void)hipStreamEndCapture(H.capture, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            NNMG_HIP(hipStreamEndCapture(H.capture, &g));
+            const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                exec = nullptr;
+                fail(NNMG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+        }
+        NNMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        NNMG_HIP(hipMemcpyAsync(H.r.ptr, b, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+        launch_fill(x, nv, NNMG_FP64, s);
+        launch_dot(b, b, n, H.partial.ptr, H.scal.ptr + 6, s, nr, kScal);
+        fetch_async();
+    }
+
+    int overall() const {
         int st = NNMG_OK;
         for (int k = 0; k < nr; ++k)
             if (res[k].status == NNMG_ERR_BREAKDOWN) st = NNMG_ERR_BREAKDOWN;
             else if (res[k].status != NNMG_OK && st == NNMG_OK) st = res[k].status;
         return st;
-    };
-    if (n_active == 0) return overall();
-    push_flags();
-    precondition();
-    launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 0, s, nr, kScal);
-    NNMG_HIP(hipMemcpyAsync(H.p.ptr, H.z.ptr, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
-    for (int it = 1; it <= o.max_it; ++it) {
-        if (L.atomic_scatter) {
-            launch_fill(H.qv.ptr, nv, NNMG_FP64, s);
-            launch_vmult_cells(L, NNMG_FP64, H.p.ptr, H.qv.ptr, s, nr, H.work[NNMG_FP64][top].contrib.ptr);
-            launch_dot(H.p.ptr, H.qv.ptr, n, H.partial.ptr, sc + 1, s, nr, kScal);
-        } else {
-            double* cb = (double*)H.work[NNMG_FP64][top].contrib.ptr;
-            launch_vmult_contrib(L, NNMG_FP64, H.p.ptr, cb, s, nr);
-            launch_gather_dot(L, cb, H.p.ptr, H.qv.ptr, H.partial.ptr, sc + 1, s, nr);
+    }
+
+    bool ready() const { return hipEventQuery(ev) == hipSuccess; }
+
+    // the scalars of the last stage are on the host: decide and launch the
+    // next stage; true when the solve has finished
+    bool step() {
+        double* hs = H.hscal;
+        double* sc = H.scal.ptr;
+        if (!started) {
+            started = true;
+            bnorm.assign((size_t)nr, 0.0);
+            active.assign((size_t)nr, 0);
+            for (int k = 0; k < nr; ++k) {
+                const double bn = std::sqrt(hs[k * kScal + 6]);
+                bnorm[(size_t)k] = bn;
+                if (o.history) o.history[(size_t)k * hlen] = 1.0;
+                res[k].iterations = 0;
+                res[k].relres = bn > 0 ? 1.0 : 0.0;
+                res[k].status = NNMG_OK;
+                if (std::isnan(bn)) {
+                    res[k].status = NNMG_ERR_BREAKDOWN;
+                } else if (bn > 0.0) {
+                    res[k].status = NNMG_ERR_NOT_CONVERGED;
+                    active[(size_t)k] = 1;
+                    ++n_active;
+                }
+                hs[k * kScal + 7] = active[(size_t)k] ? 1.0 : 0.0;
+            }
+            if (n_active == 0 || o.max_it == 0) return done = true;
+            push_flags();
+            precondition();
+            launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 0, s, nr, kScal);
+            NNMG_HIP(hipMemcpyAsync(H.p.ptr, H.z.ptr, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+            it = 1;
+            iteration_body();
+            return false;
         }
-        launch_scalar_op(sc, 0, s, nr);
-        launch_cg_update(n, x, H.r.ptr, H.p.ptr, H.qv.ptr, sc, H.partial.ptr, sc + 3, s, nr);
-        fetch();
         bool changed = false;
         for (int k = 0; k < nr; ++k) {
             if (!active[(size_t)k]) continue;
@@ -625,15 +689,67 @@ int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg
                 changed = true;
             }
         }
-        if (n_active == 0 || it == o.max_it) break;
+        if (n_active == 0 || it == o.max_it) return done = true;
         if (changed) push_flags();
         precondition();
         launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 4, s, nr, kScal);
         launch_scalar_op(sc, 1, s, nr);
         launch_cg_direction(n, H.z.ptr, H.p.ptr, sc, s, nr);
+        ++it;
+        iteration_body();
+        return false;
     }
-    return overall();
+};
+
+PcgTask* pcg_task_create(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg_result* res,
+                         int nr, hipStream_t s) {
+    auto* t = new PcgTask(H, b, x, o, res, nr, s);
+    try {
+        t->start();
+    } catch (...) {
+        delete t;
+        throw;
+    }
+    return t;
 }
+
+bool pcg_task_ready(const PcgTask* t) { return t->ready(); }
+bool pcg_task_step(PcgTask* t) { return t->step(); }
+int pcg_task_status(const PcgTask* t) { return t->overall(); }
+void pcg_task_destroy(PcgTask* t) { delete t; }
+
+int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg_result* res, int nr,
+        hipStream_t s) {
+    PcgTask t(H, b, x, o, res, nr, s);
+    t.start();
+    do {
+        NNMG_HIP(hipEventSynchronize(t.ev));
+    } while (!t.step());
+    return t.overall();
+}
+
+// device memory a solve of nr right-hand sides needs beyond the hierarchy's
+// fixed data: work vectors of both precisions, CG vectors, coarse-solve
+// vectors, contribution and restriction buffers
+size_t hierarchy_footprint(const Hierarchy& H, int nr) {
+    size_t bytes = 0;
+    for (int prec : {NNMG_FP64, NNMG_FP32}) {
+        const size_t w = prec == NNMG_FP64 ? 8 : 4;
+        for (const Level* L : H.levels)
+            bytes += (5 * (size_t)L->n_dofs + L->contrib_len * L->ncomp) * (size_t)nr * w;
+    }
+    bytes += 4 * (size_t)H.levels.back()->n_dofs * (size_t)nr * 8;
+    bytes += 2 * (size_t)H.levels[0]->n_dofs * (size_t)nr * 8;
+    for (const Transfer* t : H.transfers) bytes += 2 * restriction_scratch_bytes(*t, nr);
+    return bytes;
+}
+
+// the hierarchy's own work memory must not be shared by two solves at a time
+bool hierarchy_try_acquire(Hierarchy& H) {
+    bool expect = false;
+    return H.in_use.compare_exchange_strong(expect, true);
+}
+void hierarchy_release(Hierarchy& H) { H.in_use.store(false); }
 
 // ---------------------------------------------------------------------------
 // profiling

@@ -250,8 +250,11 @@ void launch_locate(int dim, const double* pts, int np, const double* cverts, con
                    int32_t* owner, double* xi, int32_t* flags, hipStream_t s);
 void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fine, hipStream_t s, int nr = 1);
 // coarse = P^T fine (accumulate = false) or coarse += P^T fine; constrained coarse entries untouched
+// rbuf: scratch of restriction_scratch_bytes(t, nr) for the per-cell sums, or
+// nullptr for the transfer's own buffer (calls on one transfer must then not overlap)
 void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s,
-                     int nr = 1);
+                     int nr = 1, void* rbuf = nullptr);
+size_t restriction_scratch_bytes(const Transfer& t, int nr);
 // dst[v] (+)= sum of the run of v's node, for every value v of n * nr (n vector DoFs of ncomp
 // components) whose node has one; elem holds one plane of `plane` entries per right-hand side,
 // component c of slot k at k * ncomp + c

@@ -516,7 +516,7 @@ static int log2i(int v) {
 
 template <int DIM, int N, class T>
 static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, const void* in, void* out, int nv,
-                              hipStream_t s) {
+                              void* rbuf, hipStream_t s) {
     const Level& C = *tr.coarse;
     if (tr.n_points == 0 || C.n_cells == 0) return;
     const NodeTable<N, T> nt = node_table<N, T>(C.basis);
@@ -542,19 +542,19 @@ static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, con
     const int64_t total = C.n_cells * (int64_t)nv * team;
     const dim3 grid((unsigned)((total + threads - 1) / threads));
     hipLaunchKernelGGL((restrict_kernel<DIM, N, T, S>), grid, dim3(threads), 0, s, tr.d_off.ptr, tr.d_fine.ptr, xi,
-                       tr.n_points, tr.d_rslot.ptr, (const T*)in, (T*)tr.d_rbuf.ptr, (int)C.n_cells,
+                       tr.n_points, tr.d_rslot.ptr, (const T*)in, (T*)rbuf, (int)C.n_cells,
                        log2i(team), nt, C.ncomp, nv / C.ncomp, (int64_t)(tr.n_rslots * C.ncomp));
     NNMG_HIP(hipGetLastError());
 }
 
 template <class T>
 static void transfer_prec(const Transfer& tr, bool prolong, const T* xi, const void* in, void* out, int nr,
-                          hipStream_t s) {
+                          void* rbuf, hipStream_t s) {
     const int d = tr.coarse->dim, n = tr.coarse->n;
     if (nr < 1 || nr > kMaxRhs) fail(NNMG_ERR_INVALID_ARG, "number of right-hand sides");
     const int nv = tr.coarse->ncomp * nr;
 #define NNMG_CASE(D, NN) \
-    if (d == D && n == NN) return transfer_dispatch<D, NN, T>(tr, prolong, xi, in, out, nv, s);
+    if (d == D && n == NN) return transfer_dispatch<D, NN, T>(tr, prolong, xi, in, out, nv, rbuf, s);
     NNMG_CASE(2, 2) NNMG_CASE(2, 3) NNMG_CASE(2, 4) NNMG_CASE(2, 5)
     NNMG_CASE(3, 2) NNMG_CASE(3, 3) NNMG_CASE(3, 4) NNMG_CASE(3, 5)
 #undef NNMG_CASE
@@ -563,21 +563,29 @@ static void transfer_prec(const Transfer& tr, bool prolong, const T* xi, const v
 
 void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fine, hipStream_t s, int nr) {
     if (prec == NNMG_FP64)
-        transfer_prec<double>(t, true, t.d_xi64.ptr, coarse, fine, nr, s);
+        transfer_prec<double>(t, true, t.d_xi64.ptr, coarse, fine, nr, nullptr, s);
     else
-        transfer_prec<float>(t, true, t.d_xi32.ptr, coarse, fine, nr, s);
+        transfer_prec<float>(t, true, t.d_xi32.ptr, coarse, fine, nr, nullptr, s);
 }
 
-// rbuf must hold nr values per slot: Transfer::rbuf_rhs right-hand sides
+// rbuf: restriction_scratch_bytes(t, nr) bytes of the caller's, or nullptr for
+// the transfer's own buffer (which must then hold nr right-hand sides)
 void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s,
-                     int nr) {
-    if (nr > t.rbuf_rhs) fail(NNMG_ERR_INVALID_ARG, "restriction buffer holds fewer right-hand sides");
+                     int nr, void* rbuf) {
+    if (!rbuf) {
+        if (nr > t.rbuf_rhs) fail(NNMG_ERR_INVALID_ARG, "restriction buffer holds fewer right-hand sides");
+        rbuf = t.d_rbuf.ptr;
+    }
     if (prec == NNMG_FP64)
-        transfer_prec<double>(t, false, t.d_xi64.ptr, fine, coarse, nr, s);
+        transfer_prec<double>(t, false, t.d_xi64.ptr, fine, coarse, nr, rbuf, s);
     else
-        transfer_prec<float>(t, false, t.d_xi32.ptr, fine, coarse, nr, s);
-    launch_gather_runs((size_t)t.coarse->n_dofs, t.coarse->ncomp, t.d_roff.ptr, prec, t.d_rbuf.ptr,
+        transfer_prec<float>(t, false, t.d_xi32.ptr, fine, coarse, nr, rbuf, s);
+    launch_gather_runs((size_t)t.coarse->n_dofs, t.coarse->ncomp, t.d_roff.ptr, prec, rbuf,
                        t.n_rslots * (size_t)t.coarse->ncomp, coarse, accumulate, s, nr);
+}
+
+size_t restriction_scratch_bytes(const Transfer& t, int nr) {
+    return std::max<size_t>(t.n_rslots * (size_t)t.coarse->ncomp * (size_t)nr, 1) * sizeof(double);
 }
 
 }  // namespace nnmg

@@ -17,6 +17,7 @@ from .meshes import (  # noqa: F401
     scramble,
     config_levels,
     CONFIGS,
+    SERVING_POOL,
 )
 from .sources import (  # noqa: F401
     gaussian_bumps,

@@ -220,6 +220,20 @@ def level_mesh(domain: str, dim: int, n: int, alpha: float, seed: int) -> Mesh:
     raise ValueError(domain)
 
 
+# Resident hierarchies of the serving stream: Poisson on perturbed cubes (Q2,
+# configuration 1's recipe) and on balls (Q3, configuration 2's), fine sizes
+# spread log-uniformly over 0.1M..8M DoFs, 3 to 5 independent levels each:
+# (config, cells per direction coarse -> fine, degree).
+SERVING_POOL = [
+    (1, [5, 11, 23], 2),           # 103,823 DoFs
+    (2, [4, 9, 20], 3),            # 226,981
+    (1, [4, 8, 17, 36], 2),        # 389,017
+    (2, [5, 10, 20, 40], 3),       # 1,771,561
+    (1, [6, 13, 29, 64], 2),       # 2,146,689
+    (1, [5, 10, 22, 46, 100], 2),  # 8,120,601
+]
+
+
 def config_levels(cfg, cells=None):
     """Meshes of a workload, coarse -> fine; ``cells`` overrides the per-level sizes.
 
