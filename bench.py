@@ -81,9 +81,11 @@ def transfer_bytes(coarse, n_points, word, prolong, nr=1):
 # operator, the oracle sample of the CPU baseline, and a description
 WORKLOADS = {
     "cube_q2": dict(cfg=1, cells=[6, 13, 29, 64], degree=2, operator="laplace", cpu_cells=[3, 6, 13, 29],
+                    roofline="cube_q2_64",
                     text="3D Poisson Q2 on the unit cube, non-nested perturbed hex levels 64^3/29^3/13^3/6^3 "
                          "(+-0.15h), 8 Gaussian bumps, float64 V-cycle in float64 PCG to 1e-8"),
     "beam_q2": dict(cfg=3, cells=[(14, 3, 3), (33, 7, 7), (80, 16, 16)], degree=2, operator="elasticity", rhs=4,
+                    roofline="beam_q2",
                     cpu_cells=[(10, 2, 2), (22, 5, 5), (50, 10, 10)],
                     text="3D linear elasticity, vector Q2, lambda = mu = 1, beam [0,5]x[0,1]^2 clamped at x = 0, "
                          "body load (0,0,-1) and three random smooth loads fused as 4 right-hand sides, "
@@ -242,8 +244,10 @@ ROOFLINE_WORKLOADS = {
 }
 
 KERNEL_SOURCES = ("paper_2412_10910_amd/csrc/kernels/vmult.hip", "paper_2412_10910_amd/csrc/kernels/gather.hip",
-                  "paper_2412_10910_amd/csrc/kernels/transfer.hip", "paper_2412_10910_amd/csrc/internal.hpp")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_operator_transfer_cube_q2_64.txt")
+                  "paper_2412_10910_amd/csrc/kernels/transfer.hip", "paper_2412_10910_amd/csrc/kernels/common.hpp")
+# recorded HBM traffic of the roofline workloads (profiles/traffic_operator_transfer_<workload>.txt)
+def traffic_file(tag):
+    return os.path.join(ROOT, "profiles", f"traffic_operator_transfer_{tag}.txt")
 
 
 def kernel_source_hash():
@@ -255,11 +259,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
+def recorded_traffic(tag):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary,
     or {} when it is missing or was taken on kernel sources that have changed."""
     try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
+        lines = open(traffic_file(tag)).read().splitlines()
     except OSError:
         return {}
     kv = {}
@@ -392,6 +396,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", help="also print the per-component V-cycle times")
     ap.add_argument("--roofline-reps", type=int, default=100)
+    ap.add_argument("--roofline-rhs", type=int, default=1,
+                    help="--roofline-only: also time the launches that carry this many right-hand sides")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the operator/transfer kernel loops of the two finest levels and a copy of "
                          "known size (the run that rocprofv3 traces and counts)")
@@ -441,7 +447,7 @@ def main():
         coarse = nn.Level.from_mesh(ctx, rmeshes[-2], rdeg, rop)
         tr = nn.Transfer(ctx, fine, coarse)
         nbytes = copy_calibration()
-        k = kernel_rooflines(fine, coarse, tr, args.roofline_reps)
+        k = kernel_rooflines(fine, coarse, tr, args.roofline_reps, args.roofline_rhs)
         print(json.dumps({"roofline_only": True, "workload": args.roofline_workload, "copy_bytes": nbytes, "reps": args.roofline_reps,
                           "kernels": {n: {"ms": round(v["ms"], 5), "bytes": v["bytes"], "GB/s": round(v["gbs"], 1),
                                           "frac": round(v["frac"], 4)} for n, v in k.items()}}), flush=True)
@@ -504,7 +510,7 @@ def main():
 
     log("timing the operator and transfer kernels")
     k = kernel_rooflines(fine, levels[-2], transfers[-1], args.roofline_reps, nr)
-    traffic = recorded_traffic() if args.workload == "cube_q2" else {}
+    traffic = recorded_traffic(wl["roofline"])
 
     profile = None
     if args.profile:
