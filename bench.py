@@ -84,6 +84,12 @@ WORKLOADS = {
                     roofline="cube_q2_64",
                     text="3D Poisson Q2 on the unit cube, non-nested perturbed hex levels 64^3/29^3/13^3/6^3 "
                          "(+-0.15h), 8 Gaussian bumps, float64 V-cycle in float64 PCG to 1e-8"),
+    "ball_q4": dict(cfg="2q4", cells=[5, 7, 15, 34, 75], degree=4, operator="laplace", roofline="ball_q4_75",
+                    pmg=True, cpu_cells=[5, 7, 11],
+                    text="3D Poisson Q4 on the ball, non-nested levels 75^3/34^3/15^3/7^3/5^3 (27.3M fine DoFs), "
+                         "bumps in the radius-0.8 ball; coarse solver: polynomial coarsening Q4->Q3->Q2->Q1 on the "
+                         "5^3 mesh, then the dense inverse on Q1 (compared with the dense inverse on 5^3 Q4); "
+                         "float64 V-cycle in float64 PCG to 1e-8"),
     "beam_q2": dict(cfg=3, cells=[(14, 3, 3), (33, 7, 7), (80, 16, 16)], degree=2, operator="elasticity", rhs=4,
                     roofline="beam_q2",
                     cpu_cells=[(10, 2, 2), (22, 5, 5), (50, 10, 10)],
@@ -331,7 +337,7 @@ def copy_calibration(nbytes=1 << 30):
     return nbytes
 
 
-def cpu_baseline(cells, cfg, operator="laplace"):
+def cpu_baseline(cells, cfg, operator="laplace", degree=2, pmg=False):
     """Oracle PCG on a reduced instance of the same workload recipe, 1 thread."""
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -343,8 +349,9 @@ import numpy as np
 from oracle import assemble, elasticity, multigrid, space, transfer
 from workloads import config_levels, config_source, random_vector
 meshes = config_levels({cfg!r}, cells={cells!r})
-k = 2
-sps = [space.Space(m, k) for m in meshes]
+k = {degree}
+specs = ([(meshes[0], d) for d in range(1, k)] if {pmg!r} else []) + [(m, k) for m in meshes]
+sps = [space.Space(m, d) for m, d in specs]
 if {operator!r} == "elasticity":
     nc = 3
     As = [elasticity.stiffness(s, 1.0, 1.0) for s in sps]
@@ -372,8 +379,9 @@ print(json.dumps(dict(n=sps[-1].n_dofs * nc, it=it, t=t)))
     r = json.loads(out.stdout.strip().splitlines()[-1])
     return dict(value=round(r["n"] * r["it"] / r["t"] / 1e6, 4), unit=UNIT, cores=1, kind="oracle",
                 sample=(f"oracle float64 PCG + float64 V-cycle (scipy CSR) on the same recipe at "
-                        f"{' / '.join(str(c) for c in cells[::-1])} cells "
-                        f"({r['n']} fine DoFs), {r['it']} iterations in {r['t']:.2f} s; "
+                        f"{' / '.join(str(c) for c in cells[::-1])} cells, Q{degree}"
+                        + (f" with polynomial coarsening to Q1 on the coarsest mesh" if pmg else "")
+                        + f" ({r['n']} fine DoFs), {r['it']} iterations in {r['t']:.2f} s; "
                         f"setup excluded; {wall:.1f} s wall including setup"),
                 cpu=_cpu_model(), host_cpus=os.cpu_count())
 
@@ -462,6 +470,16 @@ def main():
     t0 = time.perf_counter()
     H = nn.Hierarchy(ctx, levels, transfers)
     t_hier = time.perf_counter() - t0
+    H_mesh, t_hier_mesh = None, None
+    if wl.get("pmg"):
+        # polynomial coarsening below the coarsest mesh level, sharing the mesh levels and transfers;
+        # the hierarchy with the dense inverse on the coarsest mesh is kept for the comparison
+        t0 = time.perf_counter()
+        plevels = [nn.Level.from_mesh(ctx, meshes[0], d, operator) for d in range(1, degree)]
+        ptrs = [nn.Transfer(ctx, (plevels + [levels[0]])[i + 1], plevels[i]) for i in range(len(plevels))]
+        H_mesh, t_hier_mesh = H, t_hier
+        H = nn.Hierarchy(ctx, plevels + levels, ptrs + transfers)
+        t_hier = time.perf_counter() - t0
     tuned = None
     t_tune = 0.0
     if not args.no_tune:
@@ -483,7 +501,7 @@ def main():
     log(f"setup: levels {t_levels:.2f} s, transfers {t_transfers:.2f} s, hierarchy {t_hier:.2f} s; "
         f"fine DoFs {fine.n_dofs}")
 
-    def run(dtype, steps, warmup):
+    def run(dtype, steps, warmup, H=H):
         for _ in range(warmup):
             H.pcg_solve(b, x, rtol=1e-8, vcycle_dtype=dtype, history=False)
         torch.cuda.synchronize()
@@ -507,6 +525,17 @@ def main():
     tot32, lat32, its32, info32 = run(torch.float32, args.steps, args.warmup)
     value = fine.n_dofs * sum(its64) / tot64 / 1e6
     value32 = fine.n_dofs * sum(its32) / tot32 / 1e6
+    dense = None
+    if H_mesh is not None:
+        log("timing the dense coarse inverse on the coarsest mesh for comparison")
+        dsteps = max(1, args.steps // 5)
+        d64, _, dits64, dinfo64 = run(torch.float64, dsteps, 1, H_mesh)
+        d32, _, dits32, dinfo32 = run(torch.float32, dsteps, 1, H_mesh)
+        dense = {"setup_hierarchy_s": round(t_hier_mesh, 3), "coarse_free_dofs": H_mesh.coarse_free_dofs,
+                 "float64_mg": {"value": round(fine.n_dofs * sum(dits64) / d64 / 1e6, 2),
+                                "ms_per_step": round(d64 / dsteps * 1e3, 4), "iterations": dinfo64["iterations"]},
+                 "float32_mg": {"value": round(fine.n_dofs * sum(dits32) / d32 / 1e6, 2),
+                                "ms_per_step": round(d32 / dsteps * 1e3, 4), "iterations": dinfo32["iterations"]}}
 
     log("timing the operator and transfer kernels")
     k = kernel_rooflines(fine, levels[-2], transfers[-1], args.roofline_reps, nr)
@@ -523,7 +552,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(wl["cpu_cells"], cfg, operator)
+        cpu = cpu_baseline(wl["cpu_cells"], cfg, operator, degree, bool(wl.get("pmg")))
 
     op_key = "operator_fp64" if nr == 1 else f"operator_fp64_x{nr}"
     op = k[op_key]
@@ -587,6 +616,9 @@ def main():
     }
     if profile is not None:
         line["vcycle_profile_ms"] = profile
+    if dense is not None:
+        line["config"]["levels"] = [f"{lv.n_dofs}@Q{lv.degree}" for lv in H.levels]
+        line["coarse_dense_inverse"] = dense
     print(json.dumps(line), flush=True)
 
 

@@ -91,6 +91,10 @@ typedef struct {
     int allow_projection; /* 1: points outside every candidate are projected onto the
                              nearest candidate's reference cell (eq. closest_point);
                              0: such points are an error (default 1) */
+    int nested_p;         /* 1 (default): when both levels have the same mesh (vertices and
+                             cells) and the coarse degree is lower, the transfer is the nested
+                             polynomial one (paper §2, Coarse grid solvers): no point location,
+                             sum-factorized interpolation per cell; 0: always locate points */
 } nnmg_transfer_opts;
 
 /* Multigrid settings of nnmg_hierarchy_create (paper §4 solver recipe). */

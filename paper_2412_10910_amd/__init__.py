@@ -11,4 +11,4 @@ from ._lib import NNMGError, lib  # noqa: F401,E402
 
 lib()  # load now: no silent fallback when the HIP library is missing
 
-from .api import Context, Hierarchy, Level, Server, Ticket, Transfer  # noqa: E402,F401
+from .api import Context, Hierarchy, Level, Server, Ticket, Transfer, build_levels  # noqa: E402,F401

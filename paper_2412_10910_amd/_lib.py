@@ -66,6 +66,7 @@ class TransferOpts(C.Structure):
         ("newton_tol", C.c_double),
         ("newton_max_it", C.c_int),
         ("allow_projection", C.c_int),
+        ("nested_p", C.c_int),
     ]
 
 

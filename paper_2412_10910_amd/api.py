@@ -236,12 +236,13 @@ class Transfer:
     """Non-nested transfer between a fine and a coarse level (nnmg_transfer_create)."""
 
     def __init__(self, ctx: Context, fine: Level, coarse: Level, bbox_expand=None, inside_tol=None,
-                 newton_tol=None, newton_max_it=None, allow_projection=None):
+                 newton_tol=None, newton_max_it=None, allow_projection=None, nested_p=None):
         self.ctx, self.fine, self.coarse = ctx, fine, coarse
         o = _lib.TransferOpts()
         lib().nnmg_default_transfer_opts(C.byref(o))
         for name, val in (("bbox_expand", bbox_expand), ("inside_tol", inside_tol), ("newton_tol", newton_tol),
-                          ("newton_max_it", newton_max_it), ("allow_projection", allow_projection)):
+                          ("newton_max_it", newton_max_it), ("allow_projection", allow_projection),
+                          ("nested_p", nested_p)):
             if val is not None:
                 setattr(o, name, type(getattr(o, name))(val))
         h = C.c_void_p()
@@ -439,6 +440,11 @@ class Hierarchy:
         return dict(levels=[lv.tune(dtype, reps) for lv in self.levels],
                     transfers=[tr.tune(dtype, reps) for tr in self.transfers])
 
+    @property
+    def coarse_free_dofs(self) -> int:
+        """Unconstrained DoFs of the coarsest level: the order of the dense inverse."""
+        return self.levels[0].n_free
+
     def footprint(self, nrhs: int = 1) -> int:
         """Device bytes a solve of nrhs right-hand sides needs beyond the hierarchy's fixed data."""
         v = C.c_size_t()
@@ -541,4 +547,17 @@ class Server:
 
     def footprint(self, hierarchy: "Hierarchy", nrhs: int) -> int:
         return hierarchy.footprint(nrhs)
+
+
+def build_levels(ctx: Context, meshes, degree: int, operator: str = "laplace", lam: float = 1.0, mu: float = 1.0,
+                 p_coarsening: bool = False):
+    """Levels (coarse -> fine) and transfers of a hierarchy over independent
+    meshes.  With p_coarsening the coarsest mesh carries degrees 1, 2, ...,
+    degree below the first mesh level (paper §2, Coarse grid solvers: polynomial
+    multigrid on the coarsest triangulation), joined by nested polynomial
+    transfers; the exact coarse solve then acts on the Q1 level."""
+    specs = ([(meshes[0], d) for d in range(1, degree)] if p_coarsening else []) + [(m, degree) for m in meshes]
+    levels = [Level.from_mesh(ctx, m, d, operator, lam, mu) for m, d in specs]
+    transfers = [Transfer(ctx, levels[i + 1], levels[i]) for i in range(len(levels) - 1)]
+    return levels, transfers
 

@@ -35,6 +35,7 @@ SOURCES = [
     "kernels/transfer.hip",
     "kernels/vector.hip",
     "kernels/gather.hip",
+    "kernels/pmg.hip",
 ]
 
 ARCH = os.environ.get("NNMG_OFFLOAD_ARCH", "gfx950")

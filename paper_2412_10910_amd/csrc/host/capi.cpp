@@ -102,6 +102,7 @@ void nnmg_default_transfer_opts(nnmg_transfer_opts* o) {
     o->newton_tol = 1e-12;
     o->newton_max_it = 50;
     o->allow_projection = 1;
+    o->nested_p = 1;
 }
 
 void nnmg_default_mg_opts(nnmg_mg_opts* o) {

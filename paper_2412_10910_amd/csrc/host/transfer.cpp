@@ -13,6 +13,8 @@
 // 4. The points are counting-sorted by owner cell (stable, so fine DoF order
 //    within a cell), and the reference coordinates are stored per coordinate
 //    in float64 and float32.
+// Two levels on one mesh with a lower coarse degree get the nested polynomial
+// transfer instead (setup_nested_p, kernels/pmg.hip).
 #include <algorithm>
 #include <cmath>
 
@@ -23,6 +25,74 @@
 #endif
 
 namespace nnmg {
+
+// restriction slots: the sum of coarse cell K for node a goes to
+// rslot[K q + a], the slots of coarse node j being [roff[j], roff[j+1])
+static void build_restriction_slots(Transfer* T, Ctx* ctx) {
+    const Level* coarse = T->coarse;
+    const std::vector<int32_t>& cdm = coarse->dofmap;
+    std::vector<int32_t> roff((size_t)coarse->n_nodes + 1, 0);
+    for (size_t k = 0; k < cdm.size(); ++k)
+        if (!coarse->constrained[(size_t)cdm[k]]) roff[(size_t)cdm[k] + 1]++;
+    for (int64_t j = 0; j < coarse->n_nodes; ++j) roff[(size_t)j + 1] += roff[(size_t)j];
+    std::vector<int32_t> cur(roff.begin(), roff.end() - 1);
+    std::vector<int32_t> rslot(cdm.size(), -1);
+    for (size_t k = 0; k < cdm.size(); ++k)
+        if (!coarse->constrained[(size_t)cdm[k]]) rslot[k] = cur[(size_t)cdm[k]]++;
+    T->d_rslot.upload(ctx, rslot);
+    T->d_roff.upload(ctx, roff);
+    // ncomp values per slot: component c of slot k at ncomp * k + c
+    T->n_rslots = (size_t)roff.back();
+    T->d_rbuf.alloc(ctx, std::max<size_t>(T->n_rslots * coarse->ncomp, 1));
+}
+
+// Nested polynomial transfer (paper §2, Coarse grid solvers): both levels on
+// one mesh, coarse degree below the fine one.  Every unconstrained fine node
+// is owned by the first cell (in cell order) that holds it; P on a cell is the
+// tensor product of the 1D interpolation matrix E from the coarse Gauss-Lobatto
+// basis to the fine nodes.  The location results (owner, reference position)
+// are recorded as for the located transfer.
+static void setup_nested_p(Transfer* T, Ctx* ctx) {
+    const Level* fine = T->fine;
+    const Level* coarse = T->coarse;
+    const int dim = fine->dim, nf = fine->n, nc = coarse->n, qf = fine->q;
+    const int64_t C = fine->n_cells;
+    T->nested_p = true;
+    for (int i = 0; i < nf; ++i)
+        for (int a = 0; a < nc; ++a) {
+            double v = 1.0;
+            for (int m = 0; m < nc; ++m)
+                if (m != a) v *= (fine->basis.node[i] - coarse->basis.node[m]) / (coarse->basis.node[a] - coarse->basis.node[m]);
+            T->pmat[i * kMaxN + a] = v;
+        }
+    std::vector<int32_t> pfdm((size_t)(C * qf), -1), owner((size_t)fine->n_nodes, -1), local((size_t)fine->n_nodes, -1);
+    for (int64_t c = 0; c < C; ++c)
+        for (int a = 0; a < qf; ++a) {
+            const int32_t node = fine->dofmap[(size_t)(c * qf + a)];
+            if (fine->constrained[(size_t)node] || owner[(size_t)node] >= 0) continue;
+            owner[(size_t)node] = (int32_t)c;
+            local[(size_t)node] = a;
+            pfdm[(size_t)(c * qf + a)] = node;
+        }
+    T->d_pfdm.upload(ctx, pfdm);
+    for (int64_t i = 0; i < fine->n_nodes; ++i) {
+        if (fine->constrained[(size_t)i]) continue;
+        T->h_point_dof.push_back((int32_t)i);
+        T->h_point_owner.push_back(owner[(size_t)i]);
+        const int a = local[(size_t)i];
+        const int ax = a % nf, ay = (a / nf) % nf, az = a / (nf * nf);
+        T->h_point_xi.push_back(fine->basis.node[ax]);
+        T->h_point_xi.push_back(fine->basis.node[ay]);
+        if (dim == 3) T->h_point_xi.push_back(fine->basis.node[az]);
+    }
+    T->n_points = (int64_t)T->h_point_dof.size();
+    T->n_projected = 0;
+    build_restriction_slots(T, ctx);
+}
+
+static bool same_mesh(const Level* a, const Level* b) {
+    return a->dim == b->dim && a->vertices == b->vertices && a->cells == b->cells;
+}
 
 Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_transfer_opts& o) {
     if (!fine || !coarse) fail(NNMG_ERR_INVALID_ARG, "level is NULL");
@@ -42,6 +112,10 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
         T->coarse = coarse;
         level_retain(fine);
         level_retain(coarse);
+        if (o.nested_p && coarse->degree < fine->degree && same_mesh(fine, coarse)) {
+            setup_nested_p(T, ctx);
+            return T;
+        }
 
         // query points: the unconstrained fine nodes (P acts on every component alike)
         std::vector<double> pts;
@@ -181,24 +255,7 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
             bc[(size_t)(2 * b + 1)] = sowner[(size_t)std::min<int64_t>(np, (b + 1) * kPointBlock) - 1];
         }
         T->d_blk_cells.upload(ctx, bc);
-        // restriction slots: the sum of coarse cell K for node a goes to
-        // rslot[K q + a], the slots of coarse DoF j being [roff[j], roff[j+1])
-        {
-            const std::vector<int32_t>& cdm = coarse->dofmap;
-            std::vector<int32_t> roff((size_t)coarse->n_nodes + 1, 0);
-            for (size_t k = 0; k < cdm.size(); ++k)
-                if (!coarse->constrained[(size_t)cdm[k]]) roff[(size_t)cdm[k] + 1]++;
-            for (int64_t j = 0; j < coarse->n_nodes; ++j) roff[(size_t)j + 1] += roff[(size_t)j];
-            std::vector<int32_t> cur(roff.begin(), roff.end() - 1);
-            std::vector<int32_t> rslot(cdm.size(), -1);
-            for (size_t k = 0; k < cdm.size(); ++k)
-                if (!coarse->constrained[(size_t)cdm[k]]) rslot[k] = cur[(size_t)cdm[k]]++;
-            T->d_rslot.upload(ctx, rslot);
-            T->d_roff.upload(ctx, roff);
-            // ncomp values per slot: component c of slot k at ncomp * k + c
-            T->n_rslots = (size_t)roff.back();
-            T->d_rbuf.alloc(ctx, std::max<size_t>(T->n_rslots * coarse->ncomp, 1));
-        }
+        build_restriction_slots(T, ctx);
         T->d_off.upload(ctx, off);
         T->d_fine.upload(ctx, fidx);
         T->d_xi64.upload(ctx, xi64);

@@ -176,6 +176,10 @@ struct Transfer {
     // restriction sums per (coarse cell, node), in slots sorted by coarse DoF
     DeviceArray<int32_t> d_rslot;        // [C_coarse][q] slot of each sum, -1 for constrained DoFs
     DeviceArray<int32_t> d_roff;         // [N_coarse + 1] DoF j sums rbuf[roff[j] .. roff[j+1])
+    // nested polynomial transfer (the two levels share the mesh, the coarse degree is lower)
+    bool nested_p = false;
+    double pmat[kMaxN * kMaxN]{};        // E[i][a] = coarse basis a at fine node i, at i * kMaxN + a
+    DeviceArray<int32_t> d_pfdm;         // [C][q_fine]: the fine node a cell writes, -1 if another cell owns it
     size_t n_rslots = 0;                 // restriction slots
     DeviceArray<double> d_rbuf;          // slot values (float64 or float32)
     int rbuf_rhs = 1;                    // right-hand sides d_rbuf holds (grown on demand)
@@ -255,6 +259,9 @@ void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fi
 void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s,
                      int nr = 1, void* rbuf = nullptr);
 size_t restriction_scratch_bytes(const Transfer& t, int nr);
+// nested polynomial transfer (kernels/pmg.hip): fine += P coarse, and the restriction's per-cell sums
+void launch_pmg_prolongate(const Transfer& t, int prec, const void* coarse, void* fine, int nr, hipStream_t s);
+void launch_pmg_restrict_sums(const Transfer& t, int prec, const void* fine, void* rbuf, int nr, hipStream_t s);
 // dst[v] (+)= sum of the run of v's node, for every value v of n * nr (n vector DoFs of ncomp
 // components) whose node has one; elem holds one plane of `plane` entries per right-hand side,
 // component c of slot k at k * ncomp + c

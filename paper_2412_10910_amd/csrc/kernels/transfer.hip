@@ -562,6 +562,8 @@ static void transfer_prec(const Transfer& tr, bool prolong, const T* xi, const v
 }
 
 void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fine, hipStream_t s, int nr) {
+    if (nr < 1 || nr > kMaxRhs) fail(NNMG_ERR_INVALID_ARG, "number of right-hand sides");
+    if (t.nested_p) return launch_pmg_prolongate(t, prec, coarse, fine, nr, s);
     if (prec == NNMG_FP64)
         transfer_prec<double>(t, true, t.d_xi64.ptr, coarse, fine, nr, nullptr, s);
     else
@@ -576,7 +578,10 @@ void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse
         if (nr > t.rbuf_rhs) fail(NNMG_ERR_INVALID_ARG, "restriction buffer holds fewer right-hand sides");
         rbuf = t.d_rbuf.ptr;
     }
-    if (prec == NNMG_FP64)
+    if (nr < 1 || nr > kMaxRhs) fail(NNMG_ERR_INVALID_ARG, "number of right-hand sides");
+    if (t.nested_p)
+        launch_pmg_restrict_sums(t, prec, fine, rbuf, nr, s);
+    else if (prec == NNMG_FP64)
         transfer_prec<double>(t, false, t.d_xi64.ptr, fine, coarse, nr, rbuf, s);
     else
         transfer_prec<float>(t, false, t.d_xi32.ptr, fine, coarse, nr, rbuf, s);

@@ -141,3 +141,27 @@ def test_point_outside_every_box_is_an_error():
     c = space.Space(_free_mesh(2, 3, 0.0, 0), 1)
     with pytest.raises(transfer.PointNotFound):
         transfer.locate(np.array([[3.0, 3.0]]), c, bruteforce=True)
+
+
+@pytest.mark.parametrize("dim,kf,kc", [(2, 2, 1), (2, 4, 3), (3, 2, 1), (3, 3, 2), (3, 4, 2), (3, 4, 3)])
+def test_nested_polynomial_transfer_galerkin_identity(dim, kf, kc):
+    """Polynomial coarsening on one mesh (paper §2, Coarse grid solvers): the
+    spaces are nested, and on affine cells the Gauss rule integrates both
+    operators exactly, so P^T A_f P = A_c on the free block.  Independent of
+    how P is formed; a wrong or missing entry of P breaks it.  P also
+    reproduces Q_kc polynomials exactly."""
+    from oracle import assemble
+    n = 3 if dim == 2 else 2
+    m = structured_box(dim, n, 0.0, 1.0)
+    Vf, Vc = space.Space(m, kf), space.Space(m, kc)
+    P, _ = transfer.prolongation(Vf, Vc)
+    Af, Ac = assemble.stiffness(Vf), assemble.stiffness(Vc)
+    G = (P.T @ Af @ P).toarray()[np.ix_(Vc.free, Vc.free)]
+    R = Ac.toarray()[np.ix_(Vc.free, Vc.free)]
+    assert np.abs(G - R).max() <= 1e-12 * np.abs(R).max()
+    # exact for a polynomial of degree kc in each variable (no Dirichlet mask)
+    m.dirichlet[:] = 0
+    Vf, Vc = space.Space(m, kf), space.Space(m, kc)
+    P, _ = transfer.prolongation(Vf, Vc)
+    g = lambda x: np.prod([(x[..., a] + 0.3) ** kc - 0.5 * x[..., a] for a in range(dim)], axis=0)
+    assert np.abs(P @ g(Vc.support_points) - g(Vf.support_points)).max() <= 1e-13
