@@ -59,7 +59,57 @@ void level_release(Level* l) {
     if (l && l->refs.fetch_sub(1) == 1) delete static_cast<nnmg_level*>(l);
 }
 
-static void number_dofs(Level& L) {
+// Cell visiting order of the operator: blocks of cpb consecutive cells in
+// input order (the x-runs whose shared faces the operator kernel merges), the
+// blocks in Morton order of their centroids, so that the cells around a node
+// are processed close in time (their contribution slots share cache lines,
+// their source values L2 lines) and each XCD's contiguous range of blocks is
+// a compact region.  NNMG_CELL_ORDER=input keeps the input order.
+static std::vector<int64_t> cell_visit_order(const Level& L) {
+    const int dim = L.dim, nvx = 1 << dim;
+    const int64_t C = L.n_cells, cpb = L.cpb, nb = (C + cpb - 1) / cpb;
+    std::vector<int64_t> bperm((size_t)nb);
+    for (int64_t b = 0; b < nb; ++b) bperm[(size_t)b] = b;
+    const char* ord = std::getenv("NNMG_CELL_ORDER");
+    if (!(ord && std::string(ord) == "input") && nb > 1) {
+        std::vector<double> cen((size_t)(nb * dim), 0.0);
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t c0 = b * cpb, c1 = std::min<int64_t>(C, c0 + cpb);
+            for (int64_t c = c0; c < c1; ++c)
+                for (int v = 0; v < nvx; ++v)
+                    for (int a = 0; a < dim; ++a)
+                        cen[(size_t)(b * dim + a)] += L.vertices[(size_t)(L.cells[(size_t)(c * nvx + v)] * dim + a)];
+            for (int a = 0; a < dim; ++a) {
+                cen[(size_t)(b * dim + a)] /= (double)((c1 - c0) * nvx);
+                lo[a] = std::min(lo[a], cen[(size_t)(b * dim + a)]);
+                hi[a] = std::max(hi[a], cen[(size_t)(b * dim + a)]);
+            }
+        }
+        std::vector<uint64_t> code((size_t)nb, 0);
+        for (int64_t b = 0; b < nb; ++b) {
+            uint32_t qv[3] = {0, 0, 0};
+            for (int a = 0; a < dim; ++a) {
+                const double span = hi[a] - lo[a];
+                const double t = span > 0 ? (cen[(size_t)(b * dim + a)] - lo[a]) / span : 0.0;
+                qv[a] = (uint32_t)std::min(1023.0, std::max(0.0, std::floor(t * 1024.0)));
+            }
+            uint64_t m = 0;
+            for (int bit = 9; bit >= 0; --bit)
+                for (int a = dim - 1; a >= 0; --a) m = (m << 1) | ((qv[a] >> bit) & 1u);
+            code[(size_t)b] = m;
+        }
+        std::stable_sort(bperm.begin(), bperm.end(),
+                         [&](int64_t x, int64_t y) { return code[(size_t)x] < code[(size_t)y]; });
+    }
+    std::vector<int64_t> visit;
+    visit.reserve((size_t)C);
+    for (int64_t b : bperm)
+        for (int64_t c = b * cpb; c < std::min<int64_t>(C, (b + 1) * cpb); ++c) visit.push_back(c);
+    return visit;
+}
+
+static void number_dofs(Level& L, const std::vector<int64_t>& visit) {
     const int dim = L.dim, k = L.degree, n = L.n, q = L.q, nv = 1 << dim;
     const int64_t C = L.n_cells;
     const int64_t V = (int64_t)L.vertices.size() / dim;
@@ -74,7 +124,8 @@ static void number_dofs(Level& L) {
     const int ke = k - 1;  // interior nodes per edge direction
 
     L.dofmap.assign((size_t)(C * q), -1);
-    for (int64_t c = 0; c < C; ++c) {
+    for (int64_t vi = 0; vi < C; ++vi) {
+        const int64_t c = visit[(size_t)vi];
         const int32_t* cv = cells + c * nv;
         int64_t interior_base = -1;
         for (int a = 0; a < q; ++a) {
@@ -267,7 +318,13 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree, const nnmg_leve
         L->ncomp = opts.op == NNMG_OP_ELASTICITY ? dim : 1;
         L->lam = opts.lambda;
         L->mu = opts.mu;
-        number_dofs(*L);
+        // DoFs by first touch in input order (measured: numbering them in the
+        // blocks' Morton order made the transfers slower and cancelled the
+        // operator's gain from processing the blocks in that order)
+        std::vector<int64_t> input_order((size_t)L->n_cells);
+        for (int64_t c = 0; c < L->n_cells; ++c) input_order[(size_t)c] = c;
+        number_dofs(*L, input_order);
+        const std::vector<int64_t> visit = cell_visit_order(*L);
         find_constraints(*L, mesh->dirichlet_vertex);
         compute_support_points(*L);
         if (L->n_nodes * L->ncomp > INT32_MAX) fail(NNMG_ERR_UNSUPPORTED, "more than 2^31 DoFs");
@@ -283,11 +340,20 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree, const nnmg_leve
         std::vector<int32_t> enc(L->dofmap.size());
         for (size_t i = 0; i < enc.size(); ++i) enc[i] = L->constrained[(size_t)L->dofmap[i]] ? -1 : L->dofmap[i];
         L->d_dofmap.upload(ctx, enc);
-        // block positions: cell c at position c (the order array leaves room for a
-        // locality-improving permutation), the last block padded
+        // block positions: the cells in visiting order (blocks of cpb input-order
+        // cells, the blocks in Morton order; see cell_visit_order), the last
+        // block padded
         L->nblocks = (L->n_cells + L->cpb - 1) / L->cpb;
         L->order.assign((size_t)(L->nblocks * L->cpb), -1);
-        for (int64_t c = 0; c < L->n_cells; ++c) L->order[(size_t)c] = (int32_t)c;
+        {
+            int64_t p = 0;
+            for (int64_t i = 0; i < L->n_cells; ++i) {
+                const int64_t c = visit[(size_t)i];
+                // a padded (short) block keeps its own positions
+                if (i > 0 && c / L->cpb != visit[(size_t)(i - 1)] / L->cpb) p = ((p + L->cpb - 1) / L->cpb) * L->cpb;
+                L->order[(size_t)p++] = (int32_t)c;
+            }
+        }
         L->d_order.upload(ctx, L->order);
         // operator layout: lane (cell_in_block, line) holds the x-line `line` of its cell
         const int Lc = dim == 3 ? n * n : n, WG = L->wg;
