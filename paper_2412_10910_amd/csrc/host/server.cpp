@@ -125,6 +125,11 @@ void Server::finish(Request* r, Clock::time_point now) {
         pcg_task_destroy(r->task);
         r->task = nullptr;
     }
+    // a request that failed part-way may have launches in flight that still
+    // use its hierarchy's buffers: drain its stream before another request
+    // may take the hierarchy (a finished solve has launched nothing since the
+    // event it completed on, so this costs nothing then)
+    (void)hipStreamSynchronize(streams[(size_t)r->slot]);
     hierarchy_release(*r->H);
     slot_busy[(size_t)r->slot] = 0;
     reserved -= r->bytes;
