@@ -221,9 +221,10 @@ def level_mesh(domain: str, dim: int, n: int, alpha: float, seed: int) -> Mesh:
 
 
 # Resident hierarchies of the serving stream: Poisson on perturbed cubes (Q2,
-# configuration 1's recipe) and on balls (Q3, configuration 2's), fine sizes
-# spread log-uniformly over 0.1M..8M DoFs, 3 to 5 independent levels each:
-# (config, cells per direction coarse -> fine, degree).
+# the recipe of the 64^3 cube workload) and on balls (Q3, the recipe of the
+# 96^3 ball), fine sizes spread log-uniformly over 0.1M..8M DoFs, 3 to 5
+# independent levels each: (config key, cells per direction coarse -> fine,
+# degree).
 SERVING_POOL = [
     (1, [5, 11, 23], 2),           # 103,823 DoFs
     (2, [4, 9, 20], 3),            # 226,981
