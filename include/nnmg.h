@@ -312,7 +312,9 @@ int nnmg_level_variant(const nnmg_level* level, int* variant);
 
 /* Times the restriction (paper §2, eq. residual2) with 4 << v lanes per
  * coarse cell, v = 0..4, and keeps the fastest (same contract as
- * nnmg_level_tune).  nnmg_transfer_set_team forces a team of 4, 8, 16, 32 or
+ * nnmg_level_tune).  The restriction of 3D cells of degree 3 and 4 takes one
+ * wavefront per coarse cell and value whatever the team: there only v = 0 is
+ * timed (n_variants = 1).  nnmg_transfer_set_team forces a team of 4, 8, 16, 32 or
  * 64 lanes; nnmg_transfer_team reads it. */
 int nnmg_transfer_tune(nnmg_transfer* transfer, nnmg_prec prec, int reps, nnmg_tune_result* res);
 int nnmg_transfer_set_team(nnmg_transfer* transfer, int team);

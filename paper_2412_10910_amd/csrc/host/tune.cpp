@@ -154,10 +154,13 @@ void transfer_tune(Transfer& T, int prec, int reps, nnmg_tune_result* res) {
         DeviceArray<char> coarse;
         coarse.alloc(T.ctx, std::max<size_t>((size_t)T.coarse->n_dofs, 1) * (prec == NNMG_FP64 ? 8 : 4));
         NNMG_HIP(hipMemset(coarse.ptr, 0, coarse.bytes()));
-        res->n_variants = 5;
+        // 3D cells of degree 3 and 4 take one wavefront per cell and value
+        // whatever the team: one timing
+        const bool teamless = !T.nested_p && T.coarse->dim == 3 && T.coarse->n >= 4;
+        res->n_variants = teamless ? 1 : 5;
         for (double& t : res->ms) t = -1.0;
         int best = 0;
-        for (int v = 0; v < 5; ++v) {
+        for (int v = 0; v < res->n_variants; ++v) {
             transfer_set_team(T, 4 << v);
             res->ms[v] = time_ms([&](hipStream_t st) { launch_restrict(T, prec, fine.ptr, coarse.ptr, false, st); },
                                  reps, s);

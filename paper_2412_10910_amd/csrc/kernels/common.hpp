@@ -20,6 +20,22 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
     return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
+// LDS hand-off between the lanes of a block.  A block of one wavefront needs
+// no hardware barrier: LDS operations of a wavefront complete in issue order,
+// so it is enough to keep the compiler from moving LDS accesses across this
+// point.  Unlike a workgroup barrier this does not wait for outstanding
+// global loads, which stay in flight across the LDS stages.
+template <int WG>
+__device__ __forceinline__ void block_sync() {
+    if constexpr (WG == kWave) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <class T>
 __device__ __forceinline__ void atomic_add(T* p, T v) {
     // hardware float atomics in L2 (the library is built with -munsafe-fp-atomics)

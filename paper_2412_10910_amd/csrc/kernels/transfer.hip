@@ -221,45 +221,76 @@ struct Pow {
     static constexpr int value = DIM == 2 ? N * N : N * N * N;
 };
 
-// value at a reference point of the Q_k function with nodal values get(a) on
-// one cell, from the 1D basis values px, py (, pz) at the point's
-// coordinates: tensor-product evaluation, x direction innermost
-template <int DIM, int N, class T, class Get>
-__device__ __forceinline__ T contract_point(const T* px, const T* py, const T* pz, Get get) {
-    T val = T(0);
+// values at PPL reference points of the Q_k function with nodal values
+// get(a) on one cell, from the 1D basis values px[u], py[u] (, pz[u]) at the
+// coordinates of point u: tensor-product evaluation, x direction innermost.
+// Each nodal value is read once for all PPL points; every point's sums are
+// formed in the same order whatever PPL is.
+template <int DIM, int N, int PPL, class T, class Get>
+__device__ __forceinline__ void contract_points(const T (&px)[PPL][N], const T (&py)[PPL][N],
+                                                const T (&pz)[PPL][N], Get get, T (&val)[PPL]) {
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) val[u] = T(0);
     if constexpr (DIM == 3) {
         // one z-slice of values in flight at a time for the larger cells
         constexpr int ZU = N <= 3 ? N : 1;
 #pragma unroll ZU
         for (int c = 0; c < N; ++c) {
-            T s1 = T(0);
+            T s1[PPL];
+#pragma unroll
+            for (int u = 0; u < PPL; ++u) s1[u] = T(0);
 #pragma unroll
             for (int b = 0; b < N; ++b) {
-                T s0 = T(0);
+                T s0[PPL];
 #pragma unroll
-                for (int a = 0; a < N; ++a) s0 += px[a] * get((c * N + b) * N + a);
-                s1 += py[b] * s0;
+                for (int u = 0; u < PPL; ++u) s0[u] = T(0);
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    const T g = get((c * N + b) * N + a);
+#pragma unroll
+                    for (int u = 0; u < PPL; ++u) s0[u] += px[u][a] * g;
+                }
+#pragma unroll
+                for (int u = 0; u < PPL; ++u) s1[u] += py[u][b] * s0[u];
             }
-            val += pz[c] * s1;
+#pragma unroll
+            for (int u = 0; u < PPL; ++u) val[u] += pz[u][c] * s1[u];
         }
     } else {
-        (void)pz;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            T s0 = T(0);
+            T s0[PPL];
 #pragma unroll
-            for (int a = 0; a < N; ++a) s0 += px[a] * get(b * N + a);
-            val += py[b] * s0;
+            for (int u = 0; u < PPL; ++u) s0[u] = T(0);
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                const T g = get(b * N + a);
+#pragma unroll
+                for (int u = 0; u < PPL; ++u) s0[u] += px[u][a] * g;
+            }
+#pragma unroll
+            for (int u = 0; u < PPL; ++u) val[u] += py[u][b] * s0[u];
         }
     }
-    return val;
+}
+
+// the point-parallel prolongation takes PPL consecutive points per lane at
+// Q4 in 3D, where reading the staged q = 125 coarse values from LDS for every
+// point would bound the kernel: the points of a lane almost always share
+// their cell, and then each staged value is read once for all of them (at Q3
+// the extra registers cost more than the LDS reads saved in float64)
+template <int DIM, int N>
+constexpr int prolong_ppl() {
+    return DIM == 3 && N >= 5 ? 2 : 1;
 }
 
 // nv values per coarse node (nc components times nr interleaved right-hand
 // sides, value c of node g at g nv + c): the staged values of a cell are
 // [node][value], and the basis at a point is evaluated once for all values.
-// NVT > 0 fixes nv at compile time; NVT = 0 takes nv_in.
-template <int DIM, int N, class T, int NVT>
+// NVT > 0 fixes nv at compile time; NVT = 0 takes nv_in.  A block takes PPL
+// runs of kPointBlock points (blk_cells holds the first and last owner cell
+// of every run), lane t the points PPL t .. PPL t + PPL - 1 of the block.
+template <int DIM, int N, class T, int NVT, int PPL>
 __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
     const int32_t* __restrict__ off, const int32_t* __restrict__ fine, const T* __restrict__ xi, int64_t npts,
     const int32_t* __restrict__ blk_cells, const int32_t* __restrict__ cdm, const T* __restrict__ uc,
@@ -274,19 +305,20 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
     const int ncap = kStage / QC < kPointBlock ? kStage / QC : kPointBlock;
     const int64_t b = blockIdx.x;
     const int tid = threadIdx.x;
-    const int64_t p = b * kPointBlock + tid;
-    const bool valid = p < npts;
-    // the point's own data first, so that these loads overlap the staging
-    int f = 0;
-    T x[DIM];
+    const int64_t p0 = (b * kPointBlock + tid) * PPL;  // the lane's first point
+    // the points' own data first, so that these loads overlap the staging
+    int f[PPL];
+    T x[PPL][DIM];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) x[a] = T(0);
-    if (valid) {
-        f = fine[p];
+    for (int u = 0; u < PPL; ++u) {
+        const bool ok = p0 + u < npts;
+        f[u] = ok ? fine[p0 + u] : 0;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) x[a] = xi[a * npts + p];
+        for (int a = 0; a < DIM; ++a) x[u][a] = ok ? xi[a * npts + p0 + u] : T(0);
     }
-    const int c0 = blk_cells[2 * b], c1 = blk_cells[2 * b + 1];
+    const int64_t nrun = (npts + kPointBlock - 1) / kPointBlock;
+    const int64_t r0 = b * PPL, r1 = (r0 + PPL < nrun ? r0 + PPL : nrun) - 1;
+    const int c0 = blk_cells[2 * r0], c1 = blk_cells[2 * r1 + 1];
     const int ns = (c1 - c0 + 1) < ncap ? (c1 - c0 + 1) : ncap;  // cells staged in LDS
     for (int i = tid; i <= ns; i += kPointBlock) soff[i] = off[c0 + i];
     for (int i = tid; i < ns * QC; i += kPointBlock) {
@@ -295,39 +327,87 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
         su[i] = g >= 0 ? uc[(int64_t)g * nv + (i - a * nv)] : T(0);
     }
     __syncthreads();
-    if (!valid) return;
-    T px[N], py[N], pz[N];
-    lagrange_eval<N, T>(nt, x[0], px);
-    lagrange_eval<N, T>(nt, x[1], py);
-    if constexpr (DIM == 3) lagrange_eval<N, T>(nt, x[2], pz);
-    T* out = uf + (int64_t)f * nv;
-    if (p < soff[ns]) {
-        // largest local cell i with soff[i] <= p (empty cells have equal offsets)
-        int lo = 0, hi = ns;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (soff[mid] <= p) lo = mid; else hi = mid;
+    if (p0 >= npts) return;
+    T px[PPL][N], py[PPL][N], pz[PPL][N];
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) {
+        lagrange_eval<N, T>(nt, x[u][0], px[u]);
+        lagrange_eval<N, T>(nt, x[u][1], py[u]);
+        if constexpr (DIM == 3) {
+            lagrange_eval<N, T>(nt, x[u][2], pz[u]);
+        } else {
+#pragma unroll
+            for (int a = 0; a < N; ++a) pz[u][a] = T(0);
         }
-        const T* u = su + lo * QC;
-        if (nv == 1)  // constant LDS offsets
-            out[0] += contract_point<DIM, N, T>(px, py, pz, [&](int a) { return u[a]; });
-        else
-            for (int c = 0; c < nv; ++c)
-                out[c] += contract_point<DIM, N, T>(px, py, pz, [&](int a) { return u[a * nv + c]; });
-    } else {
-        // more cells in this block than LDS holds: search the offsets and
-        // read the coarse values from global memory
-        int lo = c0 + ns - 1, hi = c1 + 1;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (off[mid] <= p) lo = mid; else hi = mid;
+    }
+    // staged cell of each point (-1: not staged), the largest local cell i
+    // with soff[i] <= p (empty cells have equal offsets)
+    int lc[PPL];
+    bool same = true;
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) {
+        const int64_t p = p0 + u;
+        lc[u] = -1;
+        if (p < npts && p < soff[ns]) {
+            int lo = 0, hi = ns;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (soff[mid] <= p) lo = mid; else hi = mid;
+            }
+            lc[u] = lo;
         }
-        const int32_t* dm = cdm + (int64_t)lo * Q;
-        for (int c = 0; c < nv; ++c)
-            out[c] += contract_point<DIM, N, T>(px, py, pz, [&](int a) {
-                const int g = dm[a];
-                return g >= 0 ? uc[(int64_t)g * nv + c] : T(0);
-            });
+        same = same && lc[u] == lc[0] && lc[u] >= 0;
+    }
+    if (same) {
+        // every point of the lane in one staged cell
+        const T* us = su + lc[0] * QC;
+        T val[PPL];
+        for (int c = 0; c < nv; ++c) {
+            if (nv == 1)  // constant LDS offsets
+                contract_points<DIM, N, PPL, T>(px, py, pz, [&](int a) { return us[a]; }, val);
+            else
+                contract_points<DIM, N, PPL, T>(px, py, pz, [&](int a) { return us[a * nv + c]; }, val);
+#pragma unroll
+            for (int u = 0; u < PPL; ++u) uf[(int64_t)f[u] * nv + c] += val[u];
+        }
+        return;
+    }
+    // points of different cells, or of cells beyond what LDS holds: one
+    // point at a time, the latter searching the offsets and reading the
+    // coarse values from global memory
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) {
+        const int64_t p = p0 + u;
+        if (p >= npts) break;
+        T qx[1][N], qy[1][N], qz[1][N], val[1];
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            qx[0][a] = px[u][a];
+            qy[0][a] = py[u][a];
+            qz[0][a] = pz[u][a];
+        }
+        T* out = uf + (int64_t)f[u] * nv;
+        if (lc[u] >= 0) {
+            const T* us = su + lc[u] * QC;
+            for (int c = 0; c < nv; ++c) {
+                contract_points<DIM, N, 1, T>(qx, qy, qz, [&](int a) { return us[a * nv + c]; }, val);
+                out[c] += val[0];
+            }
+        } else {
+            int lo = c0 + ns - 1, hi = c1 + 1;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (off[mid] <= p) lo = mid; else hi = mid;
+            }
+            const int32_t* dm = cdm + (int64_t)lo * Q;
+            for (int c = 0; c < nv; ++c) {
+                contract_points<DIM, N, 1, T>(qx, qy, qz, [&](int a) {
+                    const int g = dm[a];
+                    return g >= 0 ? uc[(int64_t)g * nv + c] : T(0);
+                }, val);
+                out[c] += val[0];
+            }
+        }
     }
 }
 
@@ -488,6 +568,146 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
     }
 }
 
+// Restriction of Q3/Q4 cells in 3D: one wavefront per coarse cell and value.
+// The per-point work is an outer product, r Z[c] Y[b] X[a] added into the
+// cell's q sums, so splitting the sums over lanes (as the team kernel above
+// does) makes every lane that shares a point evaluate its basis again.  Here
+// the cell's points are taken in chunks of CH: lane l evaluates the basis at
+// point l of the chunk, once, and stages X, Y and r Z in LDS; then lane
+// (g, c), one of G point groups times the N values of the slowest index,
+// adds the points g, g + G, ... of the chunk into its N x N plane c of the
+// cell's sums, reading 2N + 1 staged values per point for N^2 products.  At
+// the end the G partial planes are summed in a fixed order through the same
+// LDS, a few rows at a time, and written to the slots: deterministic, like the
+// team kernel.
+template <int N>
+struct PlaneShape {
+    static constexpr int G = kWave / N;           // point groups: 16 at N = 4, 12 at N = 5
+    static constexpr int CH = G * (kWave / G);    // points per chunk: 64, 60
+    static constexpr int PT = CH / G;             // points per group and chunk
+    static constexpr int SB = CH * 3 * N;         // staged values per chunk
+    static constexpr int BR = SB / (G * N * N);   // plane rows reduced per round
+    static_assert(BR >= 1, "reduction round must hold one row");
+};
+
+template <int N, class T>
+__global__ __launch_bounds__(kWave) void restrict_planes_kernel(const int32_t* __restrict__ off,
+                                                                const int32_t* __restrict__ fine,
+                                                                const T* __restrict__ xi, int64_t npts,
+                                                                const int32_t* __restrict__ rslot,
+                                                                const T* __restrict__ rf, T* __restrict__ rbuf,
+                                                                NodeTable<N, T> nt, int nc, int nr, int64_t plane) {
+    using Sh = PlaneShape<N>;
+    constexpr int G = Sh::G, CH = Sh::CH, PT = Sh::PT, SB = Sh::SB, BR = Sh::BR;
+    constexpr int Q = N * N * N;
+    constexpr int NO = N * BR * N;  // outputs per reduction round
+    __shared__ T buf[SB];
+    const int nv = nc * nr;
+    const int64_t KC = blockIdx.x;  // (cell, value) pair
+    const int64_t K = nv == 1 ? KC : KC / nv;
+    const int comp = (int)(KC - K * nv);
+    const int cc = nr == 1 ? comp : comp / nr, rr = comp - cc * nr;
+    T* __restrict__ out = rbuf + rr * plane + cc;  // slot k at out[nc k]
+    const int lane = threadIdx.x;
+    const int p0 = off[K], p1 = off[K + 1];
+    if (p0 == p1) {
+        // a cell without points contributes zeros
+        for (int a = lane; a < Q; a += kWave) {
+            const int k = rslot[K * Q + a];
+            if (k >= 0) out[(int64_t)k * nc] = T(0);
+        }
+        return;
+    }
+    const int g = lane / N, c = lane - (lane / N) * N;
+    const bool acc = g < G;  // lanes beyond G N only stage points
+    T R[N][N];
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int a = 0; a < N; ++a) R[b][a] = T(0);
+    // point data two chunks ahead and the residual value (which needs the
+    // fine DoF) one chunk ahead, so that no load is waited for where it is used
+    auto load_point = [&](int p, int& fi, T (&xs)[3]) {
+        fi = -1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xs[a] = T(0);
+        if (lane < CH && p < p1) {
+            fi = fine[p];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xs[a] = xi[a * npts + p];
+        }
+    };
+    int fi0, fi1;
+    T xs0[3], xs1[3];
+    load_point(p0 + lane, fi0, xs0);
+    load_point(p0 + CH + lane, fi1, xs1);
+    T r0 = fi0 >= 0 ? rf[(int64_t)fi0 * nv + comp] : T(0);
+    for (int base = p0; base < p1; base += CH) {
+        // stage: basis of point `lane` of the chunk (zeros past the cell's points)
+        T px[N], py[N], pz[N];
+        lagrange_eval<N, T>(nt, xs0[0], px);
+        lagrange_eval<N, T>(nt, xs0[1], py);
+        lagrange_eval<N, T>(nt, xs0[2], pz);
+        block_sync<kWave>();  // the previous chunk's reads are done
+        if (lane < CH) {
+            T* sp = buf + lane * 3 * N;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                sp[a] = px[a];
+                sp[N + a] = py[a];
+                sp[2 * N + a] = r0 * pz[a];
+            }
+        }
+        block_sync<kWave>();
+        // advance the pipeline: residual of the next chunk, points of the one after
+        r0 = fi1 >= 0 ? rf[(int64_t)fi1 * nv + comp] : T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xs0[a] = xs1[a];
+        load_point(base + 2 * CH + lane, fi1, xs1);
+        // accumulate plane c over the group's points of the chunk
+        if (acc) {
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                const T* sp = buf + (g + G * k) * 3 * N;
+                T xv[N];
+#pragma unroll
+                for (int a = 0; a < N; ++a) xv[a] = sp[a];
+                const T z = sp[2 * N + c];
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    const T w = z * sp[N + b];
+#pragma unroll
+                    for (int a = 0; a < N; ++a) R[b][a] += w * xv[a];
+                }
+            }
+        }
+    }
+    // sum the G partial planes: rows b0 .. b0 + BR - 1 per round, partial of
+    // group g for output o = (c BR + bb) N + a at buf[g NO + o]
+#pragma unroll
+    for (int b0 = 0; b0 < N; b0 += BR) {
+        block_sync<kWave>();
+        if (acc) {
+#pragma unroll
+            for (int bb = 0; bb < BR; ++bb)
+                if (b0 + bb < N) {
+#pragma unroll
+                    for (int a = 0; a < N; ++a) buf[g * NO + (c * BR + bb) * N + a] = R[b0 + bb][a];
+                }
+        }
+        block_sync<kWave>();
+        for (int o = lane; o < NO; o += kWave) {
+            const int oc = o / (BR * N), bb = (o / N) % BR, a = o % N;
+            if (b0 + bb >= N) continue;
+            T sum = buf[o];
+#pragma unroll
+            for (int q = 1; q < G; ++q) sum += buf[q * NO + o];
+            const int k = rslot[K * Q + (oc * N + b0 + bb) * N + a];
+            if (k >= 0) out[(int64_t)k * nc] = sum;
+        }
+    }
+}
+
 // lanes sharing each point in the restriction: keep the per-lane outputs
 // (q / S accumulators) within the register budget of a few waves per SIMD
 template <int N, class T>
@@ -521,9 +741,10 @@ static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, con
     if (tr.n_points == 0 || C.n_cells == 0) return;
     const NodeTable<N, T> nt = node_table<N, T>(C.basis);
     if (prolong) {
-        const dim3 grid((unsigned)((tr.n_points + kPointBlock - 1) / kPointBlock));
+        constexpr int PPL = prolong_ppl<DIM, N>();
+        const dim3 grid((unsigned)((tr.n_points + kPointBlock * PPL - 1) / (kPointBlock * PPL)));
 #define NNMG_PROLONG(NVT)                                                                                   \
-    hipLaunchKernelGGL((prolongate_points_kernel<DIM, N, T, NVT>), grid, dim3(kPointBlock), 0, s, tr.d_off.ptr, \
+    hipLaunchKernelGGL((prolongate_points_kernel<DIM, N, T, NVT, PPL>), grid, dim3(kPointBlock), 0, s, tr.d_off.ptr, \
                        tr.d_fine.ptr, xi, tr.n_points, tr.d_blk_cells.ptr, C.d_dofmap.ptr, (const T*)in, (T*)out, \
                        nt, nv)
         if (nv == 1)
@@ -536,6 +757,14 @@ static void transfer_dispatch(const Transfer& tr, bool prolong, const T* xi, con
         NNMG_HIP(hipGetLastError());
         return;
     }
+    if constexpr (DIM == 3 && N >= 4) {
+        hipLaunchKernelGGL((restrict_planes_kernel<N, T>), dim3((unsigned)(C.n_cells * (int64_t)nv)), dim3(kWave), 0,
+                           s, tr.d_off.ptr, tr.d_fine.ptr, xi, tr.n_points, tr.d_rslot.ptr, (const T*)in, (T*)rbuf,
+                           nt, C.ncomp, nv / C.ncomp, (int64_t)(tr.n_rslots * C.ncomp));
+        NNMG_HIP(hipGetLastError());
+        return;
+    }
+    // 2D, and 3D up to Q2: the team kernel
     constexpr int S = DIM == 3 ? restrict_split<N, T>() : 1;
     const int team = std::max(tr.team, S);
     const int threads = 256;

@@ -84,22 +84,6 @@ struct OpShape {
     static constexpr int TILE = DIM == 3 ? N * N * N : N * N;
 };
 
-// LDS hand-off between the lanes of a block.  A block of one wavefront needs
-// no hardware barrier: LDS operations of a wavefront complete in issue order,
-// so it is enough to keep the compiler from moving LDS accesses across this
-// point.  Unlike a workgroup barrier this does not wait for outstanding
-// global loads, which stay in flight across the sweeps.
-template <int WG>
-__device__ __forceinline__ void block_sync() {
-    if constexpr (WG == kWave) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
-        __syncthreads();
-    }
-}
-
 constexpr int kStoredMetric = 0;
 constexpr int kTrilinear = 1;
 constexpr int kSlots = 0;
