@@ -303,7 +303,9 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
     __shared__ int32_t soff[kPointBlock + 1];
     const int QC = Q * nv;  // staged values per cell
     const int ncap = kStage / QC < kPointBlock ? kStage / QC : kPointBlock;
-    const int64_t b = blockIdx.x;
+    // consecutive runs of points on one XCD: neighbouring coarse cells share
+    // the cache lines of their fine DoFs, which then stay in one L2
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
     const int64_t p0 = (b * kPointBlock + tid) * PPL;  // the lane's first point
     // the points' own data first, so that these loads overlap the staging
@@ -472,7 +474,8 @@ __global__ __launch_bounds__(256) void restrict_kernel(const int32_t* __restrict
     constexpr int QP = next_pow2(QL);        // padded for the butterfly
     constexpr int LQ = ilog2(QP);
     constexpr int JMAX = ilog2(64 / S);      // group levels of a 64-lane team
-    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    // consecutive cells on one XCD, as in the prolongation
+    const int64_t gid = xcd_remap(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
     const int64_t KC = gid >> team_log2;     // (cell, value) pair
     const int team = 1 << team_log2;
     const int t = (int)(gid & (team - 1));
@@ -603,7 +606,7 @@ __global__ __launch_bounds__(kWave) void restrict_planes_kernel(const int32_t* _
     constexpr int NO = N * BR * N;  // outputs per reduction round
     __shared__ T buf[SB];
     const int nv = nc * nr;
-    const int64_t KC = blockIdx.x;  // (cell, value) pair
+    const int64_t KC = xcd_remap(blockIdx.x, gridDim.x);  // (cell, value) pair, consecutive ones on one XCD
     const int64_t K = nv == 1 ? KC : KC / nv;
     const int comp = (int)(KC - K * nv);
     const int cc = nr == 1 ? comp : comp / nr, rr = comp - cc * nr;
