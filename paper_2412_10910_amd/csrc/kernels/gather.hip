@@ -15,6 +15,10 @@
 
 namespace nnmg {
 
+// contribution slots of a node loaded at once (a hexahedral mesh node lies in
+// at most 8 cells where every vertex has valence 8, as in structured meshes)
+constexpr int kGatherBatch = 8;
+
 // Value v of a vector with NC components and NR right-hand sides per node
 template <int NC, int NR, class T>
 __device__ __forceinline__ T gather_sum(const int32_t* __restrict__ off, const T* __restrict__ contrib, size_t plane,
@@ -26,8 +30,23 @@ __device__ __forceinline__ T gather_sum(const int32_t* __restrict__ off, const T
     const int r = sub - c * NR;
     const T* base = contrib + (NR == 1 ? 0 : (size_t)r * plane) + c;
     const int k0 = off[node], k1 = off[node + 1];
+    // The first kGatherBatch slots of the run are loaded together and then
+    // added in slot order: one memory latency for the run instead of one per
+    // slot.  Places past the run hold -0, which leaves every sum unchanged
+    // (x + -0 = x, signed zeros included), so the result is the one of adding
+    // the run's slots one at a time.  Longer runs (nodes shared by more cells,
+    // on unstructured meshes) finish one slot at a time.
+    // (the padding is hidden from the compiler: knowing x + -0 = x, it would
+    // move the first addition next to its load and wait for that load alone)
+    T pad = T(-0.0);
+    asm volatile("" : "+v"(pad));
+    T val[kGatherBatch];
+#pragma unroll
+    for (int j = 0; j < kGatherBatch; ++j) val[j] = k0 + j < k1 ? base[(size_t)(k0 + j) * NC] : pad;
     T s = T(0);
-    for (int k = k0; k < k1; ++k) s += base[(size_t)k * NC];
+#pragma unroll
+    for (int j = 0; j < kGatherBatch; ++j) s += val[j];
+    for (int k = k0 + kGatherBatch; k < k1; ++k) s += base[(size_t)k * NC];
     return s;
 }
 
