@@ -94,8 +94,9 @@ __global__ void gather_kernel(size_t n, const int32_t* __restrict__ off, const T
                               T* __restrict__ dst, int accumulate) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         if (!has_contributions<NC * NR>(off, i)) continue;  // constrained: untouched
+        const T old = accumulate ? dst[i] : T(0);  // loaded beside the slots, not after them
         const T s = gather_sum<NC, NR>(off, elem, plane, i);
-        dst[i] = accumulate ? dst[i] + s : s;
+        dst[i] = accumulate ? old + s : s;
     }
 }
 
@@ -129,11 +130,16 @@ __global__ void cheb_step_gather_kernel(size_t n, const int32_t* __restrict__ of
                                         const T* __restrict__ dinv, T* __restrict__ x, T* __restrict__ d, T c1,
                                         T c2, int first) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const T r = f[i] - gather_sum<NC, NR>(off, elem, plane, i);
+        // the DoF's own operands are loaded first, so that they arrive with
+        // the slots instead of one after another behind them
+        const T fi = f[i];
         const T di = dinv[NR == 1 ? i : i / NR];
-        const T dn = first ? c2 * (di * r) : c1 * d[i] + c2 * (di * r);
+        const T xi = x[i];
+        const T dp = first ? T(0) : d[i];
+        const T r = fi - gather_sum<NC, NR>(off, elem, plane, i);
+        const T dn = first ? c2 * (di * r) : c1 * dp + c2 * (di * r);
         d[i] = dn;
-        x[i] += dn;
+        x[i] = xi + dn;
     }
 }
 
@@ -158,8 +164,10 @@ void launch_cheb_step_gather(const Level& L, int prec, const void* elem, const v
 template <int NC, int NR, class T>
 __global__ void residual_gather_kernel(size_t n, const int32_t* __restrict__ off, const T* __restrict__ elem,
                                        size_t plane, const T* __restrict__ f, T* __restrict__ r) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        r[i] = f[i] - gather_sum<NC, NR>(off, elem, plane, i);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const T fi = f[i];
+        r[i] = fi - gather_sum<NC, NR>(off, elem, plane, i);
+    }
 }
 
 void launch_residual_gather(const Level& L, int prec, const void* elem, const void* f, void* r, hipStream_t s,
@@ -197,9 +205,10 @@ __global__ __launch_bounds__(kRed) void gather_dot_kernel(size_t n, const int32_
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const size_t v = i * NR + r;
+            const double pv = p[v];
             const double g = gather_sum<NC, NR>(off, elem, plane, v);
             q[v] = g;
-            acc[r] += p[v] * g;
+            acc[r] += pv * g;
         }
     }
 #pragma unroll
