@@ -566,13 +566,13 @@ struct PcgTask {
         if (lv.atomic_scatter) {
             launch_fill(H.qv.ptr, nv, NNMG_FP64, s);
             launch_vmult_cells(lv, NNMG_FP64, H.p.ptr, H.qv.ptr, s, nr, H.work[NNMG_FP64][top()].contrib.ptr);
-            launch_dot(H.p.ptr, H.qv.ptr, n, H.partial.ptr, sc + 1, s, nr, kScal);
+            launch_dot(H.p.ptr, H.qv.ptr, n, H.partial.ptr, sc + 1, s, nr, kScal, sc, 0);
         } else {
             double* cb = (double*)H.work[NNMG_FP64][top()].contrib.ptr;
             launch_vmult_contrib(lv, NNMG_FP64, H.p.ptr, cb, s, nr);
-            launch_gather_dot(lv, cb, H.p.ptr, H.qv.ptr, H.partial.ptr, sc + 1, s, nr);
+            launch_gather_dot(lv, cb, H.p.ptr, H.qv.ptr, H.partial.ptr, sc + 1, s, nr, sc, 0);
         }
-        launch_scalar_op(sc, 0, s, nr);
+        // (alpha is formed by the reduction of p.q)
         launch_cg_update(n, x, H.r.ptr, H.p.ptr, H.qv.ptr, sc, H.partial.ptr, sc + 3, s, nr);
         fetch_async();
     }
@@ -692,8 +692,7 @@ struct PcgTask {
         if (n_active == 0 || it == o.max_it) return done = true;
         if (changed) push_flags();
         precondition();
-        launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 4, s, nr, kScal);
-        launch_scalar_op(sc, 1, s, nr);
+        launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 4, s, nr, kScal, sc, 1);  // and beta
         launch_cg_direction(n, H.z.ptr, H.p.ptr, sc, s, nr);
         ++it;
         iteration_body();

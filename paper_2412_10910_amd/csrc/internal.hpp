@@ -230,12 +230,15 @@ void launch_cheb_step_gather(const Level& L, int prec, const void* contrib, cons
                              void* x, void* d, double c1, double c2, bool first, hipStream_t s, int nr = 1);
 void launch_residual_gather(const Level& L, int prec, const void* contrib, const void* f, void* r, hipStream_t s,
                             int nr = 1);
-// out[r * kScal] = p_r . q_r
+// out[r * kScal] = p_r . q_r; scalar_op >= 0 also forms the CG scalar that
+// waits for the sum (0: alpha from p.q; 1: beta and rz from r.z) on the
+// scalars at scal
 void launch_gather_dot(const Level& L, const double* contrib, const double* p, double* q, double* partial,
-                       double* out, hipStream_t s, int nr = 1);
-// out[r * ostride] = sum of partial[block][r] over m blocks
+                       double* out, hipStream_t s, int nr = 1, double* scal = nullptr, int scalar_op = -1);
+// out[r * ostride] = sum of partial[block][r] over m blocks (scalar_op: as above,
+// with ostride = kScal)
 void launch_sum_partials(const double* partial, size_t m, double* out, hipStream_t s, int nr = 1,
-                         size_t ostride = 1);
+                         size_t ostride = 1, double* scal = nullptr, int scalar_op = -1);
 // dst += A src on the unconstrained rows and columns (constrained entries untouched);
 // uses `contrib`, else the level's own contribution buffer (one right-hand
 // side; not for concurrent calls on one level)
@@ -284,14 +287,13 @@ void launch_splitmix_vector(double* v, const uint8_t* mask_free, size_t n, uint6
 
 // float64 reductions: out = sum_i a_i b_i (two-stage, deterministic)
 void launch_dot(const double* a, const double* b, size_t n, double* partial, double* out, hipStream_t s,
-                int nr = 1, size_t ostride = 1);
+                int nr = 1, size_t ostride = 1, double* scal = nullptr, int scalar_op = -1);
 size_t dot_partials(size_t n);
 // CG kernels; scal layout documented in hierarchy.cpp
 // (n vector DoFs, nr interleaved right-hand sides, scalars of r at scal + r * kScal)
 void launch_cg_update(size_t n, double* x, double* r, const double* p, const double* q, const double* scal,
                       double* partial, double* rr_out, hipStream_t s, int nr = 1);
 void launch_cg_direction(size_t n, const double* z, double* p, const double* scal, hipStream_t s, int nr = 1);
-void launch_scalar_op(double* scal, int op, hipStream_t s, int nr = 1);
 void launch_jacobi(size_t n, const double* dinv, const double* r, double* z, hipStream_t s);
 void launch_axpy(size_t n, double a_sign, const double* scal_a, int idx, const double* x, double* y,
                  hipStream_t s);

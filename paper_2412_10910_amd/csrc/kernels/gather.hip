@@ -227,14 +227,14 @@ __global__ __launch_bounds__(kRed) void gather_dot_kernel(size_t n, const int32_
 }
 
 void launch_gather_dot(const Level& L, const double* elem, const double* p, double* q, double* partial,
-                       double* out, hipStream_t s, int nr) {
+                       double* out, hipStream_t s, int nr, double* scal, int scalar_op) {
     const size_t n = (size_t)L.n_dofs;
     const size_t g = dot_partials(n);
     NNMG_NV_DISPATCH(L.ncomp, nr, {
         hipLaunchKernelGGL((gather_dot_kernel<NC, NR>), dim3((unsigned)g), dim3(kRed), 0, s, n, L.d_inv_off.ptr,
                            elem, contrib_plane(L), p, q, partial);
     });
-    launch_sum_partials(partial, g, out, s, nr, kScal);
+    launch_sum_partials(partial, g, out, s, nr, kScal, scal, scalar_op);
     NNMG_HIP(hipGetLastError());
 }
 

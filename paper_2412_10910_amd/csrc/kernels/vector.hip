@@ -261,27 +261,55 @@ __global__ __launch_bounds__(kRedThreads) void dot_stage1(const double* __restri
     block_sums<NR>(s, partial + blockIdx.x * NR, 1);
 }
 
-// out[r] = sum over the m blocks of partial[block][r]; one block per column
-__global__ __launch_bounds__(kRedThreads) void sum_stage2(const double* __restrict__ partial, size_t m, int nr,
-                                                          double* __restrict__ out, size_t ostride) {
-    const int r = blockIdx.x;
-    double s[1] = {0.0};
-    for (size_t i = threadIdx.x; i < m; i += blockDim.x) s[0] += partial[i * nr + r];
-    block_sums<1>(s, out + r * ostride, 1);
+// op 0: alpha = rz / pq;  op 1: beta = rz_new / rz, rz = rz_new, with `fresh`
+// the sum just formed (pq, or rz_new).  A right-hand side that is no longer
+// active gets alpha = beta = 0 and keeps its iterate.
+__device__ inline void cg_scalar_op(double* c, int op, double fresh) {
+    const bool on = c[7] != 0.0;
+    if (op == 0) {
+        c[2] = on ? c[0] / fresh : 0.0;
+    } else {
+        c[5] = on ? fresh / c[0] : 0.0;
+        c[0] = fresh;
+    }
 }
 
-void launch_sum_partials(const double* partial, size_t m, double* out, hipStream_t s, int nr, size_t ostride) {
-    hipLaunchKernelGGL(sum_stage2, dim3((unsigned)nr), dim3(kRedThreads), 0, s, partial, m, nr, out, ostride);
+// out[r * ostride] = sum over the m blocks of partial[block][r]; one block per
+// column, the same order as block_sums.  op >= 0: the thread that holds the
+// sum also forms the CG scalar waiting for it (cg_scalar_op on the scalars of
+// right-hand side r), which saves a launch per use.
+__global__ __launch_bounds__(kRedThreads) void sum_stage2(const double* __restrict__ partial, size_t m, int nr,
+                                                          double* out, size_t ostride, double* scal, int op) {
+    __shared__ double sh[kRedThreads / kWave];
+    const int r = blockIdx.x;
+    double a = 0.0;
+    for (size_t i = threadIdx.x; i < m; i += blockDim.x) a += partial[i * nr + r];
+    for (int o = kWave / 2; o > 0; o >>= 1) a += __shfl_down(a, o, kWave);
+    if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kRedThreads / kWave; ++i) t += sh[i];
+        out[r * ostride] = t;
+        if (op >= 0) cg_scalar_op(scal + r * kScal, op, t);
+    }
+}
+
+void launch_sum_partials(const double* partial, size_t m, double* out, hipStream_t s, int nr, size_t ostride,
+                         double* scal, int op) {
+    if (op >= 0 && (scal == nullptr || ostride != (size_t)kScal)) fail(NNMG_ERR_INVALID_ARG, "CG scalar layout");
+    hipLaunchKernelGGL(sum_stage2, dim3((unsigned)nr), dim3(kRedThreads), 0, s, partial, m, nr, out, ostride, scal,
+                       op);
     NNMG_HIP(hipGetLastError());
 }
 
 void launch_dot(const double* a, const double* b, size_t n, double* partial, double* out, hipStream_t s, int nr,
-                size_t ostride) {
+                size_t ostride, double* scal, int op) {
     const size_t g = dot_partials(n);
     NNMG_NR_DISPATCH(nr, {
         hipLaunchKernelGGL((dot_stage1<NR>), dim3((unsigned)g), dim3(kRedThreads), 0, s, a, b, n, partial);
     });
-    launch_sum_partials(partial, g, out, s, nr, ostride);
+    launch_sum_partials(partial, g, out, s, nr, ostride, scal, op);
 }
 
 // CG scalars of right-hand side r at scal + r * kScal:
@@ -338,26 +366,6 @@ void launch_cg_direction(size_t n, const double* z, double* p, const double* sca
     NNMG_NR_DISPATCH(nr, {
         hipLaunchKernelGGL((cg_direction_kernel<NR>), grid_for(n), dim3(256), 0, s, n, z, p, scal);
     });
-    NNMG_HIP(hipGetLastError());
-}
-
-// op 0: alpha = rz / pq;  op 1: beta = rz_new / rz, rz = rz_new.  A right-hand
-// side that is no longer active gets alpha = beta = 0 and keeps its iterate.
-__global__ void scalar_kernel(double* scal, int op, int nr) {
-    const int k = threadIdx.x;
-    if (k >= nr) return;
-    double* c = scal + k * kScal;
-    const bool on = c[7] != 0.0;
-    if (op == 0) {
-        c[2] = on ? c[0] / c[1] : 0.0;
-    } else {
-        c[5] = on ? c[4] / c[0] : 0.0;
-        c[0] = c[4];
-    }
-}
-
-void launch_scalar_op(double* scal, int op, hipStream_t s, int nr) {
-    hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(64), 0, s, scal, op, nr);
     NNMG_HIP(hipGetLastError());
 }
 
