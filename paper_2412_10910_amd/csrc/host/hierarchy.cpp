@@ -267,15 +267,20 @@ static void op_residual(Hierarchy& H, int l, int prec, const void* f, const void
     }
 }
 
+// cast_from (float32 cycle, zero start): the right-hand side arrives in
+// float64 and the first step also writes its float32 copy into f
 static void chebyshev(Hierarchy& H, int l, int prec, const void* f, void* x, bool zero_start, int nr,
-                      hipStream_t s) {
+                      hipStream_t s, const double* cast_from = nullptr) {
     Level& L = *H.levels[l];
     WorkVectors& w = H.work[prec][l];
     const void* dinv = prec == NNMG_FP64 ? (const void*)L.d_dinv64.ptr : (const void*)L.d_dinv32.ptr;
     const double lo = H.lo[l], hi = H.hi[l];
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
-    if (zero_start)
+    if (zero_start && cast_from)
+        launch_cast_cheb_first_zero((size_t)L.n_dofs, cast_from, (float*)const_cast<void*>(f), (const float*)dinv,
+                                    (float*)x, (float*)w.d.ptr, 1.0 / theta, s, nr);
+    else if (zero_start)
         launch_cheb_first_zero(prec, (size_t)L.n_dofs, f, dinv, x, w.d.ptr, 1.0 / theta, s, nr);
     else
         op_cheb_step(H, l, prec, f, dinv, x, 0.0, 1.0 / theta, true, nr, s);
@@ -286,9 +291,16 @@ static void chebyshev(Hierarchy& H, int l, int prec, const void* f, void* x, boo
     }
 }
 
-static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, int nr, hipStream_t s) {
+// cast_from: a float32 cycle whose right-hand side f is first cast from these
+// float64 values (the cast is fused into the first smoothing step)
+static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, int nr, hipStream_t s,
+                         const double* cast_from = nullptr) {
+    if (cast_from && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "cast into a float64 cycle");
     if (l == 0) {
         Scope sc(H, 0, kCoarse, s);
+        if (cast_from)
+            launch_cast_64_to_32(cast_from, (float*)const_cast<void*>(f),
+                                 (size_t)H.levels[0]->n_dofs * (size_t)nr, s);
         coarse_solve(H, prec, f, x, nr, s);
         return;
     }
@@ -297,7 +309,7 @@ static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, 
     const Transfer& T = *H.transfers[l - 1];
     {
         Scope sc(H, l, kPre, s);
-        chebyshev(H, l, prec, f, x, true, nr, s);
+        chebyshev(H, l, prec, f, x, true, nr, s, cast_from);
     }
     {
         Scope sc(H, l, kRes, s);
@@ -529,23 +541,29 @@ struct PcgTask {
     Level& L() { return *H.levels.back(); }
     int top() const { return (int)H.levels.size() - 1; }
 
-    // z = V(r) on the hierarchy's own vectors, so the launches can be captured once
+    // z = V(r) on the hierarchy's own vectors, so the launches can be captured
+    // once.  A float32 cycle reads r through its first smoothing step and
+    // leaves its result in float32: z is formed by precondition_dot.
     void launches(hipStream_t st) {
         WorkVectors& w32 = H.work[NNMG_FP32][top()];
-        if (prec == NNMG_FP64) {
+        if (prec == NNMG_FP64)
             vcycle_level(H, top(), NNMG_FP64, H.r.ptr, H.z.ptr, nr, st);
-        } else {
-            launch_cast_64_to_32(H.r.ptr, (float*)w32.f.ptr, nv, st);
-            vcycle_level(H, top(), NNMG_FP32, w32.f.ptr, w32.x.ptr, nr, st);
-            launch_cast_32_to_64((const float*)w32.x.ptr, H.z.ptr, nv, st);
-        }
+        else
+            vcycle_level(H, top(), NNMG_FP32, w32.f.ptr, w32.x.ptr, nr, st, H.r.ptr);
     }
 
-    void precondition() {
+    // z = V(r), then r.z into out (and the CG scalar op on it, op >= 0)
+    void precondition_dot(double* out, int op) {
         if (graph)
             NNMG_HIP(hipGraphLaunch(H.precond_graph[prec][nr], s));
         else
             launches(s);
+        double* sc = op >= 0 ? H.scal.ptr : nullptr;
+        if (prec == NNMG_FP64)
+            launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, out, s, nr, kScal, sc, op);
+        else
+            launch_cast_dot(H.r.ptr, (const float*)H.work[NNMG_FP32][top()].x.ptr, H.z.ptr, n, H.partial.ptr, out,
+                            s, nr, kScal, sc, op);
     }
 
     // scalars to the host, then the event step() waits for
@@ -657,8 +675,7 @@ struct PcgTask {
             }
             if (n_active == 0 || o.max_it == 0) return done = true;
             push_flags();
-            precondition();
-            launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 0, s, nr, kScal);
+            precondition_dot(sc + 0, -1);
             NNMG_HIP(hipMemcpyAsync(H.p.ptr, H.z.ptr, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
             it = 1;
             iteration_body();
@@ -691,8 +708,7 @@ struct PcgTask {
         }
         if (n_active == 0 || it == o.max_it) return done = true;
         if (changed) push_flags();
-        precondition();
-        launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, sc + 4, s, nr, kScal, sc, 1);  // and beta
+        precondition_dot(sc + 4, 1);  // and beta
         launch_cg_direction(n, H.z.ptr, H.p.ptr, sc, s, nr);
         ++it;
         iteration_body();

@@ -277,6 +277,9 @@ size_t contrib_plane(const Level& L);
 // x = d = dinv * f * c0   (first step from a zero guess)
 void launch_cheb_first_zero(int prec, size_t n, const void* f, const void* dinv, void* x, void* d,
                             double c0, hipStream_t s, int nr = 1);
+// f32 = (float) f64, then launch_cheb_first_zero on f32 (float32 vectors)
+void launch_cast_cheb_first_zero(size_t n, const double* f64, float* f32, const float* dinv, float* x, float* d,
+                                 double c0, hipStream_t s, int nr = 1);
 // r = f - ax; ax = 0; d = c1 d + c2 dinv r (c1 = 0 for a first step); x += d
 void launch_cheb_step(int prec, size_t n, const void* f, void* ax, const void* dinv, void* x, void* d,
                       double c1, double c2, hipStream_t s, int nr = 1);
@@ -288,6 +291,9 @@ void launch_splitmix_vector(double* v, const uint8_t* mask_free, size_t n, uint6
 // float64 reductions: out = sum_i a_i b_i (two-stage, deterministic)
 void launch_dot(const double* a, const double* b, size_t n, double* partial, double* out, hipStream_t s,
                 int nr = 1, size_t ostride = 1, double* scal = nullptr, int scalar_op = -1);
+// z = (double) z32, then out = r . z as launch_dot(r, z, ...) computes it
+void launch_cast_dot(const double* r, const float* z32, double* z, size_t n, double* partial, double* out,
+                     hipStream_t s, int nr = 1, size_t ostride = 1, double* scal = nullptr, int scalar_op = -1);
 size_t dot_partials(size_t n);
 // CG kernels; scal layout documented in hierarchy.cpp
 // (n vector DoFs, nr interleaved right-hand sides, scalars of r at scal + r * kScal)

@@ -118,6 +118,32 @@ __global__ void cheb_first_zero_kernel(size_t n, const T* __restrict__ f, const 
     }
 }
 
+// the same first step on a float32 cycle whose right-hand side arrives in
+// float64: f32 = (float) f64 is stored for the later steps and used at once
+template <int NR>
+__global__ void cast_cheb_first_zero_kernel(size_t n, const double* __restrict__ f64, float* __restrict__ f32,
+                                            const float* __restrict__ dinv, float* __restrict__ x,
+                                            float* __restrict__ d, float c0) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float f = (float)f64[i];
+        f32[i] = f;
+        const float v = dinv[NR == 1 ? i : i / NR] * f * c0;
+        d[i] = v;
+        x[i] = v;
+    }
+}
+
+void launch_cast_cheb_first_zero(size_t n, const double* f64, float* f32, const float* dinv, float* x, float* d,
+                                 double c0, hipStream_t s, int nr) {
+    if (n == 0) return;
+    const size_t nv = n * (size_t)nr;
+    NNMG_NR_DISPATCH(nr, {
+        hipLaunchKernelGGL((cast_cheb_first_zero_kernel<NR>), grid_for(nv), dim3(256), 0, s, nv, f64, f32, dinv, x,
+                           d, (float)c0);
+    });
+    NNMG_HIP(hipGetLastError());
+}
+
 void launch_cheb_first_zero(int prec, size_t n, const void* f, const void* dinv, void* x, void* d, double c0,
                             hipStream_t s, int nr) {
     if (n == 0) return;
@@ -301,6 +327,36 @@ void launch_sum_partials(const double* partial, size_t m, double* out, hipStream
     hipLaunchKernelGGL(sum_stage2, dim3((unsigned)nr), dim3(kRedThreads), 0, s, partial, m, nr, out, ostride, scal,
                        op);
     NNMG_HIP(hipGetLastError());
+}
+
+// z = (double) z32 and the block partial sums of r . z, in dot_stage1's order
+template <int NR>
+__global__ __launch_bounds__(kRedThreads) void cast_dot_stage1(const double* __restrict__ r,
+                                                               const float* __restrict__ z32,
+                                                               double* __restrict__ z, size_t n,
+                                                               double* __restrict__ partial) {
+    double s[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) s[k] = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const double zv = (double)z32[i * NR + k];
+            z[i * NR + k] = zv;
+            s[k] += r[i * NR + k] * zv;
+        }
+    }
+    block_sums<NR>(s, partial + blockIdx.x * NR, 1);
+}
+
+void launch_cast_dot(const double* r, const float* z32, double* z, size_t n, double* partial, double* out,
+                     hipStream_t s, int nr, size_t ostride, double* scal, int op) {
+    const size_t g = dot_partials(n);
+    NNMG_NR_DISPATCH(nr, {
+        hipLaunchKernelGGL((cast_dot_stage1<NR>), dim3((unsigned)g), dim3(kRedThreads), 0, s, r, z32, z, n,
+                           partial);
+    });
+    launch_sum_partials(partial, g, out, s, nr, ostride, scal, op);
 }
 
 void launch_dot(const double* a, const double* b, size_t n, double* partial, double* out, hipStream_t s, int nr,
