@@ -269,15 +269,19 @@ static void op_residual(Hierarchy& H, int l, int prec, const void* f, const void
 
 // cast_from (float32 cycle, zero start): the right-hand side arrives in
 // float64 and the first step also writes its float32 copy into f
+// first_done (zero start): the first step, x = d = D^-1 f / theta, was fused
+// into the restriction that formed f
 static void chebyshev(Hierarchy& H, int l, int prec, const void* f, void* x, bool zero_start, int nr,
-                      hipStream_t s, const double* cast_from = nullptr) {
+                      hipStream_t s, const double* cast_from = nullptr, bool first_done = false) {
     Level& L = *H.levels[l];
     WorkVectors& w = H.work[prec][l];
     const void* dinv = prec == NNMG_FP64 ? (const void*)L.d_dinv64.ptr : (const void*)L.d_dinv32.ptr;
     const double lo = H.lo[l], hi = H.hi[l];
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
-    if (zero_start && cast_from)
+    if (zero_start && first_done) {
+        // x and d hold the first step already
+    } else if (zero_start && cast_from)
         launch_cast_cheb_first_zero((size_t)L.n_dofs, cast_from, (float*)const_cast<void*>(f), (const float*)dinv,
                                     (float*)x, (float*)w.d.ptr, 1.0 / theta, s, nr);
     else if (zero_start)
@@ -294,7 +298,7 @@ static void chebyshev(Hierarchy& H, int l, int prec, const void* f, void* x, boo
 // cast_from: a float32 cycle whose right-hand side f is first cast from these
 // float64 values (the cast is fused into the first smoothing step)
 static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, int nr, hipStream_t s,
-                         const double* cast_from = nullptr) {
+                         const double* cast_from = nullptr, bool first_done = false) {
     if (cast_from && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "cast into a float64 cycle");
     if (l == 0) {
         Scope sc(H, 0, kCoarse, s);
@@ -309,7 +313,7 @@ static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, 
     const Transfer& T = *H.transfers[l - 1];
     {
         Scope sc(H, l, kPre, s);
-        chebyshev(H, l, prec, f, x, true, nr, s, cast_from);
+        chebyshev(H, l, prec, f, x, true, nr, s, cast_from, first_done);
     }
     {
         Scope sc(H, l, kRes, s);
@@ -318,10 +322,19 @@ static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, 
     {
         Scope sc(H, l, kRestrict, s);
         // every unconstrained coarse DoF has restriction slots; the constrained
-        // entries of f_c are never written and stay zero
-        launch_restrict(T, prec, w.r.ptr, wc.f.ptr, false, s, nr, wc.rbuf.ptr);
+        // entries of f_c are never written and stay zero.  Above the coarsest
+        // level the coarse pre-smoothing's first step is fused in.
+        if (l - 1 >= 1) {
+            const Level& C = *H.levels[l - 1];
+            const void* dinv = prec == NNMG_FP64 ? (const void*)C.d_dinv64.ptr : (const void*)C.d_dinv32.ptr;
+            const double theta = 0.5 * (H.hi[l - 1] + H.lo[l - 1]);
+            launch_restrict_first_zero(T, prec, w.r.ptr, wc.f.ptr, dinv, wc.x.ptr, wc.d.ptr, 1.0 / theta, s, nr,
+                                       wc.rbuf.ptr);
+        } else {
+            launch_restrict(T, prec, w.r.ptr, wc.f.ptr, false, s, nr, wc.rbuf.ptr);
+        }
     }
-    vcycle_level(H, l - 1, prec, wc.f.ptr, wc.x.ptr, nr, s);
+    vcycle_level(H, l - 1, prec, wc.f.ptr, wc.x.ptr, nr, s, nullptr, l - 1 >= 1);
     {
         Scope sc(H, l, kProlong, s);
         launch_prolongate(T, prec, wc.x.ptr, x, s, nr);

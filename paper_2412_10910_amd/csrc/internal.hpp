@@ -261,6 +261,10 @@ void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fi
 // nullptr for the transfer's own buffer (calls on one transfer must then not overlap)
 void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s,
                      int nr = 1, void* rbuf = nullptr);
+// coarse = P^T fine, fused with the coarse level's first smoothing step from
+// zero: x = d = dinv * coarse * c0 (launch_cheb_first_zero), for all entries
+void launch_restrict_first_zero(const Transfer& t, int prec, const void* fine, void* coarse, const void* dinv,
+                                void* x, void* d, double c0, hipStream_t s, int nr = 1, void* rbuf = nullptr);
 size_t restriction_scratch_bytes(const Transfer& t, int nr);
 // nested polynomial transfer (kernels/pmg.hip): fine += P coarse, and the restriction's per-cell sums
 void launch_pmg_prolongate(const Transfer& t, int prec, const void* coarse, void* fine, int nr, hipStream_t s);
@@ -270,6 +274,10 @@ void launch_pmg_restrict_sums(const Transfer& t, int prec, const void* fine, voi
 // component c of slot k at k * ncomp + c
 void launch_gather_runs(size_t n, int ncomp, const int32_t* off, int prec, const void* elem, size_t plane,
                         void* dst, bool accumulate, hipStream_t s, int nr = 1);
+// launch_gather_runs into f (not accumulating), then x = d = dinv * f * c0 for every value
+void launch_gather_runs_first_zero(size_t n, int ncomp, const int32_t* off, int prec, const void* elem,
+                                   size_t plane, void* f, const void* dinv, void* x, void* d, double c0,
+                                   hipStream_t s, int nr = 1);
 // entries of one right-hand side's plane of a level's contribution buffer
 size_t contrib_plane(const Level& L);
 

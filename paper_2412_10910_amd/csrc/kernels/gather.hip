@@ -100,6 +100,47 @@ __global__ void gather_kernel(size_t n, const int32_t* __restrict__ off, const T
     }
 }
 
+// The restriction's sums into the right-hand side f of a level whose
+// smoothing starts from zero right after, fused with that first step: f =
+// the gathered sums (values without contributions, the constrained ones, keep
+// theirs) and x = d = D^-1 f c0, computed as the separate step computes it.
+template <int NC, int NR, class T>
+__global__ void gather_first_zero_kernel(size_t n, const int32_t* __restrict__ off, const T* __restrict__ elem,
+                                         size_t plane, T* __restrict__ f, const T* __restrict__ dinv,
+                                         T* __restrict__ x, T* __restrict__ d, T c0) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const T di = dinv[NR == 1 ? i : i / NR];
+        T fi;
+        if (has_contributions<NC * NR>(off, i)) {
+            fi = gather_sum<NC, NR>(off, elem, plane, i);
+            f[i] = fi;
+        } else {
+            fi = f[i];
+        }
+        const T v = di * fi * c0;
+        d[i] = v;
+        x[i] = v;
+    }
+}
+
+void launch_gather_runs_first_zero(size_t n, int ncomp, const int32_t* off, int prec, const void* elem,
+                                   size_t plane, void* f, const void* dinv, void* x, void* d, double c0,
+                                   hipStream_t s, int nr) {
+    if (n == 0) return;
+    const size_t nv = n * (size_t)nr;
+    NNMG_NV_DISPATCH(ncomp, nr, {
+        if (prec == NNMG_FP64)
+            hipLaunchKernelGGL((gather_first_zero_kernel<NC, NR, double>), grid_n(nv), dim3(256), 0, s, nv, off,
+                               (const double*)elem, plane, (double*)f, (const double*)dinv, (double*)x,
+                               (double*)d, c0);
+        else
+            hipLaunchKernelGGL((gather_first_zero_kernel<NC, NR, float>), grid_n(nv), dim3(256), 0, s, nv, off,
+                               (const float*)elem, plane, (float*)f, (const float*)dinv, (float*)x, (float*)d,
+                               (float)c0);
+    });
+    NNMG_HIP(hipGetLastError());
+}
+
 void launch_gather_runs(size_t n, int ncomp, const int32_t* off, int prec, const void* elem, size_t plane, void* dst,
                         bool accumulate, hipStream_t s, int nr) {
     if (n == 0) return;

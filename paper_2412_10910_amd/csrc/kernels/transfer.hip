@@ -802,10 +802,11 @@ void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fi
         transfer_prec<float>(t, true, t.d_xi32.ptr, coarse, fine, nr, nullptr, s);
 }
 
-// rbuf: restriction_scratch_bytes(t, nr) bytes of the caller's, or nullptr for
-// the transfer's own buffer (which must then hold nr right-hand sides)
-void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s,
-                     int nr, void* rbuf) {
+// the per-cell sums of P^T fine into the coarse-DoF slots; returns the buffer
+// used.  rbuf: restriction_scratch_bytes(t, nr) bytes of the caller's, or
+// nullptr for the transfer's own buffer (which must then hold nr right-hand sides)
+static void* restrict_sums(const Transfer& t, int prec, const void* fine, void* coarse, hipStream_t s, int nr,
+                           void* rbuf) {
     if (!rbuf) {
         if (nr > t.rbuf_rhs) fail(NNMG_ERR_INVALID_ARG, "restriction buffer holds fewer right-hand sides");
         rbuf = t.d_rbuf.ptr;
@@ -817,8 +818,21 @@ void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse
         transfer_prec<double>(t, false, t.d_xi64.ptr, fine, coarse, nr, rbuf, s);
     else
         transfer_prec<float>(t, false, t.d_xi32.ptr, fine, coarse, nr, rbuf, s);
+    return rbuf;
+}
+
+void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s,
+                     int nr, void* rbuf) {
+    rbuf = restrict_sums(t, prec, fine, coarse, s, nr, rbuf);
     launch_gather_runs((size_t)t.coarse->n_dofs, t.coarse->ncomp, t.d_roff.ptr, prec, rbuf,
                        t.n_rslots * (size_t)t.coarse->ncomp, coarse, accumulate, s, nr);
+}
+
+void launch_restrict_first_zero(const Transfer& t, int prec, const void* fine, void* coarse, const void* dinv,
+                                void* x, void* d, double c0, hipStream_t s, int nr, void* rbuf) {
+    rbuf = restrict_sums(t, prec, fine, coarse, s, nr, rbuf);
+    launch_gather_runs_first_zero((size_t)t.coarse->n_dofs, t.coarse->ncomp, t.d_roff.ptr, prec, rbuf,
+                                  t.n_rslots * (size_t)t.coarse->ncomp, coarse, dinv, x, d, c0, s, nr);
 }
 
 size_t restriction_scratch_bytes(const Transfer& t, int nr) {
