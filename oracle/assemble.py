@@ -19,6 +19,14 @@ from . import basis
 _CHUNK = 20000
 
 
+def _chunk(space) -> int:
+    """Cells per batch: at most 20,000, fewer at high degree so that a batch's
+    gradient arrays stay within a few hundred MB (memory only: every cell is
+    computed on its own)."""
+    Q = space.n ** space.dim
+    return max(64, min(_CHUNK, int(3e7 // (Q * Q))))
+
+
 def element_matrices(space, cells: np.ndarray) -> np.ndarray:
     """Local stiffness matrices of the given cells: [len(cells), q, q]."""
     xq, wq = space.quadrature()
@@ -42,8 +50,9 @@ def stiffness(space, constrain: bool = True) -> sp.csr_matrix:
     """Global stiffness matrix as CSR; identity on constrained rows/columns."""
     C, q = space.cell_dofs.shape
     rows, cols, vals = [], [], []
-    for s in range(0, C, _CHUNK):
-        cells = np.arange(s, min(C, s + _CHUNK))
+    step = _chunk(space)
+    for s in range(0, C, step):
+        cells = np.arange(s, min(C, s + step))
         Ke = element_matrices(space, cells)
         dofs = space.cell_dofs[cells]
         rows.append(np.repeat(dofs, q, axis=1).reshape(-1))
@@ -65,8 +74,9 @@ def load_vector(space, func, constrain: bool = True) -> np.ndarray:
     vals_ref = basis.shape_values(space.k, space.dim, xq)  # [Q, q]
     C, q = space.cell_dofs.shape
     b = np.zeros(space.n_dofs)
-    for s in range(0, C, _CHUNK):
-        cells = np.arange(s, min(C, s + _CHUNK))
+    step = _chunk(space)
+    for s in range(0, C, step):
+        cells = np.arange(s, min(C, s + step))
         x = space.map_points(xq, cells)  # [c, Q, d]
         detJ = np.linalg.det(space.jacobians(xq, cells))
         fq = np.asarray(func(x), dtype=np.float64) * detJ * wq[None, :]
@@ -90,8 +100,9 @@ def l2_error(space, u: np.ndarray, exact, nq: int | None = None) -> float:
     vals_ref = basis.shape_values(space.k, space.dim, xq)
     C = space.cell_dofs.shape[0]
     err2 = 0.0
-    for s in range(0, C, _CHUNK):
-        cells = np.arange(s, min(C, s + _CHUNK))
+    step = _chunk(space)
+    for s in range(0, C, step):
+        cells = np.arange(s, min(C, s + step))
         x = space.map_points(xq, cells)
         detJ = np.linalg.det(space.jacobians(xq, cells))
         uh = np.einsum("Qi,ci->cQ", vals_ref, u[space.cell_dofs[cells]])

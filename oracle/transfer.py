@@ -151,10 +151,24 @@ def candidate_pairs_bucketed(points, space, expand=EXPAND):
     return p[order], c[order]
 
 
+POINT_CHUNK = 100000
+
+
 def locate(points, coarse, bruteforce=False, expand=EXPAND, inside_tol=INSIDE_TOL,
            newton_tol=NEWTON_TOL, newton_max_it=NEWTON_MAX_IT):
-    """Owner cell, clamped reference position and projection flag of each point."""
+    """Owner cell, clamped reference position and projection flag of each point.
+
+    Every point is located on its own, so large point sets are processed in
+    slices of POINT_CHUNK points (memory only; the result is the same)."""
     points = np.asarray(points, dtype=np.float64)
+    if points.shape[0] > POINT_CHUNK:
+        parts = [_locate(points[s:s + POINT_CHUNK], coarse, bruteforce, expand, inside_tol, newton_tol,
+                         newton_max_it) for s in range(0, points.shape[0], POINT_CHUNK)]
+        return tuple(np.concatenate([pt[i] for pt in parts]) for i in range(3))
+    return _locate(points, coarse, bruteforce, expand, inside_tol, newton_tol, newton_max_it)
+
+
+def _locate(points, coarse, bruteforce, expand, inside_tol, newton_tol, newton_max_it):
     P, d = points.shape
     if bruteforce:
         p, c = candidate_pairs_bruteforce(points, coarse, expand)
