@@ -289,11 +289,14 @@ __global__ __launch_bounds__(kRedThreads) void dot_stage1(const double* __restri
 
 // op 0: alpha = rz / pq;  op 1: beta = rz_new / rz, rz = rz_new, with `fresh`
 // the sum just formed (pq, or rz_new).  A right-hand side that is no longer
-// active gets alpha = beta = 0 and keeps its iterate.
+// active gets alpha = beta = 0 and keeps its iterate.  So does one whose pq is
+// not positive or whose alpha is not finite (a CG breakdown): its last good
+// iterate stays in x while the host reports the breakdown.
 __device__ inline void cg_scalar_op(double* c, int op, double fresh) {
     const bool on = c[7] != 0.0;
     if (op == 0) {
-        c[2] = on ? c[0] / fresh : 0.0;
+        const double a = c[0] / fresh;
+        c[2] = (on && fresh > 0.0 && isfinite(a)) ? a : 0.0;
     } else {
         c[5] = on ? fresh / c[0] : 0.0;
         c[0] = fresh;
@@ -385,10 +388,15 @@ __global__ __launch_bounds__(kRedThreads) void cg_update_stage1(size_t n, double
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
+            // alpha = 0 (frozen or broken down): x and r are left as they are,
+            // even where p or q is not finite
             const size_t v = i * NR + k;
-            x[v] += alpha[k] * p[v];
-            const double rn = r[v] - alpha[k] * q[v];
-            r[v] = rn;
+            double rn = r[v];
+            if (alpha[k] != 0.0) {
+                x[v] += alpha[k] * p[v];
+                rn -= alpha[k] * q[v];
+                r[v] = rn;
+            }
             s[k] += rn * rn;
         }
     }

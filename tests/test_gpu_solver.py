@@ -97,6 +97,13 @@ def test_zero_rhs_and_not_converged(ctx):
     with pytest.raises(nn.NNMGError) as e:
         H_lib.pcg_solve(bad)
     assert e.value.name == "BREAKDOWN"
+    # an infinite entry passes the start (|b| = inf is not NaN) and breaks down
+    # at the first p.q (NaN); the returned iterate is the last good one (x0 = 0)
+    bad = b_lib.clone()
+    bad[pairs[-1].lib.constrained().argmin()] = float("inf")
+    x, info = H_lib.pcg_solve(bad, raise_on_failure=False)
+    assert info["status"] == "BREAKDOWN" and info["iterations"] == 1
+    assert bool(torch.isfinite(x).all()) and float(x.abs().max()) == 0.0
 
 
 def test_profile_components(ctx):
