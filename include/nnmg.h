@@ -302,7 +302,10 @@ typedef struct {
  *   3 stored merged metric per Gauss point,    float atomics
  * (the elasticity operator has variant 0 only).  The variants differ only
  * in the order of floating-point sums (atomics: an order that varies between
- * runs), the operator being the one of paper §3.2 throughout.  The stored
+ * runs), the operator being the one of paper §3.2 throughout.  Only the
+ * deterministic variants (0 and 2) are timed, so a tuned level stays bitwise
+ * reproducible; the others keep ms = -1 and are taken only when forced with
+ * nnmg_level_set_variant.  The stored
  * metric is computed when needed and freed when not kept.  Synchronizes the
  * device; hierarchies holding the level re-capture their V-cycle graphs.
  * nnmg_level_set_variant forces a variant, nnmg_level_variant reads it. */

@@ -213,7 +213,7 @@ class Level:
         """Time the operator variants on this GPU and keep the fastest (nnmg_level_tune)."""
         res = _lib.TuneResult()
         check(lib().nnmg_level_tune(self.handle, _DTYPE_PREC[dtype], int(reps), C.byref(res)))
-        return dict(ms={self.VARIANTS[v]: res.ms[v] for v in range(res.n_variants)},
+        return dict(ms={self.VARIANTS[v]: res.ms[v] for v in range(res.n_variants) if res.ms[v] >= 0},
                     chosen=self.VARIANTS[res.chosen])
 
     @property
@@ -476,6 +476,7 @@ class Ticket:
         res = (_lib.CgResult * self.nr)()
         times = _lib.RequestTimes()
         code = lib().nnmg_server_wait(self.server.handle, C.c_int64(self.id), res, C.byref(times))
+        self.server._live.pop(self.id, None)  # finished: the server no longer touches its data
         infos = []
         for k in range(self.nr):
             info = dict(iterations=res[k].iterations, relres=res[k].relres,
@@ -503,6 +504,11 @@ class Server:
         h = C.c_void_p()
         check(lib().nnmg_server_create(ctx.handle, C.byref(o), C.byref(h)))
         self.handle = h
+        # everything a queued or running request reads or writes (its
+        # hierarchies, b, x, the history array), by ticket id: the server's
+        # thread uses them until the request has finished, whether or not the
+        # caller keeps the ticket; released by Ticket.wait and by close()
+        self._live = {}
 
     def submit(self, hierarchy, b: torch.Tensor, x: torch.Tensor | None = None, rtol: float = 1e-8,
                max_it: int = 200, vcycle_dtype=torch.float32, history: bool = False, use_graph: bool = True) -> Ticket:
@@ -527,6 +533,7 @@ class Server:
         t = C.c_int64()
         hs = (C.c_void_p * len(replicas))(*[h.handle.value for h in replicas])
         check(lib().nnmg_server_submit_any(self.handle, hs, len(replicas), nr, bp, xp, C.byref(o), C.byref(t)))
+        self._live[t.value] = (replicas, b, x, hist)
         return Ticket(self, t.value, b, x, nr, hist, b.dim() == 2)
 
     def stats(self) -> dict:
@@ -535,9 +542,11 @@ class Server:
         return {f: getattr(st, f) for f, _ in st._fields_}
 
     def close(self):
+        """Finish every queued and running request, then stop the loop."""
         if getattr(self, "handle", None):
             lib().nnmg_server_destroy(self.handle)
             self.handle = None
+        self._live = {}
 
     def __del__(self):
         try:

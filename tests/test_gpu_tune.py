@@ -67,7 +67,8 @@ def test_tune_keeps_the_fastest_and_the_solver_still_converges(ctx):
     report = H.tune(torch.float32, reps=5)
     for lv, r in zip(levels, report["levels"]):
         ms = r["ms"]
-        assert len(ms) == 4 and all(t > 0 for t in ms.values())
+        # the float-atomic variants are not reproducible and never timed
+        assert set(ms) == {"trilinear+slots", "metric+slots"} and all(t > 0 for t in ms.values())
         assert r["chosen"] == min(ms, key=ms.get)
         assert lv.VARIANTS[lv.variant] == r["chosen"]
     for tr, r in zip(transfers, report["transfers"]):
