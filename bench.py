@@ -1,20 +1,31 @@
 """Benchmark: float64 PCG preconditioned by one non-nested multigrid V-cycle.
 
-Workload (default): 3D Poisson on the unit cube, Q2, four independent
-hexahedral meshes of 64^3, 29^3, 13^3 and 6^3 cells with interior vertices
-perturbed by +-0.15 h, zero Dirichlet data, f = sum of 8 Gaussian bumps of
-width 0.1; the V-cycle in float64 (plain) and, for comparison, in float32.
+Workload (default): 3D Poisson on the ball (a structured cube mapped by
+x -> x |x|_inf / |x|_2), Q4 on five independent non-nested meshes of
+75^3/34^3/15^3/7^3/5^3 cells (27,270,901 fine DoFs, the largest configuration
+of the paper's ball experiment that fits one GPU), zero Dirichlet data,
+f = sum of 8 Gaussian bumps of width 0.1 in the radius-0.8 ball; coarse
+solver: polynomial coarsening Q4->Q3->Q2->Q1 on the 5^3 mesh, then the dense
+float64 inverse on Q1.  The V-cycle runs in float64 (the plain method: the
+headline value) and in float32 inside the float64 CG (paper §4), and both
+reach 1e-8.  The Q3 ball on 96^3/43^3/19^3/9^3/5^3 (24,137,569 DoFs) is
+measured in the same run and reported under "extra_workloads".
 
 A step is one pcg_solve to a relative residual of 1e-8 from x0 = 0 with the
 hierarchy resident on the GPU.  value = fine DoFs x CG iterations / solve
 time, in MDoF/s per PCG iteration (DoFs counted with the boundary, as the
 paper does).  Each solve's wall time gives the p50/p99 latency.
 
-Also reported: setup times, the float32-MG solve, the operator kernel's HBM
-roofline (algorithmic bytes / measured kernel time) and the CPU oracle timed
-on a bounded sample of the same workload on this machine's host cores.
+Also reported: setup times; the per-component V-cycle times of one solve
+(pre-smoother, residual, restriction, coarse solve, prolongation,
+post-smoother, per level); the operator and transfer kernels against the HBM
+roofline (model bytes and, where recorded, measured HBM bytes per launch);
+the error against the float64 oracle, quoted from the oracle's stored
+whole-solve goldens (tests/golden/pcg_*.txt) re-solved here at the reduced
+size the oracle can solve; and the CPU oracle timed on a bounded sample of
+the same workload on this machine's host cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W] [--no-cpu-baseline]
 """
 
 from __future__ import annotations
@@ -77,27 +88,40 @@ def transfer_bytes(coarse, n_points, word, prolong, nr=1):
     return n_points * per_point + coarse.n_cells * per_cell
 
 
-# main-run workloads: config, cells per direction (coarse -> fine), degree,
-# operator, the oracle sample of the CPU baseline, and a description
+# PCG workloads: config, cells per direction (coarse -> fine), degree, operator,
+# polynomial coarsening on the coarsest mesh, the level pair whose recorded
+# traffic applies, the oracle's whole-solve golden of the same recipe at a
+# size the oracle solves, the oracle sample of the CPU baseline, a description
 WORKLOADS = {
-    "cube_q2": dict(cfg=1, cells=[6, 13, 29, 64], degree=2, operator="laplace", cpu_cells=[3, 6, 13, 29],
-                    roofline="cube_q2_64",
+    "ball_q4": dict(cfg="2q4", cells=[5, 7, 15, 34, 75], degree=4, operator="laplace", pmg=True,
+                    roofline="ball_q4_75", golden="ball_q4_24", cpu_cells=[5, 7, 11],
+                    text="3D Poisson Q4 on the ball (cube mapped by x|x|_inf/|x|_2), non-nested levels "
+                         "75^3/34^3/15^3/7^3/5^3 (27,270,901 fine DoFs), 8 Gaussian bumps in the radius-0.8 ball, "
+                         "zero Dirichlet; coarse solver: polynomial coarsening Q4->Q3->Q2->Q1 on the 5^3 mesh, "
+                         "then the dense float64 inverse on Q1; float64 V-cycle in float64 PCG to 1e-8 (value) "
+                         "and float32 V-cycle in float64 PCG to 1e-8 (fp32_mg)"),
+    "ball_q3": dict(cfg=2, cells=[5, 9, 19, 43, 96], degree=3, operator="laplace", pmg=False,
+                    roofline="ball_q3_96", golden="ball_q3_32", cpu_cells=[3, 5, 9],
+                    text="3D Poisson Q3 on the ball (cube mapped by x|x|_inf/|x|_2), non-nested levels "
+                         "96^3/43^3/19^3/9^3/5^3 (24,137,569 fine DoFs), 8 Gaussian bumps in the radius-0.8 ball, "
+                         "zero Dirichlet; dense float64 inverse on 5^3 Q3; float64 V-cycle in float64 PCG to 1e-8 "
+                         "(value) and float32 V-cycle in float64 PCG to 1e-8 (fp32_mg)"),
+    "cube_q2": dict(cfg=1, cells=[6, 13, 29, 64], degree=2, operator="laplace", pmg=False,
+                    roofline="cube_q2_64", golden="cube_q2_64", cpu_cells=[3, 6, 13, 29],
                     text="3D Poisson Q2 on the unit cube, non-nested perturbed hex levels 64^3/29^3/13^3/6^3 "
                          "(+-0.15h), 8 Gaussian bumps, float64 V-cycle in float64 PCG to 1e-8"),
-    "ball_q4": dict(cfg="2q4", cells=[5, 7, 15, 34, 75], degree=4, operator="laplace", roofline="ball_q4_75",
-                    pmg=True, cpu_cells=[5, 7, 11],
-                    text="3D Poisson Q4 on the ball, non-nested levels 75^3/34^3/15^3/7^3/5^3 (27.3M fine DoFs), "
-                         "bumps in the radius-0.8 ball; coarse solver: polynomial coarsening Q4->Q3->Q2->Q1 on the "
-                         "5^3 mesh, then the dense inverse on Q1 (compared with the dense inverse on 5^3 Q4); "
-                         "float64 V-cycle in float64 PCG to 1e-8"),
     "beam_q2": dict(cfg=3, cells=[(14, 3, 3), (33, 7, 7), (80, 16, 16)], degree=2, operator="elasticity", rhs=4,
-                    roofline="beam_q2",
+                    pmg=False, roofline="beam_q2", golden=None,
                     cpu_cells=[(10, 2, 2), (22, 5, 5), (50, 10, 10)],
                     text="3D linear elasticity, vector Q2, lambda = mu = 1, beam [0,5]x[0,1]^2 clamped at x = 0, "
                          "body load (0,0,-1) and three random smooth loads fused as 4 right-hand sides, "
                          "non-nested perturbed hex levels 80x16x16/33x7x7/14x3x3 (+-0.1h), "
                          "float64 V-cycle in float64 PCG to 1e-8"),
 }
+DEFAULT_WORKLOAD = "ball_q4"
+# measured in the same run as a workload and reported beside it
+EXTRA_WORKLOADS = {"ball_q4": ["ball_q3"]}
+
 
 def run_serving(args, ctx, nn, torch, log):
     """The serving stream: requests with Poisson arrivals on a pool of resident
@@ -194,11 +218,6 @@ def run_serving(args, ctx, nn, torch, log):
         cpu = cpu_baseline([3, 6, 13, 29], 1, "laplace")
     op = k["operator_fp32"]
 
-    def entry(name):
-        v = k[name]
-        return {"ms": round(v["ms"], 5), "bytes": v["bytes"], "achieved": round(v["gbs"], 1),
-                "frac": round(v["frac"], 4), "traffic": None}
-
     line = {
         "metric": METRIC,
         "value": round(batched["value"], 2),
@@ -228,14 +247,9 @@ def run_serving(args, ctx, nn, torch, log):
                     "speedup": round(batched["value"] / serial["value"], 3),
                     "service_ms_alone": [round(t * 1e3, 3) for t in service]},
         "setup_s": {"pool": round(t_setup, 3)},
-        "roofline": {
-            "bound": "hbm", "achieved": round(op["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(op["frac"], 4), "traffic": None,
-            "kernel": (f"operator application on the largest resident level ({big['n']} DoFs), float32 (the "
-                       "V-cycle precision): vmult_kernel + gather_kernel"),
-            "bytes_per_launch": op["bytes"], "ms_per_launch": round(op["ms"], 5),
-            "kernels": {n: entry(n) for n in k},
-        },
+        "roofline": roofline_entry(k, "operator_fp32", {}, big["levels"][-1], 4, 1,
+                                   f"operator application on the largest resident level ({big['n']} DoFs), "
+                                   "float32 (the V-cycle precision)"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -251,6 +265,8 @@ ROOFLINE_WORKLOADS = {
 
 KERNEL_SOURCES = ("paper_2412_10910_amd/csrc/kernels/vmult.hip", "paper_2412_10910_amd/csrc/kernels/gather.hip",
                   "paper_2412_10910_amd/csrc/kernels/transfer.hip", "paper_2412_10910_amd/csrc/kernels/common.hpp")
+
+
 # recorded HBM traffic of the roofline workloads (profiles/traffic_operator_transfer_<workload>.txt)
 def traffic_file(tag):
     return os.path.join(ROOT, "profiles", f"traffic_operator_transfer_{tag}.txt")
@@ -280,6 +296,24 @@ def recorded_traffic(tag):
     if kv.get("kernel_sources_sha256_16") != kernel_source_hash():
         return {}
     return {k[len("traffic_bytes."):]: float(v) for k, v in kv.items() if k.startswith("traffic_bytes.")}
+
+
+def operator_kernel_names(level, word, nr=1):
+    """The kernels one operator application (Level.vmult_add) launches, named
+    as the kernel trace names them, for the level's degree and operator variant."""
+    T = "double" if word == 8 else "float"
+    n = level.degree + 1
+    nrt = 1 if nr == 1 else 0
+    if level.operator == "elasticity":
+        return [f"elasticity_kernel<{n}, {T}, {nrt}>", f"gather_kernel<3, {nr}, {T}, nnmg::CsrRuns>"]
+    variant = level.VARIANTS[level.variant]
+    geo = 1 if variant.startswith("trilinear") else 0
+    if variant.endswith("atomic"):
+        return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 1, {nrt}>"]
+    lattice = variant.endswith("lattice")
+    runs = "nnmg::LatticeRuns" if lattice else "nnmg::CsrRuns"
+    return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, {2 if lattice else 0}, {nrt}>",
+            f"gather_kernel<1, {nr}, {T}, {runs}>"]
 
 
 def time_launches(fn, reps):
@@ -314,14 +348,57 @@ def kernel_rooflines(fine, coarse, transfer, reps, nr=1):
             csrc = torch.rand(shape_c, dtype=torch.float64, device=dev).to(dt)
             cdst = torch.zeros_like(csrc)
             ms = time_launches(lambda: fine.vmult_add(src, dst), reps)
-            out[f"operator_{tag}{sfx}"] = dict(ms=ms, bytes=vmult_bytes(fine, word, r))
+            out[f"operator_{tag}{sfx}"] = dict(ms=ms, bytes=vmult_bytes(fine, word, r),
+                                               launches=operator_kernel_names(fine, word, r))
             ms = time_launches(lambda: transfer.prolongate(csrc, dst), reps)
             out[f"prolongate_{tag}{sfx}"] = dict(ms=ms, bytes=transfer_bytes(coarse, npts, word, True, r))
             ms = time_launches(lambda: transfer.restrict(src, cdst), reps)
             out[f"restrict_{tag}{sfx}"] = dict(ms=ms, bytes=transfer_bytes(coarse, npts, word, False, r))
+            del src, dst, csrc, cdst
     for v in out.values():
         v["gbs"] = v["bytes"] / (v["ms"] * 1e-3) / 1e9
         v["frac"] = v["gbs"] / HBM_PEAK_GBS
+    return out
+
+
+def kernel_entry(v, traffic):
+    """One kernel of the roofline table: time, model bytes and their rate, and
+    the measured HBM bytes and their rate where recorded for these sources."""
+    e = {"ms": round(v["ms"], 5), "bytes": v["bytes"], "achieved": round(v["gbs"], 1),
+         "frac": round(v["frac"], 4), "traffic": traffic}
+    if traffic:
+        rate = traffic / (v["ms"] * 1e-3) / 1e9
+        e["traffic_rate"] = round(rate, 1)
+        e["traffic_frac"] = round(rate / HBM_PEAK_GBS, 4)
+    if "launches" in v:
+        e["launches"] = v["launches"]
+    return e
+
+
+def roofline_entry(k, key, traffic, fine, word, nr, what):
+    """The roofline object of the line for the dominant kernel `key`."""
+    op = k[key]
+    t = traffic.get(key)
+    names = op.get("launches", [])
+    out = {
+        "bound": "hbm",
+        "achieved": round(op["gbs"], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(op["frac"], 4),
+        "traffic": t,
+        "kernel": (what + ": " + " + ".join(names) + ", back to back on one stream; HIP events over "
+                   "the repeated launches"),
+        "model": ("algorithmic bytes of the stored-geometry operator: 2 s N vectors + 4 q C int32 map + "
+                  "s q C metric words (the library rebuilds the geometry from the trilinear map and does not "
+                  "read a metric, so achieved/frac are effective rates; traffic_rate is the measured one)"),
+        "bytes_per_launch": op["bytes"],
+        "ms_per_launch": round(op["ms"], 5),
+        "kernels": {n: kernel_entry(v, traffic.get(n)) for n, v in k.items()},
+    }
+    if t:
+        out["traffic_rate"] = round(t / (op["ms"] * 1e-3) / 1e9, 1)
+        out["traffic_frac"] = round(out["traffic_rate"] / HBM_PEAK_GBS, 4)
     return out
 
 
@@ -337,8 +414,10 @@ def copy_calibration(nbytes=1 << 30):
     return nbytes
 
 
-def cpu_baseline(cells, cfg, operator="laplace", degree=2, pmg=False):
-    """Oracle PCG on a reduced instance of the same workload recipe, 1 thread."""
+def cpu_baseline(cells, cfg, operator="laplace", degree=2, pmg=False, runs=3):
+    """The oracle (scipy CSR, 1 thread) on a reduced instance of the same
+    workload recipe: the median of `runs` PCG solves, and beside it the
+    median time of one CSR product per level and of one V-cycle."""
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
         env[k] = "1"
@@ -365,24 +444,42 @@ else:
     frees = [s.free for s in sps]
     b = assemble.load_vector(sps[-1], config_source({cfg!r}))
 H = multigrid.Hierarchy(As, frees, Ps, eig_start=[random_vector(s.n_dofs * nc, 100 + i) for i, s in enumerate(sps)])
-t0 = time.perf_counter()
-x, it, hist = H.pcg(b, rtol=1e-8)
-t = time.perf_counter() - t0
-print(json.dumps(dict(n=sps[-1].n_dofs * nc, it=it, t=t)))
+def med(f, n):
+    ts = []
+    for _ in range(n):
+        t0 = time.perf_counter(); f(); ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2], ts
+mv = []
+for A in As:
+    v = random_vector(A.shape[0], 5)
+    mv.append(med(lambda: A @ v, 5)[0])
+tv, _ = med(lambda: H.vcycle(b), 3)
+its = []
+def solve():
+    x, it, hist = H.pcg(b, rtol=1e-8)
+    its.append(it)
+t, ts = med(solve, {runs})
+print(json.dumps(dict(n=sps[-1].n_dofs * nc, it=its[0], t=t, ts=ts, mv=mv, vcycle=tv,
+                      levels=[s.n_dofs * nc for s in sps], nnz=[int(A.nnz) for A in As])))
 """
     t0 = time.perf_counter()
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=900)
     wall = time.perf_counter() - t0
     if out.returncode != 0:
         log(out.stderr[-2000:])
         return None
     r = json.loads(out.stdout.strip().splitlines()[-1])
     return dict(value=round(r["n"] * r["it"] / r["t"] / 1e6, 4), unit=UNIT, cores=1, kind="oracle",
-                sample=(f"oracle float64 PCG + float64 V-cycle (scipy CSR) on the same recipe at "
+                sample=(f"oracle float64 PCG + float64 V-cycle (scipy CSR, one thread) on the same recipe at "
                         f"{' / '.join(str(c) for c in cells[::-1])} cells, Q{degree}"
-                        + (f" with polynomial coarsening to Q1 on the coarsest mesh" if pmg else "")
-                        + f" ({r['n']} fine DoFs), {r['it']} iterations in {r['t']:.2f} s; "
-                        f"setup excluded; {wall:.1f} s wall including setup"),
+                        + (" with polynomial coarsening to Q1 on the coarsest mesh" if pmg else "")
+                        + f" ({r['n']} fine DoFs), {r['it']} iterations, median of {runs} solves "
+                        f"{r['t']:.3f} s; setup excluded; {wall:.1f} s wall including setup (the full-size "
+                        "oracle needs tens of GB of CSR and minutes of setup per level, beyond this run's budget)"),
+                solve_s=[round(t, 4) for t in r["ts"]],
+                matvec_ms_per_level=[round(t * 1e3, 3) for t in r["mv"]],
+                vcycle_ms=round(r["vcycle"] * 1e3, 2),
+                level_dofs=r["levels"], level_nnz=r["nnz"],
                 cpu=_cpu_model(), host_cpus=os.cpu_count())
 
 
@@ -396,71 +493,71 @@ def _cpu_model():
     return "unknown"
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile", action="store_true", help="also print the per-component V-cycle times")
-    ap.add_argument("--roofline-reps", type=int, default=100)
-    ap.add_argument("--roofline-rhs", type=int, default=1,
-                    help="--roofline-only: also time the launches that carry this many right-hand sides")
-    ap.add_argument("--roofline-only", action="store_true",
-                    help="only the operator/transfer kernel loops of the two finest levels and a copy of "
-                         "known size (the run that rocprofv3 traces and counts)")
-    ap.add_argument("--serving-requests", type=int, default=120)
-    ap.add_argument("--serving-load", type=float, default=1.0,
-                    help="arrival rate as a fraction of the one-request-at-a-time service rate")
-    ap.add_argument("--serving-slots", type=int, default=4)
-    ap.add_argument("--serving-replicas", type=int, default=2, help="hierarchies per resident mesh")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["serving"], default="cube_q2",
-                    help="the PCG workload (default: the 3D Poisson cube the metric is quoted on)")
-    ap.add_argument("--no-tune", action="store_true",
-                    help="skip the autotuner (operator variant per level, restriction team per transfer)")
-    ap.add_argument("--rhs", type=int, default=None,
-                    help="right-hand sides fused per solve (default: the workload's, 1 for the cube, 4 for the beam)")
-    ap.add_argument("--roofline-workload", choices=sorted(ROOFLINE_WORKLOADS), default="cube_q2_64",
-                    help="level pair of --roofline-only")
-    ap.add_argument("--geometry", choices=["trilinear", "metric"], default=None,
-                    help="operator geometry source (default: the library's choice)")
-    args = ap.parse_args()
-    if args.geometry:
-        os.environ["NNMG_GEOMETRY"] = args.geometry
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
-              file=sys.stderr)
-        sys.exit(2)
+def load_golden(name):
+    """The oracle's stored whole-solve golden (tests/golden/pcg_<name>.txt)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("_golden_io", os.path.join(ROOT, "tests", "golden", "golden_io.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.load_golden(name)
 
-    import torch
 
-    import paper_2412_10910_amd as nn
-    from workloads import config_levels, config_source, random_load
+def _cfg_key(s):
+    return int(s) if s.isdigit() else s
 
+
+def golden_check(ctx, nn, torch, name):
+    """Solve the golden's case with the library (bounds injected from the
+    golden, as the GPU parity test does) and compare: iteration counts, the
+    float64-MG residual history, and the solution at the stored points."""
+    from scipy.spatial import cKDTree
+
+    from workloads import config_levels, config_source
     dev = "cuda:0"
-    torch.cuda.init()
-    ctx = nn.Context(0)
-    if args.workload == "serving" and not args.roofline_only:
-        return run_serving(args, ctx, nn, torch, log)
-    wl = WORKLOADS[args.workload]
+    g = load_golden(name)
+    cfg = _cfg_key(g["cfg"])
+    cells = [int(c) for c in g["cells"].split()]
+    k = int(g["degree"])
+    meshes = config_levels(cfg, cells=cells)
+    levels, transfers = nn.build_levels(ctx, meshes, k, p_coarsening=bool(int(g["pmg"])))
+    assert [lv.n_dofs for lv in levels] == [int(v) for v in g["level_dofs"].split()]
+    H = nn.Hierarchy(ctx, levels, transfers)
+    for l in range(1, len(levels)):
+        lo, hi = (float(v) for v in g[f"bounds.{l}"].split())
+        H.set_cheb_bounds(l, lo, hi)
+    fine = levels[-1]
+    b = fine.assemble_rhs(torch.tensor(config_source(cfg)(fine.quadrature_points()).reshape(-1),
+                                       dtype=torch.float64, device=dev))
+    samples = g["samples"]
+    dist, idx = cKDTree(fine.support_points()).query(samples[:, :3])
+    assert dist.max() <= 1e-12
+    u = samples[:, 3]
+    out = {"dofs": fine.n_dofs, "oracle_iterations_fp64": int(g["iterations_fp64"]),
+           "oracle_iterations_fp32": int(g["iterations_fp32"]), "samples": int(u.size)}
+    hist_orc = np.array([float(v) for v in g["history_fp64"].split()])
+    for dt, tag in ((torch.float64, "fp64"), (torch.float32, "fp32")):
+        x, info = H.pcg_solve(b, rtol=1e-8, vcycle_dtype=dt)
+        xs = x[torch.tensor(idx, device=dev)].cpu().numpy()
+        out[f"iterations_{tag}"] = info["iterations"]
+        out[f"max_rel_err_{tag}"] = float(np.abs(xs - u).max() / np.abs(u).max())
+        if dt == torch.float64 and info["iterations"] == hist_orc.size - 1:
+            out["history_max_abs_diff_fp64"] = float(np.abs(info["history"] - hist_orc).max())
+    H.close()
+    for t in transfers:
+        t.close()
+    for lv in levels:
+        lv.close()
+    return out
+
+
+def run_pcg_workload(name, args, ctx, nn, torch, steps, warmup, with_cpu):
+    """Build, tune and time one PCG workload; returns the fields of its line."""
+    from workloads import config_levels, config_source, random_load
+    dev = "cuda:0"
+    wl = WORKLOADS[name]
     cfg, cells, degree, operator = wl["cfg"], wl["cells"], wl["degree"], wl["operator"]
-
-    log("generating meshes")
-    meshes = config_levels(cfg, cells=cells) if not args.roofline_only else None
-
-    if args.roofline_only:
-        rcfg, rcells, rdeg, rop = ROOFLINE_WORKLOADS[args.roofline_workload]
-        rmeshes = config_levels(rcfg, cells=rcells)
-        fine = nn.Level.from_mesh(ctx, rmeshes[-1], rdeg, rop)
-        coarse = nn.Level.from_mesh(ctx, rmeshes[-2], rdeg, rop)
-        tr = nn.Transfer(ctx, fine, coarse)
-        nbytes = copy_calibration()
-        k = kernel_rooflines(fine, coarse, tr, args.roofline_reps, args.roofline_rhs)
-        print(json.dumps({"roofline_only": True, "workload": args.roofline_workload, "copy_bytes": nbytes, "reps": args.roofline_reps,
-                          "kernels": {n: {"ms": round(v["ms"], 5), "bytes": v["bytes"], "GB/s": round(v["gbs"], 1),
-                                          "frac": round(v["frac"], 4)} for n, v in k.items()}}), flush=True)
-        return
-
+    log(f"[{name}] generating meshes")
+    meshes = config_levels(cfg, cells=cells)
     t0 = time.perf_counter()
     levels = [nn.Level.from_mesh(ctx, m, degree, operator) for m in meshes]
     t_levels = time.perf_counter() - t0
@@ -471,6 +568,7 @@ def main():
     H = nn.Hierarchy(ctx, levels, transfers)
     t_hier = time.perf_counter() - t0
     H_mesh, t_hier_mesh = None, None
+    all_levels, all_transfers = levels, transfers
     if wl.get("pmg"):
         # polynomial coarsening below the coarsest mesh level, sharing the mesh levels and transfers;
         # the hierarchy with the dense inverse on the coarsest mesh is kept for the comparison
@@ -480,13 +578,15 @@ def main():
         H_mesh, t_hier_mesh = H, t_hier
         H = nn.Hierarchy(ctx, plevels + levels, ptrs + transfers)
         t_hier = time.perf_counter() - t0
+        all_levels, all_transfers = plevels + levels, ptrs + transfers
     tuned = None
     t_tune = 0.0
     if not args.no_tune:
         t0 = time.perf_counter()
         rep = H.tune(torch.float64, reps=10)
         t_tune = time.perf_counter() - t0
-        tuned = dict(levels=[r["chosen"] for r in rep["levels"]], restriction_teams=[r["chosen"] for r in rep["transfers"]])
+        tuned = dict(levels=[r["chosen"] for r in rep["levels"]],
+                     restriction_teams=[r["chosen"] for r in rep["transfers"]])
     fine = levels[-1]
     nr = args.rhs if args.rhs is not None else wl.get("rhs", 1)
     if operator == "elasticity":
@@ -495,10 +595,11 @@ def main():
         srcs = [config_source(cfg, i) for i in range(nr)]
     qp = fine.quadrature_points()
     cols = [fine.assemble_rhs(torch.tensor(f(qp).reshape(-1), dtype=torch.float64, device=dev)) for f in srcs]
+    del qp
     b = cols[0] if nr == 1 else torch.stack(cols, dim=1).contiguous()
     x = torch.empty_like(b)
     torch.cuda.synchronize()
-    log(f"setup: levels {t_levels:.2f} s, transfers {t_transfers:.2f} s, hierarchy {t_hier:.2f} s; "
+    log(f"[{name}] setup: levels {t_levels:.2f} s, transfers {t_transfers:.2f} s, hierarchy {t_hier:.2f} s; "
         f"fine DoFs {fine.n_dofs}")
 
     def run(dtype, steps, warmup, H=H):
@@ -517,77 +618,83 @@ def main():
                         relres=max(i["relres"] for i in infos))
         torch.cuda.synchronize()
         total = time.perf_counter() - t_start
-        return total, lat, its, info
+        # the true residual of the last solution, with the library's float64 operator
+        true = float((b - fine.vmult(x)).norm() / b.norm())
+        return total, lat, its, info, true
 
-    log("timing float64-MG PCG")
-    tot64, lat64, its64, info64 = run(torch.float64, args.steps, args.warmup)
-    log("timing float32-MG PCG")
-    tot32, lat32, its32, info32 = run(torch.float32, args.steps, args.warmup)
+    log(f"[{name}] timing float64-MG PCG")
+    tot64, lat64, its64, info64, true64 = run(torch.float64, steps, warmup)
+    log(f"[{name}] timing float32-MG PCG")
+    tot32, lat32, its32, info32, true32 = run(torch.float32, steps, warmup)
     value = fine.n_dofs * sum(its64) / tot64 / 1e6
     value32 = fine.n_dofs * sum(its32) / tot32 / 1e6
     dense = None
     if H_mesh is not None:
-        log("timing the dense coarse inverse on the coarsest mesh for comparison")
-        dsteps = max(1, args.steps // 5)
-        d64, _, dits64, dinfo64 = run(torch.float64, dsteps, 1, H_mesh)
-        d32, _, dits32, dinfo32 = run(torch.float32, dsteps, 1, H_mesh)
+        log(f"[{name}] timing the dense coarse inverse on the coarsest mesh for comparison")
+        dsteps = max(1, steps // 5)
+        d64, _, dits64, dinfo64, _ = run(torch.float64, dsteps, 1, H_mesh)
+        d32, _, dits32, dinfo32, _ = run(torch.float32, dsteps, 1, H_mesh)
         dense = {"setup_hierarchy_s": round(t_hier_mesh, 3), "coarse_free_dofs": H_mesh.coarse_free_dofs,
                  "float64_mg": {"value": round(fine.n_dofs * sum(dits64) / d64 / 1e6, 2),
                                 "ms_per_step": round(d64 / dsteps * 1e3, 4), "iterations": dinfo64["iterations"]},
                  "float32_mg": {"value": round(fine.n_dofs * sum(dits32) / d32 / 1e6, 2),
                                 "ms_per_step": round(d32 / dsteps * 1e3, 4), "iterations": dinfo32["iterations"]}}
+        H_mesh.close()
 
-    log("timing the operator and transfer kernels")
+    profile = None
+    if not args.no_profile:
+        # the six components of Algorithm V_cycle per level, one solve each,
+        # events around every component (slower than the graph-replayed solve)
+        profile = {}
+        for dt, tag in ((torch.float64, "fp64_mg"), (torch.float32, "fp32_mg")):
+            H.set_profiling(True)
+            H.pcg_solve(b, x, rtol=1e-8, vcycle_dtype=dt, history=False)
+            ms = H.profile()
+            H.set_profiling(False)
+            tot = {c: float(ms[:, j].sum()) for j, c in enumerate(H.COMPONENTS)}
+            s = sum(tot.values())
+            profile[tag] = {
+                "ms_per_level": {c: [round(float(v), 4) for v in ms[:, j]] for j, c in enumerate(H.COMPONENTS)},
+                "ms_total": {c: round(v, 4) for c, v in tot.items()},
+                "share": {c: round(v / s, 4) for c, v in tot.items()} if s > 0 else None,
+                "levels": [f"{lv.n_dofs}@Q{lv.degree}" for lv in all_levels],
+            }
+
+    log(f"[{name}] timing the operator and transfer kernels")
     k = kernel_rooflines(fine, levels[-2], transfers[-1], args.roofline_reps, nr)
     traffic = recorded_traffic(wl["roofline"])
 
-    profile = None
-    if args.profile:
-        H.set_profiling(True)
-        H.pcg_solve(b, x, rtol=1e-8, vcycle_dtype=torch.float64, history=False)
-        ms = H.profile()
-        H.set_profiling(False)
-        profile = {name: [round(float(v), 4) for v in ms[:, j]] for j, name in enumerate(H.COMPONENTS)}
+    golden = None
+    if wl.get("golden") and not args.no_golden:
+        log(f"[{name}] re-solving the oracle's golden {wl['golden']}")
+        golden = golden_check(ctx, nn, torch, wl["golden"])
 
     cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
+    if with_cpu:
+        log(f"[{name}] timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(wl["cpu_cells"], cfg, operator, degree, bool(wl.get("pmg")))
 
     op_key = "operator_fp64" if nr == 1 else f"operator_fp64_x{nr}"
-    op = k[op_key]
-
-    def entry(name):
-        v = k[name]
-        return {"ms": round(v["ms"], 5), "bytes": v["bytes"], "achieved": round(v["gbs"], 1),
-                "frac": round(v["frac"], 4), "traffic": traffic.get(name)}
-
-    line = {
-        "metric": METRIC,
+    res = {
         "value": round(value, 2),
-        "unit": UNIT,
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(tot64 / args.steps * 1e3, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
+        "ms_per_step": round(tot64 / steps * 1e3, 4),
         "config": {
             "workload": wl["text"],
             "fine_dofs": fine.n_dofs,
-            "level_dofs": [lv.n_dofs for lv in levels],
+            "level_dofs": [lv.n_dofs for lv in all_levels],
+            "level_degrees": [lv.degree for lv in all_levels],
             "rhs": nr,
             "iterations": info64["iterations"],
         },
         "latency_ms": {"p50": round(percentile(lat64, 50) * 1e3, 4), "p99": round(percentile(lat64, 99) * 1e3, 4)},
+        "relres": info64["relres"],
+        "true_relres": true64,
         "fp32_mg": {
             "value": round(value32, 2),
-            "ms_per_step": round(tot32 / args.steps * 1e3, 4),
+            "ms_per_step": round(tot32 / steps * 1e3, 4),
             "iterations": info32["iterations"],
             "relres": info32["relres"],
+            "true_relres": true32,
             "latency_ms": {"p50": round(percentile(lat32, 50) * 1e3, 4),
                            "p99": round(percentile(lat32, 99) * 1e3, 4)},
             "speedup_vs_fp64_mg": round(tot64 / tot32, 3),
@@ -595,30 +702,120 @@ def main():
         "setup_s": {"levels": round(t_levels, 3), "transfers": round(t_transfers, 3), "hierarchy": round(t_hier, 3),
                     "tune": round(t_tune, 3)},
         "tuned": tuned,
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(op["gbs"], 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(op["frac"], 4),
-            "traffic": traffic.get(op_key),
-            "kernel": (f"operator application on the finest level ({fine.n_dofs} DoFs"
-                       + (f", {nr} fused right-hand sides" if nr > 1 else "") + "), float64: "
-                       + (f"vmult_kernel<3,3,double,1,0,{1 if nr == 1 else 0}>" if operator == "laplace"
-                          else f"elasticity_kernel<3,double,{1 if nr == 1 else 0}>")
-                       + " (per-cell sum factorization) + gather_kernel (per-DoF sum of the cell "
-                         "contributions), back to back on one stream"),
-            "bytes_per_launch": op["bytes"],
-            "ms_per_launch": round(op["ms"], 5),
-            "kernels": {n: entry(n) for n in k},
+        "roofline": roofline_entry(k, op_key, traffic, fine, 8, nr,
+                                   f"operator application on the finest level ({fine.n_dofs} DoFs"
+                                   + (f", {nr} fused right-hand sides" if nr > 1 else "") + "), float64"),
+        "error_vs_oracle": {
+            "golden": golden,
+            "note": ("the full-size solve is beyond the oracle (tens of GB of CSR); the same recipe at the size "
+                     "of the oracle's stored golden is re-solved here with the golden's smoother bounds and "
+                     "compared with it; true_relres is ||b - A x|| / ||b|| of the full-size solution with the "
+                     "library's float64 operator") if golden else None,
         },
         "cpu_baseline": cpu,
     }
     if profile is not None:
-        line["vcycle_profile_ms"] = profile
+        res["vcycle_profile"] = profile
     if dense is not None:
-        line["config"]["levels"] = [f"{lv.n_dofs}@Q{lv.degree}" for lv in H.levels]
-        line["coarse_dense_inverse"] = dense
+        res["coarse_dense_inverse"] = dense
+    H.close()
+    for t in all_transfers:
+        t.close()
+    for lv in all_levels:
+        lv.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-component V-cycle times")
+    ap.add_argument("--no-golden", action="store_true", help="skip the re-solve of the oracle's golden")
+    ap.add_argument("--no-extra", action="store_true", help="skip the extra workloads measured beside the default")
+    ap.add_argument("--roofline-reps", type=int, default=100)
+    ap.add_argument("--roofline-rhs", type=int, default=1,
+                    help="--roofline-only: also time the launches that carry this many right-hand sides")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the operator/transfer kernel loops of the two finest levels and a copy of "
+                         "known size (the run that rocprofv3 traces and counts)")
+    ap.add_argument("--serving-requests", type=int, default=120)
+    ap.add_argument("--serving-load", type=float, default=1.0,
+                    help="arrival rate as a fraction of the one-request-at-a-time service rate")
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-replicas", type=int, default=2, help="hierarchies per resident mesh")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["serving"], default=DEFAULT_WORKLOAD,
+                    help="the PCG workload (default: the Q4 ball, the largest single-GPU configuration)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (operator variant per level, restriction team per transfer)")
+    ap.add_argument("--rhs", type=int, default=None,
+                    help="right-hand sides fused per solve (default: the workload's, 1 for Poisson, 4 for the beam)")
+    ap.add_argument("--roofline-workload", choices=sorted(ROOFLINE_WORKLOADS), default="ball_q4_75",
+                    help="level pair of --roofline-only")
+    ap.add_argument("--geometry", choices=["trilinear", "metric"], default=None,
+                    help="operator geometry source (default: the library's choice)")
+    args = ap.parse_args()
+    if args.geometry:
+        os.environ["NNMG_GEOMETRY"] = args.geometry
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2412_10910_amd as nn
+    from workloads import config_levels
+
+    torch.cuda.init()
+    ctx = nn.Context(0)
+    if args.workload == "serving" and not args.roofline_only:
+        return run_serving(args, ctx, nn, torch, log)
+
+    if args.roofline_only:
+        rcfg, rcells, rdeg, rop = ROOFLINE_WORKLOADS[args.roofline_workload]
+        rmeshes = config_levels(rcfg, cells=rcells)
+        fine = nn.Level.from_mesh(ctx, rmeshes[-1], rdeg, rop)
+        coarse = nn.Level.from_mesh(ctx, rmeshes[-2], rdeg, rop)
+        tr = nn.Transfer(ctx, fine, coarse)
+        nbytes = copy_calibration()
+        k = kernel_rooflines(fine, coarse, tr, args.roofline_reps, args.roofline_rhs)
+        print(json.dumps({"roofline_only": True, "workload": args.roofline_workload, "copy_bytes": nbytes,
+                          "reps": args.roofline_reps,
+                          "kernels": {n: {"ms": round(v["ms"], 5), "bytes": v["bytes"], "GB/s": round(v["gbs"], 1),
+                                          "frac": round(v["frac"], 4), "launches": v.get("launches")}
+                                      for n, v in k.items()}}), flush=True)
+        return
+
+    main_res = run_pcg_workload(args.workload, args, ctx, nn, torch, args.steps, args.warmup,
+                                not args.no_cpu_baseline)
+    extras = {}
+    if not args.no_extra:
+        for name in EXTRA_WORKLOADS.get(args.workload, []):
+            torch.cuda.empty_cache()
+            r = run_pcg_workload(name, args, ctx, nn, torch, args.steps, args.warmup, False)
+            r.pop("cpu_baseline", None)
+            extras[name] = r
+    line = {
+        "metric": METRIC,
+        "value": main_res.pop("value"),
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res.pop("ms_per_step"),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": main_res.pop("config"),
+    }
+    line.update(main_res)
+    if extras:
+        line["extra_workloads"] = extras
     print(json.dumps(line), flush=True)
 
 

@@ -94,6 +94,44 @@ def test_committed_traffic_summaries_parse():
         assert all(float(kv["traffic_bytes." + k]) > 0 for k in keys), tag
 
 
+def test_operator_kernel_names_follow_degree_and_variant():
+    lv = SimpleNamespace(dim=3, degree=4, operator="laplace", VARIANTS=("trilinear+slots", "trilinear+atomic",
+                                                                        "metric+slots", "metric+atomic",
+                                                                        "trilinear+lattice", "metric+lattice"),
+                         variant=0)
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1>",
+                                                  "gather_kernel<1, 1, double, nnmg::CsrRuns>"]
+    lv.variant = 2
+    assert bench.operator_kernel_names(lv, 4, nr=4) == ["vmult_kernel<3, 5, float, 0, 0, 0>",
+                                                        "gather_kernel<1, 4, float, nnmg::CsrRuns>"]
+    lv.variant = 3
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 0, 1, 1>"]
+    lv.variant = 4
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 2, 1>",
+                                                  "gather_kernel<1, 1, double, nnmg::LatticeRuns>"]
+    el = SimpleNamespace(dim=3, degree=2, operator="elasticity")
+    assert bench.operator_kernel_names(el, 8, nr=4) == ["elasticity_kernel<3, double, 0>",
+                                                        "gather_kernel<3, 4, double, nnmg::CsrRuns>"]
+
+
+def test_default_workload_is_the_largest_single_gpu_ball():
+    wl = bench.WORKLOADS[bench.DEFAULT_WORKLOAD]
+    # Q4 on 75^3: (4 * 75 + 1)^3 = 27,270,901 DoFs, five non-nested levels
+    assert wl["degree"] == 4 and wl["cells"][-1] == 75 and len(wl["cells"]) == 5
+    assert (wl["degree"] * wl["cells"][-1] + 1) ** 3 == 27_270_901
+    assert bench.EXTRA_WORKLOADS[bench.DEFAULT_WORKLOAD] == ["ball_q3"]
+    assert (3 * bench.WORKLOADS["ball_q3"]["cells"][-1] + 1) ** 3 == 24_137_569
+
+
+def test_goldens_quoted_by_the_bench_parse():
+    for name in {w["golden"] for w in bench.WORKLOADS.values() if w.get("golden")}:
+        g = bench.load_golden(name)
+        levels = [int(v) for v in g["level_dofs"].split()]
+        assert len(g["samples"]) == int(g["samples"].shape[0]) > 0 and g["samples"].shape[1] == 4
+        assert int(g["iterations_fp64"]) == len(g["history_fp64"].split()) - 1
+        assert all(f"bounds.{l}" in g for l in range(1, len(levels)))
+
+
 def test_more_than_one_gpu_is_refused_before_any_gpu_work():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
