@@ -214,6 +214,21 @@ int nnmg_level_assemble_rhs(nnmg_level* level, const double* f_qp_dev, double* b
  * unconstrained rows.  src and dst must not alias.  Asynchronous. */
 int nnmg_vmult(const nnmg_level* level, nnmg_prec prec, const void* src_dev, void* dst_dev, void* stream);
 
+/* nnmg_vmult for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same result, computed by the same kernels in the same order (the
+ * deterministic contribution-slot path, whatever variant the level is tuned
+ * to), with the per-(cell, node) contribution slots kept in one static device
+ * array of 64 MiB per GPU (held from the library's loading until the process
+ * ends) instead of the level's own buffer.  The call allocates nothing and
+ * calls no allocating routine.  Arguments as for nnmg_vmult (one right-hand
+ * side).  Errors: NNMG_ERR_UNSUPPORTED when the level's slots need more than
+ * 64 MiB in this precision (slots x components x 8 or 4 bytes; use
+ * nnmg_vmult), NNMG_ERR_INVALID_ARG as for nnmg_vmult.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (unordered streams
+ * or threads) race and must be serialised by the caller.  Asynchronous. */
+int nnmg_vmult_noalloc(const nnmg_level* level, nnmg_prec prec, const void* src_dev, void* dst_dev, void* stream);
+
 /* dst += A_l src restricted to the unconstrained rows and columns: the cell
  * loop of nnmg_vmult alone (constrained entries of src are read as zero and
  * constrained entries of dst are left unchanged).  One kernel launch; used to

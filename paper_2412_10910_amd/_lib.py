@@ -133,6 +133,7 @@ SIGNATURES = {
     "nnmg_level_assemble_rhs": (C.c_int, [_vp, _vp, _vp, _vp]),
     "nnmg_vmult": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "nnmg_vmult_add": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "nnmg_vmult_noalloc": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "nnmg_vmult_multi": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp]),
     "nnmg_vmult_add_multi": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp]),
     "nnmg_level_diagonal": (C.c_int, [_vp, C.c_int, _vp, _vp]),

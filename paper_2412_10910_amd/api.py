@@ -194,6 +194,16 @@ class Level:
             check(lib().nnmg_vmult_multi(self.handle, _DTYPE_PREC[src.dtype], nr, s, d, _stream()))
         return dst
 
+    def vmult_noalloc(self, src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:
+        """dst = A src (one right-hand side) with the contribution slots in the library's
+        static per-GPU array: the call allocates no device memory (nnmg_vmult_noalloc)."""
+        if dst.dtype != src.dtype or dst.shape != src.shape or src.dim() != 1:
+            raise ValueError("src and dst must be vectors of the same dtype and shape")
+        s = _vec(src, self.n_dofs, self.ctx.device, name="src")
+        d = _vec(dst, self.n_dofs, self.ctx.device, name="dst")
+        check(lib().nnmg_vmult_noalloc(self.handle, _DTYPE_PREC[src.dtype], s, d, _stream()))
+        return dst
+
     def vmult_add(self, src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:
         """dst += A src over the unconstrained rows and columns (one kernel launch)."""
         if dst.dtype != src.dtype or dst.shape != src.shape:

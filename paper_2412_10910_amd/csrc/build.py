@@ -36,6 +36,7 @@ SOURCES = [
     "kernels/vector.hip",
     "kernels/gather.hip",
     "kernels/pmg.hip",
+    "kernels/noalloc.hip",
 ]
 
 ARCH = os.environ.get("NNMG_OFFLOAD_ARCH", "gfx950")

@@ -139,8 +139,12 @@ int nnmg_ctx_create(int device, const nnmg_allocator* allocator, nnmg_ctx** out)
         if (allocator && (!allocator->alloc || !allocator->free))
             fail(NNMG_ERR_INVALID_ARG, "allocator needs both alloc and free");
         NNMG_HIP(hipSetDevice(device));
+        // the static scratch array's device address, taken once per device
+        // with the device current (nnmg_vmult_noalloc uses it)
+        void* scratch = noalloc_scratch_init(device);
         auto* c = new nnmg_ctx();
         c->device = device;
+        c->noalloc_scratch = scratch;
         if (allocator) {
             c->alloc = *allocator;
             c->custom = true;
@@ -251,6 +255,17 @@ static void vmult_impl(const nnmg_level* l, int prec, int nr, const void* src, v
 int nnmg_vmult(const nnmg_level* l, nnmg_prec prec, const void* src, void* dst, void* stream) {
     return guarded([&] {
         vmult_impl(l, prec, 1, src, dst, false, stream);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_vmult_noalloc(const nnmg_level* l, nnmg_prec prec, const void* src, void* dst, void* stream) {
+    return guarded([&] {
+        if (!l || !src || !dst) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (src == dst) fail(NNMG_ERR_INVALID_ARG, "src and dst alias");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        NNMG_HIP(hipSetDevice(l->ctx->device));
+        vmult_noalloc(*l, prec, src, dst, l->ctx->noalloc_scratch, as_stream(stream));
         return NNMG_OK;
     });
 }

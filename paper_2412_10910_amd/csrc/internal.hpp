@@ -36,6 +36,7 @@ struct Ctx {
     int device = 0;
     nnmg_allocator alloc{};
     bool custom = false;
+    void* noalloc_scratch = nullptr;  // device address of this device's static scratch array
     void* allocate(size_t bytes);
     void release(void* p);
 };
@@ -220,6 +221,12 @@ void launch_copy_constrained(const int32_t* idx, size_t n, const void* src, void
 
 // operator apply: dst += A src over the cells (constrained rows untouched)
 void vmult_shape(int dim, int n, int* wg, int* cells_per_block);
+
+// operator application with its contribution slots in a static device array
+// (no allocation; see kernels/noalloc.hip)
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+void* noalloc_scratch_init(int device);  // once per device, with the device current
+void vmult_noalloc(const Level& L, int prec, const void* src, void* dst, void* scratch_dev, hipStream_t s);
 // contrib = the (cell, node) contributions of A src, in DoF-sorted slots
 void launch_vmult_contrib(const Level& L, int prec, const void* src, void* contrib, hipStream_t s, int nr = 1);
 // consumers of a contribution buffer (kernels/gather.hip); constrained rows are not written
