@@ -300,20 +300,21 @@ def recorded_traffic(tag):
 
 def operator_kernel_names(level, word, nr=1):
     """The kernels one operator application (Level.vmult_add) launches, named
-    as the kernel trace names them, for the level's degree and operator variant."""
+    as the kernel trace names them, for the level's degree and operator variant
+    (vmult_kernel<dim, n, T, geometry, scatter, nrt, index layout>), with the
+    operator variant of the precision of that word size."""
     T = "double" if word == 8 else "float"
     n = level.degree + 1
     nrt = 1 if nr == 1 else 0
     if level.operator == "elasticity":
-        return [f"elasticity_kernel<{n}, {T}, {nrt}>", f"gather_kernel<3, {nr}, {T}, nnmg::CsrRuns>"]
-    variant = level.VARIANTS[level.variant]
+        return [f"elasticity_kernel<{n}, {T}, {nrt}>", f"gather_kernel<3, {nr}, {T}>"]
+    import torch
+    variant = level.VARIANTS[level.variant_of(torch.float64 if word == 8 else torch.float32)]
     geo = 1 if variant.startswith("trilinear") else 0
     if variant.endswith("atomic"):
-        return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 1, {nrt}>"]
-    lattice = variant.endswith("lattice")
-    runs = "nnmg::LatticeRuns" if lattice else "nnmg::CsrRuns"
-    return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, {2 if lattice else 0}, {nrt}>",
-            f"gather_kernel<1, {nr}, {T}, {runs}>"]
+        return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 1, {nrt}, 0>"]
+    idx = 1 if variant.endswith("entity") else 0
+    return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 0, {nrt}, {idx}>", f"gather_kernel<1, {nr}, {T}>"]
 
 
 def time_launches(fn, reps):
@@ -583,9 +584,13 @@ def run_pcg_workload(name, args, ctx, nn, torch, steps, warmup, with_cpu):
     t_tune = 0.0
     if not args.no_tune:
         t0 = time.perf_counter()
+        # each precision has its own operator variant: float64 for the plain
+        # method, float32 for the float32 V-cycle
         rep = H.tune(torch.float64, reps=10)
+        rep32 = [lv.tune(torch.float32, reps=10) for lv in H.levels]
         t_tune = time.perf_counter() - t0
-        tuned = dict(levels=[r["chosen"] for r in rep["levels"]],
+        tuned = dict(levels_fp64=[r["chosen"] for r in rep["levels"]],
+                     levels_fp32=[r["chosen"] for r in rep32],
                      restriction_teams=[r["chosen"] for r in rep["transfers"]])
     fine = levels[-1]
     nr = args.rhs if args.rhs is not None else wl.get("rhs", 1)

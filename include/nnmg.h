@@ -308,25 +308,34 @@ typedef struct {
     int chosen;      /* index of the variant now in use */
 } nnmg_tune_result;
 
-/* Times the variants of the level's operator application as the V-cycle uses
- * it (product and the residual that consumes it, reps calls each after two
- * warm-up calls, on a private stream, in `prec`) and keeps the fastest:
+/* Times the variants of the level's operator application in precision `prec`
+ * as the V-cycle uses it (product and the residual that consumes it, reps
+ * calls each after two warm-up calls, on a private stream) and keeps the
+ * fastest for that precision; each precision has its own variant:
  *   0 geometry rebuilt from the trilinear map, contributions in slots
  *   1 geometry rebuilt from the trilinear map, float atomics
  *   2 stored merged metric per Gauss point,    contributions in slots
  *   3 stored merged metric per Gauss point,    float atomics
- * (the elasticity operator has variant 0 only).  The variants differ only
- * in the order of floating-point sums (atomics: an order that varies between
- * runs), the operator being the one of paper §3.2 throughout.  Only the
- * deterministic variants (0 and 2) are timed, so a tuned level stays bitwise
- * reproducible; the others keep ms = -1 and are taken only when forced with
- * nnmg_level_set_variant.  The stored
- * metric is computed when needed and freed when not kept.  Synchronizes the
- * device; hierarchies holding the level re-capture their V-cycle graphs.
- * nnmg_level_set_variant forces a variant, nnmg_level_variant reads it. */
+ *   4 as 0, with entity-compressed indices: per cell one record of the first
+ *     DoF, first contribution slot, writer count and orientation of each of
+ *     its 27 mesh entities instead of one DoF index and one slot per node
+ *   5 as 2, with entity-compressed indices
+ * (variants 4 and 5 exist for 3D Laplace levels of degree >= 3, otherwise
+ * NNMG_ERR_UNSUPPORTED; the elasticity operator has variant 0 only).  The
+ * variants differ only in the order of floating-point sums (atomics: an
+ * order that varies between runs), the operator being the one of paper §3.2
+ * throughout.  Only the deterministic variants (0, 2, 4, 5) are timed, so a
+ * tuned level stays bitwise reproducible; the others keep ms = -1 and are
+ * taken only when forced.  The stored metric is computed when a precision
+ * needs it and freed when none does.  Synchronizes the device; hierarchies
+ * holding the level re-capture their V-cycle graphs.
+ * nnmg_level_set_variant forces a variant for both precisions,
+ * nnmg_level_set_variant_prec for one; nnmg_level_variant reads the variant
+ * of one precision. */
 int nnmg_level_tune(nnmg_level* level, nnmg_prec prec, int reps, nnmg_tune_result* res);
 int nnmg_level_set_variant(nnmg_level* level, int variant);
-int nnmg_level_variant(const nnmg_level* level, int* variant);
+int nnmg_level_set_variant_prec(nnmg_level* level, nnmg_prec prec, int variant);
+int nnmg_level_variant(const nnmg_level* level, nnmg_prec prec, int* variant);
 
 /* Times the restriction (paper §2, eq. residual2) with 4 << v lanes per
  * coarse cell, v = 0..4, and keeps the fastest (same contract as

@@ -167,7 +167,8 @@ SIGNATURES = {
     "nnmg_server_get_stats": (C.c_int, [_vp, C.POINTER(ServerStats)]),
     "nnmg_level_tune": (C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(TuneResult)]),
     "nnmg_level_set_variant": (C.c_int, [_vp, C.c_int]),
-    "nnmg_level_variant": (C.c_int, [_vp, C.POINTER(C.c_int)]),
+    "nnmg_level_set_variant_prec": (C.c_int, [_vp, C.c_int, C.c_int]),
+    "nnmg_level_variant": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int)]),
     "nnmg_transfer_tune": (C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(TuneResult)]),
     "nnmg_transfer_set_team": (C.c_int, [_vp, C.c_int]),
     "nnmg_transfer_team": (C.c_int, [_vp, C.POINTER(C.c_int)]),

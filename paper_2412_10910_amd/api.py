@@ -217,23 +217,34 @@ class Level:
             check(lib().nnmg_vmult_add_multi(self.handle, _DTYPE_PREC[src.dtype], nr, s, d, _stream()))
         return dst
 
-    VARIANTS = ("trilinear+slots", "trilinear+atomic", "metric+slots", "metric+atomic")
+    VARIANTS = ("trilinear+slots", "trilinear+atomic", "metric+slots", "metric+atomic",
+                "trilinear+entity", "metric+entity")
 
     def tune(self, dtype=torch.float32, reps: int = 10) -> dict:
-        """Time the operator variants on this GPU and keep the fastest (nnmg_level_tune)."""
+        """Time the operator variants in `dtype` on this GPU and keep the fastest for
+        that precision (nnmg_level_tune; each precision has its own variant)."""
         res = _lib.TuneResult()
         check(lib().nnmg_level_tune(self.handle, _DTYPE_PREC[dtype], int(reps), C.byref(res)))
         return dict(ms={self.VARIANTS[v]: res.ms[v] for v in range(res.n_variants) if res.ms[v] >= 0},
                     chosen=self.VARIANTS[res.chosen])
 
-    @property
-    def variant(self) -> int:
+    def variant_of(self, dtype) -> int:
+        """The operator variant the `dtype` kernels use (index into VARIANTS)."""
         v = C.c_int()
-        check(lib().nnmg_level_variant(self.handle, C.byref(v)))
+        check(lib().nnmg_level_variant(self.handle, _DTYPE_PREC[dtype], C.byref(v)))
         return v.value
 
-    def set_variant(self, variant: int):
-        check(lib().nnmg_level_set_variant(self.handle, int(variant)))
+    @property
+    def variant(self) -> int:
+        """The float64 operator variant (see variant_of)."""
+        return self.variant_of(torch.float64)
+
+    def set_variant(self, variant: int, dtype=None):
+        """Force an operator variant for one precision, or for both (dtype None)."""
+        if dtype is None:
+            check(lib().nnmg_level_set_variant(self.handle, int(variant)))
+        else:
+            check(lib().nnmg_level_set_variant_prec(self.handle, _DTYPE_PREC[dtype], int(variant)))
 
     def diagonal(self, dtype=torch.float64) -> torch.Tensor:
         out = self.empty(dtype)

@@ -470,15 +470,25 @@ int nnmg_level_tune(nnmg_level* level, nnmg_prec prec, int reps, nnmg_tune_resul
 int nnmg_level_set_variant(nnmg_level* level, int variant) {
     return guarded([&] {
         if (!level) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
-        level_set_variant(*level, variant);
+        level_set_variant(*level, -1, variant);
         return NNMG_OK;
     });
 }
 
-int nnmg_level_variant(const nnmg_level* level, int* variant) {
+int nnmg_level_set_variant_prec(nnmg_level* level, nnmg_prec prec, int variant) {
+    return guarded([&] {
+        if (!level) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        level_set_variant(*level, prec, variant);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_level_variant(const nnmg_level* level, nnmg_prec prec, int* variant) {
     return guarded([&] {
         if (!level || !variant) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
-        *variant = level_variant(*level);
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        *variant = level_variant(*level, prec);
         return NNMG_OK;
     });
 }

@@ -245,7 +245,7 @@ static void op_cheb_step(Hierarchy& H, int l, int prec, const void* f, const voi
                          double c2, bool first, int nr, hipStream_t s) {
     Level& L = *H.levels[l];
     WorkVectors& w = H.work[prec][l];
-    if (L.atomic_scatter) {
+    if (L.var[prec].atomic) {
         launch_vmult_cells(L, prec, x, w.ax.ptr, s, nr, w.contrib.ptr);
         launch_cheb_step(prec, (size_t)L.n_dofs, f, w.ax.ptr, dinv, x, w.d.ptr, first ? 0.0 : c1, c2, s, nr);
     } else {
@@ -258,7 +258,7 @@ static void op_cheb_step(Hierarchy& H, int l, int prec, const void* f, const voi
 static void op_residual(Hierarchy& H, int l, int prec, const void* f, const void* x, void* r, int nr, hipStream_t s) {
     Level& L = *H.levels[l];
     WorkVectors& w = H.work[prec][l];
-    if (L.atomic_scatter) {
+    if (L.var[prec].atomic) {
         launch_vmult_cells(L, prec, x, w.ax.ptr, s, nr, w.contrib.ptr);
         launch_residual(prec, (size_t)L.n_dofs * (size_t)nr, f, w.ax.ptr, r, s);
     } else {
@@ -594,7 +594,7 @@ struct PcgTask {
     void iteration_body() {
         double* sc = H.scal.ptr;
         Level& lv = L();
-        if (lv.atomic_scatter) {
+        if (lv.var[NNMG_FP64].atomic) {
             launch_fill(H.qv.ptr, nv, NNMG_FP64, s);
             launch_vmult_cells(lv, NNMG_FP64, H.p.ptr, H.qv.ptr, s, nr, H.work[NNMG_FP64][top()].contrib.ptr);
             launch_dot(H.p.ptr, H.qv.ptr, n, H.partial.ptr, sc + 1, s, nr, kScal, sc, 0);

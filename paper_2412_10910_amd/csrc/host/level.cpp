@@ -217,6 +217,132 @@ static void number_dofs(Level& L, const std::vector<int64_t>& visit) {
     L.n_nodes = next;
 }
 
+// Entity-compressed operator indices (layout in Level::d_ent_rec).  The DoFs
+// of every mesh entity are contiguous in a canonical orientation (see
+// number_dofs), so a cell needs one DoF base and one orientation code per
+// entity instead of one index per local node.  The orientation is found by
+// trying the codes against the cell's DoF map, so the record reproduces the
+// map exactly whatever the numbering rule.  The x-face between consecutive
+// cells of a block is merged (summed in the kernel before the store) where
+// every line of the two cells meets on it, and the slots are laid out
+// DoF-major with one slot per writing cell in visiting order, so the slot
+// offsets stay sorted by DoF and every sum keeps a fixed order.  Returns
+// false, leaving the level on the per-node layout, where the mesh does not fit
+// the record: an entity with constrained and unconstrained nodes, no code
+// reproducing the map, or more than 15 writers of one entity.
+static bool build_entity_records(const Level& L, std::vector<int32_t>& rec, std::vector<int32_t>& off) {
+    const int n = L.n, k = L.degree, ke = k - 1, q = L.q, cpb = L.cpb;
+    struct Node {
+        int a, u, v, w;
+    };
+    std::vector<Node> nodes[27];
+    int edim[27] = {};
+    for (int a = 0; a < q; ++a) {
+        const int id[3] = {a % n, (a / n) % n, a / (n * n)};
+        int cls[3], loc[3] = {0, 0, 0}, m = 0;
+        for (int d = 0; d < 3; ++d) {
+            cls[d] = id[d] == 0 ? 0 : (id[d] == k ? 2 : 1);
+            if (cls[d] == 1) loc[m++] = id[d] - 1;
+        }
+        const int e = cls[0] + 3 * cls[1] + 9 * cls[2];
+        nodes[e].push_back({a, loc[0], loc[1], loc[2]});
+        edim[e] = m;
+    }
+    auto canon = [&](const Node& nd, int o) {
+        int u = (o & 1) ? ke - 1 - nd.u : nd.u;
+        int v = (o & 2) ? ke - 1 - nd.v : nd.v;
+        if (o & 4) std::swap(u, v);
+        return u + ke * (v + ke * nd.w);
+    };
+    const int64_t P = L.nblocks * cpb;
+    std::vector<int32_t> base((size_t)(P * 27), -1), rank((size_t)(P * 27), -1);
+    std::vector<uint8_t> orient((size_t)(P * 27), 0), flags((size_t)P, 0);
+    std::vector<int32_t> ndof_at((size_t)L.n_nodes, 0);
+    for (int64_t p = 0; p < P; ++p) {
+        const int64_t c = L.order[(size_t)p];
+        if (c < 0) continue;
+        const int32_t* dm = &L.dofmap[(size_t)(c * q)];
+        for (int e = 0; e < 27; ++e) {
+            int32_t b = INT32_MAX;
+            int ncons = 0;
+            for (const Node& nd : nodes[e]) {
+                b = std::min(b, dm[nd.a]);
+                ncons += L.constrained[(size_t)dm[nd.a]];
+            }
+            if (ncons != 0 && ncons != (int)nodes[e].size()) return false;
+            const int no = edim[e] == 1 ? 2 : (edim[e] == 2 ? 8 : 1);
+            int found = -1;
+            for (int o = 0; o < no && found < 0; ++o) {
+                bool same = true;
+                for (const Node& nd : nodes[e])
+                    if (dm[nd.a] != b + canon(nd, o)) {
+                        same = false;
+                        break;
+                    }
+                if (same) found = o;
+            }
+            if (found < 0) return false;
+            base[(size_t)(p * 27 + e)] = b;
+            orient[(size_t)(p * 27 + e)] = (uint8_t)found;
+            ndof_at[(size_t)b] = (int32_t)nodes[e].size();
+        }
+        // merge with the previous cell of the block across a shared x-face
+        if (p % cpb > 0 && L.order[(size_t)(p - 1)] >= 0) {
+            const int32_t* dp = &L.dofmap[(size_t)(L.order[(size_t)(p - 1)] * q)];
+            bool same = true;
+            for (int line = 0; line < n * n && same; ++line) same = dp[k + n * line] == dm[n * line];
+            if (same) {
+                flags[(size_t)(p - 1)] |= 2;
+                flags[(size_t)p] |= 1;
+            }
+        }
+    }
+    // writers of every entity, ranked in visiting order
+    std::vector<int32_t> cnt((size_t)L.n_nodes, 0);
+    for (int64_t p = 0; p < P; ++p) {
+        if (L.order[(size_t)p] < 0) continue;
+        for (int e = 0; e < 27; ++e) {
+            const int32_t b = base[(size_t)(p * 27 + e)];
+            if (L.constrained[(size_t)b]) continue;
+            if (e % 3 == 0 && (flags[(size_t)p] & 1)) continue;  // added by the previous cell
+            rank[(size_t)(p * 27 + e)] = cnt[(size_t)b]++;
+            if (cnt[(size_t)b] > 15) return false;
+        }
+    }
+    off.assign((size_t)L.n_nodes + 1, 0);
+    int64_t cur = 0;
+    for (int64_t d = 0; d < L.n_nodes;) {
+        const int nd = ndof_at[(size_t)d];
+        if (nd <= 0) return false;  // not the first DoF of an entity: numbering not entity-contiguous
+        const int c = L.constrained[(size_t)d] ? 0 : cnt[(size_t)d];
+        for (int t = 0; t < nd; ++t) off[(size_t)(d + t)] = (int32_t)(cur + (int64_t)t * c);
+        cur += (int64_t)nd * c;
+        if (cur >= (int64_t)kMergeNext) return false;
+        d += nd;
+    }
+    off[(size_t)L.n_nodes] = (int32_t)cur;
+    rec.assign((size_t)(L.nblocks * kEntWords * cpb), 0);
+    for (int64_t p = 0; p < P; ++p) {
+        const int64_t blk = p / cpb, cell = p % cpb;
+        auto W = [&](int w) -> int32_t& { return rec[(size_t)((blk * kEntWords + w) * cpb + cell)]; };
+        if (L.order[(size_t)p] < 0) {
+            for (int e = 0; e < 27; ++e) W(e) = W(27 + e) = -1;
+            continue;
+        }
+        for (int e = 0; e < 27; ++e) {
+            const int32_t b = base[(size_t)(p * 27 + e)];
+            const bool cons = L.constrained[(size_t)b] != 0;
+            const int32_t r = rank[(size_t)(p * 27 + e)];
+            W(e) = cons ? -1 : b;
+            W(27 + e) = (cons || r < 0) ? -1 : off[(size_t)b] + r;
+            const int32_t code = (cons ? 0 : cnt[(size_t)b]) | (orient[(size_t)(p * 27 + e)] << 4);
+            W(54 + e / 4) |= code << (8 * (e % 4));
+        }
+        W(61) = flags[(size_t)p];
+    }
+    return true;
+}
+
 static void find_constraints(Level& L, const uint8_t* dirichlet) {
     const int dim = L.dim, k = L.degree, n = L.n, q = L.q, nv = 1 << dim;
     const int64_t C = L.n_cells;
@@ -403,9 +529,22 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree, const nnmg_leve
             L->d_inv_off.upload(ctx, off);
             L->d_pos_blk.upload(ctx, pos);
             L->contrib_len = (size_t)off[(size_t)L->n_nodes];
-            // ncomp values per slot: component c of slot k at ncomp * k + c
-            L->d_contrib.alloc(ctx, std::max<size_t>(L->contrib_len * L->ncomp, 1) * sizeof(double));
         }
+        // the entity-compressed indices of the same operator (3D Laplace,
+        // degree >= 3, where a cell has far more nodes than entities)
+        if (dim == 3 && L->op == NNMG_OP_LAPLACE && degree >= 3) {
+            std::vector<int32_t> rec, off2;
+            if (build_entity_records(*L, rec, off2)) {
+                L->d_ent_rec.upload(ctx, rec);
+                L->d_inv_off_ent.upload(ctx, off2);
+                L->contrib_len = std::max(L->contrib_len, (size_t)off2[(size_t)L->n_nodes]);
+                const char* ix = std::getenv("NNMG_INDEX");
+                if (ix && std::string(ix) == "entity") L->var[0].index_layout = L->var[1].index_layout = 1;
+            }
+        }
+        // ncomp values per slot: component c of slot k at ncomp * k + c (sized
+        // for the larger of the two index layouts)
+        L->d_contrib.alloc(ctx, std::max<size_t>(L->contrib_len * L->ncomp, 1) * sizeof(double));
         L->d_constrained.upload(ctx, L->constrained_idx);
         std::vector<double> cv((size_t)(L->n_cells * nv * dim));
         for (int64_t c = 0; c < L->n_cells; ++c)
@@ -478,10 +617,13 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree, const nnmg_leve
         L->d_coef32.upload(ctx, coef32);
         const char* mode = std::getenv("NNMG_GEOMETRY");
         // the elasticity operator rebuilds J from the map coefficients
-        L->geometry_mode = (mode && std::string(mode) == "metric" && L->op == NNMG_OP_LAPLACE) ? 0 : 1;
         const char* scatter = std::getenv("NNMG_SCATTER");
-        L->atomic_scatter = scatter && std::string(scatter) == "atomic" && L->op == NNMG_OP_LAPLACE;
-        if (L->geometry_mode == 1) {
+        for (auto& vr : L->var) {
+            vr.geometry_mode = (mode && std::string(mode) == "metric" && L->op == NNMG_OP_LAPLACE) ? 0 : 1;
+            vr.atomic = scatter && std::string(scatter) == "atomic" && L->op == NNMG_OP_LAPLACE;
+            if (vr.atomic) vr.index_layout = 0;
+        }
+        if (L->var[0].geometry_mode == 1) {
             NNMG_HIP(hipDeviceSynchronize());
             L->d_metric64.reset();
             L->d_metric32.reset();

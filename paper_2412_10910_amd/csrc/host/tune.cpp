@@ -7,12 +7,18 @@
 //   1  geometry rebuilt from the trilinear map, float atomics into the output
 //   2  stored merged metric per Gauss point,    contributions in slots + gather
 //   3  stored merged metric per Gauss point,    float atomics into the output
-// The elasticity operator has variant 0 only.  Transfer variants: the lanes
+//   4  as 0, with the entity-compressed indices (one record per cell)
+//   5  as 2, with the entity-compressed indices
+// Variants 4 and 5 exist for 3D Laplace levels of degree >= 3 (where the
+// records were built).  The elasticity operator has variant 0 only.  Transfer variants: the lanes
 // per coarse cell of the restriction, 4 << v for v = 0..4.
+//
+// Each precision has its own variant: the float64 and float32 kernels of one
+// level are timed and chosen separately.
 //
 // Every choice changes only the order in which floating-point sums are formed
 // (atomics: an order that varies from run to run), never what is summed.  The
-// tuner times the deterministic variants only (0 and 2), so that a tuned
+// tuner times the deterministic variants only (0, 2, 4, 5), so that a tuned
 // hierarchy stays bitwise reproducible; the atomic ones are an explicit opt-in
 // through level_set_variant.
 #include <algorithm>
@@ -70,14 +76,29 @@ void ensure_metric(Level& L) {
     NNMG_HIP(hipDeviceSynchronize());
 }
 
-void apply_variant(Level& L, int v) {
+bool has_entity_variants(const Level& L) { return L.d_ent_rec.ptr != nullptr; }
+
+Level::OpVariant variant_state(int v) {
+    Level::OpVariant s;
+    s.geometry_mode = (v == 2 || v == 3 || v == 5) ? 0 : 1;
+    s.atomic = v == 1 || v == 3;
+    s.index_layout = v >= 4 ? 1 : 0;
+    return s;
+}
+
+// prec: NNMG_FP64, NNMG_FP32, or -1 for both
+void apply_variant(Level& L, int prec, int v) {
     if (L.op != NNMG_OP_LAPLACE && v != 0) fail(NNMG_ERR_UNSUPPORTED, "the elasticity operator has variant 0 only");
-    if (v < 0 || v > 3) fail(NNMG_ERR_INVALID_ARG, "operator variant must be in 0..3");
+    if (v < 0 || v > 5) fail(NNMG_ERR_INVALID_ARG, "operator variant must be in 0..5");
+    if (v >= 4 && !has_entity_variants(L))
+        fail(NNMG_ERR_UNSUPPORTED, "variants 4 and 5 (entity-compressed indices) need a 3D Laplace level of degree >= 3");
     NNMG_HIP(hipDeviceSynchronize());  // launches of the previous variant may be in flight
-    if (v >= 2) ensure_metric(L);
-    L.geometry_mode = v >= 2 ? 0 : 1;
-    L.atomic_scatter = (v & 1) != 0;
-    if (L.geometry_mode == 1) {
+    const Level::OpVariant st = variant_state(v);
+    if (st.geometry_mode == 0) ensure_metric(L);
+    for (int p = 0; p < 2; ++p)
+        if (prec < 0 || prec == p) L.var[p] = st;
+    if (L.var[0].geometry_mode == 1 && L.var[1].geometry_mode == 1) {
+        // no precision reads the stored metric any more
         L.d_metric64.reset();
         L.d_metric32.reset();
     }
@@ -86,18 +107,22 @@ void apply_variant(Level& L, int v) {
 
 }  // namespace
 
-int level_variant(const Level& L) { return (L.geometry_mode == 0 ? 2 : 0) + (L.atomic_scatter ? 1 : 0); }
+int level_variant(const Level& L, int prec) {
+    const Level::OpVariant& s = L.var[prec];
+    if (s.index_layout == 1) return s.geometry_mode == 0 ? 5 : 4;
+    return (s.geometry_mode == 0 ? 2 : 0) + (s.atomic ? 1 : 0);
+}
 
-void level_set_variant(Level& L, int v) {
+void level_set_variant(Level& L, int prec, int v) {
     NNMG_HIP(hipSetDevice(L.ctx->device));
-    apply_variant(L, v);
+    apply_variant(L, prec, v);
 }
 
 void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res) {
     if (reps < 1) fail(NNMG_ERR_INVALID_ARG, "reps must be positive");
     NNMG_HIP(hipSetDevice(L.ctx->device));
     const size_t n = (size_t)L.n_dofs;
-    const int nvar = L.op == NNMG_OP_LAPLACE ? 4 : 1;
+    const int nvar = L.op != NNMG_OP_LAPLACE ? 1 : (has_entity_variants(L) ? 6 : 4);
     hipStream_t s;
     NNMG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     try {
@@ -113,22 +138,17 @@ void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res) {
         for (double& t : res->ms) t = -1.0;
         int best = 0;
         for (int v = 0; v < nvar; ++v) {
-            if (v & 1) continue;  // float atomics: not reproducible, never picked by the tuner
-            apply_variant(L, v);
+            if (v == 1 || v == 3) continue;  // float atomics: not reproducible, never picked by the tuner
+            apply_variant(L, prec, v);
             res->ms[v] = time_ms(
                 [&](hipStream_t st) {
-                    if (L.atomic_scatter) {
-                        launch_vmult_cells(L, prec, x.ptr, ax.ptr, st);
-                        launch_residual(prec, n, f.ptr, ax.ptr, r.ptr, st);
-                    } else {
-                        launch_vmult_contrib(L, prec, x.ptr, L.d_contrib.ptr, st);
-                        launch_residual_gather(L, prec, L.d_contrib.ptr, f.ptr, r.ptr, st);
-                    }
+                    launch_vmult_contrib(L, prec, x.ptr, L.d_contrib.ptr, st);
+                    launch_residual_gather(L, prec, L.d_contrib.ptr, f.ptr, r.ptr, st);
                 },
                 reps, s);
             if (res->ms[v] < res->ms[best]) best = v;
         }
-        apply_variant(L, best);
+        apply_variant(L, prec, best);
         res->chosen = best;
     } catch (...) {
         (void)hipStreamSynchronize(s);

@@ -129,8 +129,7 @@ struct Level {
 
     DeviceArray<int32_t> d_dofmap;      // [C][q], -1 for constrained DoFs
     DeviceArray<int32_t> d_dofmap_blk;  // operator layout [blk][n][wg], -1 for constrained / padding
-    int geometry_mode = 1;              // 0: stored metric per Gauss point, 1: trilinear coefficients
-    DeviceArray<double> d_metric64;     // operator layout [blk][M][n][wg] (kept after setup in mode 0)
+    DeviceArray<double> d_metric64;     // operator layout [blk][M][n][wg] (kept while a precision reads it)
     DeviceArray<float> d_metric32;
     DeviceArray<double> d_coef64;       // [blk][NC][cpb] Q1 map coefficients (mode 1)
     DeviceArray<float> d_coef32;
@@ -138,14 +137,39 @@ struct Level {
     DeviceArray<int32_t> d_constrained;
     std::vector<int32_t> order;         // [nblocks * cpb] cell at each block position, -1 = padding
     DeviceArray<int32_t> d_order;
-    DeviceArray<int32_t> d_inv_off;     // [N+1] contributions of DoF i: contrib[off[i] .. off[i+1])
+    DeviceArray<int32_t> d_inv_off;     // [N+1] contributions of DoF i: contrib[off[i] .. off[i+1]) (per-node layout)
     DeviceArray<int32_t> d_pos_blk;     // operator layout: contribution slot of each (lane, node), -1 = none,
                                         // | kMergeNext: add the next cell's first node of the line first
-    size_t contrib_len = 0;             // number of contribution slots
+    // Entity-compressed operator indices (3D Laplace, degree >= 3; see
+    // build_entity_records in host/level.cpp).  Every local node of a cell
+    // lies on one of its 27 mesh entities (8 vertices, 12 edges, 6 faces, the
+    // interior), whose DoFs are numbered contiguously in a canonical
+    // orientation and whose contribution slots are laid out DoF-major with one
+    // slot per writing cell.  Per block position a record of kEntWords words:
+    //   [0, 27)   D_e: first DoF of entity e (-1: constrained)
+    //   [27, 54)  SR_e: first slot of entity e + this cell's rank among its
+    //             writers (-1: constrained, or added by the previous cell)
+    //   [54, 61)  8 bits per entity (4 per word): bits 0-3 the number of
+    //             writers c_e, bits 4-6 the orientation (1: reverse the first
+    //             entity axis, 2: reverse the second, 4: swap them)
+    //   61        flags: 1 = the x-min face is added by the previous cell of
+    //             the block, 2 = this cell adds the next cell's x-min face
+    // Node (local coordinates u, v, w on its entity) then has DoF D_e + m and
+    // slot SR_e + m c_e, with m the canonical index of (u, v, w).
+    DeviceArray<int32_t> d_ent_rec;     // [blk][kEntWords][cpb]
+    DeviceArray<int32_t> d_inv_off_ent; // [N+1] slot offsets of the entity layout
+    size_t contrib_len = 0;             // number of contribution slots (the larger of the two layouts)
     DeviceArray<char> d_contrib;        // contribution buffer of the level's own operator calls
     int contrib_rhs = 1;                // right-hand sides d_contrib holds (grown on demand)
     int config_version = 0;             // bumped when the autotuner changes the kernel variant
-    bool atomic_scatter = false;        // float atomics into the output instead of contribution slots
+    // operator variant of each precision ([NNMG_FP64], [NNMG_FP32]; host/tune.cpp)
+    struct OpVariant {
+        int geometry_mode = 1;  // 0: stored metric per Gauss point, 1: trilinear coefficients
+        bool atomic = false;    // float atomics into the output instead of contribution slots
+        int index_layout = 0;   // 0: per-node indices and slots (d_dofmap_blk, d_pos_blk), 1: entity records
+    } var[2];
+    // the slot offsets the consumers of a `prec` operator product read
+    const int32_t* inv_off(int prec) const { return var[prec].index_layout ? d_inv_off_ent.ptr : d_inv_off.ptr; }
     DeviceArray<double> d_diag64;       // operator diagonal, 1 on constrained
     DeviceArray<double> d_dinv64;       // inverse diagonal, 0 on constrained
     DeviceArray<float> d_dinv32;
@@ -197,12 +221,13 @@ void level_reserve_rhs(Level& l, int nr);
 void transfer_reserve_rhs(Transfer& t, int nr);
 
 // autotuner (host/tune.cpp)
-int level_variant(const Level& L);
-void level_set_variant(Level& L, int v);
+int level_variant(const Level& L, int prec);
+void level_set_variant(Level& L, int prec, int v);  // prec -1: both precisions
 void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res);
 void transfer_set_team(Transfer& T, int team);
 void transfer_tune(Transfer& T, int prec, int reps, nnmg_tune_result* res);
 constexpr int32_t kMergeNext = 1 << 30;  // flag in a contribution slot index (see Level::d_pos_blk)
+constexpr int kEntWords = 62;            // words per cell of the entity-compressed operator indices
 constexpr int kWaveLanes = 64;           // CDNA wavefront width  // points per block of the point-parallel transfer kernels
 
 void transfer_retain(Transfer* t);

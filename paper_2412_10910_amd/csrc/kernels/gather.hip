@@ -159,7 +159,7 @@ void launch_gather_runs(size_t n, int ncomp, const int32_t* off, int prec, const
 size_t contrib_plane(const Level& L) { return L.contrib_len * (size_t)L.ncomp; }
 
 void launch_gather(const Level& L, int prec, const void* elem, void* dst, bool accumulate, hipStream_t s, int nr) {
-    launch_gather_runs((size_t)L.n_dofs, L.ncomp, L.d_inv_off.ptr, prec, elem, contrib_plane(L), dst, accumulate, s,
+    launch_gather_runs((size_t)L.n_dofs, L.ncomp, L.inv_off(prec), prec, elem, contrib_plane(L), dst, accumulate, s,
                        nr);
 }
 
@@ -191,11 +191,11 @@ void launch_cheb_step_gather(const Level& L, int prec, const void* elem, const v
     NNMG_NV_DISPATCH(L.ncomp, nr, {
         if (prec == NNMG_FP64)
             hipLaunchKernelGGL((cheb_step_gather_kernel<NC, NR, double>), grid_n(n), dim3(256), 0, s, n,
-                               L.d_inv_off.ptr, (const double*)elem, contrib_plane(L), (const double*)f,
+                               L.inv_off(prec), (const double*)elem, contrib_plane(L), (const double*)f,
                                (const double*)dinv, (double*)x, (double*)d, c1, c2, (int)first);
         else
             hipLaunchKernelGGL((cheb_step_gather_kernel<NC, NR, float>), grid_n(n), dim3(256), 0, s, n,
-                               L.d_inv_off.ptr, (const float*)elem, contrib_plane(L), (const float*)f,
+                               L.inv_off(prec), (const float*)elem, contrib_plane(L), (const float*)f,
                                (const float*)dinv, (float*)x, (float*)d, (float)c1, (float)c2, (int)first);
     });
     NNMG_HIP(hipGetLastError());
@@ -218,10 +218,10 @@ void launch_residual_gather(const Level& L, int prec, const void* elem, const vo
     NNMG_NV_DISPATCH(L.ncomp, nr, {
         if (prec == NNMG_FP64)
             hipLaunchKernelGGL((residual_gather_kernel<NC, NR, double>), grid_n(n), dim3(256), 0, s, n,
-                               L.d_inv_off.ptr, (const double*)elem, contrib_plane(L), (const double*)f, (double*)r);
+                               L.inv_off(prec), (const double*)elem, contrib_plane(L), (const double*)f, (double*)r);
         else
             hipLaunchKernelGGL((residual_gather_kernel<NC, NR, float>), grid_n(n), dim3(256), 0, s, n,
-                               L.d_inv_off.ptr, (const float*)elem, contrib_plane(L), (const float*)f, (float*)r);
+                               L.inv_off(prec), (const float*)elem, contrib_plane(L), (const float*)f, (float*)r);
     });
     NNMG_HIP(hipGetLastError());
 }
@@ -272,7 +272,7 @@ void launch_gather_dot(const Level& L, const double* elem, const double* p, doub
     const size_t n = (size_t)L.n_dofs;
     const size_t g = dot_partials(n);
     NNMG_NV_DISPATCH(L.ncomp, nr, {
-        hipLaunchKernelGGL((gather_dot_kernel<NC, NR>), dim3((unsigned)g), dim3(kRed), 0, s, n, L.d_inv_off.ptr,
+        hipLaunchKernelGGL((gather_dot_kernel<NC, NR>), dim3((unsigned)g), dim3(kRed), 0, s, n, L.inv_off(NNMG_FP64),
                            elem, contrib_plane(L), p, q, partial);
     });
     launch_sum_partials(partial, g, out, s, nr, kScal, scal, scalar_op);

@@ -88,6 +88,8 @@ constexpr int kStoredMetric = 0;
 constexpr int kTrilinear = 1;
 constexpr int kSlots = 0;
 constexpr int kAtomic = 1;
+constexpr int kIdxNodes = 0;   // per-node DoF indices and slots, dofmap_blk / pos_blk
+constexpr int kIdxEntity = 1;  // one record of entity bases and slot bases per cell
 
 #ifndef NNMG_VMULT_MINWAVES
 #define NNMG_VMULT_MINWAVES 1
@@ -100,8 +102,26 @@ constexpr int kAtomic = 1;
 // would write partial cache lines); the atomic variant adds into the
 // interleaved output vector.  NRT = 1 fixes nr = 1 at
 // compile time (the loop disappears); NRT = 0 takes nr_in.
-template <int DIM, int N, class T, int GEO, int SCATTER, int NRT>
-__global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vmult_kernel(const int32_t* __restrict__ dmap,
+//
+// Index layouts (IDX).  kIdxNodes reads each lane's N DoF indices and N slots
+// from dofmap_blk / slots.  kIdxEntity reads one record per cell, in the block
+// layout rec[(blk * kEntWords + word) * CPB + cell]: the first DoF D_e and the
+// first slot (plus the cell's rank) SR_e of each of the cell's 27 mesh
+// entities, 8 bits of writer count and orientation per entity, and the x-face
+// merge flags.  The block's records go through LDS, and each lane derives its
+// nodes' DoFs D_e + m and slots SR_e + m c_e from the canonical index m of the
+// node on its entity: a record of 62 words per cell instead of 2 q words
+// (q = 64 at Q3, 125 at Q4).
+// waves per SIMD the register allocation must allow: 4 for the float64 Q3
+// single-vector kernel with entity records (it would otherwise take 150
+// VGPRs, 3 waves; at 128 it spills 5)
+template <int N, class T, int NRT, int IDX>
+constexpr int vmult_min_waves() {
+    return (IDX == 1 && N == 4 && sizeof(T) == 8 && NRT == 1) ? 4 : NNMG_VMULT_MINWAVES;
+}
+
+template <int DIM, int N, class T, int GEO, int SCATTER, int NRT, int IDX = kIdxNodes>
+__global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, IDX>())) void vmult_kernel(const int32_t* __restrict__ dmap,
                                                                     const T* __restrict__ geo,
                                                                     const T* __restrict__ src,
                                                                     const int32_t* __restrict__ slots,
@@ -128,15 +148,26 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
     // lane's line, the cell's map coefficients and the 1D tables (both bound
     // for LDS), then the source gathers, which wait only for the indices; the
     // LDS stores come last so that no load waits behind them.
-    const int32_t* dm = dmap + b * (N * WG) + lane;
+    static_assert(IDX == kIdxNodes || (DIM == 3 && SCATTER == kSlots && N >= 3),
+                  "entity records: 3D, contribution slots");
     int32_t idx[N], slot[N];
     T u[N], v[N];
+    constexpr int EW = kEntWords;
+    constexpr int RE = IDX == kIdxEntity ? (EW * CPB + WG - 1) / WG : 1;  // record words per lane
+    int32_t rv[RE];
+    if constexpr (IDX == kIdxEntity) {
+        const int32_t* gr = dmap + b * (EW * CPB);
 #pragma unroll
-    for (int i = 0; i < N; ++i) idx[i] = dm[i * WG];
-    if constexpr (SCATTER == kSlots) {
-        const int32_t* ps = slots + b * (N * WG) + lane;
+        for (int r = 0; r < RE; ++r) rv[r] = lane + r * WG < EW * CPB ? gr[lane + r * WG] : 0;
+    } else {
+        const int32_t* dm = dmap + b * (N * WG) + lane;
 #pragma unroll
-        for (int i = 0; i < N; ++i) slot[i] = ps[i * WG];
+        for (int i = 0; i < N; ++i) idx[i] = dm[i * WG];
+        if constexpr (SCATTER == kSlots) {
+            const int32_t* ps = slots + b * (N * WG) + lane;
+#pragma unroll
+            for (int i = 0; i < N; ++i) slot[i] = ps[i * WG];
+        }
     }
     // the cell's map coefficients: each lane turns them into the constants of
     // its line just before the geometry step, so they hold no registers
@@ -163,6 +194,51 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
 #pragma unroll
     for (int e = 0; e < TE; ++e)
         tv[e] = lane + e * WG < NT ? reinterpret_cast<const T*>(&tb)[lane + e * WG] : T(0);
+    // Entity records (IDX == kIdxEntity): node i of the lane's line has classes
+    // (cx, cy, cz) in {0: first, 1: inside, 2: last} per direction, lies on
+    // entity e = cx + 3 cy + 9 cz, and has local coordinates (u, v, w) = its
+    // indices - 1 along the entity's own (inside) directions in x, y, z order;
+    // the record's orientation code maps them to the canonical index m.  The
+    // DoFs are decoded here, the slots only at the store, so that they hold no
+    // registers during the sweeps.
+    __shared__ int32_t lrec[IDX == kIdxEntity ? CPB : 1][IDX == kIdxEntity ? EW : 1];
+    constexpr int K1 = N - 2;  // DoFs along an edge
+    const int ecy = j == 0 ? 0 : (j == N - 1 ? 2 : 1);
+    const int ecz = t == 0 ? 0 : (t == N - 1 ? 2 : 1);
+    const int ea = ecy == 1 ? j - 1 : (ecz == 1 ? t - 1 : 0);
+    const int eb = (ecy == 1 && ecz == 1) ? t - 1 : 0;
+    auto ent_node = [&](int i, int& e, int& m, int& code) {
+        const int cx = i == 0 ? 0 : (i == N - 1 ? 2 : 1);
+        e = cx + 3 * ecy + 9 * ecz;
+        const int eu = cx == 1 ? i - 1 : ea;
+        const int ev = cx == 1 ? ea : eb;
+        const int ew = cx == 1 ? eb : 0;
+        code = (lrec[cb][54 + (e >> 2)] >> ((e & 3) * 8)) & 0xff;
+        int u1 = (code & 16) ? K1 - 1 - eu : eu;
+        int v1 = (code & 32) ? K1 - 1 - ev : ev;
+        if (code & 64) {
+            const int tmp = u1;
+            u1 = v1;
+            v1 = tmp;
+        }
+        m = u1 + K1 * (v1 + K1 * ew);
+    };
+    if constexpr (IDX == kIdxEntity) {
+        // the block's records to LDS, transposed to [cell][word]
+#pragma unroll
+        for (int r = 0; r < RE; ++r) {
+            const int wd = lane + r * WG;
+            if (wd < EW * CPB) lrec[wd % CPB][wd / CPB] = rv[r];
+        }
+        block_sync<WG>();
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            int e, m, code;
+            ent_node(i, e, m, code);
+            const int32_t D = lrec[cb][e];
+            idx[i] = (act && D >= 0) ? D + m : -1;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < N; ++i) u[i] = idx[i] >= 0 ? src[(int64_t)idx[i] * nr] : T(0);
     if constexpr (GEO == kTrilinear) {
@@ -193,8 +269,8 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
         for (int i = 0; i < N; ++i) un[i] = idx[i] >= 0 ? src[(int64_t)idx[i] * nr + rhs + 1] : T(0);
     }
     // ---- forward --------------------------------------------------------
+    T gx[N], gy[N], gz[N];  // reference gradient at the Gauss points of the line (2D: x, gz = y)
     line_apply<N, T, false>(tb.S, u, v);  // x: nodes -> Gauss points
-    T gz[N];                              // derivative along the last direction
     if constexpr (DIM == 3) {
         // y: interpolate
         if (act) {
@@ -249,7 +325,6 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
         }
     }
     // v: values at the Gauss points of the line; x (and y) derivatives
-    T gx[N], gy[N];
     line_apply<N, T, false>(tb.D, v, gx);
     if constexpr (DIM == 3) {
         if (act) {
@@ -265,6 +340,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
             gy[i] = s;
         }
     }
+
 
     // ---- geometry at the Gauss points of the line ------------------------
     if constexpr (GEO == kStoredMetric) {
@@ -417,8 +493,28 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), NNMG_VMULT_MINWAVES) void vm
     line_apply<N, T, true>(tb.S, u, v);  // x: S^T
     if constexpr (SCATTER == kSlots) {
         // the next cell's first node of this line, added here where setup found
-        // it to be the same DoF as this line's last node (same wavefront)
-        const T nxt = __shfl_down(v[0], L, kWave);
+        // it to be the same DoF as this line's last node (per-node layout: in
+        // the same wavefront; entity records of blocks wider than a wavefront:
+        // through LDS, for every pair of cells of the block)
+        if constexpr (IDX == kIdxEntity) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                int e, m, code;
+                ent_node(i, e, m, code);
+                const int32_t SR = lrec[cb][27 + e];
+                slot[i] = (act && SR >= 0) ? SR + m * (code & 15) : -1;
+            }
+            if ((lrec[cb][EW - 1] & 2) && slot[N - 1] >= 0) slot[N - 1] |= kMergeNext;
+        }
+        T nxt;
+        if constexpr (IDX == kIdxEntity && WG > kWave) {
+            __shared__ T lxm[CPB][L];
+            if (act) lxm[cb][line] = v[0];
+            block_sync<WG>();
+            nxt = (act && cb + 1 < CPB) ? lxm[cb + 1][line] : T(0);
+        } else {
+            nxt = __shfl_down(v[0], L, kWave);
+        }
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             int32_t k = slot[i];
@@ -752,6 +848,17 @@ static void vmult_launches(const Level& L, const T* geo, bool atomic, const void
         else
             hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kAtomic, 0>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
                                (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane);
+    } else if (L.var[sizeof(T) == 8 ? NNMG_FP64 : NNMG_FP32].index_layout == 1) {
+        if constexpr (DIM == 3 && N >= 4) {
+            if (nr == 1)
+                hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 1, kIdxEntity>), grid, block, 0, s,
+                                   L.d_ent_rec.ptr, geo, (const T*)src, nullptr, (T*)dst, tb, nr, plane);
+            else
+                hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 0, kIdxEntity>), grid, block, 0, s,
+                                   L.d_ent_rec.ptr, geo, (const T*)src, nullptr, (T*)dst, tb, nr, plane);
+        } else {
+            fail(NNMG_ERR_UNSUPPORTED, "entity records: 3D, degree >= 3");
+        }
     } else {
         if (nr == 1)
             hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 1>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
@@ -802,7 +909,7 @@ static void vmult_prec(const Level& L, const T* geo, int mode, bool atomic, cons
 }
 
 static void launch_op(const Level& L, int prec, bool atomic, const void* src, void* dst, int nr, hipStream_t s) {
-    const int mode = L.geometry_mode;
+    const int mode = L.var[prec].geometry_mode;
     const void* geo = mode == kTrilinear ? (prec == NNMG_FP64 ? (const void*)L.d_coef64.ptr : (const void*)L.d_coef32.ptr)
                                          : (prec == NNMG_FP64 ? (const void*)L.d_metric64.ptr
                                                               : (const void*)L.d_metric32.ptr);
@@ -820,7 +927,7 @@ void launch_vmult_contrib(const Level& L, int prec, const void* src, void* contr
 
 void launch_vmult_cells(const Level& L, int prec, const void* src, void* dst, hipStream_t s, int nr,
                         void* contrib) {
-    if (L.atomic_scatter && L.op == NNMG_OP_LAPLACE) {
+    if (L.var[prec].atomic && L.op == NNMG_OP_LAPLACE) {
         launch_op(L, prec, true, src, dst, nr, s);
     } else {
         void* cb = contrib ? contrib : (void*)L.d_contrib.ptr;

@@ -97,21 +97,25 @@ def test_committed_traffic_summaries_parse():
 def test_operator_kernel_names_follow_degree_and_variant():
     lv = SimpleNamespace(dim=3, degree=4, operator="laplace", VARIANTS=("trilinear+slots", "trilinear+atomic",
                                                                         "metric+slots", "metric+atomic",
-                                                                        "trilinear+lattice", "metric+lattice"),
+                                                                        "trilinear+entity", "metric+entity"),
                          variant=0)
-    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1>",
-                                                  "gather_kernel<1, 1, double, nnmg::CsrRuns>"]
+    lv.variant_of = lambda dtype: lv.variant
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1, 0>",
+                                                  "gather_kernel<1, 1, double>"]
     lv.variant = 2
-    assert bench.operator_kernel_names(lv, 4, nr=4) == ["vmult_kernel<3, 5, float, 0, 0, 0>",
-                                                        "gather_kernel<1, 4, float, nnmg::CsrRuns>"]
+    assert bench.operator_kernel_names(lv, 4, nr=4) == ["vmult_kernel<3, 5, float, 0, 0, 0, 0>",
+                                                        "gather_kernel<1, 4, float>"]
     lv.variant = 3
-    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 0, 1, 1>"]
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 0, 1, 1, 0>"]
     lv.variant = 4
-    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 2, 1>",
-                                                  "gather_kernel<1, 1, double, nnmg::LatticeRuns>"]
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1, 1>",
+                                                  "gather_kernel<1, 1, double>"]
+    lv.variant = 5
+    assert bench.operator_kernel_names(lv, 4) == ["vmult_kernel<3, 5, float, 0, 0, 1, 1>",
+                                                  "gather_kernel<1, 1, float>"]
     el = SimpleNamespace(dim=3, degree=2, operator="elasticity")
     assert bench.operator_kernel_names(el, 8, nr=4) == ["elasticity_kernel<3, double, 0>",
-                                                        "gather_kernel<3, 4, double, nnmg::CsrRuns>"]
+                                                        "gather_kernel<3, 4, double>"]
 
 
 def test_default_workload_is_the_largest_single_gpu_ball():
