@@ -166,16 +166,25 @@ def run_serving(args, ctx, nn, torch, log):
             ts.append(time.perf_counter() - t1)
         service.append(sum(ts) / len(ts))
     mean_service = sum(service) / len(service)
-    rate = args.serving_load / mean_service
-    rng = np.random.default_rng(4000)
     n_req = args.serving_requests
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    rng = np.random.default_rng(4000)
+    # one trace shape for every load: unit-rate exponential gaps, scaled by the load's rate
+    gaps = rng.exponential(1.0, n_req)
     which = rng.integers(len(pool), size=n_req)
     nrs = rng.integers(1, 9, size=n_req)
-    log(f"serving: {n_req} requests at {rate:.1f}/s (offered load {args.serving_load} of one-at-a-time capacity)")
+    # size-aware admission: a request of at least this many fine DoFs x right-hand
+    # sides is large (here: every 8.1M-DoF request, the 2.1M/1.8M ones with several
+    # right-hand sides), and large requests run one at a time beside small ones
+    large_work = 4e6
+    MODES = {"one_at_a_time": dict(max_active=1),
+             "batching_arrival": dict(max_active=args.serving_slots),
+             "batching_sized": dict(max_active=args.serving_slots, policy="smallest", aging_ms=250.0,
+                                    large_work=large_work, max_large=1)}
 
-    def replay(max_active):
-        srv = nn.Server(ctx, max_active=max_active)
+    def replay(mode, load):
+        rate = load / mean_service
+        arrivals = np.cumsum(gaps / rate)
+        srv = nn.Server(ctx, **MODES[mode])
         torch.cuda.synchronize()
         tickets = []
         t_start = time.perf_counter()
@@ -200,15 +209,22 @@ def run_serving(args, ctx, nn, torch, log):
         st = srv.stats()
         srv.close()
         makespan = max(ends)
-        return dict(value=work / makespan / 1e6, makespan_s=round(makespan, 4),
+        return dict(value=round(work / makespan / 1e6, 2), makespan_s=round(makespan, 4),
                     latency_ms={"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3)},
                     mean_queued_ms=round(sum(queued) / len(queued), 3), max_running=st["max_running"],
                     mean_iterations=round(sum(its_all) / len(its_all), 2))
 
-    log("replay: one request at a time")
-    serial = replay(1)
-    log(f"replay: continuous batching, {args.serving_slots} slots")
-    batched = replay(args.serving_slots)
+    # offered-load sweep: the same request sequence at each load, replayed in each mode
+    loads = sorted({0.5, 1.0, 1.5, args.serving_load})
+    sweep = {}
+    for load in loads:
+        sweep[str(load)] = {}
+        for mode in MODES:
+            log(f"replay: load {load}, {mode}")
+            sweep[str(load)][mode] = replay(mode, load)
+    at = sweep[str(args.serving_load)]
+    serial, batched = at["one_at_a_time"], at["batching_sized"]
+    rate = args.serving_load / mean_service
     big = pool[-1]
     log("timing the operator and transfer kernels of the largest hierarchy")
     k = kernel_rooflines(big["levels"][-1], big["levels"][-2], big["trs"][-1], args.roofline_reps)
@@ -241,10 +257,13 @@ def run_serving(args, ctx, nn, torch, log):
             "offered_load": args.serving_load,
             "slots": args.serving_slots,
             "replicas_per_mesh": args.serving_replicas,
+            "admission": ("smallest expected work (fine DoFs x right-hand sides) first, aging bound 250 ms, "
+                          f"requests of >= {large_work:.0f} DoF x rhs run one at a time"),
         },
         "latency_ms": batched["latency_ms"],
         "serving": {"continuous_batching": batched, "one_at_a_time": serial,
                     "speedup": round(batched["value"] / serial["value"], 3),
+                    "load_sweep": sweep,
                     "service_ms_alone": [round(t * 1e3, 3) for t in service]},
         "setup_s": {"pool": round(t_setup, 3)},
         "roofline": roofline_entry(k, "operator_fp32", {}, big["levels"][-1], 4, 1,
@@ -301,7 +320,7 @@ def recorded_traffic(tag):
 def operator_kernel_names(level, word, nr=1):
     """The kernels one operator application (Level.vmult_add) launches, named
     as the kernel trace names them, for the level's degree and operator variant
-    (vmult_kernel<dim, n, T, geometry, scatter, nrt, index layout>), with the
+    (vmult_kernel<dim, n, T, geometry, scatter, nrt, index layout, sweep>), with the
     operator variant of the precision of that word size."""
     T = "double" if word == 8 else "float"
     n = level.degree + 1
@@ -311,10 +330,11 @@ def operator_kernel_names(level, word, nr=1):
     import torch
     variant = level.VARIANTS[level.variant_of(torch.float64 if word == 8 else torch.float32)]
     geo = 1 if variant.startswith("trilinear") else 0
+    sw = 1 if variant.endswith("+transposed") else 0
     if variant.endswith("atomic"):
-        return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 1, {nrt}, 0>"]
-    idx = 1 if variant.endswith("entity") else 0
-    return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 0, {nrt}, {idx}>", f"gather_kernel<1, {nr}, {T}>"]
+        return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 1, {nrt}, 0, 0>"]
+    idx = 1 if "+entity" in variant else 0
+    return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 0, {nrt}, {idx}, {sw}>", f"gather_kernel<1, {nr}, {T}>"]
 
 
 def time_launches(fn, reps):
@@ -785,6 +805,11 @@ def main():
         fine = nn.Level.from_mesh(ctx, rmeshes[-1], rdeg, rop)
         coarse = nn.Level.from_mesh(ctx, rmeshes[-2], rdeg, rop)
         tr = nn.Transfer(ctx, fine, coarse)
+        if not args.no_tune:
+            # the kernels the tuned solve runs: one operator variant per precision
+            for dt in (torch.float64, torch.float32):
+                fine.tune(dt, reps=10)
+            tr.tune(torch.float64, reps=10)
         nbytes = copy_calibration()
         k = kernel_rooflines(fine, coarse, tr, args.roofline_reps, args.roofline_rhs)
         print(json.dumps({"roofline_only": True, "workload": args.roofline_workload, "copy_bytes": nbytes,

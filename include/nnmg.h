@@ -304,8 +304,12 @@ int nnmg_restrict_multi(const nnmg_transfer* transfer, nnmg_prec prec, int nrhs,
 /* Timings of the variants of an operation and the one kept. */
 typedef struct {
     int n_variants;  /* entries of ms that were timed */
-    double ms[8];    /* average milliseconds per call of each variant, -1 where not timed */
+    double ms[16];   /* average milliseconds per call of each variant, -1 where not timed */
     int chosen;      /* index of the variant now in use */
+    int rhs_split;   /* nnmg_level_tune: several right-hand sides run one grid row each (1) or
+                        every block loops over them (0) */
+    double ms_rhs[2]; /* nnmg_level_tune: milliseconds of the 4-right-hand-side product looping (0) and
+                         split (1), timed on small levels only (-1 otherwise) */
 } nnmg_tune_result;
 
 /* Times the variants of the level's operator application in precision `prec`
@@ -320,11 +324,15 @@ typedef struct {
  *     DoF, first contribution slot, writer count and orientation of each of
  *     its 27 mesh entities instead of one DoF index and one slot per node
  *   5 as 2, with entity-compressed indices
- * (variants 4 and 5 exist for 3D Laplace levels of degree >= 3, otherwise
- * NNMG_ERR_UNSUPPORTED; the elasticity operator has variant 0 only).  The
- * variants differ only in the order of floating-point sums (atomics: an
- * order that varies between runs), the operator being the one of paper §3.2
- * throughout.  Only the deterministic variants (0, 2, 4, 5) are timed, so a
+ *   6..11 as 0..5 with transposed sweeps: between the contraction stages the
+ *     lanes of a cell swap the line they own (x, y, z lines) through LDS, so
+ *     every 1D contraction runs in registers (7 and 9 do not exist)
+ * (variants 4, 5, 10 and 11 exist for 3D Laplace levels of degree >= 3,
+ * otherwise NNMG_ERR_UNSUPPORTED; the elasticity operator has variant 0
+ * only).  The variants differ only in the order of floating-point sums
+ * (atomics: an order that varies between runs), the operator being the one of
+ * paper §3.2 throughout.  Only the deterministic variants (0, 2, 4, 5, 6, 8,
+ * 10, 11) are timed, so a
  * tuned level stays bitwise reproducible; the others keep ms = -1 and are
  * taken only when forced.  The stored metric is computed when a precision
  * needs it and freed when none does.  Synchronizes the device; hierarchies
@@ -336,6 +344,13 @@ int nnmg_level_tune(nnmg_level* level, nnmg_prec prec, int reps, nnmg_tune_resul
 int nnmg_level_set_variant(nnmg_level* level, int variant);
 int nnmg_level_set_variant_prec(nnmg_level* level, nnmg_prec prec, int variant);
 int nnmg_level_variant(const nnmg_level* level, nnmg_prec prec, int* variant);
+/* Several right-hand sides in one operator launch (the _multi calls and the
+ * solves with several right-hand sides): split = 1 gives each right-hand side
+ * its own row of workgroups, split = 0 lets every workgroup loop over them.
+ * nnmg_level_tune times both on small levels (fewer than 16384 wavefronts
+ * per launch) and keeps the faster.  Same results either way (each
+ * right-hand side is summed in the same order). */
+int nnmg_level_set_rhs_split(nnmg_level* level, nnmg_prec prec, int split);
 
 /* Times the restriction (paper §2, eq. residual2) with 4 << v lanes per
  * coarse cell, v = 0..4, and keeps the fastest (same contract as
@@ -416,10 +431,11 @@ int nnmg_hierarchy_footprint(const nnmg_hierarchy* h, int nrhs, size_t* bytes);
 /* A server owns one loop thread and max_active streams.  Requests name a
  * resident hierarchy and nrhs right-hand sides (the solve of
  * nnmg_pcg_solve_multi, paper §4 recipe).  The loop admits queued requests,
- * in arrival order but without letting one that does not fit hold back later
- * ones, whenever a slot is free, the request's footprint fits the memory
- * budget beside the running ones (a request alone is always admitted), and
- * its hierarchy serves no other request.  Running requests advance one CG
+ * in the policy's order but without letting one that does not fit hold back
+ * later ones, whenever a slot is free, the request's footprint fits the
+ * memory budget beside the running ones (a request alone is always
+ * admitted), a large request would not exceed max_large running large ones,
+ * and its hierarchy serves no other request.  Running requests advance one CG
  * stage at a time on their own streams, so their kernels overlap on the
  * device.  Each request makes exactly the launches of nnmg_pcg_solve_multi:
  * its result is the same alone and in the mix.  A hierarchy must not be used
@@ -429,7 +445,17 @@ typedef struct nnmg_server nnmg_server;
 typedef struct {
     int max_active;        /* requests running at once (default 4, 1..64) */
     size_t memory_budget;  /* bytes of footprint the running requests may hold together (default 64 GiB) */
+    int policy;            /* admission order: NNMG_ADMIT_ARRIVAL (default) or NNMG_ADMIT_SMALLEST */
+    double aging_ms;       /* NNMG_ADMIT_SMALLEST: a request queued this long is taken in arrival order,
+                              before every younger one (default 250) */
+    double large_work;     /* a request whose expected work (fine DoFs x nrhs) is at least this is large
+                              (default 0: no request is large) */
+    int max_large;         /* large requests running at once (default 64: no limit below max_active) */
 } nnmg_server_opts;
+
+/* Admission orders of the serving loop: arrival order, or smallest expected
+ * work (fine DoFs x nrhs) first with the aging bound of nnmg_server_opts. */
+enum { NNMG_ADMIT_ARRIVAL = 0, NNMG_ADMIT_SMALLEST = 1 };
 
 typedef struct {
     double queued_ms;  /* submit -> admitted */

@@ -95,11 +95,13 @@ class CgResult(C.Structure):
 
 
 class TuneResult(C.Structure):
-    _fields_ = [("n_variants", C.c_int), ("ms", C.c_double * 8), ("chosen", C.c_int)]
+    _fields_ = [("n_variants", C.c_int), ("ms", C.c_double * 16), ("chosen", C.c_int),
+                ("rhs_split", C.c_int), ("ms_rhs", C.c_double * 2)]
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("max_active", C.c_int), ("memory_budget", C.c_size_t)]
+    _fields_ = [("max_active", C.c_int), ("memory_budget", C.c_size_t), ("policy", C.c_int),
+                ("aging_ms", C.c_double), ("large_work", C.c_double), ("max_large", C.c_int)]
 
 
 class RequestTimes(C.Structure):
@@ -169,6 +171,7 @@ SIGNATURES = {
     "nnmg_level_set_variant": (C.c_int, [_vp, C.c_int]),
     "nnmg_level_set_variant_prec": (C.c_int, [_vp, C.c_int, C.c_int]),
     "nnmg_level_variant": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int)]),
+    "nnmg_level_set_rhs_split": (C.c_int, [_vp, C.c_int, C.c_int]),
     "nnmg_transfer_tune": (C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(TuneResult)]),
     "nnmg_transfer_set_team": (C.c_int, [_vp, C.c_int]),
     "nnmg_transfer_team": (C.c_int, [_vp, C.POINTER(C.c_int)]),

@@ -218,7 +218,9 @@ class Level:
         return dst
 
     VARIANTS = ("trilinear+slots", "trilinear+atomic", "metric+slots", "metric+atomic",
-                "trilinear+entity", "metric+entity")
+                "trilinear+entity", "metric+entity",
+                "trilinear+slots+transposed", None, "metric+slots+transposed", None,
+                "trilinear+entity+transposed", "metric+entity+transposed")
 
     def tune(self, dtype=torch.float32, reps: int = 10) -> dict:
         """Time the operator variants in `dtype` on this GPU and keep the fastest for
@@ -226,7 +228,13 @@ class Level:
         res = _lib.TuneResult()
         check(lib().nnmg_level_tune(self.handle, _DTYPE_PREC[dtype], int(reps), C.byref(res)))
         return dict(ms={self.VARIANTS[v]: res.ms[v] for v in range(res.n_variants) if res.ms[v] >= 0},
-                    chosen=self.VARIANTS[res.chosen])
+                    chosen=self.VARIANTS[res.chosen], rhs_split=bool(res.rhs_split),
+                    ms_rhs4={"loop": res.ms_rhs[0], "split": res.ms_rhs[1]} if res.ms_rhs[0] >= 0 else None)
+
+    def set_rhs_split(self, split: bool, dtype=torch.float64):
+        """Several right-hand sides: one row of workgroups each (True) or every
+        workgroup looping over them (False), for the `dtype` kernels."""
+        check(lib().nnmg_level_set_rhs_split(self.handle, _DTYPE_PREC[dtype], int(bool(split))))
 
     def variant_of(self, dtype) -> int:
         """The operator variant the `dtype` kernels use (index into VARIANTS)."""
@@ -516,12 +524,22 @@ class Server:
     resident hierarchies are admitted as slots and memory free up and run
     overlapped on their own streams."""
 
-    def __init__(self, ctx: Context, max_active: int = 4, memory_budget: int = 64 << 30):
+    POLICIES = {"arrival": 0, "smallest": 1}
+
+    def __init__(self, ctx: Context, max_active: int = 4, memory_budget: int = 64 << 30, policy: str = "arrival",
+                 aging_ms: float = 250.0, large_work: float = 0.0, max_large: int = 64):
+        """policy "smallest": smallest expected work (fine DoFs x nrhs) first, a
+        request queued for aging_ms taken in arrival order; at most max_large
+        requests of expected work >= large_work run at once."""
         self.ctx = ctx
+        if policy not in self.POLICIES:
+            raise ValueError(f"policy must be one of {sorted(self.POLICIES)}")
         o = _lib.ServerOpts()
         lib().nnmg_default_server_opts(C.byref(o))
         o.max_active = int(max_active)
         o.memory_budget = int(memory_budget)
+        o.policy = self.POLICIES[policy]
+        o.aging_ms, o.large_work, o.max_large = float(aging_ms), float(large_work), int(max_large)
         h = C.c_void_p()
         check(lib().nnmg_server_create(ctx.handle, C.byref(o), C.byref(h)))
         self.handle = h

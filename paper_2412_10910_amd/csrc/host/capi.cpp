@@ -484,6 +484,15 @@ int nnmg_level_set_variant_prec(nnmg_level* level, nnmg_prec prec, int variant) 
     });
 }
 
+int nnmg_level_set_rhs_split(nnmg_level* level, nnmg_prec prec, int split) {
+    return guarded([&] {
+        if (!level) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        level_set_rhs_split(*level, prec, split);
+        return NNMG_OK;
+    });
+}
+
 int nnmg_level_variant(const nnmg_level* level, nnmg_prec prec, int* variant) {
     return guarded([&] {
         if (!level || !variant) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
@@ -531,6 +540,10 @@ void nnmg_default_server_opts(nnmg_server_opts* o) {
     if (!o) return;
     o->max_active = 4;
     o->memory_budget = (size_t)64 << 30;
+    o->policy = NNMG_ADMIT_ARRIVAL;
+    o->aging_ms = 250.0;
+    o->large_work = 0.0;
+    o->max_large = 64;
 }
 
 int nnmg_server_create(nnmg_ctx* ctx, const nnmg_server_opts* opts, nnmg_server** out) {

@@ -772,6 +772,8 @@ size_t hierarchy_footprint(const Hierarchy& H, int nr) {
     return bytes;
 }
 
+int64_t hierarchy_fine_dofs(const Hierarchy& H) { return H.levels.back()->n_dofs; }
+
 // the hierarchy's own work memory must not be shared by two solves at a time
 bool hierarchy_try_acquire(Hierarchy& H) {
     bool expect = false;

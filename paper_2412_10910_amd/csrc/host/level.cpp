@@ -618,7 +618,9 @@ Level* level_create(Ctx* ctx, const nnmg_mesh* mesh, int degree, const nnmg_leve
         const char* mode = std::getenv("NNMG_GEOMETRY");
         // the elasticity operator rebuilds J from the map coefficients
         const char* scatter = std::getenv("NNMG_SCATTER");
+        const char* sweep = std::getenv("NNMG_SWEEP");
         for (auto& vr : L->var) {
+            vr.sweep = sweep && std::string(sweep) == "transposed" && L->op == NNMG_OP_LAPLACE ? 1 : 0;
             vr.geometry_mode = (mode && std::string(mode) == "metric" && L->op == NNMG_OP_LAPLACE) ? 0 : 1;
             vr.atomic = scatter && std::string(scatter) == "atomic" && L->op == NNMG_OP_LAPLACE;
             if (vr.atomic) vr.index_layout = 0;

@@ -3,8 +3,10 @@
 // Requests (a resident hierarchy, or a set of equivalent replicas of one,
 // nrhs right-hand sides, CG options) are queued by submit() and admitted by
 // one loop thread whenever a slot is free, the request's working memory fits
-// the budget, and one of its hierarchies is not serving another request.  The
-// queue is scanned in arrival order, and a request that does not fit yet does
+// the budget, a large request would not exceed the running large ones
+// allowed, and one of its hierarchies is not serving another request.  The
+// queue is scanned in arrival order, or smallest expected work (fine DoFs x
+// nrhs) first with an aging bound, and a request that does not fit yet does
 // not hold back later ones that do.  Each
 // admitted request runs as a resumable PCG task (host/hierarchy.cpp) on a
 // stream of its own, so the kernels of all admitted requests overlap on the
@@ -33,6 +35,7 @@ bool pcg_task_step(PcgTask* t);
 int pcg_task_status(const PcgTask* t);
 void pcg_task_destroy(PcgTask* t);
 size_t hierarchy_footprint(const Hierarchy& H, int nr);
+int64_t hierarchy_fine_dofs(const Hierarchy& H);
 bool hierarchy_try_acquire(Hierarchy& H);
 void hierarchy_release(Hierarchy& H);
 
@@ -53,6 +56,8 @@ struct Request {
     double* x = nullptr;
     nnmg_cg_opts o{};
     size_t bytes = 0;
+    double work = 0;     // expected work: fine DoFs x nrhs
+    bool large = false;  // work >= opts.large_work
     std::vector<nnmg_cg_result> res;
     int status = NNMG_OK;
     std::string error;
@@ -75,6 +80,7 @@ struct Server {
     std::vector<hipStream_t> streams;
     std::vector<char> slot_busy;
     size_t reserved = 0;
+    int running_large = 0;
     int64_t next_id = 1;
     bool stop = false;
     nnmg_server_stats stats{};
@@ -87,31 +93,39 @@ struct Server {
 
 void Server::admit(std::vector<Request*>& started) {
     // called with mu held
-    for (auto it = pending.begin(); it != pending.end();) {
-        Request* r = *it;
+    std::vector<Request*> order(pending.begin(), pending.end());
+    if (opts.policy == NNMG_ADMIT_SMALLEST) {
+        // requests past the aging bound first, oldest first; then the others
+        // by expected work, ties in arrival order
+        const auto now = Clock::now();
+        auto aged = [&](const Request* r) { return ms_since(r->t_submit, now) >= opts.aging_ms; };
+        std::stable_sort(order.begin(), order.end(), [&](const Request* a, const Request* b) {
+            const bool ga = aged(a), gb = aged(b);
+            if (ga != gb) return ga;
+            if (ga) return a->id < b->id;
+            return a->work < b->work;
+        });
+    }
+    for (Request* r : order) {
         if ((int)running.size() >= opts.max_active) break;
-        if (reserved + r->bytes > opts.memory_budget && !running.empty()) {
-            ++it;  // does not fit yet; later requests may
-            continue;
-        }
+        if (reserved + r->bytes > opts.memory_budget && !running.empty()) continue;  // does not fit yet
+        if (r->large && running_large >= opts.max_large) continue;
         r->H = nullptr;
         for (Hierarchy* h : r->replicas)
             if (hierarchy_try_acquire(*h)) {
                 r->H = h;
                 break;
             }
-        if (!r->H) {
-            ++it;  // every replica serves another request
-            continue;
-        }
+        if (!r->H) continue;  // every replica serves another request
         int slot = 0;
         while (slot_busy[(size_t)slot]) ++slot;
         slot_busy[(size_t)slot] = 1;
         r->slot = slot;
         reserved += r->bytes;
+        running_large += r->large ? 1 : 0;
         running.push_back(r);
         started.push_back(r);
-        it = pending.erase(it);
+        pending.erase(std::find(pending.begin(), pending.end(), r));
         stats.max_running = std::max(stats.max_running, (int)running.size());
         stats.max_reserved = std::max(stats.max_reserved, reserved);
     }
@@ -133,6 +147,7 @@ void Server::finish(Request* r, Clock::time_point now) {
     hierarchy_release(*r->H);
     slot_busy[(size_t)r->slot] = 0;
     reserved -= r->bytes;
+    running_large -= r->large ? 1 : 0;
     running.erase(std::find(running.begin(), running.end(), r));
     ++stats.completed;
     cv_done.notify_all();
@@ -201,6 +216,9 @@ void Server::run() {
 
 Server* server_create(Ctx* ctx, const nnmg_server_opts& o) {
     if (o.max_active < 1 || o.max_active > 64) fail(NNMG_ERR_INVALID_ARG, "max_active must be in 1..64");
+    if (o.policy != NNMG_ADMIT_ARRIVAL && o.policy != NNMG_ADMIT_SMALLEST) fail(NNMG_ERR_INVALID_ARG, "policy");
+    if (!(o.aging_ms >= 0.0) || !(o.large_work >= 0.0) || o.max_large < 1)
+        fail(NNMG_ERR_INVALID_ARG, "aging_ms and large_work must be >= 0, max_large >= 1");
     auto* S = new Server();
     S->ctx = ctx;
     S->opts = o;
@@ -248,6 +266,8 @@ int64_t server_submit(Server* S, Hierarchy* const* replicas, int n_replicas, int
     r->x = x;
     r->o = o;
     r->bytes = hierarchy_footprint(*replicas[0], nr);
+    r->work = (double)hierarchy_fine_dofs(*replicas[0]) * nr;
+    r->large = S->opts.large_work > 0.0 && r->work >= S->opts.large_work;
     r->res.assign((size_t)nr, nnmg_cg_result{0, 0.0, NNMG_OK});
     r->t_submit = Clock::now();
     int64_t id;

@@ -9,8 +9,14 @@
 //   3  stored merged metric per Gauss point,    float atomics into the output
 //   4  as 0, with the entity-compressed indices (one record per cell)
 //   5  as 2, with the entity-compressed indices
-// Variants 4 and 5 exist for 3D Laplace levels of degree >= 3 (where the
-// records were built).  The elasticity operator has variant 0 only.  Transfer variants: the lanes
+// With several right-hand sides, a small level (a grid of few wavefronts)
+// also times one grid row per right-hand side against every block looping
+// over them, with four right-hand sides, and keeps the faster.
+//   6..11  as 0..5 with the transposed sweeps: the lanes of a cell swap the
+//          line they own through LDS between the contraction stages, so
+//          every contraction runs in registers (7 and 9, atomics, do not exist)
+// Variants 4, 5, 10 and 11 exist for 3D Laplace levels of degree >= 3 (where
+// the records were built).  The elasticity operator has variant 0 only.  Transfer variants: the lanes
 // per coarse cell of the restriction, 4 << v for v = 0..4.
 //
 // Each precision has its own variant: the float64 and float32 kernels of one
@@ -18,7 +24,7 @@
 //
 // Every choice changes only the order in which floating-point sums are formed
 // (atomics: an order that varies from run to run), never what is summed.  The
-// tuner times the deterministic variants only (0, 2, 4, 5), so that a tuned
+// tuner times the deterministic variants only (0, 2, 4, 5, 6, 8, 10, 11), so that a tuned
 // hierarchy stays bitwise reproducible; the atomic ones are an explicit opt-in
 // through level_set_variant.
 #include <algorithm>
@@ -79,24 +85,38 @@ void ensure_metric(Level& L) {
 bool has_entity_variants(const Level& L) { return L.d_ent_rec.ptr != nullptr; }
 
 Level::OpVariant variant_state(int v) {
+    const int b = v % 6;
     Level::OpVariant s;
-    s.geometry_mode = (v == 2 || v == 3 || v == 5) ? 0 : 1;
-    s.atomic = v == 1 || v == 3;
-    s.index_layout = v >= 4 ? 1 : 0;
+    s.geometry_mode = (b == 2 || b == 3 || b == 5) ? 0 : 1;
+    s.atomic = b == 1 || b == 3;
+    s.index_layout = b >= 4 ? 1 : 0;
+    s.sweep = v / 6;
     return s;
 }
+
+bool atomic_variant(int v) { return v % 6 == 1 || v % 6 == 3; }
+
+// levels whose operator grid has fewer wavefronts than this (a few per SIMD)
+// also time the several-right-hand-side launch with one grid row per
+// right-hand side
+constexpr int64_t kSmallLevelWaves = 16384;
 
 // prec: NNMG_FP64, NNMG_FP32, or -1 for both
 void apply_variant(Level& L, int prec, int v) {
     if (L.op != NNMG_OP_LAPLACE && v != 0) fail(NNMG_ERR_UNSUPPORTED, "the elasticity operator has variant 0 only");
-    if (v < 0 || v > 5) fail(NNMG_ERR_INVALID_ARG, "operator variant must be in 0..5");
-    if (v >= 4 && !has_entity_variants(L))
-        fail(NNMG_ERR_UNSUPPORTED, "variants 4 and 5 (entity-compressed indices) need a 3D Laplace level of degree >= 3");
+    if (v < 0 || v > 11) fail(NNMG_ERR_INVALID_ARG, "operator variant must be in 0..11");
+    if (v == 7 || v == 9) fail(NNMG_ERR_INVALID_ARG, "the atomic variants have no transposed-sweep form");
+    if (v % 6 >= 4 && !has_entity_variants(L))
+        fail(NNMG_ERR_UNSUPPORTED, "variants 4, 5, 10, 11 (entity-compressed indices) need a 3D Laplace level of degree >= 3");
     NNMG_HIP(hipDeviceSynchronize());  // launches of the previous variant may be in flight
     const Level::OpVariant st = variant_state(v);
     if (st.geometry_mode == 0) ensure_metric(L);
     for (int p = 0; p < 2; ++p)
-        if (prec < 0 || prec == p) L.var[p] = st;
+        if (prec < 0 || prec == p) {
+            const int split = L.var[p].rhs_split;  // a separate choice (level_tune)
+            L.var[p] = st;
+            L.var[p].rhs_split = split;
+        }
     if (L.var[0].geometry_mode == 1 && L.var[1].geometry_mode == 1) {
         // no precision reads the stored metric any more
         L.d_metric64.reset();
@@ -109,8 +129,9 @@ void apply_variant(Level& L, int prec, int v) {
 
 int level_variant(const Level& L, int prec) {
     const Level::OpVariant& s = L.var[prec];
-    if (s.index_layout == 1) return s.geometry_mode == 0 ? 5 : 4;
-    return (s.geometry_mode == 0 ? 2 : 0) + (s.atomic ? 1 : 0);
+    const int b = s.index_layout == 1 ? (s.geometry_mode == 0 ? 5 : 4)
+                                      : (s.geometry_mode == 0 ? 2 : 0) + (s.atomic ? 1 : 0);
+    return b + 6 * s.sweep;
 }
 
 void level_set_variant(Level& L, int prec, int v) {
@@ -118,11 +139,20 @@ void level_set_variant(Level& L, int prec, int v) {
     apply_variant(L, prec, v);
 }
 
+void level_set_rhs_split(Level& L, int prec, int split) {
+    if (split != 0 && split != 1) fail(NNMG_ERR_INVALID_ARG, "rhs split must be 0 or 1");
+    NNMG_HIP(hipSetDevice(L.ctx->device));
+    NNMG_HIP(hipDeviceSynchronize());
+    for (int p = 0; p < 2; ++p)
+        if (prec < 0 || prec == p) L.var[p].rhs_split = split;
+    ++L.config_version;
+}
+
 void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res) {
     if (reps < 1) fail(NNMG_ERR_INVALID_ARG, "reps must be positive");
     NNMG_HIP(hipSetDevice(L.ctx->device));
     const size_t n = (size_t)L.n_dofs;
-    const int nvar = L.op != NNMG_OP_LAPLACE ? 1 : (has_entity_variants(L) ? 6 : 4);
+    const int nvar = L.op != NNMG_OP_LAPLACE ? 1 : 12;
     hipStream_t s;
     NNMG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     try {
@@ -138,7 +168,8 @@ void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res) {
         for (double& t : res->ms) t = -1.0;
         int best = 0;
         for (int v = 0; v < nvar; ++v) {
-            if (v == 1 || v == 3) continue;  // float atomics: not reproducible, never picked by the tuner
+            if (atomic_variant(v)) continue;  // float atomics: not reproducible, never picked by the tuner
+            if (v % 6 >= 4 && !has_entity_variants(L)) continue;
             apply_variant(L, prec, v);
             res->ms[v] = time_ms(
                 [&](hipStream_t st) {
@@ -150,6 +181,31 @@ void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res) {
         }
         apply_variant(L, prec, best);
         res->chosen = best;
+        // several right-hand sides on a small level (a grid of few wavefronts):
+        // one grid row per right-hand side, or every block looping over them
+        res->rhs_split = L.var[prec].rhs_split;
+        res->ms_rhs[0] = res->ms_rhs[1] = -1.0;
+        const int64_t waves = L.nblocks * (L.wg / 64);
+        if (waves < kSmallLevelWaves) {
+            constexpr int nr = 4;
+            level_reserve_rhs(L, nr);
+            DeviceArray<char> x4 = scratch_vector(L.ctx, n * nr, prec, 0x7E5Aull, s);
+            DeviceArray<char> f4 = scratch_vector(L.ctx, n * nr, prec, 0x7E5Bull, s);
+            DeviceArray<char> r4;
+            r4.alloc(L.ctx, std::max<size_t>(n * nr, 1) * (prec == NNMG_FP64 ? 8 : 4));
+            for (int split = 0; split < 2; ++split) {
+                L.var[prec].rhs_split = split;
+                res->ms_rhs[split] = time_ms(
+                    [&](hipStream_t st) {
+                        launch_vmult_contrib(L, prec, x4.ptr, L.d_contrib.ptr, st, nr);
+                        launch_residual_gather(L, prec, L.d_contrib.ptr, f4.ptr, r4.ptr, st, nr);
+                    },
+                    reps, s);
+            }
+            L.var[prec].rhs_split = res->ms_rhs[1] < res->ms_rhs[0] ? 1 : 0;
+            res->rhs_split = L.var[prec].rhs_split;
+            ++L.config_version;
+        }
     } catch (...) {
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);

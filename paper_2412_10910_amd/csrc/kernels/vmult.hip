@@ -37,6 +37,9 @@
 //    cross products of the columns of J, so G grad = (w / det J) R^T (R grad)
 //    with R the matrix of those rows.  This moves 21 words per cell instead
 //    of 6 per Gauss point, for about 60 flops per Gauss point.
+#include <cstdlib>
+#include <string>
+
 #include "../internal.hpp"
 #include "common.hpp"
 
@@ -113,26 +116,31 @@ constexpr int kIdxEntity = 1;  // one record of entity bases and slot bases per 
 // node on its entity: a record of 62 words per cell instead of 2 q words
 // (q = 64 at Q3, 125 at Q4).
 // waves per SIMD the register allocation must allow: 4 for the float64 Q3
-// single-vector kernel with entity records (it would otherwise take 150
-// VGPRs, 3 waves; at 128 it spills 5)
-template <int N, class T, int NRT, int IDX>
+// single-vector kernels with entity records or transposed sweeps (they would
+// otherwise take 132-150 VGPRs, 3 waves; at 128 they spill a few)
+template <int N, class T, int NRT, int IDX, int SW>
 constexpr int vmult_min_waves() {
-    return (IDX == 1 && N == 4 && sizeof(T) == 8 && NRT == 1) ? 4 : NNMG_VMULT_MINWAVES;
+    return ((IDX == 1 || SW == 1) && N == 4 && sizeof(T) == 8 && NRT == 1) ? 4 : NNMG_VMULT_MINWAVES;
 }
 
-template <int DIM, int N, class T, int GEO, int SCATTER, int NRT, int IDX = kIdxNodes>
-__global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, IDX>())) void vmult_kernel(const int32_t* __restrict__ dmap,
+template <int DIM, int N, class T, int GEO, int SCATTER, int NRT, int IDX = kIdxNodes, int SW = 0>
+__global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, IDX, SW>())) void vmult_kernel(const int32_t* __restrict__ dmap,
                                                                     const T* __restrict__ geo,
                                                                     const T* __restrict__ src,
                                                                     const int32_t* __restrict__ slots,
                                                                     T* __restrict__ dst, OpTables<N, T> tb,
                                                                     int nr_in, int64_t plane) {
     const int nr = NRT > 0 ? NRT : nr_in;
+    // right-hand sides of this block: all of them one after the other, or,
+    // when the grid has one row per right-hand side (small meshes, where a
+    // loop would leave the device idle), the one of its row
+    const int rhs0 = NRT == 0 ? (int)blockIdx.y : 0;
+    const int rhs_end = (NRT == 0 && gridDim.y > 1) ? rhs0 + 1 : nr;
     using Sh = OpShape<DIM, N>;
     constexpr int L = Sh::L, WG = Sh::WG, CPB = Sh::CPB, TILE = Sh::TILE;
     constexpr int M = DIM * (DIM + 1) / 2;
     constexpr int NC = DIM == 3 ? 21 : 6;
-    __shared__ T lds[3][CPB][TILE];
+    __shared__ T lds[SW == 1 ? 5 : 3][CPB][TILE];
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     const int cell = lane / L;
@@ -240,7 +248,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, 
         }
     }
 #pragma unroll
-    for (int i = 0; i < N; ++i) u[i] = idx[i] >= 0 ? src[(int64_t)idx[i] * nr] : T(0);
+    for (int i = 0; i < N; ++i) u[i] = idx[i] >= 0 ? src[(int64_t)idx[i] * nr + rhs0] : T(0);
     if constexpr (GEO == kTrilinear) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -261,86 +269,172 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, 
     T* B = lds[1][cb];
     T* Cc = lds[2][cb];
 
-    for (int rhs = 0;;) {
+    for (int rhs = rhs0;;) {
     // the next right-hand side's values are loaded while this one is swept
     T un[N];
-    if (NRT != 1 && rhs + 1 < nr) {
+    if (NRT != 1 && rhs + 1 < rhs_end) {
 #pragma unroll
         for (int i = 0; i < N; ++i) un[i] = idx[i] >= 0 ? src[(int64_t)idx[i] * nr + rhs + 1] : T(0);
     }
     // ---- forward --------------------------------------------------------
     T gx[N], gy[N], gz[N];  // reference gradient at the Gauss points of the line (2D: x, gz = y)
-    line_apply<N, T, false>(tb.S, u, v);  // x: nodes -> Gauss points
-    if constexpr (DIM == 3) {
-        // y: interpolate
+    if constexpr (SW == 1) {
+        // Transposed sweeps: between the stages the lanes of a cell swap the
+        // line they own through LDS (x-line (j, t) = (a, b), y-line (i, t) =
+        // (a, b), z-line (i, j) = (a, b) for a = line % N, b = line / N), so
+        // every contraction runs in registers with the 1D tables as constants
+        // and each stage moves N values per lane through LDS, instead of N^2
+        // tile and N^2 table reads per lane for a contraction across lanes.
+        // The y (2D) / y and z (3D) derivatives come from the DS table (the
+        // derivative of the interpolant at the Gauss points) in the stage that
+        // interpolates along that direction.
+        T* T0 = lds[0][cb];
+        T* T1 = lds[1][cb];
+        T* T2 = lds[2][cb];
+        line_apply<N, T, false>(tb.S, u, v);  // x: nodes -> Gauss points
         if (act) {
 #pragma unroll
-            for (int i = 0; i < N; ++i) A[row + i] = v[i];
+            for (int i = 0; i < N; ++i) T0[row + i] = v[i];
         }
         block_sync<WG>();
+        if constexpr (DIM == 3) {
+            T* T3 = lds[3][cb];
+            T* T4 = lds[4][cb];
+            // y-line (i, t) = (j, t) of this lane's indices
+            T a[N], w[N], wy[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T s = lS[j * N + 0] * A[(t * N + 0) * N + i];
+            for (int c = 0; c < N; ++c) a[c] = T0[(t * N + c) * N + j];
+            line_apply<N, T, false>(tb.S, a, w);
+            line_apply<N, T, false>(tb.DS, a, wy);
+            if (act) {
 #pragma unroll
-            for (int c = 1; c < N; ++c) s += lS[j * N + c] * A[(t * N + c) * N + i];
-            u[i] = s;
-        }
-        // z: interpolate and differentiate
-        if (act) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) B[row + i] = u[i];
-        }
-        block_sync<WG>();
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const T w0 = B[(0 * N + j) * N + i];
-            T s0 = lS[t * N + 0] * w0, s1 = lDS[t * N + 0] * w0;
-#pragma unroll
-            for (int c = 1; c < N; ++c) {
-                const T w = B[(c * N + j) * N + i];
-                s0 += lS[t * N + c] * w;
-                s1 += lDS[t * N + c] * w;
+                for (int c = 0; c < N; ++c) {
+                    T1[(t * N + c) * N + j] = w[c];
+                    T2[(t * N + c) * N + j] = wy[c];
+                }
             }
-            v[i] = s0;
-            gz[i] = s1;
+            block_sync<WG>();
+            // z-line (i, j) = (j, t) of this lane's indices: values, z and y derivatives
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                a[c] = T1[(c * N + t) * N + j];
+                w[c] = T2[(c * N + t) * N + j];
+            }
+            T zv[N], zz[N], zy[N];
+            line_apply<N, T, false>(tb.S, a, zv);
+            line_apply<N, T, false>(tb.DS, a, zz);
+            line_apply<N, T, false>(tb.S, w, zy);
+            if (act) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    T0[(c * N + t) * N + j] = zv[c];
+                    T3[(c * N + t) * N + j] = zz[c];
+                    T4[(c * N + t) * N + j] = zy[c];
+                }
+            }
+            block_sync<WG>();
+            // back on the x-line
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                v[i] = T0[row + i];
+                gy[i] = T4[row + i];
+                gz[i] = T3[row + i];
+            }
+        } else {
+            // y-line i = t of this lane's index
+            T a[N], w[N], wy[N];
+#pragma unroll
+            for (int c = 0; c < N; ++c) a[c] = T0[c * N + t];
+            line_apply<N, T, false>(tb.S, a, w);
+            line_apply<N, T, false>(tb.DS, a, wy);
+            if (act) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    T1[c * N + t] = w[c];
+                    T2[c * N + t] = wy[c];
+                }
+            }
+            block_sync<WG>();
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                v[i] = T1[row + i];
+                gz[i] = T2[row + i];
+            }
         }
+        line_apply<N, T, false>(tb.D, v, gx);
     } else {
-        if (act) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) A[row + i] = v[i];
-        }
-        block_sync<WG>();
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const T w0 = A[0 * N + i];
-            T s0 = lS[t * N + 0] * w0, s1 = lDS[t * N + 0] * w0;
-#pragma unroll
-            for (int c = 1; c < N; ++c) {
-                const T w = A[c * N + i];
-                s0 += lS[t * N + c] * w;
-                s1 += lDS[t * N + c] * w;
+        line_apply<N, T, false>(tb.S, u, v);  // x: nodes -> Gauss points
+        if constexpr (DIM == 3) {
+            // y: interpolate
+            if (act) {
+    #pragma unroll
+                for (int i = 0; i < N; ++i) A[row + i] = v[i];
             }
-            v[i] = s0;
-            gz[i] = s1;
+            block_sync<WG>();
+    #pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T s = lS[j * N + 0] * A[(t * N + 0) * N + i];
+    #pragma unroll
+                for (int c = 1; c < N; ++c) s += lS[j * N + c] * A[(t * N + c) * N + i];
+                u[i] = s;
+            }
+            // z: interpolate and differentiate
+            if (act) {
+    #pragma unroll
+                for (int i = 0; i < N; ++i) B[row + i] = u[i];
+            }
+            block_sync<WG>();
+    #pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const T w0 = B[(0 * N + j) * N + i];
+                T s0 = lS[t * N + 0] * w0, s1 = lDS[t * N + 0] * w0;
+    #pragma unroll
+                for (int c = 1; c < N; ++c) {
+                    const T w = B[(c * N + j) * N + i];
+                    s0 += lS[t * N + c] * w;
+                    s1 += lDS[t * N + c] * w;
+                }
+                v[i] = s0;
+                gz[i] = s1;
+            }
+        } else {
+            if (act) {
+    #pragma unroll
+                for (int i = 0; i < N; ++i) A[row + i] = v[i];
+            }
+            block_sync<WG>();
+    #pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const T w0 = A[0 * N + i];
+                T s0 = lS[t * N + 0] * w0, s1 = lDS[t * N + 0] * w0;
+    #pragma unroll
+                for (int c = 1; c < N; ++c) {
+                    const T w = A[c * N + i];
+                    s0 += lS[t * N + c] * w;
+                    s1 += lDS[t * N + c] * w;
+                }
+                v[i] = s0;
+                gz[i] = s1;
+            }
         }
-    }
-    // v: values at the Gauss points of the line; x (and y) derivatives
-    line_apply<N, T, false>(tb.D, v, gx);
-    if constexpr (DIM == 3) {
-        if (act) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) Cc[row + i] = v[i];
+        // v: values at the Gauss points of the line; x (and y) derivatives
+        line_apply<N, T, false>(tb.D, v, gx);
+        if constexpr (DIM == 3) {
+            if (act) {
+    #pragma unroll
+                for (int i = 0; i < N; ++i) Cc[row + i] = v[i];
+            }
+            block_sync<WG>();
+    #pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T s = lD[j * N + 0] * Cc[(t * N + 0) * N + i];
+    #pragma unroll
+                for (int c = 1; c < N; ++c) s += lD[j * N + c] * Cc[(t * N + c) * N + i];
+                gy[i] = s;
+            }
         }
-        block_sync<WG>();
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T s = lD[j * N + 0] * Cc[(t * N + 0) * N + i];
-#pragma unroll
-            for (int c = 1; c < N; ++c) s += lD[j * N + c] * Cc[(t * N + c) * N + i];
-            gy[i] = s;
-        }
-    }
 
+    }
 
     // ---- geometry at the Gauss points of the line ------------------------
     if constexpr (GEO == kStoredMetric) {
@@ -427,70 +521,153 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, 
     }
 
     // ---- backward -------------------------------------------------------
-    line_apply<N, T, true>(tb.D, gx, u);  // Dx^T fx
-    if constexpr (DIM == 3) {
-        // + Dy^T fy
-        if (act) {
+    if constexpr (SW == 1) {
+        // out = Sx^T Sy^T Sz^T (Dx^T fx) + Sx^T DSy^T Sz^T fy + Sx^T Sy^T DSz^T fz
+        // (2D: Sx^T Sy^T (Dx^T fx) + Sx^T DSy^T fy), the stages in reverse
+        T* T0 = lds[0][cb];
+        T* T1 = lds[1][cb];
+        T* T2 = lds[2][cb];
+        line_apply<N, T, true>(tb.D, gx, u);  // Dx^T fx
+        block_sync<WG>();                     // every lane has read the forward tiles
+        if constexpr (DIM == 3) {
+            T* T3 = lds[3][cb];
+            T* T4 = lds[4][cb];
+            if (act) {
 #pragma unroll
-            for (int i = 0; i < N; ++i) A[row + i] = gy[i];
-        }
-        block_sync<WG>();
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T s = u[i];
-#pragma unroll
-            for (int c = 0; c < N; ++c) s += lD[c * N + j] * A[(t * N + c) * N + i];
-            u[i] = s;
-        }
-        // z: S^T (sum) + DS^T fz
-        if (act) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                B[row + i] = u[i];
-                Cc[row + i] = gz[i];
+                for (int i = 0; i < N; ++i) {
+                    T0[row + i] = u[i];
+                    T1[row + i] = gy[i];
+                    T2[row + i] = gz[i];
+                }
             }
+            block_sync<WG>();
+            // z-line (i, j) = (j, t) of this lane's indices
+            T a[N], b2[N], c2[N], r0[N], r1[N];
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                a[c] = T0[(c * N + t) * N + j];
+                b2[c] = T1[(c * N + t) * N + j];
+                c2[c] = T2[(c * N + t) * N + j];
+            }
+            line_apply<N, T, true>(tb.S, a, r0);
+            line_apply<N, T, true>(tb.DS, c2, r1);
+            line_apply<N, T, true>(tb.S, b2, a);
+            if (act) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    T3[(c * N + t) * N + j] = r0[c] + r1[c];
+                    T4[(c * N + t) * N + j] = a[c];
+                }
+            }
+            block_sync<WG>();
+            // y-line (i, t) = (j, t) of this lane's indices
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                a[c] = T3[(t * N + c) * N + j];
+                b2[c] = T4[(t * N + c) * N + j];
+            }
+            line_apply<N, T, true>(tb.S, a, r0);
+            line_apply<N, T, true>(tb.DS, b2, r1);
+            if (act) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) T0[(t * N + c) * N + j] = r0[c] + r1[c];
+            }
+            block_sync<WG>();
+#pragma unroll
+            for (int i = 0; i < N; ++i) u[i] = T0[row + i];
+        } else {
+            if (act) {
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    T0[row + i] = u[i];
+                    T1[row + i] = gz[i];
+                }
+            }
+            block_sync<WG>();
+            // y-line i = t of this lane's index
+            T a[N], b2[N], r0[N], r1[N];
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                a[c] = T0[c * N + t];
+                b2[c] = T1[c * N + t];
+            }
+            line_apply<N, T, true>(tb.S, a, r0);
+            line_apply<N, T, true>(tb.DS, b2, r1);
+            if (act) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) T2[c * N + t] = r0[c] + r1[c];
+            }
+            block_sync<WG>();
+#pragma unroll
+            for (int i = 0; i < N; ++i) u[i] = T2[row + i];
         }
-        block_sync<WG>();
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T s = lS[0 * N + t] * B[(0 * N + j) * N + i] + lDS[0 * N + t] * Cc[(0 * N + j) * N + i];
-#pragma unroll
-            for (int q = 1; q < N; ++q)
-                s += lS[q * N + t] * B[(q * N + j) * N + i] + lDS[q * N + t] * Cc[(q * N + j) * N + i];
-            v[i] = s;
-        }
-        // y: S^T
-        if (act) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) A[row + i] = v[i];
-        }
-        block_sync<WG>();
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T s = lS[0 * N + j] * A[(t * N + 0) * N + i];
-#pragma unroll
-            for (int q = 1; q < N; ++q) s += lS[q * N + j] * A[(t * N + q) * N + i];
-            u[i] = s;
-        }
+        line_apply<N, T, true>(tb.S, u, v);  // x: S^T
     } else {
-        // y: S^T (sum) + DS^T fy
-        if (act) {
-#pragma unroll
+        line_apply<N, T, true>(tb.D, gx, u);  // Dx^T fx
+        if constexpr (DIM == 3) {
+            // + Dy^T fy
+            if (act) {
+    #pragma unroll
+                for (int i = 0; i < N; ++i) A[row + i] = gy[i];
+            }
+            block_sync<WG>();
+    #pragma unroll
             for (int i = 0; i < N; ++i) {
-                B[row + i] = u[i];
-                Cc[row + i] = gz[i];
+                T s = u[i];
+    #pragma unroll
+                for (int c = 0; c < N; ++c) s += lD[c * N + j] * A[(t * N + c) * N + i];
+                u[i] = s;
+            }
+            // z: S^T (sum) + DS^T fz
+            if (act) {
+    #pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    B[row + i] = u[i];
+                    Cc[row + i] = gz[i];
+                }
+            }
+            block_sync<WG>();
+    #pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T s = lS[0 * N + t] * B[(0 * N + j) * N + i] + lDS[0 * N + t] * Cc[(0 * N + j) * N + i];
+    #pragma unroll
+                for (int q = 1; q < N; ++q)
+                    s += lS[q * N + t] * B[(q * N + j) * N + i] + lDS[q * N + t] * Cc[(q * N + j) * N + i];
+                v[i] = s;
+            }
+            // y: S^T
+            if (act) {
+    #pragma unroll
+                for (int i = 0; i < N; ++i) A[row + i] = v[i];
+            }
+            block_sync<WG>();
+    #pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T s = lS[0 * N + j] * A[(t * N + 0) * N + i];
+    #pragma unroll
+                for (int q = 1; q < N; ++q) s += lS[q * N + j] * A[(t * N + q) * N + i];
+                u[i] = s;
+            }
+        } else {
+            // y: S^T (sum) + DS^T fy
+            if (act) {
+    #pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    B[row + i] = u[i];
+                    Cc[row + i] = gz[i];
+                }
+            }
+            block_sync<WG>();
+    #pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T s = lS[0 * N + t] * B[0 * N + i] + lDS[0 * N + t] * Cc[0 * N + i];
+    #pragma unroll
+                for (int q = 1; q < N; ++q) s += lS[q * N + t] * B[q * N + i] + lDS[q * N + t] * Cc[q * N + i];
+                u[i] = s;
             }
         }
-        block_sync<WG>();
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T s = lS[0 * N + t] * B[0 * N + i] + lDS[0 * N + t] * Cc[0 * N + i];
-#pragma unroll
-            for (int q = 1; q < N; ++q) s += lS[q * N + t] * B[q * N + i] + lDS[q * N + t] * Cc[q * N + i];
-            u[i] = s;
-        }
+        line_apply<N, T, true>(tb.S, u, v);  // x: S^T
     }
-    line_apply<N, T, true>(tb.S, u, v);  // x: S^T
     if constexpr (SCATTER == kSlots) {
         // the next cell's first node of this line, added here where setup found
         // it to be the same DoF as this line's last node (per-node layout: in
@@ -531,7 +708,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, 
         for (int i = 0; i < N; ++i)
             if (idx[i] >= 0) atomic_add(dst + (int64_t)idx[i] * nr + rhs, v[i]);
     }
-    if (++rhs >= nr) break;
+    if (++rhs >= rhs_end) break;
     // the tiles are rewritten by the next right-hand side
     block_sync<WG>();
 #pragma unroll
@@ -563,6 +740,8 @@ __global__ __launch_bounds__((OpShape<3, N>::WG)) void elasticity_kernel(const i
                                                                          T* __restrict__ dst, OpTables<N, T> tb,
                                                                          T lam, T mu, int nr_in, int64_t plane) {
     const int nr = NRT > 0 ? NRT : nr_in;  // as in vmult_kernel
+    const int rhs0 = NRT == 0 ? (int)blockIdx.y : 0;
+    const int rhs_end = (NRT == 0 && gridDim.y > 1) ? rhs0 + 1 : nr;
     using Sh = OpShape<3, N>;
     constexpr int L = Sh::L, WG = Sh::WG, CPB = Sh::CPB, TILE = Sh::TILE;
     constexpr int NC = 21;
@@ -607,7 +786,7 @@ __global__ __launch_bounds__((OpShape<3, N>::WG)) void elasticity_kernel(const i
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int i = 0; i < N; ++i) uc[c][i] = idx[i] >= 0 ? src[((int64_t)idx[i] * 3 + c) * nr] : T(0);
+        for (int i = 0; i < N; ++i) uc[c][i] = idx[i] >= 0 ? src[((int64_t)idx[i] * 3 + c) * nr + rhs0] : T(0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int m = line + r * L;
@@ -626,10 +805,10 @@ __global__ __launch_bounds__((OpShape<3, N>::WG)) void elasticity_kernel(const i
     T* Cc = lds[2][cb];
     auto G = [&](int c, int k, int i) -> T& { return lg9[(c * 3 + k) * N + i][lane]; };
 
-    for (int rhs = 0;;) {
+    for (int rhs = rhs0;;) {
     // the next right-hand side's values are loaded while this one is swept
     T ucn[3][N];
-    if (NRT != 1 && rhs + 1 < nr) {
+    if (NRT != 1 && rhs + 1 < rhs_end) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -811,7 +990,7 @@ __global__ __launch_bounds__((OpShape<3, N>::WG)) void elasticity_kernel(const i
         }
         block_sync<WG>();
     }
-    if (++rhs >= nr) break;
+    if (++rhs >= rhs_end) break;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -834,6 +1013,24 @@ static OpTables<N, T> make_tables(const Basis1D& b) {
     return t;
 }
 
+// contribution-slot launches of one index layout and sweep form
+// (several right-hand sides: one grid row per right-hand side when the
+// precision's variant splits them, else every block loops over them)
+template <int DIM, int N, class T, int GEO, int IDX, int SW>
+static void launch_slots(const Level& L, const T* geo, const int32_t* dmap, const int32_t* slots, const void* src,
+                         void* dst, const OpTables<N, T>& tb, int nr, int64_t plane, hipStream_t s) {
+    const dim3 block(OpShape<DIM, N>::WG);
+    if (nr == 1) {
+        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 1, IDX, SW>), dim3((unsigned)L.nblocks), block, 0, s,
+                           dmap, geo, (const T*)src, slots, (T*)dst, tb, nr, plane);
+    } else {
+        const bool split = L.var[sizeof(T) == 8 ? NNMG_FP64 : NNMG_FP32].rhs_split != 0;
+        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 0, IDX, SW>),
+                           dim3((unsigned)L.nblocks, split ? (unsigned)nr : 1u), block, 0, s, dmap, geo,
+                           (const T*)src, slots, (T*)dst, tb, nr, plane);
+    }
+}
+
 template <int DIM, int N, class T, int GEO>
 static void vmult_launches(const Level& L, const T* geo, bool atomic, const void* src, void* dst, int nr,
                            hipStream_t s) {
@@ -841,6 +1038,7 @@ static void vmult_launches(const Level& L, const T* geo, bool atomic, const void
     const OpTables<N, T> tb = make_tables<N, T>(L.basis);
     const dim3 grid((unsigned)L.nblocks), block(Sh::WG);
     const int64_t plane = (int64_t)contrib_plane(L);
+    const bool sw = L.var[sizeof(T) == 8 ? NNMG_FP64 : NNMG_FP32].sweep == 1;
     if (atomic) {
         if (nr == 1)
             hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kAtomic, 1>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
@@ -850,22 +1048,20 @@ static void vmult_launches(const Level& L, const T* geo, bool atomic, const void
                                (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane);
     } else if (L.var[sizeof(T) == 8 ? NNMG_FP64 : NNMG_FP32].index_layout == 1) {
         if constexpr (DIM == 3 && N >= 4) {
-            if (nr == 1)
-                hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 1, kIdxEntity>), grid, block, 0, s,
-                                   L.d_ent_rec.ptr, geo, (const T*)src, nullptr, (T*)dst, tb, nr, plane);
+            if (sw)
+                launch_slots<DIM, N, T, GEO, kIdxEntity, 1>(L, geo, L.d_ent_rec.ptr, nullptr, src, dst, tb, nr, plane, s);
             else
-                hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 0, kIdxEntity>), grid, block, 0, s,
-                                   L.d_ent_rec.ptr, geo, (const T*)src, nullptr, (T*)dst, tb, nr, plane);
+                launch_slots<DIM, N, T, GEO, kIdxEntity, 0>(L, geo, L.d_ent_rec.ptr, nullptr, src, dst, tb, nr, plane, s);
         } else {
             fail(NNMG_ERR_UNSUPPORTED, "entity records: 3D, degree >= 3");
         }
     } else {
-        if (nr == 1)
-            hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 1>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
-                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane);
+        if (sw)
+            launch_slots<DIM, N, T, GEO, kIdxNodes, 1>(L, geo, L.d_dofmap_blk.ptr, L.d_pos_blk.ptr, src, dst, tb, nr,
+                                                      plane, s);
         else
-            hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 0>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
-                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane);
+            launch_slots<DIM, N, T, GEO, kIdxNodes, 0>(L, geo, L.d_dofmap_blk.ptr, L.d_pos_blk.ptr, src, dst, tb, nr,
+                                                      plane, s);
     }
     NNMG_HIP(hipGetLastError());
 }
@@ -884,7 +1080,10 @@ static void vmult_dispatch(const Level& L, const T* geo, int mode, bool atomic, 
                                    s, L.d_dofmap_blk.ptr, geo, (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, (T)L.lam,
                                    (T)L.mu, nr, plane);
             else
-                hipLaunchKernelGGL((elasticity_kernel<N, T, 0>), dim3((unsigned)L.nblocks), dim3(OpShape<3, N>::WG), 0,
+                hipLaunchKernelGGL((elasticity_kernel<N, T, 0>),
+                                   dim3((unsigned)L.nblocks,
+                                        L.var[sizeof(T) == 8 ? NNMG_FP64 : NNMG_FP32].rhs_split ? (unsigned)nr : 1u),
+                                   dim3(OpShape<3, N>::WG), 0,
                                    s, L.d_dofmap_blk.ptr, geo, (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, (T)L.lam,
                                    (T)L.mu, nr, plane);
             NNMG_HIP(hipGetLastError());

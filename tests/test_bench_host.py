@@ -97,21 +97,28 @@ def test_committed_traffic_summaries_parse():
 def test_operator_kernel_names_follow_degree_and_variant():
     lv = SimpleNamespace(dim=3, degree=4, operator="laplace", VARIANTS=("trilinear+slots", "trilinear+atomic",
                                                                         "metric+slots", "metric+atomic",
-                                                                        "trilinear+entity", "metric+entity"),
+                                                                        "trilinear+entity", "metric+entity",
+                                                                        "trilinear+slots+transposed", None,
+                                                                        "metric+slots+transposed", None,
+                                                                        "trilinear+entity+transposed",
+                                                                        "metric+entity+transposed"),
                          variant=0)
     lv.variant_of = lambda dtype: lv.variant
-    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1, 0>",
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1, 0, 0>",
                                                   "gather_kernel<1, 1, double>"]
     lv.variant = 2
-    assert bench.operator_kernel_names(lv, 4, nr=4) == ["vmult_kernel<3, 5, float, 0, 0, 0, 0>",
+    assert bench.operator_kernel_names(lv, 4, nr=4) == ["vmult_kernel<3, 5, float, 0, 0, 0, 0, 0>",
                                                         "gather_kernel<1, 4, float>"]
     lv.variant = 3
-    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 0, 1, 1, 0>"]
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 0, 1, 1, 0, 0>"]
     lv.variant = 4
-    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1, 1>",
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1, 1, 0>",
                                                   "gather_kernel<1, 1, double>"]
     lv.variant = 5
-    assert bench.operator_kernel_names(lv, 4) == ["vmult_kernel<3, 5, float, 0, 0, 1, 1>",
+    assert bench.operator_kernel_names(lv, 4) == ["vmult_kernel<3, 5, float, 0, 0, 1, 1, 0>",
+                                                  "gather_kernel<1, 1, float>"]
+    lv.variant = 10
+    assert bench.operator_kernel_names(lv, 4) == ["vmult_kernel<3, 5, float, 1, 0, 1, 1, 1>",
                                                   "gather_kernel<1, 1, float>"]
     el = SimpleNamespace(dim=3, degree=2, operator="elasticity")
     assert bench.operator_kernel_names(el, 8, nr=4) == ["elasticity_kernel<3, double, 0>",

@@ -48,7 +48,7 @@ def test_entity_variants_match_assembled_operator(ctx, k, n, scram):
     free = p.orc.free
     base = random_vector(p.orc.n_dofs, 9)
     expect_add = base + np.where(free, p.A @ np.where(free, x, 0.0), 0.0)
-    for v in (4, 5):
+    for v in (4, 5, 10, 11):
         p.lib.set_variant(v)
         assert p.lib.variant == v
         for dt, tol in ((torch.float64, TOL64), (torch.float32, TOL32)):
@@ -82,7 +82,7 @@ def test_each_precision_keeps_its_own_variant(ctx):
         assert rel_err(p.to_orc(p.lib.vmult(p.to_lib(x, torch.float64))), ref) <= TOL64
         assert rel_err(p.to_orc(p.lib.vmult(p.to_lib(x, torch.float32))), ref) <= TOL32
     r = p.lib.tune(torch.float32, reps=2)
-    assert set(r["ms"]) == {"trilinear+slots", "metric+slots", "trilinear+entity", "metric+entity"}
+    assert set(r["ms"]) == {"trilinear+slots", "metric+slots", "trilinear+slots+transposed", "metric+slots+transposed"} | {"trilinear+entity", "metric+entity", "trilinear+entity+transposed", "metric+entity+transposed"}
     assert p.lib.VARIANTS[p.lib.variant_of(torch.float32)] == r["chosen"]
     assert p.lib.variant_of(torch.float64) == 4  # untouched by the float32 tuning
 
@@ -93,7 +93,7 @@ def test_entity_variant_not_offered_below_degree_3(ctx):
     with pytest.raises(nn.NNMGError):
         lv.set_variant(4)
     r = lv.tune(torch.float32, reps=2)
-    assert set(r["ms"]) == {"trilinear+slots", "metric+slots"}
+    assert set(r["ms"]) == {"trilinear+slots", "metric+slots", "trilinear+slots+transposed", "metric+slots+transposed"}
 
 
 @pytest.mark.parametrize("cells,k", [([3, 5, 9], 3), ([3, 7], 4)])

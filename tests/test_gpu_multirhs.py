@@ -42,11 +42,15 @@ def _same(a: torch.Tensor, b: torch.Tensor):
 @pytest.mark.parametrize("operator,cfg,cells,k", [("laplace", 1, [5, 11], 2), ("laplace", 2, [3, 7], 3),
                                                   ("laplace", 0, [6, 13], 1), ("elasticity", 3, [(3, 1, 1), (7, 2, 2)], 2)])
 @pytest.mark.parametrize("nr", [2, 3, 8])
-def test_operator_and_transfers_match_single(ctx, operator, cfg, cells, k, nr):
+@pytest.mark.parametrize("split", [False, True], ids=["loop", "split"])
+def test_operator_and_transfers_match_single(ctx, operator, cfg, cells, k, nr, split):
+    """split: one row of workgroups per right-hand side instead of a loop."""
     import paper_2412_10910_amd as nn
     coarse_m, fine_m = config_levels(cfg, cells=cells)
     fine = nn.Level.from_mesh(ctx, fine_m, k, operator)
     coarse = nn.Level.from_mesh(ctx, coarse_m, k, operator)
+    for dt in (torch.float64, torch.float32):
+        fine.set_rhs_split(split, dt)
     tr = nn.Transfer(ctx, fine, coarse)
     for dt in (torch.float64, torch.float32):
         X = _columns(fine.n_dofs, nr, 11, dt)
@@ -77,8 +81,12 @@ def _hierarchy(ctx, cfg, cells, k, operator="laplace"):
 
 @pytest.mark.parametrize("operator,cfg,cells,k", [("laplace", 1, [3, 6, 13], 2),
                                                   ("elasticity", 3, [(3, 1, 1), (7, 2, 2), (14, 3, 3)], 2)])
-def test_vcycle_and_pcg_match_single(ctx, operator, cfg, cells, k):
+@pytest.mark.parametrize("split", [False, True], ids=["loop", "split"])
+def test_vcycle_and_pcg_match_single(ctx, operator, cfg, cells, k, split):
     H, levels = _hierarchy(ctx, cfg, cells, k, operator)
+    for lv in levels:
+        for dt in (torch.float64, torch.float32):
+            lv.set_rhs_split(split, dt)
     fine = levels[-1]
     free = ~fine.constrained()
     nr = 4
