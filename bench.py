@@ -302,7 +302,11 @@ def kernel_source_hash():
 
 def recorded_traffic(tag):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary,
-    or {} when it is missing or was taken on kernel sources that have changed."""
+    or {} when it is missing or was taken on kernel sources that have changed.
+    Keys: the roofline entries (operator_fp64, ...) and, per kernel, the
+    operator kernels of every variant the tuner ran ("kernel:<name>", the
+    fine-level gather as "kernel:<name>@fine"), so that an operator entry is
+    priced by the variant the tuner chose in this run."""
     try:
         lines = open(traffic_file(tag)).read().splitlines()
     except OSError:
@@ -314,11 +318,26 @@ def recorded_traffic(tag):
             kv[k.strip()] = v.strip()
     if kv.get("kernel_sources_sha256_16") != kernel_source_hash():
         return {}
-    return {k[len("traffic_bytes."):]: float(v) for k, v in kv.items() if k.startswith("traffic_bytes.")}
+    out = {k[len("traffic_bytes."):]: float(v) for k, v in kv.items() if k.startswith("traffic_bytes.")}
+    out.update({"kernel:" + k[len("traffic_kernel."):]: float(v) for k, v in kv.items()
+                if k.startswith("traffic_kernel.")})
+    return out
+
+
+def entry_traffic(traffic, key, v):
+    """Measured bytes of one roofline entry: the sum over its launches where
+    the per-kernel values were recorded (operators), else the entry's value."""
+    names = v.get("launches")
+    if names:
+        keys = ["kernel:" + names[0]] + ["kernel:" + n + "@fine" for n in names[1:]]
+        if all(k in traffic for k in keys):
+            return sum(traffic[k] for k in keys)
+        return None
+    return traffic.get(key)
 
 
 def operator_kernel_names(level, word, nr=1):
-    """The kernels one operator application (Level.vmult_add) launches, named
+    """The kernels one operator application (Level.vmult, dst = A src) launches, named
     as the kernel trace names them, for the level's degree and operator variant
     (vmult_kernel<dim, n, T, geometry, scatter, nrt, index layout, sweep>), with the
     operator variant of the precision of that word size."""
@@ -326,15 +345,17 @@ def operator_kernel_names(level, word, nr=1):
     n = level.degree + 1
     nrt = 1 if nr == 1 else 0
     if level.operator == "elasticity":
-        return [f"elasticity_kernel<{n}, {T}, {nrt}>", f"gather_kernel<3, {nr}, {T}>"]
+        return [f"elasticity_kernel<{n}, {T}, {nrt}>", f"gather_kernel<3, {nr}, {T}>", f"copy_idx_kernel<{T}>"]
     import torch
     variant = level.VARIANTS[level.variant_of(torch.float64 if word == 8 else torch.float32)]
     geo = 1 if variant.startswith("trilinear") else 0
     sw = 1 if variant.endswith("+transposed") else 0
     if variant.endswith("atomic"):
-        return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 1, {nrt}, 0, 0>"]
+        return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 1, {nrt}, 0, 0>", f"fill_kernel<{T}>",
+                f"copy_idx_kernel<{T}>"]
     idx = 1 if "+entity" in variant else 0
-    return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 0, {nrt}, {idx}, {sw}>", f"gather_kernel<1, {nr}, {T}>"]
+    return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 0, {nrt}, {idx}, {sw}>", f"gather_kernel<1, {nr}, {T}>",
+            f"copy_idx_kernel<{T}>"]
 
 
 def time_launches(fn, reps):
@@ -368,7 +389,9 @@ def kernel_rooflines(fine, coarse, transfer, reps, nr=1):
             dst = torch.zeros_like(src)
             csrc = torch.rand(shape_c, dtype=torch.float64, device=dev).to(dt)
             cdst = torch.zeros_like(csrc)
-            ms = time_launches(lambda: fine.vmult_add(src, dst), reps)
+            # the operator application dst = A src (nnmg_vmult): the cell
+            # kernel, the gather that writes dst, the identity on constrained rows
+            ms = time_launches(lambda: fine.vmult(src, dst), reps)
             out[f"operator_{tag}{sfx}"] = dict(ms=ms, bytes=vmult_bytes(fine, word, r),
                                                launches=operator_kernel_names(fine, word, r))
             ms = time_launches(lambda: transfer.prolongate(csrc, dst), reps)
@@ -399,7 +422,7 @@ def kernel_entry(v, traffic):
 def roofline_entry(k, key, traffic, fine, word, nr, what):
     """The roofline object of the line for the dominant kernel `key`."""
     op = k[key]
-    t = traffic.get(key)
+    t = entry_traffic(traffic, key, op)
     names = op.get("launches", [])
     out = {
         "bound": "hbm",
@@ -415,7 +438,7 @@ def roofline_entry(k, key, traffic, fine, word, nr, what):
                   "read a metric, so achieved/frac are effective rates; traffic_rate is the measured one)"),
         "bytes_per_launch": op["bytes"],
         "ms_per_launch": round(op["ms"], 5),
-        "kernels": {n: kernel_entry(v, traffic.get(n)) for n, v in k.items()},
+        "kernels": {n: kernel_entry(v, entry_traffic(traffic, n, v)) for n, v in k.items()},
     }
     if t:
         out["traffic_rate"] = round(t / (op["ms"] * 1e-3) / 1e9, 1)
@@ -807,9 +830,11 @@ def main():
         tr = nn.Transfer(ctx, fine, coarse)
         if not args.no_tune:
             # the kernels the tuned solve runs: one operator variant per precision
+            # the fine level's operator variants only: the restriction team
+            # stays at its default, so that every profiling pass of this
+            # command launches the same transfer kernels
             for dt in (torch.float64, torch.float32):
                 fine.tune(dt, reps=10)
-            tr.tune(torch.float64, reps=10)
         nbytes = copy_calibration()
         k = kernel_rooflines(fine, coarse, tr, args.roofline_reps, args.roofline_rhs)
         print(json.dumps({"roofline_only": True, "workload": args.roofline_workload, "copy_bytes": nbytes,

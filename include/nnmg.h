@@ -218,7 +218,8 @@ int nnmg_vmult(const nnmg_level* level, nnmg_prec prec, const void* src_dev, voi
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same result, computed by the same kernels in the same order (the
  * deterministic contribution-slot path, whatever variant the level is tuned
- * to), with the per-(cell, node) contribution slots kept in one static device
+ * to, where nnmg_vmult takes the slot path), with the per-(cell, node)
+ * contribution slots kept in one static device
  * array of 64 MiB per GPU (held from the library's loading until the process
  * ends) instead of the level's own buffer.  The call allocates nothing and
  * calls no allocating routine.  Arguments as for nnmg_vmult (one right-hand

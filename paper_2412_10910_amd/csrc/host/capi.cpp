@@ -246,8 +246,17 @@ static void vmult_impl(const nnmg_level* l, int prec, int nr, const void* src, v
     Level& L = const_cast<nnmg_level&>(*l);
     level_reserve_rhs(L, nr);
     const hipStream_t s = as_stream(stream);
-    if (!add) launch_fill(dst, (size_t)L.n_dofs * (size_t)nr, prec, s);
-    launch_vmult_cells(L, prec, src, dst, s, nr, L.d_contrib.ptr);
+    if (add) {
+        launch_vmult_cells(L, prec, src, dst, s, nr, L.d_contrib.ptr);
+    } else if (L.var[prec].atomic && L.op == NNMG_OP_LAPLACE) {
+        launch_fill(dst, (size_t)L.n_dofs * (size_t)nr, prec, s);  // the atomics add into dst
+        launch_vmult_cells(L, prec, src, dst, s, nr, L.d_contrib.ptr);
+    } else {
+        // every unconstrained value has contribution slots, so the gather
+        // writes all of them: no fill and no read of dst
+        launch_vmult_contrib(L, prec, src, L.d_contrib.ptr, s, nr);
+        launch_gather(L, prec, L.d_contrib.ptr, dst, false, s, nr);
+    }
     if (!add)
         launch_copy_constrained(L.d_constrained.ptr, L.constrained_idx.size(), src, dst, prec, s, nr);
 }

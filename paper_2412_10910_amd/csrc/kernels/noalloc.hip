@@ -56,10 +56,10 @@ void vmult_noalloc(const Level& L, int prec, const void* src, void* dst, void* s
                                        " bytes of contribution slots in this precision; the static scratch holds " +
                                        std::to_string(kNoallocScratchBytes) + " (use nnmg_vmult)");
     // the same kernels as nnmg_vmult's slot path, with the slots in the static
-    // array: fill, cell kernel, gather into dst, identity on constrained rows
-    launch_fill(dst, (size_t)L.n_dofs, prec, s);
+    // array: cell kernel, gather into dst (every unconstrained value has
+    // slots, so it writes all of them), identity on constrained rows
     launch_vmult_contrib(L, prec, src, scratch_dev, s, 1);
-    launch_gather(L, prec, scratch_dev, dst, true, s, 1);
+    launch_gather(L, prec, scratch_dev, dst, false, s, 1);
     launch_copy_constrained(L.d_constrained.ptr, L.constrained_idx.size(), src, dst, prec, s, 1);
 }
 

@@ -79,6 +79,19 @@ def test_recorded_traffic_is_dropped_when_the_kernels_changed(tmp_path, monkeypa
     assert bench.recorded_traffic("missing") == {}
 
 
+def test_operator_traffic_follows_the_variant_that_ran():
+    traffic = {"operator_fp64": 1.0, "kernel:vmult_kernel<3, 5, double, 1, 0, 1, 0, 1>": 100.0,
+               "kernel:gather_kernel<1, 1, double>@fine": 20.0, "kernel:copy_idx_kernel<double>@fine": 1.5,
+               "prolongate_fp64": 7.0}
+    ran = {"launches": ["vmult_kernel<3, 5, double, 1, 0, 1, 0, 1>", "gather_kernel<1, 1, double>",
+                        "copy_idx_kernel<double>"]}
+    other = {"launches": ["vmult_kernel<3, 5, double, 1, 0, 1, 1, 0>", "gather_kernel<1, 1, double>",
+                          "copy_idx_kernel<double>"]}
+    assert bench.entry_traffic(traffic, "operator_fp64", ran) == 121.5
+    assert bench.entry_traffic(traffic, "operator_fp64", other) is None  # not profiled: no claim
+    assert bench.entry_traffic(traffic, "prolongate_fp64", {}) == 7.0
+
+
 def test_committed_traffic_summaries_parse():
     keys = {"operator_fp64", "operator_fp32", "prolongate_fp64", "prolongate_fp32", "restrict_fp64",
             "restrict_fp32"}
@@ -105,24 +118,25 @@ def test_operator_kernel_names_follow_degree_and_variant():
                          variant=0)
     lv.variant_of = lambda dtype: lv.variant
     assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1, 0, 0>",
-                                                  "gather_kernel<1, 1, double>"]
+                                                  "gather_kernel<1, 1, double>", "copy_idx_kernel<double>"]
     lv.variant = 2
     assert bench.operator_kernel_names(lv, 4, nr=4) == ["vmult_kernel<3, 5, float, 0, 0, 0, 0, 0>",
-                                                        "gather_kernel<1, 4, float>"]
+                                                        "gather_kernel<1, 4, float>", "copy_idx_kernel<float>"]
     lv.variant = 3
-    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 0, 1, 1, 0, 0>"]
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 0, 1, 1, 0, 0>", "fill_kernel<double>",
+                                                  "copy_idx_kernel<double>"]
     lv.variant = 4
     assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1, 1, 0>",
-                                                  "gather_kernel<1, 1, double>"]
+                                                  "gather_kernel<1, 1, double>", "copy_idx_kernel<double>"]
     lv.variant = 5
     assert bench.operator_kernel_names(lv, 4) == ["vmult_kernel<3, 5, float, 0, 0, 1, 1, 0>",
-                                                  "gather_kernel<1, 1, float>"]
+                                                  "gather_kernel<1, 1, float>", "copy_idx_kernel<float>"]
     lv.variant = 10
     assert bench.operator_kernel_names(lv, 4) == ["vmult_kernel<3, 5, float, 1, 0, 1, 1, 1>",
-                                                  "gather_kernel<1, 1, float>"]
+                                                  "gather_kernel<1, 1, float>", "copy_idx_kernel<float>"]
     el = SimpleNamespace(dim=3, degree=2, operator="elasticity")
     assert bench.operator_kernel_names(el, 8, nr=4) == ["elasticity_kernel<3, double, 0>",
-                                                        "gather_kernel<3, 4, double>"]
+                                                        "gather_kernel<3, 4, double>", "copy_idx_kernel<double>"]
 
 
 def test_default_workload_is_the_largest_single_gpu_ball():

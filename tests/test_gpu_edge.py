@@ -111,3 +111,25 @@ def test_rhs_counts_out_of_range(ctx):
             lv.vmult(X)
         with pytest.raises(nn.NNMGError):
             H.vcycle(X)
+
+
+@pytest.mark.parametrize("cells", [(1, 1, 1), (1, 5, 4), (2, 3, 3), (13, 1, 2)])
+@pytest.mark.parametrize("dirichlet", [True, False])
+def test_operator_variants_on_edge_meshes(ctx, cells, dirichlet):
+    """Every operator variant (per-node or entity-compressed indices, base or
+    transposed sweeps, trilinear or stored geometry) on single cells and on
+    meshes one or two cells thick, where x-runs are shorter than a block and
+    many entities are constrained or shared by few cells."""
+    hi = tuple(0.3 * c for c in cells)
+    m = structured_brick(cells, (0.0, 0.0, 0.0), hi)
+    m = perturb_interior(m, 0.2, [hi[a] / cells[a] for a in range(3)], np.random.default_rng(7 + sum(cells)))
+    if not dirichlet:
+        m.dirichlet[:] = 0
+    for k in (3, 4):
+        p = Pair(ctx, m, k)
+        x = random_vector(p.orc.n_dofs, 9)
+        ref = p.A @ x
+        for v in (0, 2, 4, 5, 6, 8, 10, 11):
+            p.lib.set_variant(v)
+            for dt, tol in ((torch.float64, 1e-12), (torch.float32, 2e-5)):
+                assert rel_err(p.to_orc(p.lib.vmult(p.to_lib(x, dt))), ref) <= tol, (k, v, dt)

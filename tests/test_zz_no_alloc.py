@@ -78,3 +78,21 @@ def test_noalloc_rejects_a_level_beyond_the_static_array(ctx):
     assert torch.count_nonzero(dst) == 0  # nothing ran
     ref, out = _both(lv, x64.float())
     assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("variant", [4, 10, 6])
+def test_noalloc_follows_the_level_variant(ctx, variant):
+    """The static-scratch call runs the level's tuned slot variant (entity
+    records, transposed sweeps) with the same bits as nnmg_vmult, and an
+    elasticity level (three values per slot) after it."""
+    import paper_2412_10910_amd as nn
+    lv = nn.Level.from_mesh(ctx, config_levels(2, cells=[6])[0], 4)
+    lv.set_variant(variant)
+    for dtype, seed in ((torch.float64, 21), (torch.float32, 22)):
+        x = torch.tensor(random_vector(lv.n_dofs, seed), dtype=dtype, device="cuda:0")
+        ref, out = _both(lv, x)
+        assert torch.equal(out, ref)
+    el = nn.Level.from_mesh(ctx, config_levels(3, cells=[(7, 2, 2)])[0], 2, "elasticity")
+    x = torch.tensor(random_vector(el.n_dofs, 23), dtype=torch.float64, device="cuda:0")
+    ref, out = _both(el, x)
+    assert torch.equal(out, ref)
