@@ -339,23 +339,26 @@ def entry_traffic(traffic, key, v):
 def operator_kernel_names(level, word, nr=1):
     """The kernels one operator application (Level.vmult, dst = A src) launches, named
     as the kernel trace names them, for the level's degree and operator variant
-    (vmult_kernel<dim, n, T, geometry, scatter, nrt, index layout, sweep>), with the
-    operator variant of the precision of that word size."""
+    (vmult_kernel<dim, n, T, geometry, scatter, nrt, index layout, sweep, layout
+    blocks per workgroup>), with the operator variant of the precision of that
+    word size."""
     T = "double" if word == 8 else "float"
     n = level.degree + 1
     nrt = 1 if nr == 1 else 0
     if level.operator == "elasticity":
         return [f"elasticity_kernel<{n}, {T}, {nrt}>", f"gather_kernel<3, {nr}, {T}>", f"copy_idx_kernel<{T}>"]
     import torch
-    variant = level.VARIANTS[level.variant_of(torch.float64 if word == 8 else torch.float32)]
+    dt = torch.float64 if word == 8 else torch.float32
+    variant = level.VARIANTS[level.variant_of(dt)]
     geo = 1 if variant.startswith("trilinear") else 0
     sw = 1 if variant.endswith("+transposed") else 0
     if variant.endswith("atomic"):
-        return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 1, {nrt}, 0, 0>", f"fill_kernel<{T}>",
+        return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 1, {nrt}, 0, 0, 1>", f"fill_kernel<{T}>",
                 f"copy_idx_kernel<{T}>"]
     idx = 1 if "+entity" in variant else 0
-    return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 0, {nrt}, {idx}, {sw}>", f"gather_kernel<1, {nr}, {T}>",
-            f"copy_idx_kernel<{T}>"]
+    cells, base = level.cells_per_block(dt)[:2]
+    return [f"vmult_kernel<{level.dim}, {n}, {T}, {geo}, 0, {nrt}, {idx}, {sw}, {cells // base}>",
+            f"gather_kernel<1, {nr}, {T}>", f"copy_idx_kernel<{T}>"]
 
 
 def time_launches(fn, reps):
@@ -634,6 +637,9 @@ def run_pcg_workload(name, args, ctx, nn, torch, steps, warmup, with_cpu):
         t_tune = time.perf_counter() - t0
         tuned = dict(levels_fp64=[r["chosen"] for r in rep["levels"]],
                      levels_fp32=[r["chosen"] for r in rep32],
+                     cells_per_block_fp64=[r["cells_per_block"] for r in rep["levels"]],
+                     cells_per_block_fp32=[r["cells_per_block"] for r in rep32],
+                     fine_ms_cells_fp64=rep["levels"][-1]["ms_cells"], fine_ms_cells_fp32=rep32[-1]["ms_cells"],
                      restriction_teams=[r["chosen"] for r in rep["transfers"]])
     fine = levels[-1]
     nr = args.rhs if args.rhs is not None else wl.get("rhs", 1)

@@ -311,6 +311,9 @@ typedef struct {
                         every block loops over them (0) */
     double ms_rhs[2]; /* nnmg_level_tune: milliseconds of the 4-right-hand-side product looping (0) and
                          split (1), timed on small levels only (-1 otherwise) */
+    int cells_per_block; /* nnmg_level_tune: cells per workgroup of the operator kept */
+    double ms_cpb[2];    /* nnmg_level_tune: milliseconds of the variant kept with one (0) and two (1)
+                            layout blocks per workgroup (-1 where not timed) */
 } nnmg_tune_result;
 
 /* Times the variants of the level's operator application in precision `prec`
@@ -336,8 +339,11 @@ typedef struct {
  * 10, 11) are timed, so a
  * tuned level stays bitwise reproducible; the others keep ms = -1 and are
  * taken only when forced.  The stored metric is computed when a precision
- * needs it and freed when none does.  Synchronizes the device; hierarchies
- * holding the level re-capture their V-cycle graphs.
+ * needs it and freed when none does.  For the variant kept it then times one
+ * and two layout blocks per workgroup (nnmg_level_set_cells_per_block) and,
+ * on small levels, the two forms of several right-hand sides
+ * (nnmg_level_set_rhs_split), keeping the faster of each.  Synchronizes the
+ * device; hierarchies holding the level re-capture their V-cycle graphs.
  * nnmg_level_set_variant forces a variant for both precisions,
  * nnmg_level_set_variant_prec for one; nnmg_level_variant reads the variant
  * of one precision. */
@@ -352,6 +358,24 @@ int nnmg_level_variant(const nnmg_level* level, nnmg_prec prec, int* variant);
  * per launch) and keeps the faster.  Same results either way (each
  * right-hand side is summed in the same order). */
 int nnmg_level_set_rhs_split(nnmg_level* level, nnmg_prec prec, int split);
+/* Cells per workgroup of the operator kernels (the tile each workgroup
+ * sweeps).  The level's data are laid out in blocks of `layout_cells` cells
+ * (3D: 16, 7, 4, 5 for degree 1..4; 2D: 64 / (k+1)), one block per wavefront
+ * (degree 4 in 3D: two); a workgroup takes one block or two consecutive ones,
+ * `cells` = layout_cells or 2 layout_cells.  The two layout blocks of a
+ * workgroup keep separate LDS regions and sum in the same order as alone, so
+ * the results are bitwise the same either way.  Two blocks apply to the
+ * Laplace contribution-slot variants; the atomic variants and the elasticity
+ * operator take one (setting two there: NNMG_ERR_UNSUPPORTED for elasticity,
+ * ignored by the atomic variants, which report layout_cells).
+ * nnmg_level_tune times both for the variant it keeps and keeps the faster.
+ * nnmg_level_cells_per_block also returns the number of layout blocks (with
+ * two per workgroup, an odd count leaves the last workgroup half idle).
+ * Other values of `cells`: NNMG_ERR_INVALID_ARG.  Synchronizes the device;
+ * hierarchies holding the level re-capture their graphs. */
+int nnmg_level_set_cells_per_block(nnmg_level* level, nnmg_prec prec, int cells);
+int nnmg_level_cells_per_block(const nnmg_level* level, nnmg_prec prec, int* cells, int* layout_cells,
+                               int64_t* layout_blocks);
 
 /* Times the restriction (paper §2, eq. residual2) with 4 << v lanes per
  * coarse cell, v = 0..4, and keeps the fastest (same contract as

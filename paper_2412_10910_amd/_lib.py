@@ -96,7 +96,8 @@ class CgResult(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("n_variants", C.c_int), ("ms", C.c_double * 16), ("chosen", C.c_int),
-                ("rhs_split", C.c_int), ("ms_rhs", C.c_double * 2)]
+                ("rhs_split", C.c_int), ("ms_rhs", C.c_double * 2),
+                ("cells_per_block", C.c_int), ("ms_cpb", C.c_double * 2)]
 
 
 class ServerOpts(C.Structure):
@@ -172,6 +173,8 @@ SIGNATURES = {
     "nnmg_level_set_variant_prec": (C.c_int, [_vp, C.c_int, C.c_int]),
     "nnmg_level_variant": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int)]),
     "nnmg_level_set_rhs_split": (C.c_int, [_vp, C.c_int, C.c_int]),
+    "nnmg_level_set_cells_per_block": (C.c_int, [_vp, C.c_int, C.c_int]),
+    "nnmg_level_cells_per_block": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _i64p]),
     "nnmg_transfer_tune": (C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(TuneResult)]),
     "nnmg_transfer_set_team": (C.c_int, [_vp, C.c_int]),
     "nnmg_transfer_team": (C.c_int, [_vp, C.POINTER(C.c_int)]),

@@ -229,7 +229,24 @@ class Level:
         check(lib().nnmg_level_tune(self.handle, _DTYPE_PREC[dtype], int(reps), C.byref(res)))
         return dict(ms={self.VARIANTS[v]: res.ms[v] for v in range(res.n_variants) if res.ms[v] >= 0},
                     chosen=self.VARIANTS[res.chosen], rhs_split=bool(res.rhs_split),
-                    ms_rhs4={"loop": res.ms_rhs[0], "split": res.ms_rhs[1]} if res.ms_rhs[0] >= 0 else None)
+                    ms_rhs4={"loop": res.ms_rhs[0], "split": res.ms_rhs[1]} if res.ms_rhs[0] >= 0 else None,
+                    cells_per_block=res.cells_per_block,
+                    ms_cells={"one block": res.ms_cpb[0], "two blocks": res.ms_cpb[1]}
+                    if res.ms_cpb[0] >= 0 else None)
+
+    def set_cells_per_block(self, cells: int, dtype=None):
+        """Cells per workgroup of the operator: one layout block or two
+        (nnmg_level_set_cells_per_block), for one precision or both (dtype None)."""
+        for dt in ((torch.float64, torch.float32) if dtype is None else (dtype,)):
+            check(lib().nnmg_level_set_cells_per_block(self.handle, _DTYPE_PREC[dt], int(cells)))
+
+    def cells_per_block(self, dtype=torch.float64) -> tuple:
+        """(cells per workgroup in use, cells per layout block, layout blocks) of
+        the `dtype` kernels."""
+        c, base, nb = C.c_int(), C.c_int(), C.c_int64()
+        check(lib().nnmg_level_cells_per_block(self.handle, _DTYPE_PREC[dtype], C.byref(c), C.byref(base),
+                                               C.byref(nb)))
+        return c.value, base.value, nb.value
 
     def set_rhs_split(self, split: bool, dtype=torch.float64):
         """Several right-hand sides: one row of workgroups each (True) or every

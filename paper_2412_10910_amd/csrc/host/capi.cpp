@@ -502,6 +502,27 @@ int nnmg_level_set_rhs_split(nnmg_level* level, nnmg_prec prec, int split) {
     });
 }
 
+int nnmg_level_set_cells_per_block(nnmg_level* level, nnmg_prec prec, int cells) {
+    return guarded([&] {
+        if (!level) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        level_set_cells_per_block(*level, prec, cells);
+        return NNMG_OK;
+    });
+}
+
+int nnmg_level_cells_per_block(const nnmg_level* level, nnmg_prec prec, int* cells, int* layout_cells,
+                               int64_t* layout_blocks) {
+    return guarded([&] {
+        if (!level || !cells || !layout_cells || !layout_blocks) fail(NNMG_ERR_INVALID_ARG, "NULL argument");
+        if (prec != NNMG_FP64 && prec != NNMG_FP32) fail(NNMG_ERR_INVALID_ARG, "precision");
+        *cells = level_cells_per_block(*level, prec);
+        *layout_cells = level->cpb;
+        *layout_blocks = level->nblocks;
+        return NNMG_OK;
+    });
+}
+
 int nnmg_level_variant(const nnmg_level* level, nnmg_prec prec, int* variant) {
     return guarded([&] {
         if (!level || !variant) fail(NNMG_ERR_INVALID_ARG, "NULL argument");

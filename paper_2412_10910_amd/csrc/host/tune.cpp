@@ -9,14 +9,16 @@
 //   3  stored merged metric per Gauss point,    float atomics into the output
 //   4  as 0, with the entity-compressed indices (one record per cell)
 //   5  as 2, with the entity-compressed indices
-// With several right-hand sides, a small level (a grid of few wavefronts)
-// also times one grid row per right-hand side against every block looping
-// over them, with four right-hand sides, and keeps the faster.
 //   6..11  as 0..5 with the transposed sweeps: the lanes of a cell swap the
 //          line they own through LDS between the contraction stages, so
 //          every contraction runs in registers (7 and 9, atomics, do not exist)
 // Variants 4, 5, 10 and 11 exist for 3D Laplace levels of degree >= 3 (where
-// the records were built).  The elasticity operator has variant 0 only.  Transfer variants: the lanes
+// the records were built).  The elasticity operator has variant 0 only.
+// Two further axes are timed for the variant kept: the cells per workgroup
+// (one or two layout blocks of cpb cells per workgroup, Laplace slot
+// variants), and, on a small level (a grid of few wavefronts), several
+// right-hand sides as one grid row per right-hand side against every block
+// looping over them (four right-hand sides).  Transfer variants: the lanes
 // per coarse cell of the restriction, 4 << v for v = 0..4.
 //
 // Each precision has its own variant: the float64 and float32 kernels of one
@@ -113,9 +115,11 @@ void apply_variant(Level& L, int prec, int v) {
     if (st.geometry_mode == 0) ensure_metric(L);
     for (int p = 0; p < 2; ++p)
         if (prec < 0 || prec == p) {
-            const int split = L.var[p].rhs_split;  // a separate choice (level_tune)
+            // separate choices (level_tune): kept across variant changes
+            const int split = L.var[p].rhs_split, group = L.var[p].group;
             L.var[p] = st;
             L.var[p].rhs_split = split;
+            L.var[p].group = group;
         }
     if (L.var[0].geometry_mode == 1 && L.var[1].geometry_mode == 1) {
         // no precision reads the stored metric any more
@@ -147,6 +151,23 @@ void level_set_rhs_split(Level& L, int prec, int split) {
         if (prec < 0 || prec == p) L.var[p].rhs_split = split;
     ++L.config_version;
 }
+
+void level_set_cells_per_block(Level& L, int prec, int cells) {
+    int group = 0;
+    if (cells == L.cpb) group = 1;
+    else if (cells == 2 * L.cpb) group = 2;
+    else fail(NNMG_ERR_INVALID_ARG, "cells per block must be " + std::to_string(L.cpb) + " or " +
+                                        std::to_string(2 * L.cpb) + " on this level");
+    if (group == 2 && L.op != NNMG_OP_LAPLACE)
+        fail(NNMG_ERR_UNSUPPORTED, "the elasticity operator runs one layout block per workgroup");
+    NNMG_HIP(hipSetDevice(L.ctx->device));
+    NNMG_HIP(hipDeviceSynchronize());
+    for (int p = 0; p < 2; ++p)
+        if (prec < 0 || prec == p) L.var[p].group = group;
+    ++L.config_version;
+}
+
+int level_cells_per_block(const Level& L, int prec) { return L.var[prec].atomic ? L.cpb : L.var[prec].group * L.cpb; }
 
 void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res) {
     if (reps < 1) fail(NNMG_ERR_INVALID_ARG, "reps must be positive");
@@ -181,6 +202,23 @@ void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res) {
         }
         apply_variant(L, prec, best);
         res->chosen = best;
+        // cells per workgroup: one or two layout blocks (same sums either way)
+        res->cells_per_block = level_cells_per_block(L, prec);
+        res->ms_cpb[0] = res->ms_cpb[1] = -1.0;
+        if (L.op == NNMG_OP_LAPLACE && !L.var[prec].atomic && L.nblocks > 0) {
+            for (int g = 1; g <= 2; ++g) {
+                L.var[prec].group = g;
+                res->ms_cpb[g - 1] = time_ms(
+                    [&](hipStream_t st) {
+                        launch_vmult_contrib(L, prec, x.ptr, L.d_contrib.ptr, st);
+                        launch_residual_gather(L, prec, L.d_contrib.ptr, f.ptr, r.ptr, st);
+                    },
+                    reps, s);
+            }
+            L.var[prec].group = res->ms_cpb[1] < res->ms_cpb[0] ? 2 : 1;
+            res->cells_per_block = level_cells_per_block(L, prec);
+            ++L.config_version;
+        }
         // several right-hand sides on a small level (a grid of few wavefronts):
         // one grid row per right-hand side, or every block looping over them
         res->rhs_split = L.var[prec].rhs_split;

@@ -169,6 +169,8 @@ struct Level {
         int index_layout = 0;   // 0: per-node indices and slots (d_dofmap_blk, d_pos_blk), 1: entity records
         int sweep = 0;          // 0: contractions across lanes through LDS, 1: lines swapped through LDS
         int rhs_split = 0;      // several right-hand sides: 0 each block loops over them, 1 one grid row each
+        int group = 1;          // layout blocks per workgroup of the slot kernels (1 or 2): cells per workgroup
+                                // = group * cpb; the atomic variants run one
     } var[2];
     // the slot offsets the consumers of a `prec` operator product read
     const int32_t* inv_off(int prec) const { return var[prec].index_layout ? d_inv_off_ent.ptr : d_inv_off.ptr; }
@@ -226,6 +228,8 @@ void transfer_reserve_rhs(Transfer& t, int nr);
 int level_variant(const Level& L, int prec);
 void level_set_variant(Level& L, int prec, int v);  // prec -1: both precisions
 void level_set_rhs_split(Level& L, int prec, int split);
+void level_set_cells_per_block(Level& L, int prec, int cells);  // cells: cpb or 2 cpb
+int level_cells_per_block(const Level& L, int prec);
 void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res);
 void transfer_set_team(Transfer& T, int team);
 void transfer_tune(Transfer& T, int prec, int reps, nnmg_tune_result* res);

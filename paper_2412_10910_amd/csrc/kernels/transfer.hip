@@ -318,6 +318,13 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
 #pragma unroll
         for (int a = 0; a < DIM; ++a) x[u][a] = ok ? xi[a * npts + p0 + u] : T(0);
     }
+    // single values: the fine values the lane adds to are loaded here too,
+    // so that their latency hides behind the staging and the contraction
+    T old[PPL];
+    if constexpr (NVT == 1) {
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) old[u] = p0 + u < npts ? uf[f[u]] : T(0);
+    }
     const int64_t nrun = (npts + kPointBlock - 1) / kPointBlock;
     const int64_t r0 = b * PPL, r1 = (r0 + PPL < nrun ? r0 + PPL : nrun) - 1;
     const int c0 = blk_cells[2 * r0], c1 = blk_cells[2 * r1 + 1];
@@ -369,6 +376,11 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
                 contract_points<DIM, N, PPL, T>(px, py, pz, [&](int a) { return us[a]; }, val);
             else
                 contract_points<DIM, N, PPL, T>(px, py, pz, [&](int a) { return us[a * nv + c]; }, val);
+            if constexpr (NVT == 1) {
+#pragma unroll
+                for (int u = 0; u < PPL; ++u) uf[f[u]] = old[u] + val[u];
+                continue;
+            }
 #pragma unroll
             for (int u = 0; u < PPL; ++u) uf[(int64_t)f[u] * nv + c] += val[u];
         }

@@ -118,18 +118,20 @@ constexpr int kIdxEntity = 1;  // one record of entity bases and slot bases per 
 // waves per SIMD the register allocation must allow: 4 for the float64 Q3
 // single-vector kernels with entity records or transposed sweeps (they would
 // otherwise take 132-150 VGPRs, 3 waves; at 128 they spill a few)
-template <int N, class T, int NRT, int IDX, int SW>
+template <int N, class T, int NRT, int IDX, int SW, int G>
 constexpr int vmult_min_waves() {
-    return ((IDX == 1 || SW == 1) && N == 4 && sizeof(T) == 8 && NRT == 1) ? 4 : NNMG_VMULT_MINWAVES;
+    // two layout blocks per workgroup double the LDS of a workgroup: three
+    // waves per SIMD is what the LDS then holds
+    return ((IDX == 1 || SW == 1) && N == 4 && sizeof(T) == 8 && NRT == 1) ? (G == 1 ? 4 : 3) : NNMG_VMULT_MINWAVES;
 }
 
-template <int DIM, int N, class T, int GEO, int SCATTER, int NRT, int IDX = kIdxNodes, int SW = 0>
-__global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, IDX, SW>())) void vmult_kernel(const int32_t* __restrict__ dmap,
+template <int DIM, int N, class T, int GEO, int SCATTER, int NRT, int IDX = kIdxNodes, int SW = 0, int G = 1>
+__global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, NRT, IDX, SW, G>())) void vmult_kernel(const int32_t* __restrict__ dmap,
                                                                     const T* __restrict__ geo,
                                                                     const T* __restrict__ src,
                                                                     const int32_t* __restrict__ slots,
                                                                     T* __restrict__ dst, OpTables<N, T> tb,
-                                                                    int nr_in, int64_t plane) {
+                                                                    int nr_in, int64_t plane, int64_t nblk) {
     const int nr = NRT > 0 ? NRT : nr_in;
     // right-hand sides of this block: all of them one after the other, or,
     // when the grid has one row per right-hand side (small meshes, where a
@@ -140,13 +142,23 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, 
     constexpr int L = Sh::L, WG = Sh::WG, CPB = Sh::CPB, TILE = Sh::TILE;
     constexpr int M = DIM * (DIM + 1) / 2;
     constexpr int NC = DIM == 3 ? 21 : 6;
-    __shared__ T lds[SW == 1 ? 5 : 3][CPB][TILE];
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x;
+    // G layout blocks of WG lanes per workgroup (G CPB cells): the lanes of
+    // layout block `sub` own LDS regions of their own and synchronize among
+    // themselves only.  In the last workgroup of an odd block count, the
+    // block past the end repeats the loads of the last block and stores
+    // nothing.
+    static_assert(G == 1 || SCATTER == kSlots, "several layout blocks per workgroup: contribution slots only");
+    __shared__ T lds[SW == 1 ? 5 : 3][G * CPB][TILE];
+    const int sub = G == 1 ? 0 : (int)threadIdx.x / WG;
+    const int64_t bg = G == 1 ? xcd_remap(blockIdx.x, gridDim.x) : xcd_remap(blockIdx.x, gridDim.x) * G + sub;
+    const bool bok = G == 1 || bg < nblk;
+    const int64_t b = bok ? bg : nblk - 1;
+    const int lane = (int)threadIdx.x - sub * WG;
     const int cell = lane / L;
     const int line = lane - cell * L;
-    const bool act = cell < CPB;
-    const int cb = act ? cell : 0;
+    const bool act = cell < CPB && bok;
+    const int cbl = act ? cell : 0;  // cell within the layout block
+    const int cb = sub * CPB + cbl;  // cell within the workgroup (LDS)
     // 3D: line = j + N t (y index j, z index t); 2D: line = t (y index)
     const int j = DIM == 3 ? line % N : 0;
     const int t = DIM == 3 ? line / N : line;
@@ -174,17 +186,17 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, 
         if constexpr (SCATTER == kSlots) {
             const int32_t* ps = slots + b * (N * WG) + lane;
 #pragma unroll
-            for (int i = 0; i < N; ++i) slot[i] = ps[i * WG];
+            for (int i = 0; i < N; ++i) slot[i] = bok ? ps[i * WG] : -1;
         }
     }
     // the cell's map coefficients: each lane turns them into the constants of
     // its line just before the geometry step, so they hold no registers
     // during the sweeps
-    __shared__ T lcf[CPB][GEO == kTrilinear ? NC : 1];
+    __shared__ T lcf[G * CPB][GEO == kTrilinear ? NC : 1];
     constexpr int R = GEO == kTrilinear ? (NC + L - 1) / L : 1;
     T cv[R];
     if constexpr (GEO == kTrilinear) {
-        const T* gc = geo + b * (NC * CPB) + cb;
+        const T* gc = geo + b * (NC * CPB) + cbl;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int m = line + r * L;
@@ -197,7 +209,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, 
     constexpr int NT = 3 * N * N + 2 * N;
     static_assert(sizeof(OpTables<N, T>) == NT * sizeof(T), "OpTables must be a flat array of T");
     constexpr int TE = (NT + WG - 1) / WG;  // table entries per lane
-    __shared__ T ltab[NT];
+    __shared__ T ltab[G][NT];
     T tv[TE];
 #pragma unroll
     for (int e = 0; e < TE; ++e)
@@ -209,7 +221,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, 
     // the record's orientation code maps them to the canonical index m.  The
     // DoFs are decoded here, the slots only at the store, so that they hold no
     // registers during the sweeps.
-    __shared__ int32_t lrec[IDX == kIdxEntity ? CPB : 1][IDX == kIdxEntity ? EW : 1];
+    __shared__ int32_t lrec[IDX == kIdxEntity ? G * CPB : 1][IDX == kIdxEntity ? EW : 1];
     constexpr int K1 = N - 2;  // DoFs along an edge
     const int ecy = j == 0 ? 0 : (j == N - 1 ? 2 : 1);
     const int ecz = t == 0 ? 0 : (t == N - 1 ? 2 : 1);
@@ -236,7 +248,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, 
 #pragma unroll
         for (int r = 0; r < RE; ++r) {
             const int wd = lane + r * WG;
-            if (wd < EW * CPB) lrec[wd % CPB][wd / CPB] = rv[r];
+            if (wd < EW * CPB) lrec[sub * CPB + wd % CPB][wd / CPB] = rv[r];
         }
         block_sync<WG>();
 #pragma unroll
@@ -258,11 +270,11 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, 
     }
 #pragma unroll
     for (int e = 0; e < TE; ++e)
-        if (lane + e * WG < NT) ltab[lane + e * WG] = tv[e];
-    const T* lS = ltab;
-    const T* lDS = ltab + N * N;
-    const T* lD = ltab + 2 * N * N;
-    const T* lg = ltab + 3 * N * N;
+        if (lane + e * WG < NT) ltab[sub][lane + e * WG] = tv[e];
+    const T* lS = ltab[sub];
+    const T* lDS = lS + N * N;
+    const T* lD = lS + 2 * N * N;
+    const T* lg = lS + 3 * N * N;
     const T* lw = lg + N;
 
     T* A = lds[0][cb];
@@ -685,10 +697,10 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG), (vmult_min_waves<N, T, NRT, 
         }
         T nxt;
         if constexpr (IDX == kIdxEntity && WG > kWave) {
-            __shared__ T lxm[CPB][L];
+            __shared__ T lxm[G * CPB][L];
             if (act) lxm[cb][line] = v[0];
             block_sync<WG>();
-            nxt = (act && cb + 1 < CPB) ? lxm[cb + 1][line] : T(0);
+            nxt = (act && cbl + 1 < CPB) ? lxm[cb + 1][line] : T(0);
         } else {
             nxt = __shfl_down(v[0], L, kWave);
         }
@@ -1013,22 +1025,32 @@ static OpTables<N, T> make_tables(const Basis1D& b) {
     return t;
 }
 
-// contribution-slot launches of one index layout and sweep form
-// (several right-hand sides: one grid row per right-hand side when the
-// precision's variant splits them, else every block loops over them)
+// contribution-slot launches of one index layout, sweep form and number G
+// of layout blocks per workgroup (several right-hand sides: one grid row per
+// right-hand side when the precision's variant splits them, else every block
+// loops over them)
+template <int DIM, int N, class T, int GEO, int IDX, int SW, int G>
+static void launch_slots_g(const Level& L, const T* geo, const int32_t* dmap, const int32_t* slots, const void* src,
+                           void* dst, const OpTables<N, T>& tb, int nr, int64_t plane, hipStream_t s) {
+    const dim3 block(OpShape<DIM, N>::WG * G);
+    const unsigned gx = (unsigned)((L.nblocks + G - 1) / G);
+    if (nr == 1) {
+        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 1, IDX, SW, G>), dim3(gx), block, 0, s, dmap, geo,
+                           (const T*)src, slots, (T*)dst, tb, nr, plane, (int64_t)L.nblocks);
+    } else {
+        const bool split = L.var[sizeof(T) == 8 ? NNMG_FP64 : NNMG_FP32].rhs_split != 0;
+        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 0, IDX, SW, G>), dim3(gx, split ? (unsigned)nr : 1u),
+                           block, 0, s, dmap, geo, (const T*)src, slots, (T*)dst, tb, nr, plane, (int64_t)L.nblocks);
+    }
+}
+
 template <int DIM, int N, class T, int GEO, int IDX, int SW>
 static void launch_slots(const Level& L, const T* geo, const int32_t* dmap, const int32_t* slots, const void* src,
                          void* dst, const OpTables<N, T>& tb, int nr, int64_t plane, hipStream_t s) {
-    const dim3 block(OpShape<DIM, N>::WG);
-    if (nr == 1) {
-        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 1, IDX, SW>), dim3((unsigned)L.nblocks), block, 0, s,
-                           dmap, geo, (const T*)src, slots, (T*)dst, tb, nr, plane);
-    } else {
-        const bool split = L.var[sizeof(T) == 8 ? NNMG_FP64 : NNMG_FP32].rhs_split != 0;
-        hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 0, IDX, SW>),
-                           dim3((unsigned)L.nblocks, split ? (unsigned)nr : 1u), block, 0, s, dmap, geo,
-                           (const T*)src, slots, (T*)dst, tb, nr, plane);
-    }
+    if (L.var[sizeof(T) == 8 ? NNMG_FP64 : NNMG_FP32].group == 2)
+        launch_slots_g<DIM, N, T, GEO, IDX, SW, 2>(L, geo, dmap, slots, src, dst, tb, nr, plane, s);
+    else
+        launch_slots_g<DIM, N, T, GEO, IDX, SW, 1>(L, geo, dmap, slots, src, dst, tb, nr, plane, s);
 }
 
 template <int DIM, int N, class T, int GEO>
@@ -1042,10 +1064,10 @@ static void vmult_launches(const Level& L, const T* geo, bool atomic, const void
     if (atomic) {
         if (nr == 1)
             hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kAtomic, 1>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
-                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane);
+                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane, (int64_t)L.nblocks);
         else
             hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kAtomic, 0>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
-                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane);
+                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane, (int64_t)L.nblocks);
     } else if (L.var[sizeof(T) == 8 ? NNMG_FP64 : NNMG_FP32].index_layout == 1) {
         if constexpr (DIM == 3 && N >= 4) {
             if (sw)

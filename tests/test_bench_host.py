@@ -80,12 +80,12 @@ def test_recorded_traffic_is_dropped_when_the_kernels_changed(tmp_path, monkeypa
 
 
 def test_operator_traffic_follows_the_variant_that_ran():
-    traffic = {"operator_fp64": 1.0, "kernel:vmult_kernel<3, 5, double, 1, 0, 1, 0, 1>": 100.0,
+    traffic = {"operator_fp64": 1.0, "kernel:vmult_kernel<3, 5, double, 1, 0, 1, 0, 1, 1>": 100.0,
                "kernel:gather_kernel<1, 1, double>@fine": 20.0, "kernel:copy_idx_kernel<double>@fine": 1.5,
                "prolongate_fp64": 7.0}
-    ran = {"launches": ["vmult_kernel<3, 5, double, 1, 0, 1, 0, 1>", "gather_kernel<1, 1, double>",
+    ran = {"launches": ["vmult_kernel<3, 5, double, 1, 0, 1, 0, 1, 1>", "gather_kernel<1, 1, double>",
                         "copy_idx_kernel<double>"]}
-    other = {"launches": ["vmult_kernel<3, 5, double, 1, 0, 1, 1, 0>", "gather_kernel<1, 1, double>",
+    other = {"launches": ["vmult_kernel<3, 5, double, 1, 0, 1, 1, 0, 1>", "gather_kernel<1, 1, double>",
                           "copy_idx_kernel<double>"]}
     assert bench.entry_traffic(traffic, "operator_fp64", ran) == 121.5
     assert bench.entry_traffic(traffic, "operator_fp64", other) is None  # not profiled: no claim
@@ -115,25 +115,31 @@ def test_operator_kernel_names_follow_degree_and_variant():
                                                                         "metric+slots+transposed", None,
                                                                         "trilinear+entity+transposed",
                                                                         "metric+entity+transposed"),
-                         variant=0)
+                         variant=0, group=1)
     lv.variant_of = lambda dtype: lv.variant
-    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1, 0, 0>",
+    lv.cells_per_block = lambda dtype: (5 * lv.group, 5, 101)
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1, 0, 0, 1>",
                                                   "gather_kernel<1, 1, double>", "copy_idx_kernel<double>"]
     lv.variant = 2
-    assert bench.operator_kernel_names(lv, 4, nr=4) == ["vmult_kernel<3, 5, float, 0, 0, 0, 0, 0>",
+    assert bench.operator_kernel_names(lv, 4, nr=4) == ["vmult_kernel<3, 5, float, 0, 0, 0, 0, 0, 1>",
                                                         "gather_kernel<1, 4, float>", "copy_idx_kernel<float>"]
     lv.variant = 3
-    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 0, 1, 1, 0, 0>", "fill_kernel<double>",
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 0, 1, 1, 0, 0, 1>", "fill_kernel<double>",
                                                   "copy_idx_kernel<double>"]
     lv.variant = 4
-    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1, 1, 0>",
+    assert bench.operator_kernel_names(lv, 8) == ["vmult_kernel<3, 5, double, 1, 0, 1, 1, 0, 1>",
                                                   "gather_kernel<1, 1, double>", "copy_idx_kernel<double>"]
     lv.variant = 5
-    assert bench.operator_kernel_names(lv, 4) == ["vmult_kernel<3, 5, float, 0, 0, 1, 1, 0>",
+    assert bench.operator_kernel_names(lv, 4) == ["vmult_kernel<3, 5, float, 0, 0, 1, 1, 0, 1>",
                                                   "gather_kernel<1, 1, float>", "copy_idx_kernel<float>"]
     lv.variant = 10
-    assert bench.operator_kernel_names(lv, 4) == ["vmult_kernel<3, 5, float, 1, 0, 1, 1, 1>",
+    assert bench.operator_kernel_names(lv, 4) == ["vmult_kernel<3, 5, float, 1, 0, 1, 1, 1, 1>",
                                                   "gather_kernel<1, 1, float>", "copy_idx_kernel<float>"]
+    lv.group = 2
+    assert bench.operator_kernel_names(lv, 4) == ["vmult_kernel<3, 5, float, 1, 0, 1, 1, 1, 2>",
+                                                  "gather_kernel<1, 1, float>", "copy_idx_kernel<float>"]
+    lv.variant = 3  # the atomic variants run one layout block per workgroup
+    assert bench.operator_kernel_names(lv, 8)[0] == "vmult_kernel<3, 5, double, 0, 1, 1, 0, 0, 1>"
     el = SimpleNamespace(dim=3, degree=2, operator="elasticity")
     assert bench.operator_kernel_names(el, 8, nr=4) == ["elasticity_kernel<3, double, 0>",
                                                         "gather_kernel<3, 4, double>", "copy_idx_kernel<double>"]

@@ -1,5 +1,5 @@
-"""The autotuner: every operator variant and every restriction team size must
-give the oracle's result (float64 within 1e-12, float32 within 2e-5 of the
+"""The autotuner: every operator variant, both cells-per-workgroup sizes and
+every restriction team size must give the oracle's result (float64 within 1e-12, float32 within 2e-5 of the
 largest entry; the variants only reorder floating-point sums), tuning must
 keep the fastest variant it timed, and a hierarchy must re-capture its V-cycle
 graph when a variant under it changes.
@@ -38,6 +38,62 @@ def test_operator_variants_match_oracle(ctx, cfg, cells, k):
             assert rel_err(p.to_orc(p.lib.vmult(p.to_lib(x, dt))), ref) <= tol, (v, dt)
 
 
+@pytest.mark.parametrize("cfg,cells,k", [(0, [13], 1), (0, [9], 4), (1, [5], 2), (1, [4], 1), (1, [3], 2),
+                                         (2, [4], 3), (2, [3], 4), (2, [5], 4)])
+def test_two_layout_blocks_per_workgroup(ctx, cfg, cells, k):
+    """Cells per workgroup: a workgroup of two layout blocks gives the oracle's
+    product, and bitwise the product of one layout block per workgroup, for
+    every slot variant, with one and with three right-hand sides (looping and
+    split); the cases include odd numbers of layout blocks (the last
+    workgroup then has a block past the end, which must store nothing)."""
+    (m,) = config_levels(cfg, cells=cells)
+    p = Pair(ctx, m, k)
+    x = random_vector(p.orc.n_dofs, 5)
+    ref = p.A @ x
+    cells1, base, nblk = p.lib.cells_per_block()
+    assert cells1 == base and nblk >= 1
+    variants = [0, 2, 6, 8] + ([4, 5, 10, 11] if (k >= 3 and p.lib.dim == 3) else [])
+    for v in variants:
+        p.lib.set_variant(v)
+        for dt, tol in ((torch.float64, TOL64), (torch.float32, TOL32)):
+            xl = p.to_lib(x, dt)
+            X = torch.stack([p.to_lib(random_vector(p.orc.n_dofs, 30 + r), dt) for r in range(3)], 1).contiguous()
+            p.lib.set_cells_per_block(base, dt)
+            y1 = p.lib.vmult(xl)
+            Y1 = p.lib.vmult(X)
+            p.lib.set_cells_per_block(2 * base, dt)
+            assert p.lib.cells_per_block(dt)[0] == 2 * base
+            y2 = p.lib.vmult(xl)
+            assert torch.equal(y1, y2), (v, dt, nblk)
+            assert rel_err(p.to_orc(y2), ref) <= tol, (v, dt)
+            for split in (False, True):
+                p.lib.set_rhs_split(split, dt)
+                assert torch.equal(p.lib.vmult(X), Y1), (v, dt, split)
+            p.lib.set_rhs_split(False, dt)
+            p.lib.set_cells_per_block(base, dt)
+    # the other sizes are refused; the atomic variants run one block and say so
+    import paper_2412_10910_amd as nn
+    for bad in (base + 1, 3 * base, 0):
+        with pytest.raises(nn.NNMGError):
+            p.lib.set_cells_per_block(bad)
+    p.lib.set_cells_per_block(2 * base)
+    p.lib.set_variant(1)
+    assert p.lib.cells_per_block()[0] == base
+    p.lib.set_variant(0)
+    assert p.lib.cells_per_block()[0] == 2 * base
+    p.lib.set_cells_per_block(base)
+
+
+def test_elasticity_runs_one_layout_block_per_workgroup(ctx):
+    import paper_2412_10910_amd as nn
+    (m,) = config_levels(3, cells=[(3, 1, 1)])
+    lv = nn.Level.from_mesh(ctx, m, 2, "elasticity")
+    c, base, _ = lv.cells_per_block()
+    assert c == base
+    with pytest.raises(nn.NNMGError):
+        lv.set_cells_per_block(2 * base)
+
+
 @pytest.mark.parametrize("cfg,cells,k", [(1, [3, 7], 2), (2, [3, 6], 3), (3, [(3, 1, 1), (7, 2, 2)], 2)])
 def test_restriction_teams_match_oracle(ctx, cfg, cells, k):
     import paper_2412_10910_amd as nn
@@ -72,6 +128,12 @@ def test_tune_keeps_the_fastest_and_the_solver_still_converges(ctx):
         assert set(ms) == {"trilinear+slots", "metric+slots", "trilinear+slots+transposed", "metric+slots+transposed"} and all(t > 0 for t in ms.values())
         assert r["chosen"] == min(ms, key=ms.get)
         assert lv.VARIANTS[lv.variant_of(torch.float32)] == r["chosen"]
+        # cells per workgroup: both timed for the variant kept, the faster in use
+        mc = r["ms_cells"]
+        base = lv.cells_per_block(torch.float32)[1]
+        assert mc is not None and all(t > 0 for t in mc.values())
+        want = 2 * base if mc["two blocks"] < mc["one block"] else base
+        assert r["cells_per_block"] == want == lv.cells_per_block(torch.float32)[0]
     for tr, r in zip(transfers, report["transfers"]):
         assert r["chosen"] == min(r["ms"], key=r["ms"].get) and tr.team == r["chosen"]
     for dt in (torch.float32, torch.float64):
