@@ -37,6 +37,7 @@
 //    cross products of the columns of J, so G grad = (w / det J) R^T (R grad)
 //    with R the matrix of those rows.  This moves 21 words per cell instead
 //    of 6 per Gauss point, for about 60 flops per Gauss point.
+#include <cmath>
 #include <cstdlib>
 #include <string>
 
@@ -77,6 +78,74 @@ __device__ __forceinline__ void line_apply(const T (&M)[N][N], const T* in, T* o
         for (int a = 1; a < N; ++a) s += (TRANS ? M[a][i] : M[i][a]) * in[a];
         out[i] = s;
     }
+}
+
+// Even-odd form of an N x N matrix M with M[N-1-i][N-1-j] = sig M[i][j]
+// (sig = +1: the values of the nodal basis at the Gauss points, S; sig = -1:
+// the derivative matrices DS and D, as the node and point sets are symmetric
+// about 1/2).  With e_j = u_j + u_{N-1-j}, o_j = u_j - u_{N-1-j} (j < N/2) and
+// the middle value m = u_{N/2} (odd N), row i < N/2 and its mirror are
+//   (M u)_i = E_i + O_i,   (M u)_{N-1-i} = sig (E_i - O_i),
+//   E_i = sum_j P_ij e_j + c_i m,   O_i = sum_j Q_ij o_j,
+//   P_ij = (M_ij + M_i,N-1-j) / 2,  Q_ij = (M_ij - M_i,N-1-j) / 2,  c_i = M_i,N/2,
+// and the middle row (odd N) is E (sig = +1) or O (sig = -1) alone: at N = 5
+// 21 (sig = +1) or 20 (sig = -1) operations instead of 25.  Below N = 5 the
+// split costs as much as it saves, and the plain product is used.
+template <int N, class T>
+struct EOMat {
+    T P[(N + 1) / 2][N / 2];
+    T Q[(N + 1) / 2][N / 2];
+    T c[(N + 1) / 2];
+};
+
+template <int N, class T>
+struct OpEO {  // even-odd forms of S, DS, D and their transposes (N >= 5)
+    EOMat<N, T> S, St, DS, DSt, D, Dt;
+};
+
+template <int N, class T, int SIG>
+__device__ __forceinline__ void line_apply_eo(const EOMat<N, T>& M, const T* in, T* out) {
+    constexpr int H = N / 2;
+    T e[H], o[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        e[j] = in[j] + in[N - 1 - j];
+        o[j] = in[j] - in[N - 1 - j];
+    }
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        T E = M.P[i][0] * e[0];
+#pragma unroll
+        for (int j = 1; j < H; ++j) E += M.P[i][j] * e[j];
+        if constexpr (N % 2 == 1) E += M.c[i] * in[H];
+        T O = M.Q[i][0] * o[0];
+#pragma unroll
+        for (int j = 1; j < H; ++j) O += M.Q[i][j] * o[j];
+        out[i] = E + O;
+        out[N - 1 - i] = SIG > 0 ? E - O : O - E;
+    }
+    if constexpr (N % 2 == 1) {
+        if constexpr (SIG > 0) {
+            T E = M.P[H][0] * e[0];
+#pragma unroll
+            for (int j = 1; j < H; ++j) E += M.P[H][j] * e[j];
+            out[H] = E + M.c[H] * in[H];
+        } else {
+            T O = M.Q[H][0] * o[0];
+#pragma unroll
+            for (int j = 1; j < H; ++j) O += M.Q[H][j] * o[j];
+            out[H] = O;
+        }
+    }
+}
+
+// the 1D contractions of the Laplace kernel: the even-odd form from N = 5 on
+template <int N, class T, bool TRANS, int SIG>
+__device__ __forceinline__ void line_apply_sym(const T (&M)[N][N], const EOMat<N, T>& E, const T* in, T* out) {
+    if constexpr (N >= 5)
+        line_apply_eo<N, T, SIG>(E, in, out);
+    else
+        line_apply<N, T, TRANS>(M, in, out);
 }
 
 template <int DIM, int N>
@@ -131,7 +200,8 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
                                                                     const T* __restrict__ src,
                                                                     const int32_t* __restrict__ slots,
                                                                     T* __restrict__ dst, OpTables<N, T> tb,
-                                                                    int nr_in, int64_t plane, int64_t nblk) {
+                                                                    OpEO<N, T> eo, int nr_in, int64_t plane,
+                                                                    int64_t nblk) {
     const int nr = NRT > 0 ? NRT : nr_in;
     // right-hand sides of this block: all of them one after the other, or,
     // when the grid has one row per right-hand side (small meshes, where a
@@ -303,7 +373,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
         T* T0 = lds[0][cb];
         T* T1 = lds[1][cb];
         T* T2 = lds[2][cb];
-        line_apply<N, T, false>(tb.S, u, v);  // x: nodes -> Gauss points
+        line_apply_sym<N, T, false, 1>(tb.S, eo.S, u, v);  // x: nodes -> Gauss points
         if (act) {
 #pragma unroll
             for (int i = 0; i < N; ++i) T0[row + i] = v[i];
@@ -316,8 +386,8 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
             T a[N], w[N], wy[N];
 #pragma unroll
             for (int c = 0; c < N; ++c) a[c] = T0[(t * N + c) * N + j];
-            line_apply<N, T, false>(tb.S, a, w);
-            line_apply<N, T, false>(tb.DS, a, wy);
+            line_apply_sym<N, T, false, 1>(tb.S, eo.S, a, w);
+            line_apply_sym<N, T, false, -1>(tb.DS, eo.DS, a, wy);
             if (act) {
 #pragma unroll
                 for (int c = 0; c < N; ++c) {
@@ -333,9 +403,9 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
                 w[c] = T2[(c * N + t) * N + j];
             }
             T zv[N], zz[N], zy[N];
-            line_apply<N, T, false>(tb.S, a, zv);
-            line_apply<N, T, false>(tb.DS, a, zz);
-            line_apply<N, T, false>(tb.S, w, zy);
+            line_apply_sym<N, T, false, 1>(tb.S, eo.S, a, zv);
+            line_apply_sym<N, T, false, -1>(tb.DS, eo.DS, a, zz);
+            line_apply_sym<N, T, false, 1>(tb.S, eo.S, w, zy);
             if (act) {
 #pragma unroll
                 for (int c = 0; c < N; ++c) {
@@ -357,8 +427,8 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
             T a[N], w[N], wy[N];
 #pragma unroll
             for (int c = 0; c < N; ++c) a[c] = T0[c * N + t];
-            line_apply<N, T, false>(tb.S, a, w);
-            line_apply<N, T, false>(tb.DS, a, wy);
+            line_apply_sym<N, T, false, 1>(tb.S, eo.S, a, w);
+            line_apply_sym<N, T, false, -1>(tb.DS, eo.DS, a, wy);
             if (act) {
 #pragma unroll
                 for (int c = 0; c < N; ++c) {
@@ -373,9 +443,9 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
                 gz[i] = T2[row + i];
             }
         }
-        line_apply<N, T, false>(tb.D, v, gx);
+        line_apply_sym<N, T, false, -1>(tb.D, eo.D, v, gx);
     } else {
-        line_apply<N, T, false>(tb.S, u, v);  // x: nodes -> Gauss points
+        line_apply_sym<N, T, false, 1>(tb.S, eo.S, u, v);  // x: nodes -> Gauss points
         if constexpr (DIM == 3) {
             // y: interpolate
             if (act) {
@@ -430,7 +500,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
             }
         }
         // v: values at the Gauss points of the line; x (and y) derivatives
-        line_apply<N, T, false>(tb.D, v, gx);
+        line_apply_sym<N, T, false, -1>(tb.D, eo.D, v, gx);
         if constexpr (DIM == 3) {
             if (act) {
     #pragma unroll
@@ -539,7 +609,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
         T* T0 = lds[0][cb];
         T* T1 = lds[1][cb];
         T* T2 = lds[2][cb];
-        line_apply<N, T, true>(tb.D, gx, u);  // Dx^T fx
+        line_apply_sym<N, T, true, -1>(tb.D, eo.Dt, gx, u);  // Dx^T fx
         block_sync<WG>();                     // every lane has read the forward tiles
         if constexpr (DIM == 3) {
             T* T3 = lds[3][cb];
@@ -561,9 +631,9 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
                 b2[c] = T1[(c * N + t) * N + j];
                 c2[c] = T2[(c * N + t) * N + j];
             }
-            line_apply<N, T, true>(tb.S, a, r0);
-            line_apply<N, T, true>(tb.DS, c2, r1);
-            line_apply<N, T, true>(tb.S, b2, a);
+            line_apply_sym<N, T, true, 1>(tb.S, eo.St, a, r0);
+            line_apply_sym<N, T, true, -1>(tb.DS, eo.DSt, c2, r1);
+            line_apply_sym<N, T, true, 1>(tb.S, eo.St, b2, a);
             if (act) {
 #pragma unroll
                 for (int c = 0; c < N; ++c) {
@@ -578,8 +648,8 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
                 a[c] = T3[(t * N + c) * N + j];
                 b2[c] = T4[(t * N + c) * N + j];
             }
-            line_apply<N, T, true>(tb.S, a, r0);
-            line_apply<N, T, true>(tb.DS, b2, r1);
+            line_apply_sym<N, T, true, 1>(tb.S, eo.St, a, r0);
+            line_apply_sym<N, T, true, -1>(tb.DS, eo.DSt, b2, r1);
             if (act) {
 #pragma unroll
                 for (int c = 0; c < N; ++c) T0[(t * N + c) * N + j] = r0[c] + r1[c];
@@ -603,8 +673,8 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
                 a[c] = T0[c * N + t];
                 b2[c] = T1[c * N + t];
             }
-            line_apply<N, T, true>(tb.S, a, r0);
-            line_apply<N, T, true>(tb.DS, b2, r1);
+            line_apply_sym<N, T, true, 1>(tb.S, eo.St, a, r0);
+            line_apply_sym<N, T, true, -1>(tb.DS, eo.DSt, b2, r1);
             if (act) {
 #pragma unroll
                 for (int c = 0; c < N; ++c) T2[c * N + t] = r0[c] + r1[c];
@@ -613,9 +683,9 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
 #pragma unroll
             for (int i = 0; i < N; ++i) u[i] = T2[row + i];
         }
-        line_apply<N, T, true>(tb.S, u, v);  // x: S^T
+        line_apply_sym<N, T, true, 1>(tb.S, eo.St, u, v);  // x: S^T
     } else {
-        line_apply<N, T, true>(tb.D, gx, u);  // Dx^T fx
+        line_apply_sym<N, T, true, -1>(tb.D, eo.Dt, gx, u);  // Dx^T fx
         if constexpr (DIM == 3) {
             // + Dy^T fy
             if (act) {
@@ -678,7 +748,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
                 u[i] = s;
             }
         }
-        line_apply<N, T, true>(tb.S, u, v);  // x: S^T
+        line_apply_sym<N, T, true, 1>(tb.S, eo.St, u, v);  // x: S^T
     }
     if constexpr (SCATTER == kSlots) {
         // the next cell's first node of this line, added here where setup found
@@ -1010,6 +1080,38 @@ __global__ __launch_bounds__((OpShape<3, N>::WG)) void elasticity_kernel(const i
     }
 }
 
+// even-odd form of M (or of M^T): rows 0 .. (N-1)/2 of P, Q and c; the
+// mirror rows are implied by M[N-1-i][N-1-j] = sig M[i][j], checked here
+template <int N, class T>
+static EOMat<N, T> make_eo(const double (&M)[kMaxN][kMaxN], bool trans, int sig) {
+    auto m = [&](int i, int j) { return trans ? M[j][i] : M[i][j]; };
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            if (std::fabs(m(N - 1 - i, N - 1 - j) - sig * m(i, j)) > 1e-12 * (1.0 + std::fabs(m(i, j))))
+                fail(NNMG_ERR_UNSUPPORTED, "1D basis matrix without the mirror symmetry of its node and point sets");
+    EOMat<N, T> e{};
+    for (int i = 0; i < (N + 1) / 2; ++i) {
+        for (int j = 0; j < N / 2; ++j) {
+            e.P[i][j] = (T)(0.5 * (m(i, j) + m(i, N - 1 - j)));
+            e.Q[i][j] = (T)(0.5 * (m(i, j) - m(i, N - 1 - j)));
+        }
+        e.c[i] = (N % 2 == 1) ? (T)m(i, N / 2) : T(0);
+    }
+    return e;
+}
+
+template <int N, class T>
+static OpEO<N, T> make_op_eo(const Basis1D& b) {
+    OpEO<N, T> t;
+    t.S = make_eo<N, T>(b.S, false, 1);
+    t.St = make_eo<N, T>(b.S, true, 1);
+    t.DS = make_eo<N, T>(b.DS, false, -1);
+    t.DSt = make_eo<N, T>(b.DS, true, -1);
+    t.D = make_eo<N, T>(b.D, false, -1);
+    t.Dt = make_eo<N, T>(b.D, true, -1);
+    return t;
+}
+
 template <int N, class T>
 static OpTables<N, T> make_tables(const Basis1D& b) {
     OpTables<N, T> t;
@@ -1034,13 +1136,15 @@ static void launch_slots_g(const Level& L, const T* geo, const int32_t* dmap, co
                            void* dst, const OpTables<N, T>& tb, int nr, int64_t plane, hipStream_t s) {
     const dim3 block(OpShape<DIM, N>::WG * G);
     const unsigned gx = (unsigned)((L.nblocks + G - 1) / G);
+    const OpEO<N, T> eo = make_op_eo<N, T>(L.basis);
     if (nr == 1) {
         hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 1, IDX, SW, G>), dim3(gx), block, 0, s, dmap, geo,
-                           (const T*)src, slots, (T*)dst, tb, nr, plane, (int64_t)L.nblocks);
+                           (const T*)src, slots, (T*)dst, tb, eo, nr, plane, (int64_t)L.nblocks);
     } else {
         const bool split = L.var[sizeof(T) == 8 ? NNMG_FP64 : NNMG_FP32].rhs_split != 0;
         hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kSlots, 0, IDX, SW, G>), dim3(gx, split ? (unsigned)nr : 1u),
-                           block, 0, s, dmap, geo, (const T*)src, slots, (T*)dst, tb, nr, plane, (int64_t)L.nblocks);
+                           block, 0, s, dmap, geo, (const T*)src, slots, (T*)dst, tb, eo, nr, plane,
+                           (int64_t)L.nblocks);
     }
 }
 
@@ -1062,12 +1166,13 @@ static void vmult_launches(const Level& L, const T* geo, bool atomic, const void
     const int64_t plane = (int64_t)contrib_plane(L);
     const bool sw = L.var[sizeof(T) == 8 ? NNMG_FP64 : NNMG_FP32].sweep == 1;
     if (atomic) {
+        const OpEO<N, T> eo = make_op_eo<N, T>(L.basis);
         if (nr == 1)
             hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kAtomic, 1>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
-                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane, (int64_t)L.nblocks);
+                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, eo, nr, plane, (int64_t)L.nblocks);
         else
             hipLaunchKernelGGL((vmult_kernel<DIM, N, T, GEO, kAtomic, 0>), grid, block, 0, s, L.d_dofmap_blk.ptr, geo,
-                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, nr, plane, (int64_t)L.nblocks);
+                               (const T*)src, L.d_pos_blk.ptr, (T*)dst, tb, eo, nr, plane, (int64_t)L.nblocks);
     } else if (L.var[sizeof(T) == 8 ? NNMG_FP64 : NNMG_FP32].index_layout == 1) {
         if constexpr (DIM == 3 && N >= 4) {
             if (sw)
