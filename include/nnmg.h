@@ -313,7 +313,8 @@ typedef struct {
                          split (1), timed on small levels only (-1 otherwise) */
     int cells_per_block; /* nnmg_level_tune: cells per workgroup of the operator kept */
     double ms_cpb[2];    /* nnmg_level_tune: milliseconds of the variant kept with one (0) and two (1)
-                            layout blocks per workgroup (-1 where not timed) */
+                            layout blocks per workgroup (-1 where not timed); ms[v] is the faster of
+                            the two for each variant v */
 } nnmg_tune_result;
 
 /* Times the variants of the level's operator application in precision `prec`
@@ -339,10 +340,11 @@ typedef struct {
  * 10, 11) are timed, so a
  * tuned level stays bitwise reproducible; the others keep ms = -1 and are
  * taken only when forced.  The stored metric is computed when a precision
- * needs it and freed when none does.  For the variant kept it then times one
- * and two layout blocks per workgroup (nnmg_level_set_cells_per_block) and,
- * on small levels, the two forms of several right-hand sides
- * (nnmg_level_set_rhs_split), keeping the faster of each.  Synchronizes the
+ * needs it and freed when none does.  Each variant is timed with one and
+ * with two layout blocks per workgroup (nnmg_level_set_cells_per_block) and
+ * the fastest pair is kept (ms[v]: the faster of the two; ms_cpb: both, for
+ * the variant kept); on small levels the two forms of several right-hand
+ * sides (nnmg_level_set_rhs_split) are then timed and the faster kept.  Synchronizes the
  * device; hierarchies holding the level re-capture their V-cycle graphs.
  * nnmg_level_set_variant forces a variant for both precisions,
  * nnmg_level_set_variant_prec for one; nnmg_level_variant reads the variant

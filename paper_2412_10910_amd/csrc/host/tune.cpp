@@ -14,11 +14,11 @@
 //          every contraction runs in registers (7 and 9, atomics, do not exist)
 // Variants 4, 5, 10 and 11 exist for 3D Laplace levels of degree >= 3 (where
 // the records were built).  The elasticity operator has variant 0 only.
-// Two further axes are timed for the variant kept: the cells per workgroup
-// (one or two layout blocks of cpb cells per workgroup, Laplace slot
-// variants), and, on a small level (a grid of few wavefronts), several
-// right-hand sides as one grid row per right-hand side against every block
-// looping over them (four right-hand sides).  Transfer variants: the lanes
+// Each variant is timed with one and with two layout blocks of cpb cells per
+// workgroup (Laplace slot variants), and the fastest pair is kept.  On a
+// small level (a grid of few wavefronts) the variant kept is then timed with
+// four right-hand sides as one grid row per right-hand side against every
+// block looping over them.  Transfer variants: the lanes
 // per coarse cell of the restriction, 4 << v for v = 0..4.
 //
 // Each precision has its own variant: the float64 and float32 kernels of one
@@ -187,38 +187,42 @@ void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res) {
         level_reserve_rhs(L, 1);
         res->n_variants = nvar;
         for (double& t : res->ms) t = -1.0;
-        int best = 0;
+        // every variant with one and with two layout blocks per workgroup (the
+        // Laplace slot variants; same sums either way): ms[v] is the faster
+        // of the two, ms_cpb the pair of the variant kept
+        const bool grouped = L.op == NNMG_OP_LAPLACE && L.nblocks > 0;
+        double ms_g[16][2];
+        double best_ms = -1.0;
+        int best = 0, best_g = 1;
         for (int v = 0; v < nvar; ++v) {
+            ms_g[v][0] = ms_g[v][1] = -1.0;
             if (atomic_variant(v)) continue;  // float atomics: not reproducible, never picked by the tuner
             if (v % 6 >= 4 && !has_entity_variants(L)) continue;
             apply_variant(L, prec, v);
-            res->ms[v] = time_ms(
-                [&](hipStream_t st) {
-                    launch_vmult_contrib(L, prec, x.ptr, L.d_contrib.ptr, st);
-                    launch_residual_gather(L, prec, L.d_contrib.ptr, f.ptr, r.ptr, st);
-                },
-                reps, s);
-            if (res->ms[v] < res->ms[best]) best = v;
-        }
-        apply_variant(L, prec, best);
-        res->chosen = best;
-        // cells per workgroup: one or two layout blocks (same sums either way)
-        res->cells_per_block = level_cells_per_block(L, prec);
-        res->ms_cpb[0] = res->ms_cpb[1] = -1.0;
-        if (L.op == NNMG_OP_LAPLACE && !L.var[prec].atomic && L.nblocks > 0) {
-            for (int g = 1; g <= 2; ++g) {
+            for (int g = 1; g <= (grouped ? 2 : 1); ++g) {
                 L.var[prec].group = g;
-                res->ms_cpb[g - 1] = time_ms(
+                ms_g[v][g - 1] = time_ms(
                     [&](hipStream_t st) {
                         launch_vmult_contrib(L, prec, x.ptr, L.d_contrib.ptr, st);
                         launch_residual_gather(L, prec, L.d_contrib.ptr, f.ptr, r.ptr, st);
                     },
                     reps, s);
+                const double t = ms_g[v][g - 1];
+                if (res->ms[v] < 0 || t < res->ms[v]) res->ms[v] = t;
+                if (best_ms < 0 || t < best_ms) {
+                    best_ms = t;
+                    best = v;
+                    best_g = g;
+                }
             }
-            L.var[prec].group = res->ms_cpb[1] < res->ms_cpb[0] ? 2 : 1;
-            res->cells_per_block = level_cells_per_block(L, prec);
-            ++L.config_version;
         }
+        apply_variant(L, prec, best);
+        L.var[prec].group = best_g;
+        ++L.config_version;
+        res->chosen = best;
+        res->cells_per_block = level_cells_per_block(L, prec);
+        res->ms_cpb[0] = ms_g[best][0];
+        res->ms_cpb[1] = grouped ? ms_g[best][1] : -1.0;
         // several right-hand sides on a small level (a grid of few wavefronts):
         // one grid row per right-hand side, or every block looping over them
         res->rhs_split = L.var[prec].rhs_split;

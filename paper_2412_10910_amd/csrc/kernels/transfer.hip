@@ -318,10 +318,12 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
 #pragma unroll
         for (int a = 0; a < DIM; ++a) x[u][a] = ok ? xi[a * npts + p0 + u] : T(0);
     }
-    // single values: the fine values the lane adds to are loaded here too,
-    // so that their latency hides behind the staging and the contraction
-    T old[PPL];
-    if constexpr (NVT == 1) {
+    // single values at Q4 in 3D: the fine values the lane adds to are loaded
+    // here too, so that their latency hides behind the staging and the long
+    // contraction (at lower degrees the registers cost more than that saves)
+    constexpr bool kEarly = NVT == 1 && DIM == 3 && N >= 5;
+    [[maybe_unused]] T old[PPL];
+    if constexpr (kEarly) {
 #pragma unroll
         for (int u = 0; u < PPL; ++u) old[u] = p0 + u < npts ? uf[f[u]] : T(0);
     }
@@ -376,7 +378,7 @@ __global__ __launch_bounds__(kPointBlock) void prolongate_points_kernel(
                 contract_points<DIM, N, PPL, T>(px, py, pz, [&](int a) { return us[a]; }, val);
             else
                 contract_points<DIM, N, PPL, T>(px, py, pz, [&](int a) { return us[a * nv + c]; }, val);
-            if constexpr (NVT == 1) {
+            if constexpr (kEarly) {
 #pragma unroll
                 for (int u = 0; u < PPL; ++u) uf[f[u]] = old[u] + val[u];
                 continue;
