@@ -46,6 +46,10 @@ if ROOT not in sys.path:
 METRIC = "MDoF/s per PCG iteration and solve time to 1e-8 (FP32-MG vs FP64-MG); p50/p99 latency"
 UNIT = "MDoF/s per PCG iteration"
 HBM_PEAK_GBS = 8000.0
+# published vector peaks of MI355X (float32 with packed math, which this build
+# does not use: its float32 vector issue rate equals the float64 one)
+FP64_PEAK_GFLOPS = 78_600.0
+FP32_PEAK_GFLOPS = 157_300.0
 
 
 def log(msg):
@@ -71,6 +75,30 @@ def vmult_bytes(level, word, nr=1):
     q = (level.degree + 1) ** level.dim
     m = level.dim * (level.dim + 1) // 2 if level.ncomp == 1 else level.dim * level.dim + 1
     return 2 * word * level.n_dofs * nr + 4 * level.n_cells * q + word * level.n_cells * q * m
+
+
+def vmult_flops(level, nr=1):
+    """Algorithmic flops of one Laplace operator application: per cell and
+    right-hand side 4d sum-factorization sweeps of 2 n^(d+1) flops (d
+    interpolations and d collocation derivatives forward, their transposes
+    backward) and the symmetric d x d metric times the gradient at each of the
+    n^d Gauss points (d^2 multiplications and d(d-1) additions).  None for
+    elasticity (no single count of its stress evaluation is used here)."""
+    if level.ncomp != 1:
+        return None
+    n, d = level.degree + 1, level.dim
+    return nr * level.n_cells * (4 * d * 2 * n ** (d + 1) + (2 * d * d - d) * n ** d)
+
+
+def transfer_flops(coarse, n_points, nr=1):
+    """Algorithmic flops of one prolongation or restriction: per fine point the
+    d 1D Lagrange bases at its reference coordinates (5n - 1 flops each: the
+    differences, the prefix and suffix products and the barycentric scaling)
+    and, per value, the tensor-product contraction of n^d + ... + n
+    multiply-adds (2 flops each)."""
+    n, d = coarse.degree + 1, coarse.dim
+    contraction = 2 * sum(n ** e for e in range(1, d + 1))
+    return n_points * (d * (5 * n - 1) + coarse.ncomp * nr * contraction)
 
 
 def transfer_bytes(coarse, n_points, word, prolong, nr=1):
@@ -394,13 +422,16 @@ def kernel_rooflines(fine, coarse, transfer, reps, nr=1):
             cdst = torch.zeros_like(csrc)
             # the operator application dst = A src (nnmg_vmult): the cell
             # kernel, the gather that writes dst, the identity on constrained rows
+            peak = FP64_PEAK_GFLOPS if word == 8 else FP32_PEAK_GFLOPS
             ms = time_launches(lambda: fine.vmult(src, dst), reps)
-            out[f"operator_{tag}{sfx}"] = dict(ms=ms, bytes=vmult_bytes(fine, word, r),
-                                               launches=operator_kernel_names(fine, word, r))
+            out[f"operator_{tag}{sfx}"] = dict(ms=ms, bytes=vmult_bytes(fine, word, r), flops=vmult_flops(fine, r),
+                                               flop_peak=peak, launches=operator_kernel_names(fine, word, r))
             ms = time_launches(lambda: transfer.prolongate(csrc, dst), reps)
-            out[f"prolongate_{tag}{sfx}"] = dict(ms=ms, bytes=transfer_bytes(coarse, npts, word, True, r))
+            out[f"prolongate_{tag}{sfx}"] = dict(ms=ms, bytes=transfer_bytes(coarse, npts, word, True, r),
+                                                 flops=transfer_flops(coarse, npts, r), flop_peak=peak)
             ms = time_launches(lambda: transfer.restrict(src, cdst), reps)
-            out[f"restrict_{tag}{sfx}"] = dict(ms=ms, bytes=transfer_bytes(coarse, npts, word, False, r))
+            out[f"restrict_{tag}{sfx}"] = dict(ms=ms, bytes=transfer_bytes(coarse, npts, word, False, r),
+                                               flops=transfer_flops(coarse, npts, r), flop_peak=peak)
             del src, dst, csrc, cdst
     for v in out.values():
         v["gbs"] = v["bytes"] / (v["ms"] * 1e-3) / 1e9
@@ -417,6 +448,12 @@ def kernel_entry(v, traffic):
         rate = traffic / (v["ms"] * 1e-3) / 1e9
         e["traffic_rate"] = round(rate, 1)
         e["traffic_frac"] = round(rate / HBM_PEAK_GBS, 4)
+    if v.get("flops"):
+        # the arithmetic side of the same launch, against the published vector
+        # peak of its precision (float32: the packed-math figure)
+        e["flops"] = v["flops"]
+        e["gflops"] = round(v["flops"] / (v["ms"] * 1e-3) / 1e9, 1)
+        e["flop_frac"] = round(e["gflops"] / v["flop_peak"], 4)
     if "launches" in v:
         e["launches"] = v["launches"]
     return e
@@ -446,6 +483,10 @@ def roofline_entry(k, key, traffic, fine, word, nr, what):
     if t:
         out["traffic_rate"] = round(t / (op["ms"] * 1e-3) / 1e9, 1)
         out["traffic_frac"] = round(out["traffic_rate"] / HBM_PEAK_GBS, 4)
+    if op.get("flops"):
+        out["flops_per_launch"] = op["flops"]
+        out["gflops"] = round(op["flops"] / (op["ms"] * 1e-3) / 1e9, 1)
+        out["flop_frac"] = round(out["gflops"] / op["flop_peak"], 4)
     return out
 
 

@@ -63,6 +63,20 @@ def test_transfer_bytes_of_the_64_cube():
     assert bench.transfer_bytes(coarse, npts, 4, False) == 49_064_808
 
 
+def test_flop_counts_at_the_full_sizes():
+    # 75^3 Q4 ball: C = 421,875 cells, n = 5: 12 sweeps of 2 n^4 and 15 flops per Gauss point
+    fine = _level(3, 4, 301 ** 3, 75 ** 3)
+    assert bench.vmult_flops(fine) == 421_875 * (24 * 625 + 15 * 125) == 7_119_140_625
+    assert bench.vmult_flops(fine, nr=4) == 4 * 7_119_140_625
+    # 2D Q1: 8 sweeps of 2 n^3 and 6 flops per point
+    assert bench.vmult_flops(_level(2, 1, 65 ** 2, 64 ** 2)) == 64 ** 2 * (8 * 2 * 8 + 6 * 4)
+    assert bench.vmult_flops(_level(3, 2, 100, 10, ncomp=3)) is None
+    # transfer at Q4: 3 bases of 24 flops and 2 (125 + 25 + 5) per value
+    coarse = _level(3, 4, 137 ** 3, 34 ** 3)
+    assert bench.transfer_flops(coarse, 1000) == 1000 * (72 + 310)
+    assert bench.transfer_flops(coarse, 1000, nr=2) == 1000 * (72 + 620)
+
+
 def test_recorded_traffic_is_dropped_when_the_kernels_changed(tmp_path, monkeypatch):
     good = tmp_path / "good.txt"
     good.write_text("# comment\n"
