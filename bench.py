@@ -491,15 +491,23 @@ def roofline_entry(k, key, traffic, fine, word, nr, what):
 
 
 def copy_calibration(nbytes=1 << 30):
-    """A plain device copy of known size: its FETCH_SIZE/WRITE_SIZE readings
-    scale the counters of the other kernels to bytes."""
+    """A plain device copy of known size, three times: its FETCH_SIZE/WRITE_SIZE
+    readings scale the counters of the other kernels to bytes, and its rate
+    (bytes read plus written over the median time, HIP events) is what HBM
+    gives a streaming kernel on this GPU.  Returns (bytes, GB/s)."""
     import torch
     a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
     b = torch.empty_like(a)
+    times = []
     for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         b.copy_(a)
-    torch.cuda.synchronize()
-    return nbytes
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del a, b
+    return nbytes, 2 * nbytes / (sorted(times)[1] * 1e-3) / 1e9
 
 
 def cpu_baseline(cells, cfg, operator="laplace", degree=2, pmg=False, runs=3):
@@ -758,6 +766,7 @@ def run_pcg_workload(name, args, ctx, nn, torch, steps, warmup, with_cpu):
     log(f"[{name}] timing the operator and transfer kernels")
     k = kernel_rooflines(fine, levels[-2], transfers[-1], args.roofline_reps, nr)
     traffic = recorded_traffic(wl["roofline"])
+    _, copy_gbs = copy_calibration()
 
     golden = None
     if wl.get("golden") and not args.no_golden:
@@ -797,9 +806,10 @@ def run_pcg_workload(name, args, ctx, nn, torch, steps, warmup, with_cpu):
         "setup_s": {"levels": round(t_levels, 3), "transfers": round(t_transfers, 3), "hierarchy": round(t_hier, 3),
                     "tune": round(t_tune, 3)},
         "tuned": tuned,
-        "roofline": roofline_entry(k, op_key, traffic, fine, 8, nr,
-                                   f"operator application on the finest level ({fine.n_dofs} DoFs"
-                                   + (f", {nr} fused right-hand sides" if nr > 1 else "") + "), float64"),
+        "roofline": dict(roofline_entry(k, op_key, traffic, fine, 8, nr,
+                                        f"operator application on the finest level ({fine.n_dofs} DoFs"
+                                        + (f", {nr} fused right-hand sides" if nr > 1 else "") + "), float64"),
+                         copy_gbs=round(copy_gbs, 1)),
         "error_vs_oracle": {
             "golden": golden,
             "note": ("the full-size solve is beyond the oracle (tens of GB of CSR); the same recipe at the size "
@@ -882,10 +892,10 @@ def main():
             # command launches the same transfer kernels
             for dt in (torch.float64, torch.float32):
                 fine.tune(dt, reps=10)
-        nbytes = copy_calibration()
+        nbytes, copy_gbs = copy_calibration()
         k = kernel_rooflines(fine, coarse, tr, args.roofline_reps, args.roofline_rhs)
         print(json.dumps({"roofline_only": True, "workload": args.roofline_workload, "copy_bytes": nbytes,
-                          "reps": args.roofline_reps,
+                          "copy_gbs": round(copy_gbs, 1), "reps": args.roofline_reps,
                           "kernels": {n: {"ms": round(v["ms"], 5), "bytes": v["bytes"], "GB/s": round(v["gbs"], 1),
                                           "frac": round(v["frac"], 4), "launches": v.get("launches")}
                                       for n, v in k.items()}}), flush=True)
