@@ -689,6 +689,8 @@ def run_pcg_workload(name, args, ctx, nn, torch, steps, warmup, with_cpu):
                      cells_per_block_fp64=[r["cells_per_block"] for r in rep["levels"]],
                      cells_per_block_fp32=[r["cells_per_block"] for r in rep32],
                      fine_ms_cells_fp64=rep["levels"][-1]["ms_cells"], fine_ms_cells_fp32=rep32[-1]["ms_cells"],
+                     rhs_split_fp64=[r["rhs_split"] for r in rep["levels"]],
+                     rhs_split_fp32=[r["rhs_split"] for r in rep32],
                      restriction_teams=[r["chosen"] for r in rep["transfers"]])
     fine = levels[-1]
     nr = args.rhs if args.rhs is not None else wl.get("rhs", 1)
