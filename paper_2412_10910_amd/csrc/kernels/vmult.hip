@@ -187,6 +187,19 @@ constexpr int kIdxEntity = 1;  // one record of entity bases and slot bases per 
 // waves per SIMD the register allocation must allow: 4 for the float64 Q3
 // single-vector kernels with entity records or transposed sweeps (they would
 // otherwise take 132-150 VGPRs, 3 waves; at 128 they spill a few)
+// The float64 degree-4 transposed kernel keeps its per-point state in LDS:
+// three tiles instead of five (the z stages wait for every lane's reads before
+// overwriting their inputs), the z-stage outputs computed and stored one at a
+// time, and the geometry step run one point at a time on the lane's own tile
+// positions.  Holding the whole line's gradient and geometry in registers took
+// 148 VGPRs and 26.5 KB of LDS per workgroup (three waves per SIMD); this form
+// takes 83 VGPRs and 16.5 KB (four).  At lower degrees and in float32 the
+// register form is as fast or faster.
+template <int N, class T, int SW>
+constexpr bool vmult_lds_geometry() {
+    return SW == 1 && N == 5 && sizeof(T) == 8;
+}
+
 template <int N, class T, int NRT, int IDX, int SW, int G>
 constexpr int vmult_min_waves() {
     // two layout blocks per workgroup double the LDS of a workgroup: three
@@ -218,7 +231,8 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
     // block past the end repeats the loads of the last block and stores
     // nothing.
     static_assert(G == 1 || SCATTER == kSlots, "several layout blocks per workgroup: contribution slots only");
-    __shared__ T lds[SW == 1 ? 5 : 3][G * CPB][TILE];
+    constexpr bool kSeq = DIM == 3 && vmult_lds_geometry<N, T, SW>();
+    __shared__ T lds[SW == 1 && !kSeq ? 5 : 3][G * CPB][TILE];
     const int sub = G == 1 ? 0 : (int)threadIdx.x / WG;
     const int64_t bg = G == 1 ? xcd_remap(blockIdx.x, gridDim.x) : xcd_remap(blockIdx.x, gridDim.x) * G + sub;
     const bool bok = G == 1 || bg < nblk;
@@ -380,8 +394,8 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
         }
         block_sync<WG>();
         if constexpr (DIM == 3) {
-            T* T3 = lds[3][cb];
-            T* T4 = lds[4][cb];
+            T* T3 = lds[kSeq ? 1 : 3][cb];
+            T* T4 = lds[kSeq ? 2 : 4][cb];
             // y-line (i, t) = (j, t) of this lane's indices
             T a[N], w[N], wy[N];
 #pragma unroll
@@ -402,25 +416,61 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
                 a[c] = T1[(c * N + t) * N + j];
                 w[c] = T2[(c * N + t) * N + j];
             }
-            T zv[N], zz[N], zy[N];
-            line_apply_sym<N, T, false, 1>(tb.S, eo.S, a, zv);
-            line_apply_sym<N, T, false, -1>(tb.DS, eo.DS, a, zz);
-            line_apply_sym<N, T, false, 1>(tb.S, eo.S, w, zy);
-            if (act) {
+            if constexpr (kSeq) {
+                block_sync<WG>();  // T1 and T2 are overwritten below
+                T o[N];
+                line_apply_sym<N, T, false, 1>(tb.S, eo.S, a, o);
+                if (act) {
 #pragma unroll
-                for (int c = 0; c < N; ++c) {
-                    T0[(c * N + t) * N + j] = zv[c];
-                    T3[(c * N + t) * N + j] = zz[c];
-                    T4[(c * N + t) * N + j] = zy[c];
+                    for (int c = 0; c < N; ++c) T0[(c * N + t) * N + j] = o[c];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                line_apply_sym<N, T, false, -1>(tb.DS, eo.DS, a, o);
+                if (act) {
+#pragma unroll
+                    for (int c = 0; c < N; ++c) T3[(c * N + t) * N + j] = o[c];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                line_apply_sym<N, T, false, 1>(tb.S, eo.S, w, o);
+                if (act) {
+#pragma unroll
+                    for (int c = 0; c < N; ++c) T4[(c * N + t) * N + j] = o[c];
+                }
+            } else {
+                T zv[N], zz[N], zy[N];
+                line_apply_sym<N, T, false, 1>(tb.S, eo.S, a, zv);
+                line_apply_sym<N, T, false, -1>(tb.DS, eo.DS, a, zz);
+                line_apply_sym<N, T, false, 1>(tb.S, eo.S, w, zy);
+                if (act) {
+#pragma unroll
+                    for (int c = 0; c < N; ++c) {
+                        T0[(c * N + t) * N + j] = zv[c];
+                        T3[(c * N + t) * N + j] = zz[c];
+                        T4[(c * N + t) * N + j] = zy[c];
+                    }
                 }
             }
             block_sync<WG>();
-            // back on the x-line
+            if constexpr (kSeq) {
+                // back on the x-line: the x derivative replaces the values in
+                // place; the y and z derivatives stay in their tiles for the
+                // geometry step, which works on one point at a time
+                T dx[N];
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                v[i] = T0[row + i];
-                gy[i] = T4[row + i];
-                gz[i] = T3[row + i];
+                for (int i = 0; i < N; ++i) v[i] = T0[row + i];
+                line_apply_sym<N, T, false, -1>(tb.D, eo.D, v, dx);
+                if (act) {
+#pragma unroll
+                    for (int i = 0; i < N; ++i) T0[row + i] = dx[i];
+                }
+            } else {
+                // back on the x-line
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    v[i] = T0[row + i];
+                    gy[i] = T4[row + i];
+                    gz[i] = T3[row + i];
+                }
             }
         } else {
             // y-line i = t of this lane's index
@@ -443,7 +493,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
                 gz[i] = T2[row + i];
             }
         }
-        line_apply_sym<N, T, false, -1>(tb.D, eo.D, v, gx);
+        if constexpr (!kSeq) line_apply_sym<N, T, false, -1>(tb.D, eo.D, v, gx);
     } else {
         line_apply_sym<N, T, false, 1>(tb.S, eo.S, u, v);  // x: nodes -> Gauss points
         if constexpr (DIM == 3) {
@@ -519,7 +569,72 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
     }
 
     // ---- geometry at the Gauss points of the line ------------------------
-    if constexpr (GEO == kStoredMetric) {
+    if constexpr (kSeq) {
+        // one point at a time, the reference gradient read from and the
+        // result written back to the lane's own positions of the tiles (x in
+        // tile 0, z in tile 1, y in tile 2): the same arithmetic as below with
+        // the registers of one point instead of the whole line
+        T* Gx = lds[0][cb];
+        T* Gz = lds[1][cb];
+        T* Gy = lds[2][cb];
+        if constexpr (GEO == kStoredMetric) {
+            const T* mt = geo + b * (M * N * WG) + lane;
+#pragma unroll 1
+            for (int i = 0; i < N; ++i) {
+                const T g00 = mt[(0 * N + i) * WG], g11 = mt[(1 * N + i) * WG], g22 = mt[(2 * N + i) * WG];
+                const T g01 = mt[(3 * N + i) * WG], g02 = mt[(4 * N + i) * WG], g12 = mt[(5 * N + i) * WG];
+                const T x = Gx[row + i], y = Gy[row + i], z = Gz[row + i];
+                const T ox = g00 * x + g01 * y + g02 * z;
+                const T oy = g01 * x + g11 * y + g12 * z;
+                const T oz = g02 * x + g12 * y + g22 * z;
+                if (act) {
+                    Gx[row + i] = ox;
+                    Gy[row + i] = oy;
+                    Gz[row + i] = oz;
+                }
+            }
+        } else {
+            T c0[3], C1[3], E1[3], D2[3], F2[3];
+            const T* cf = lcf[cb];
+            const T eta = lg[j], zeta = lg[t];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                c0[k] = cf[0 + k] + cf[9 + k] * eta + (cf[12 + k] + cf[18 + k] * eta) * zeta;
+                C1[k] = cf[3 + k] + cf[15 + k] * zeta;
+                E1[k] = cf[9 + k] + cf[18 + k] * zeta;
+                D2[k] = cf[6 + k] + cf[15 + k] * eta;
+                F2[k] = cf[12 + k] + cf[18 + k] * eta;
+            }
+            const T wl = lw[j] * lw[t];
+#pragma unroll 1
+            for (int i = 0; i < N; ++i) {
+                const T xi = lg[i];
+                T c1[3], c2[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    c1[k] = C1[k] + E1[k] * xi;
+                    c2[k] = D2[k] + F2[k] * xi;
+                }
+                const T r0[3] = {c1[1] * c2[2] - c1[2] * c2[1], c1[2] * c2[0] - c1[0] * c2[2],
+                                 c1[0] * c2[1] - c1[1] * c2[0]};
+                const T r1[3] = {c2[1] * c0[2] - c2[2] * c0[1], c2[2] * c0[0] - c2[0] * c0[2],
+                                 c2[0] * c0[1] - c2[1] * c0[0]};
+                const T r2[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2],
+                                 c0[0] * c1[1] - c0[1] * c1[0]};
+                const T det = c0[0] * r0[0] + c0[1] * r0[1] + c0[2] * r0[2];
+                const T s = lw[i] * wl * recip(det);
+                const T x = Gx[row + i], y = Gy[row + i], z = Gz[row + i];
+                T p[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) p[k] = (r0[k] * x + r1[k] * y + r2[k] * z) * s;
+                if (act) {
+                    Gx[row + i] = r0[0] * p[0] + r0[1] * p[1] + r0[2] * p[2];
+                    Gy[row + i] = r1[0] * p[0] + r1[1] * p[1] + r1[2] * p[2];
+                    Gz[row + i] = r2[0] * p[0] + r2[1] * p[1] + r2[2] * p[2];
+                }
+            }
+        }
+    } else if constexpr (GEO == kStoredMetric) {
         const T* mt = geo + b * (M * N * WG) + lane;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -609,36 +724,67 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
         T* T0 = lds[0][cb];
         T* T1 = lds[1][cb];
         T* T2 = lds[2][cb];
-        line_apply_sym<N, T, true, -1>(tb.D, eo.Dt, gx, u);  // Dx^T fx
-        block_sync<WG>();                     // every lane has read the forward tiles
+        if constexpr (kSeq) {
+            // the geometry step left f_x, f_z, f_y in the lane's positions of
+            // tiles 0, 1, 2: Dx^T f_x replaces f_x in place
+            T g0[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) g0[i] = T0[row + i];
+            line_apply_sym<N, T, true, -1>(tb.D, eo.Dt, g0, u);  // Dx^T fx
+        } else {
+            line_apply_sym<N, T, true, -1>(tb.D, eo.Dt, gx, u);  // Dx^T fx
+            block_sync<WG>();                     // every lane has read the forward tiles
+        }
         if constexpr (DIM == 3) {
-            T* T3 = lds[3][cb];
-            T* T4 = lds[4][cb];
+            // outputs of the z stage (T3, T4) and of the y stage (Ty)
+            T* T3 = lds[kSeq ? 0 : 3][cb];
+            T* T4 = lds[kSeq ? 1 : 4][cb];
+            T* Ty = lds[kSeq ? 2 : 0][cb];
             if (act) {
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     T0[row + i] = u[i];
-                    T1[row + i] = gy[i];
-                    T2[row + i] = gz[i];
+                    if constexpr (!kSeq) {
+                        T1[row + i] = gy[i];
+                        T2[row + i] = gz[i];
+                    }
                 }
             }
             block_sync<WG>();
-            // z-line (i, j) = (j, t) of this lane's indices
+            // z-line (i, j) = (j, t) of this lane's indices: Dx^T f_x, f_y, f_z
+            T* Fy = kSeq ? T2 : T1;
+            T* Fz = kSeq ? T1 : T2;
             T a[N], b2[N], c2[N], r0[N], r1[N];
 #pragma unroll
             for (int c = 0; c < N; ++c) {
                 a[c] = T0[(c * N + t) * N + j];
-                b2[c] = T1[(c * N + t) * N + j];
-                c2[c] = T2[(c * N + t) * N + j];
+                b2[c] = Fy[(c * N + t) * N + j];
+                c2[c] = Fz[(c * N + t) * N + j];
             }
-            line_apply_sym<N, T, true, 1>(tb.S, eo.St, a, r0);
-            line_apply_sym<N, T, true, -1>(tb.DS, eo.DSt, c2, r1);
-            line_apply_sym<N, T, true, 1>(tb.S, eo.St, b2, a);
-            if (act) {
+            if constexpr (kSeq) {
+                block_sync<WG>();  // T0 and T1 are overwritten below
+                line_apply_sym<N, T, true, 1>(tb.S, eo.St, a, r0);
+                line_apply_sym<N, T, true, -1>(tb.DS, eo.DSt, c2, r1);
+                if (act) {
 #pragma unroll
-                for (int c = 0; c < N; ++c) {
-                    T3[(c * N + t) * N + j] = r0[c] + r1[c];
-                    T4[(c * N + t) * N + j] = a[c];
+                    for (int c = 0; c < N; ++c) T3[(c * N + t) * N + j] = r0[c] + r1[c];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                line_apply_sym<N, T, true, 1>(tb.S, eo.St, b2, a);
+                if (act) {
+#pragma unroll
+                    for (int c = 0; c < N; ++c) T4[(c * N + t) * N + j] = a[c];
+                }
+            } else {
+                line_apply_sym<N, T, true, 1>(tb.S, eo.St, a, r0);
+                line_apply_sym<N, T, true, -1>(tb.DS, eo.DSt, c2, r1);
+                line_apply_sym<N, T, true, 1>(tb.S, eo.St, b2, a);
+                if (act) {
+#pragma unroll
+                    for (int c = 0; c < N; ++c) {
+                        T3[(c * N + t) * N + j] = r0[c] + r1[c];
+                        T4[(c * N + t) * N + j] = a[c];
+                    }
                 }
             }
             block_sync<WG>();
@@ -652,11 +798,11 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
             line_apply_sym<N, T, true, -1>(tb.DS, eo.DSt, b2, r1);
             if (act) {
 #pragma unroll
-                for (int c = 0; c < N; ++c) T0[(t * N + c) * N + j] = r0[c] + r1[c];
+                for (int c = 0; c < N; ++c) Ty[(t * N + c) * N + j] = r0[c] + r1[c];
             }
             block_sync<WG>();
 #pragma unroll
-            for (int i = 0; i < N; ++i) u[i] = T0[row + i];
+            for (int i = 0; i < N; ++i) u[i] = Ty[row + i];
         } else {
             if (act) {
 #pragma unroll
