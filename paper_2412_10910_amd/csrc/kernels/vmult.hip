@@ -290,14 +290,18 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
     // the 1D tables: rows selected by the lane's y/z index are read from LDS
     // (indexing the by-value argument with a lane-dependent index would be a
     // global load on the critical path of every sweep)
+    // (the transposed sweeps contract with the by-value tables alone and stage
+    // only the Gauss points and weights)
     constexpr int NT = 3 * N * N + 2 * N;
     static_assert(sizeof(OpTables<N, T>) == NT * sizeof(T), "OpTables must be a flat array of T");
-    constexpr int TE = (NT + WG - 1) / WG;  // table entries per lane
-    __shared__ T ltab[G][NT];
+    constexpr int TOFF = SW == 1 ? 3 * N * N : 0;  // first table entry staged in LDS
+    constexpr int NTL = NT - TOFF;                 // entries staged
+    constexpr int TE = (NTL + WG - 1) / WG;        // table entries per lane
+    __shared__ T ltab[G][NTL];
     T tv[TE];
 #pragma unroll
     for (int e = 0; e < TE; ++e)
-        tv[e] = lane + e * WG < NT ? reinterpret_cast<const T*>(&tb)[lane + e * WG] : T(0);
+        tv[e] = lane + e * WG < NTL ? reinterpret_cast<const T*>(&tb)[TOFF + lane + e * WG] : T(0);
     // Entity records (IDX == kIdxEntity): node i of the lane's line has classes
     // (cx, cy, cz) in {0: first, 1: inside, 2: last} per direction, lies on
     // entity e = cx + 3 cy + 9 cz, and has local coordinates (u, v, w) = its
@@ -354,11 +358,11 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
     }
 #pragma unroll
     for (int e = 0; e < TE; ++e)
-        if (lane + e * WG < NT) ltab[sub][lane + e * WG] = tv[e];
-    const T* lS = ltab[sub];
-    const T* lDS = lS + N * N;
-    const T* lD = lS + 2 * N * N;
-    const T* lg = lS + 3 * N * N;
+        if (lane + e * WG < NTL) ltab[sub][lane + e * WG] = tv[e];
+    [[maybe_unused]] const T* lS = SW == 1 ? nullptr : ltab[sub];
+    [[maybe_unused]] const T* lDS = SW == 1 ? nullptr : ltab[sub] + N * N;
+    [[maybe_unused]] const T* lD = SW == 1 ? nullptr : ltab[sub] + 2 * N * N;
+    const T* lg = ltab[sub] + (3 * N * N - TOFF);
     const T* lw = lg + N;
 
     T* A = lds[0][cb];
