@@ -341,8 +341,10 @@ typedef struct {
  * tuned level stays bitwise reproducible; the others keep ms = -1 and are
  * taken only when forced.  The stored metric is computed when a precision
  * needs it and freed when none does.  Each variant is timed with one and
- * with two layout blocks per workgroup (nnmg_level_set_cells_per_block) and
- * the fastest pair is kept (ms[v]: the faster of the two; ms_cpb: both, for
+ * with two layout blocks per workgroup (nnmg_level_set_cells_per_block), in
+ * two passes over the candidates (the second in reverse order, the times
+ * averaged, so that a drift of the clocks favours none), and the fastest pair
+ * is kept (ms[v]: the faster of the two; ms_cpb: both, for
  * the variant kept); on small levels the two forms of several right-hand
  * sides (nnmg_level_set_rhs_split) are then timed and the faster kept.  Synchronizes the
  * device; hierarchies holding the level re-capture their V-cycle graphs.

@@ -15,7 +15,9 @@
 // Variants 4, 5, 10 and 11 exist for 3D Laplace levels of degree >= 3 (where
 // the records were built).  The elasticity operator has variant 0 only.
 // Each variant is timed with one and with two layout blocks of cpb cells per
-// workgroup (Laplace slot variants), and the fastest pair is kept.  On a
+// workgroup (Laplace slot variants), in two passes over the candidates (the
+// second in reverse order, the two times averaged), and the fastest pair is
+// kept.  On a
 // small level (a grid of few wavefronts) the variant kept is then timed with
 // four right-hand sides as one grid row per right-hand side against every
 // block looping over them.  Transfer variants: the lanes
@@ -31,6 +33,8 @@
 // through level_set_variant.
 #include <algorithm>
 #include <functional>
+#include <utility>
+#include <vector>
 
 #include "../internal.hpp"
 
@@ -188,32 +192,43 @@ void level_tune(Level& L, int prec, int reps, nnmg_tune_result* res) {
         res->n_variants = nvar;
         for (double& t : res->ms) t = -1.0;
         // every variant with one and with two layout blocks per workgroup (the
-        // Laplace slot variants; same sums either way): ms[v] is the faster
-        // of the two, ms_cpb the pair of the variant kept
+        // Laplace slot variants; same sums either way), timed in two passes,
+        // the second in reverse order, and averaged, so that a drift of the
+        // clocks over the tuning does not favour the candidates timed first:
+        // ms[v] is the faster of the variant's two sizes, ms_cpb the pair of
+        // the variant kept
         const bool grouped = L.op == NNMG_OP_LAPLACE && L.nblocks > 0;
-        double ms_g[16][2];
-        double best_ms = -1.0;
-        int best = 0, best_g = 1;
+        std::vector<std::pair<int, int>> cand;  // (variant, layout blocks per workgroup)
         for (int v = 0; v < nvar; ++v) {
-            ms_g[v][0] = ms_g[v][1] = -1.0;
             if (atomic_variant(v)) continue;  // float atomics: not reproducible, never picked by the tuner
             if (v % 6 >= 4 && !has_entity_variants(L)) continue;
-            apply_variant(L, prec, v);
-            for (int g = 1; g <= (grouped ? 2 : 1); ++g) {
-                L.var[prec].group = g;
-                ms_g[v][g - 1] = time_ms(
+            for (int g = 1; g <= (grouped ? 2 : 1); ++g) cand.emplace_back(v, g);
+        }
+        std::vector<double> t(cand.size(), 0.0);
+        for (int pass = 0; pass < 2; ++pass)
+            for (size_t k = 0; k < cand.size(); ++k) {
+                const size_t c = pass == 0 ? k : cand.size() - 1 - k;
+                apply_variant(L, prec, cand[c].first);
+                L.var[prec].group = cand[c].second;
+                t[c] += 0.5 * time_ms(
                     [&](hipStream_t st) {
                         launch_vmult_contrib(L, prec, x.ptr, L.d_contrib.ptr, st);
                         launch_residual_gather(L, prec, L.d_contrib.ptr, f.ptr, r.ptr, st);
                     },
                     reps, s);
-                const double t = ms_g[v][g - 1];
-                if (res->ms[v] < 0 || t < res->ms[v]) res->ms[v] = t;
-                if (best_ms < 0 || t < best_ms) {
-                    best_ms = t;
-                    best = v;
-                    best_g = g;
-                }
+            }
+        double ms_g[16][2];
+        for (auto& m : ms_g) m[0] = m[1] = -1.0;
+        double best_ms = -1.0;
+        int best = 0, best_g = 1;
+        for (size_t c = 0; c < cand.size(); ++c) {
+            const int v = cand[c].first, g = cand[c].second;
+            ms_g[v][g - 1] = t[c];
+            if (res->ms[v] < 0 || t[c] < res->ms[v]) res->ms[v] = t[c];
+            if (best_ms < 0 || t[c] < best_ms) {
+                best_ms = t[c];
+                best = v;
+                best_g = g;
             }
         }
         apply_variant(L, prec, best);
