@@ -17,11 +17,10 @@
 // Each variant is timed with one and with two layout blocks of cpb cells per
 // workgroup (Laplace slot variants), in two passes over the candidates (the
 // second in reverse order, the two times averaged), and the fastest pair is
-// kept.  On a
-// small level (a grid of few wavefronts) the variant kept is then timed with
-// four right-hand sides as one grid row per right-hand side against every
-// block looping over them.  Transfer variants: the lanes
-// per coarse cell of the restriction, 4 << v for v = 0..4.
+// kept.  On a small level (a grid of few wavefronts) the variant kept is then
+// timed with four right-hand sides as one grid row per right-hand side
+// against every block looping over them.  Transfer variants: the lanes per
+// coarse cell of the restriction, 4 << v for v = 0..4.
 //
 // Each precision has its own variant: the float64 and float32 kernels of one
 // level are timed and chosen separately.
