@@ -307,8 +307,11 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
     // entity e = cx + 3 cy + 9 cz, and has local coordinates (u, v, w) = its
     // indices - 1 along the entity's own (inside) directions in x, y, z order;
     // the record's orientation code maps them to the canonical index m.  The
-    // DoFs are decoded here, the slots only at the store, so that they hold no
-    // registers during the sweeps.
+    // DoFs are decoded here and, where registers allow, the slots with them
+    // (they then hold N registers through the sweeps; decoding them again at
+    // the store costs instructions).  The float64 degree-3 kernels, capped at
+    // four waves per SIMD, decode the slots at the store.
+    constexpr bool kSlotsEarly = SCATTER == kSlots && !(N == 4 && sizeof(T) == 8);
     __shared__ int32_t lrec[IDX == kIdxEntity ? G * CPB : 1][IDX == kIdxEntity ? EW : 1];
     constexpr int K1 = N - 2;  // DoFs along an edge
     const int ecy = j == 0 ? 0 : (j == N - 1 ? 2 : 1);
@@ -345,7 +348,13 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
             ent_node(i, e, m, code);
             const int32_t D = lrec[cb][e];
             idx[i] = (act && D >= 0) ? D + m : -1;
+            if constexpr (kSlotsEarly) {
+                const int32_t SR = lrec[cb][27 + e];
+                slot[i] = (act && SR >= 0) ? SR + m * (code & 15) : -1;
+            }
         }
+        if constexpr (kSlotsEarly)
+            if ((lrec[cb][EW - 1] & 2) && slot[N - 1] >= 0) slot[N - 1] |= kMergeNext;
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) u[i] = idx[i] >= 0 ? src[(int64_t)idx[i] * nr + rhs0] : T(0);
@@ -905,7 +914,7 @@ __global__ __launch_bounds__((OpShape<DIM, N>::WG * G), (vmult_min_waves<N, T, N
         // it to be the same DoF as this line's last node (per-node layout: in
         // the same wavefront; entity records of blocks wider than a wavefront:
         // through LDS, for every pair of cells of the block)
-        if constexpr (IDX == kIdxEntity) {
+        if constexpr (IDX == kIdxEntity && !kSlotsEarly) {
 #pragma unroll
             for (int i = 0; i < N; ++i) {
                 int e, m, code;
