@@ -163,6 +163,14 @@ void nnmg_default_cg_opts(nnmg_cg_opts* opts);
 /* Sets up one level: DoF numbering (Gauss-Lobatto support points), the
  * cell-to-DoF map, the constrained set, the geometry at the (k+1)^d Gauss
  * points (paper §4) and the inverse Jacobi diagonal.  Synchronous.
+ * The operator starts in variant 0 (nnmg_level_tune) with one layout block
+ * per workgroup in both precisions, unless the environment at creation asks
+ * otherwise: NNMG_GEOMETRY=metric (stored metric), NNMG_SCATTER=atomic (float
+ * atomics), NNMG_SWEEP=transposed (transposed sweeps), NNMG_INDEX=entity
+ * (entity-compressed indices, 3D Laplace, degree >= 3); NNMG_CELL_ORDER=input
+ * keeps the cell blocks in input order instead of the Morton order of their
+ * centroids.  All of them give the same operator up to the order of
+ * floating-point sums.
  * Errors: UNSUPPORTED (degree or dim), INVALID_ARG, MESH (vertex index out
  * of range, repeated vertex in a cell, non-positive Jacobian at a Gauss
  * point), OOM, HIP. */
