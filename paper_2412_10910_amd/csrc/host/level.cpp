@@ -124,15 +124,23 @@ static void number_dofs(Level& L, const std::vector<int64_t>& visit) {
     const int ke = k - 1;  // interior nodes per edge direction
 
     L.dofmap.assign((size_t)(C * q), -1);
+    // per cell, the base of each edge and face met so far and its orientation
+    // (entity e = cx + 3 cy + 9 cz of the node classes 0 / inside / k): one
+    // lookup per entity instead of one per node, the same first-touch order
+    int64_t ebase[27];
+    int eflip[27];
     for (int64_t vi = 0; vi < C; ++vi) {
         const int64_t c = visit[(size_t)vi];
         const int32_t* cv = cells + c * nv;
         int64_t interior_base = -1;
+        for (int e = 0; e < 27; ++e) ebase[e] = -1;
         for (int a = 0; a < q; ++a) {
             int id[3] = {a % n, (a / n) % n, dim == 3 ? a / (n * n) : 0};
             int n_int = 0, int_axes[3];
             for (int d = 0; d < dim; ++d)
                 if (id[d] > 0 && id[d] < k) int_axes[n_int++] = d;
+            int ent = 0;
+            for (int d = dim - 1; d >= 0; --d) ent = 3 * ent + (id[d] == 0 ? 0 : (id[d] == k ? 2 : 1));
             int64_t dof;
             if (n_int == 0) {
                 int b = 0;
@@ -142,59 +150,64 @@ static void number_dofs(Level& L, const std::vector<int64_t>& visit) {
                 dof = vertex_base[v];
             } else if (n_int == 1 && n_int < dim) {
                 const int ax = int_axes[0];
-                int b0 = 0;
-                for (int d = 0; d < dim; ++d)
-                    if (d != ax) b0 |= (id[d] == k ? 1 : 0) << d;
-                const int32_t v0 = cv[b0], v1 = cv[b0 | (1 << ax)];
-                const uint64_t key = edge_key(v0, v1);
-                auto it = edge_base.find(key);
-                int64_t base;
-                if (it == edge_base.end()) {
-                    base = next;
-                    next += ke;
-                    edge_base.emplace(key, base);
-                } else {
-                    base = it->second;
+                if (ebase[ent] < 0) {
+                    int b0 = 0;
+                    for (int d = 0; d < dim; ++d)
+                        if (d != ax) b0 |= (id[d] == k ? 1 : 0) << d;
+                    const int32_t v0 = cv[b0], v1 = cv[b0 | (1 << ax)];
+                    const uint64_t key = edge_key(v0, v1);
+                    auto it = edge_base.find(key);
+                    if (it == edge_base.end()) {
+                        ebase[ent] = next;
+                        next += ke;
+                        edge_base.emplace(key, ebase[ent]);
+                    } else {
+                        ebase[ent] = it->second;
+                    }
+                    eflip[ent] = v0 < v1 ? 0 : 1;
                 }
                 const int t = id[ax];
-                const int pos = v0 < v1 ? t - 1 : k - t - 1;
-                dof = base + pos;
+                const int pos = eflip[ent] == 0 ? t - 1 : k - t - 1;
+                dof = ebase[ent] + pos;
             } else if (n_int == 2 && dim == 3) {
                 const int a0 = int_axes[0], a1 = int_axes[1];
-                int fixed = 3 - a0 - a1;
-                const int bf = (id[fixed] == k ? 1 : 0) << fixed;
-                auto corner = [&](int s, int t) { return cv[bf | (s << a0) | (t << a1)]; };
-                const int32_t c00 = corner(0, 0), c10 = corner(1, 0), c01 = corner(0, 1), c11 = corner(1, 1);
-                std::array<int32_t, 4> key{c00, c10, c01, c11};
-                std::sort(key.begin(), key.end());
-                auto it = face_base.find(key);
-                int64_t base;
-                if (it == face_base.end()) {
-                    base = next;
-                    next += (int64_t)ke * ke;
-                    face_base.emplace(key, base);
-                } else {
-                    base = it->second;
+                if (ebase[ent] < 0) {
+                    int fixed = 3 - a0 - a1;
+                    const int bf = (id[fixed] == k ? 1 : 0) << fixed;
+                    auto corner = [&](int s, int t) { return cv[bf | (s << a0) | (t << a1)]; };
+                    const int32_t c00 = corner(0, 0), c10 = corner(1, 0), c01 = corner(0, 1), c11 = corner(1, 1);
+                    std::array<int32_t, 4> key{c00, c10, c01, c11};
+                    std::sort(key.begin(), key.end());
+                    auto it = face_base.find(key);
+                    if (it == face_base.end()) {
+                        ebase[ent] = next;
+                        next += (int64_t)ke * ke;
+                        face_base.emplace(key, ebase[ent]);
+                    } else {
+                        ebase[ent] = it->second;
+                    }
+                    // origin corner: lowest vertex id
+                    int os = 0, ot = 0;
+                    int32_t best = c00;
+                    if (c10 < best) { best = c10; os = 1; ot = 0; }
+                    if (c01 < best) { best = c01; os = 0; ot = 1; }
+                    if (c11 < best) { best = c11; os = 1; ot = 1; }
+                    const int32_t nb_s = corner(1 - os, ot);  // neighbour along axis a0
+                    const int32_t nb_t = corner(os, 1 - ot);  // neighbour along axis a1
+                    eflip[ent] = os | (ot << 1) | ((nb_s < nb_t ? 0 : 1) << 2);
                 }
-                // origin corner: lowest vertex id
-                int os = 0, ot = 0;
-                int32_t best = c00;
-                if (c10 < best) { best = c10; os = 1; ot = 0; }
-                if (c01 < best) { best = c01; os = 0; ot = 1; }
-                if (c11 < best) { best = c11; os = 1; ot = 1; }
-                const int32_t nb_s = corner(1 - os, ot);  // neighbour along axis a0
-                const int32_t nb_t = corner(os, 1 - ot);  // neighbour along axis a1
+                const int os = eflip[ent] & 1, ot = (eflip[ent] >> 1) & 1;
                 const int ds = os == 0 ? id[a0] : k - id[a0];
                 const int dt = ot == 0 ? id[a1] : k - id[a1];
                 int u, w;
-                if (nb_s < nb_t) {
+                if (((eflip[ent] >> 2) & 1) == 0) {
                     u = ds;
                     w = dt;
                 } else {
                     u = dt;
                     w = ds;
                 }
-                dof = base + (u - 1) + (int64_t)(w - 1) * ke;
+                dof = ebase[ent] + (u - 1) + (int64_t)(w - 1) * ke;
             } else {
                 // cell interior: the block is reserved when its first node is met
                 if (interior_base < 0) {
@@ -350,7 +363,6 @@ static void find_constraints(Level& L, const uint8_t* dirichlet) {
     if (!dirichlet) return;
     const int fv = 1 << (dim - 1);
     std::unordered_map<std::array<int32_t, 4>, int, Key4Hash> count;
-    count.reserve((size_t)(C * dim + 16));
     auto facet_key = [&](int64_t c, int ax, int side) {
         std::array<int32_t, 4> key{-1, -1, -1, -1};
         int m = 0;
@@ -359,17 +371,24 @@ static void find_constraints(Level& L, const uint8_t* dirichlet) {
         std::sort(key.begin(), key.begin() + fv);
         return key;
     };
+    // only a facet whose vertices are all Dirichlet-marked can be constrained,
+    // and every cell holding such a facet sees the same vertices: counting
+    // those facets alone tells which of them lie on the boundary
+    auto all_marked = [&](int64_t c, int ax, int side) {
+        for (int b = 0; b < nv; ++b)
+            if (((b >> ax) & 1) == side && !dirichlet[L.cells[(size_t)(c * nv + b)]]) return false;
+        return true;
+    };
     for (int64_t c = 0; c < C; ++c)
         for (int ax = 0; ax < dim; ++ax)
-            for (int side = 0; side < 2; ++side) count[facet_key(c, ax, side)]++;
+            for (int side = 0; side < 2; ++side)
+                if (all_marked(c, ax, side)) count[facet_key(c, ax, side)]++;
     for (int64_t c = 0; c < C; ++c)
         for (int ax = 0; ax < dim; ++ax)
             for (int side = 0; side < 2; ++side) {
+                if (!all_marked(c, ax, side)) continue;
                 const auto key = facet_key(c, ax, side);
                 if (count[key] != 1) continue;
-                bool all = true;
-                for (int m = 0; m < fv; ++m) all = all && dirichlet[key[m]];
-                if (!all) continue;
                 for (int a = 0; a < q; ++a) {
                     const int id = ax == 0 ? a % n : (ax == 1 ? (a / n) % n : a / (n * n));
                     if (id == side * k) L.constrained[(size_t)L.dofmap[(size_t)(c * q + a)]] = 1;
@@ -381,20 +400,29 @@ static void compute_support_points(Level& L) {
     const int dim = L.dim, n = L.n, q = L.q, nv = 1 << dim;
     L.support.assign((size_t)(L.n_nodes * dim), 0.0);
     std::vector<char> done((size_t)L.n_nodes, 0);
+    // the trilinear weights of the vertices at each local node (the same
+    // products, in the same order, for every cell)
+    std::vector<double> W((size_t)(q * nv));
+    for (int a = 0; a < q; ++a) {
+        const double xi[3] = {L.basis.node[a % n], L.basis.node[(a / n) % n],
+                              dim == 3 ? L.basis.node[a / (n * n)] : 0.0};
+        for (int b = 0; b < nv; ++b) {
+            double N = 1.0;
+            for (int d = 0; d < dim; ++d) N *= ((b >> d) & 1) ? xi[d] : 1.0 - xi[d];
+            W[(size_t)(a * nv + b)] = N;
+        }
+    }
+    // each DoF takes the coordinates its first cell gives it
     for (int64_t c = 0; c < L.n_cells; ++c) {
         const int32_t* cv = &L.cells[(size_t)(c * nv)];
         for (int a = 0; a < q; ++a) {
             const int32_t dof = L.dofmap[(size_t)(c * q + a)];
             if (done[(size_t)dof]) continue;
             done[(size_t)dof] = 1;
-            double xi[3] = {L.basis.node[a % n], L.basis.node[(a / n) % n], dim == 3 ? L.basis.node[a / (n * n)] : 0.0};
+            const double* w = &W[(size_t)(a * nv)];
             for (int i = 0; i < dim; ++i) {
                 double x = 0.0;
-                for (int b = 0; b < nv; ++b) {
-                    double N = 1.0;
-                    for (int d = 0; d < dim; ++d) N *= ((b >> d) & 1) ? xi[d] : 1.0 - xi[d];
-                    x += N * L.vertices[(size_t)(cv[b] * dim + i)];
-                }
+                for (int b = 0; b < nv; ++b) x += w[b] * L.vertices[(size_t)(cv[b] * dim + i)];
                 L.support[(size_t)(dof * dim + i)] = x;
             }
         }
