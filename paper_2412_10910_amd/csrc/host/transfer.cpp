@@ -17,6 +17,8 @@
 // transfer instead (setup_nested_p, kernels/pmg.hip).
 #include <algorithm>
 #include <cmath>
+#include <memory>
+#include <thread>
 
 #include "../internal.hpp"
 
@@ -25,6 +27,27 @@
 #endif
 
 namespace nnmg {
+
+// host threads for the setup's passes over all fine points
+static int sort_threads() {
+    const unsigned h = std::thread::hardware_concurrency();
+    return (int)std::min(8u, std::max(1u, h));
+}
+
+// fn(0) .. fn(n - 1), each on its own thread (fn(0) on the caller's)
+template <class F>
+static void run_threads(int n, F&& fn) {
+    std::vector<std::thread> th;
+    for (int t = 1; t < n; ++t) th.emplace_back([&fn, t] { fn(t); });
+    fn(0);
+    for (auto& x : th) x.join();
+}
+
+// host storage that is written in full before it is read, left uninitialised
+template <class V>
+static std::unique_ptr<V[]> host_buffer(size_t n) {
+    return std::unique_ptr<V[]>(new V[n]);
+}
 
 // restriction slots: the sum of coarse cell K for node a goes to
 // rslot[K q + a], the slots of coarse node j being [roff[j], roff[j+1])
@@ -117,21 +140,30 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
             return T;
         }
 
-        // query points: the unconstrained fine nodes (P acts on every component alike)
-        std::vector<double> pts;
-        for (int64_t i = 0; i < fine->n_nodes; ++i) {
-            if (fine->constrained[(size_t)i]) continue;
-            T->h_point_dof.push_back((int32_t)i);
-            for (int a = 0; a < dim; ++a) pts.push_back(fine->support[(size_t)(i * dim + a)]);
-        }
-        const int64_t np = (int64_t)T->h_point_dof.size();
-        T->n_points = np;
+        // query points: the unconstrained fine nodes (P acts on every component alike),
+        // and their bounds, which the bucket grid covers with the grown boxes
+        int64_t np = 0;
+        for (int64_t i = 0; i < fine->n_nodes; ++i) np += fine->constrained[(size_t)i] ? 0 : 1;
         if (np > INT32_MAX) fail(NNMG_ERR_UNSUPPORTED, "too many points");
+        T->n_points = np;
+        T->h_point_dof.resize((size_t)np);
+        std::unique_ptr<double[]> pts = host_buffer<double>((size_t)(np * dim));
+        double glo[3] = {1e300, 1e300, 1e300}, ghi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t i = 0, p = 0; i < fine->n_nodes; ++i) {
+            if (fine->constrained[(size_t)i]) continue;
+            T->h_point_dof[(size_t)p] = (int32_t)i;
+            for (int a = 0; a < dim; ++a) {
+                const double x = fine->support[(size_t)(i * dim + a)];
+                pts[(size_t)(p * dim + a)] = x;
+                glo[a] = std::min(glo[a], x);
+                ghi[a] = std::max(ghi[a], x);
+            }
+            ++p;
+        }
 
         // grown boxes of the coarse cells
         const int64_t C = coarse->n_cells;
         std::vector<double> boxes((size_t)(C * 2 * dim));
-        double glo[3] = {1e300, 1e300, 1e300}, ghi[3] = {-1e300, -1e300, -1e300};
         std::vector<double> ext[3];
         for (int a = 0; a < dim; ++a) ext[a].resize((size_t)C);
         for (int64_t c = 0; c < C; ++c) {
@@ -156,11 +188,6 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
                 ext[a][(size_t)c] = h - l;
             }
         }
-        for (int64_t i = 0; i < np; ++i)
-            for (int a = 0; a < dim; ++a) {
-                glo[a] = std::min(glo[a], pts[(size_t)(i * dim + a)]);
-                ghi[a] = std::max(ghi[a], pts[(size_t)(i * dim + a)]);
-            }
         // bucket size: half the median grown-box extent per axis
         double step[3];
         int nb[3] = {1, 1, 1};
@@ -203,7 +230,7 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
         // locate on the GPU
         DeviceArray<double> d_pts, d_boxes, d_xi;
         DeviceArray<int32_t> d_boff, d_bcells, d_owner, d_flags;
-        d_pts.upload(ctx, pts);
+        d_pts.upload(ctx, pts.get(), (size_t)(np * dim));
         d_boxes.upload(ctx, boxes);
         d_boff.upload(ctx, boff);
         d_bcells.upload(ctx, bcells);
@@ -227,39 +254,71 @@ Transfer* transfer_create(Ctx* ctx, Level* fine, Level* coarse, const nnmg_trans
             fail(NNMG_ERR_POINT_NOT_FOUND, std::to_string(projected) + " fine points lie outside the coarse mesh");
         T->n_projected = projected;
 
-        // group by owner (stable counting sort)
+        // group by owner: a stable counting sort, split into contiguous ranges of
+        // points, one per thread; range t places its points of cell c after those
+        // of cell c in the ranges before it, so the result is that of one pass
         std::vector<int32_t> off((size_t)(C + 1), 0);
-        for (int64_t i = 0; i < np; ++i) off[(size_t)T->h_point_owner[(size_t)i] + 1]++;
-        for (int64_t c = 0; c < C; ++c) off[(size_t)(c + 1)] += off[(size_t)c];
-        std::vector<int32_t> fidx((size_t)np), sowner((size_t)np);
-        std::vector<double> xi64((size_t)(np * dim));
-        std::vector<float> xi32((size_t)(np * dim));
+        std::unique_ptr<int32_t[]> fidx = host_buffer<int32_t>((size_t)np);
+        std::unique_ptr<double[]> xi64 = host_buffer<double>((size_t)(np * dim));
+        std::unique_ptr<float[]> xi32 = host_buffer<float>((size_t)(np * dim));
         {
-            std::vector<int32_t> cur(off.begin(), off.end() - 1);
-            for (int64_t i = 0; i < np; ++i) {
-                const int32_t p = cur[(size_t)T->h_point_owner[(size_t)i]]++;
-                fidx[(size_t)p] = T->h_point_dof[(size_t)i];
-                sowner[(size_t)p] = T->h_point_owner[(size_t)i];
-                for (int a = 0; a < dim; ++a) {
-                    const double x = T->h_point_xi[(size_t)(i * dim + a)];
-                    xi64[(size_t)(a * np + p)] = x;
-                    xi32[(size_t)(a * np + p)] = (float)x;
+            const int64_t per = 1 << 20;
+            const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(sort_threads(), (np + per - 1) / per));
+            const int32_t* own = T->h_point_owner.data();
+            auto range = [&](int t, int64_t& i0, int64_t& i1) {
+                i0 = np * t / nt;
+                i1 = np * (t + 1) / nt;
+            };
+            std::vector<std::vector<int32_t>> cur((size_t)nt, std::vector<int32_t>((size_t)C, 0));
+            run_threads(nt, [&](int t) {
+                int64_t i0, i1;
+                range(t, i0, i1);
+                int32_t* cnt = cur[(size_t)t].data();
+                for (int64_t i = i0; i < i1; ++i) cnt[own[i]]++;
+            });
+            // cur[t][c] becomes the first position of range t's points of cell c
+            int32_t pos = 0;
+            for (int64_t c = 0; c < C; ++c) {
+                off[(size_t)c] = pos;
+                for (int t = 0; t < nt; ++t) {
+                    const int32_t k = cur[(size_t)t][(size_t)c];
+                    cur[(size_t)t][(size_t)c] = pos;
+                    pos += k;
                 }
             }
+            off[(size_t)C] = pos;
+            run_threads(nt, [&](int t) {
+                int64_t i0, i1;
+                range(t, i0, i1);
+                int32_t* next = cur[(size_t)t].data();
+                for (int64_t i = i0; i < i1; ++i) {
+                    const int32_t p = next[own[i]]++;
+                    fidx[(size_t)p] = T->h_point_dof[(size_t)i];
+                    for (int a = 0; a < dim; ++a) {
+                        const double x = T->h_point_xi[(size_t)(i * dim + a)];
+                        xi64[(size_t)(a * np + p)] = x;
+                        xi32[(size_t)(a * np + p)] = (float)x;
+                    }
+                }
+            });
         }
+        // owner of sorted point p: the last cell whose run starts at or before p
+        auto owner_of = [&](int64_t p) {
+            return (int32_t)(std::upper_bound(off.begin(), off.begin() + C, (int32_t)p) - off.begin() - 1);
+        };
         // owner cells of the first and last point of every block of kPointBlock points
         const int64_t nblk = (np + kPointBlock - 1) / kPointBlock;
         std::vector<int32_t> bc((size_t)(2 * nblk));
         for (int64_t b = 0; b < nblk; ++b) {
-            bc[(size_t)(2 * b)] = sowner[(size_t)(b * kPointBlock)];
-            bc[(size_t)(2 * b + 1)] = sowner[(size_t)std::min<int64_t>(np, (b + 1) * kPointBlock) - 1];
+            bc[(size_t)(2 * b)] = owner_of(b * kPointBlock);
+            bc[(size_t)(2 * b + 1)] = owner_of(std::min<int64_t>(np, (b + 1) * kPointBlock) - 1);
         }
         T->d_blk_cells.upload(ctx, bc);
         build_restriction_slots(T, ctx);
         T->d_off.upload(ctx, off);
-        T->d_fine.upload(ctx, fidx);
-        T->d_xi64.upload(ctx, xi64);
-        T->d_xi32.upload(ctx, xi32);
+        T->d_fine.upload(ctx, fidx.get(), (size_t)np);
+        T->d_xi64.upload(ctx, xi64.get(), (size_t)(np * dim));
+        T->d_xi32.upload(ctx, xi32.get(), (size_t)(np * dim));
         // lanes per coarse cell and component of the restriction: about
         // avg / NNMG_RESTRICT_PTS_PER_LANE, 4..64 (the kernel multiplies by the
         // lanes that share a point)
