@@ -240,17 +240,18 @@ static void coarse_solve(Hierarchy& H, int prec, const void* f, void* x, int nr,
 // ---------------------------------------------------------------------------
 // smoother and V-cycle
 // ---------------------------------------------------------------------------
-// x <- x + d with d <- c1 d + c2 D^{-1} (f - A x)   (c1 unused when first)
+// x <- x + d with d <- c1 d + c2 D^{-1} (f - A x); mode (kCheb*): the old d
+// is 0 (c1 unused) or x, and the new d is dropped after the last step
 static void op_cheb_step(Hierarchy& H, int l, int prec, const void* f, const void* dinv, void* x, double c1,
-                         double c2, bool first, int nr, hipStream_t s) {
+                         double c2, int mode, int nr, hipStream_t s) {
     Level& L = *H.levels[l];
     WorkVectors& w = H.work[prec][l];
     if (L.var[prec].atomic) {
         launch_vmult_cells(L, prec, x, w.ax.ptr, s, nr, w.contrib.ptr);
-        launch_cheb_step(prec, (size_t)L.n_dofs, f, w.ax.ptr, dinv, x, w.d.ptr, first ? 0.0 : c1, c2, s, nr);
+        launch_cheb_step(prec, (size_t)L.n_dofs, f, w.ax.ptr, dinv, x, w.d.ptr, c1, c2, mode, s, nr);
     } else {
         launch_vmult_contrib(L, prec, x, w.contrib.ptr, s, nr);
-        launch_cheb_step_gather(L, prec, w.contrib.ptr, f, dinv, x, w.d.ptr, c1, c2, first, s, nr);
+        launch_cheb_step_gather(L, prec, w.contrib.ptr, f, dinv, x, w.d.ptr, c1, c2, mode, s, nr);
     }
 }
 
@@ -269,28 +270,30 @@ static void op_residual(Hierarchy& H, int l, int prec, const void* f, const void
 
 // cast_from (float32 cycle, zero start): the right-hand side arrives in
 // float64 and the first step also writes its float32 copy into f
-// first_done (zero start): the first step, x = d = D^-1 f / theta, was fused
-// into the restriction that formed f
+// first_done (zero start): the first step, x = D^-1 f / theta, was fused
+// into the restriction that formed f.  A first step from zero leaves d = x and
+// stores only x; the second step reads x as d.  The last step does not store d.
 static void chebyshev(Hierarchy& H, int l, int prec, const void* f, void* x, bool zero_start, int nr,
                       hipStream_t s, const double* cast_from = nullptr, bool first_done = false) {
     Level& L = *H.levels[l];
-    WorkVectors& w = H.work[prec][l];
     const void* dinv = prec == NNMG_FP64 ? (const void*)L.d_dinv64.ptr : (const void*)L.d_dinv32.ptr;
     const double lo = H.lo[l], hi = H.hi[l];
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
+    const int deg = H.opts.cheb_degree;
     if (zero_start && first_done) {
-        // x and d hold the first step already
+        // x holds the first step already
     } else if (zero_start && cast_from)
         launch_cast_cheb_first_zero((size_t)L.n_dofs, cast_from, (float*)const_cast<void*>(f), (const float*)dinv,
-                                    (float*)x, (float*)w.d.ptr, 1.0 / theta, s, nr);
+                                    (float*)x, 1.0 / theta, s, nr);
     else if (zero_start)
-        launch_cheb_first_zero(prec, (size_t)L.n_dofs, f, dinv, x, w.d.ptr, 1.0 / theta, s, nr);
+        launch_cheb_first_zero(prec, (size_t)L.n_dofs, f, dinv, x, 1.0 / theta, s, nr);
     else
-        op_cheb_step(H, l, prec, f, dinv, x, 0.0, 1.0 / theta, true, nr, s);
-    for (int j = 1; j < H.opts.cheb_degree; ++j) {
+        op_cheb_step(H, l, prec, f, dinv, x, 0.0, 1.0 / theta, kChebFirst | (deg == 1 ? kChebLast : 0), nr, s);
+    for (int j = 1; j < deg; ++j) {
         const double rho_new = 1.0 / (2.0 * sigma - rho);
-        op_cheb_step(H, l, prec, f, dinv, x, rho_new * rho, 2.0 * rho_new / delta, false, nr, s);
+        const int mode = (j == 1 && zero_start ? kChebDIsX : 0) | (j == deg - 1 ? kChebLast : 0);
+        op_cheb_step(H, l, prec, f, dinv, x, rho_new * rho, 2.0 * rho_new / delta, mode, nr, s);
         rho = rho_new;
     }
 }
@@ -328,7 +331,7 @@ static void vcycle_level(Hierarchy& H, int l, int prec, const void* f, void* x, 
             const Level& C = *H.levels[l - 1];
             const void* dinv = prec == NNMG_FP64 ? (const void*)C.d_dinv64.ptr : (const void*)C.d_dinv32.ptr;
             const double theta = 0.5 * (H.hi[l - 1] + H.lo[l - 1]);
-            launch_restrict_first_zero(T, prec, w.r.ptr, wc.f.ptr, dinv, wc.x.ptr, wc.d.ptr, 1.0 / theta, s, nr,
+            launch_restrict_first_zero(T, prec, w.r.ptr, wc.f.ptr, dinv, wc.x.ptr, 1.0 / theta, s, nr,
                                        wc.rbuf.ptr);
         } else {
             launch_restrict(T, prec, w.r.ptr, wc.f.ptr, false, s, nr, wc.rbuf.ptr);

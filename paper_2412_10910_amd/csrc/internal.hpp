@@ -265,8 +265,13 @@ void launch_vmult_contrib(const Level& L, int prec, const void* src, void* contr
 // (nr interleaved right-hand sides; the vectors hold n_dofs * nr values)
 void launch_gather(const Level& L, int prec, const void* contrib, void* dst, bool accumulate, hipStream_t s,
                    int nr = 1);
+// Chebyshev step modes (kernels/gather.hip, kernels/vector.hip): what the
+// previous direction d is, and whether the new one is stored
+constexpr int kChebFirst = 1;  // d = 0: the first step from a given x
+constexpr int kChebDIsX = 2;   // d = x: the step after a first step from zero, which sets d = x
+constexpr int kChebLast = 4;   // the new d is not stored: no later step reads it
 void launch_cheb_step_gather(const Level& L, int prec, const void* contrib, const void* f, const void* dinv,
-                             void* x, void* d, double c1, double c2, bool first, hipStream_t s, int nr = 1);
+                             void* x, void* d, double c1, double c2, int mode, hipStream_t s, int nr = 1);
 void launch_residual_gather(const Level& L, int prec, const void* contrib, const void* f, void* r, hipStream_t s,
                             int nr = 1);
 // out[r * kScal] = p_r . q_r; scalar_op >= 0 also forms the CG scalar that
@@ -301,9 +306,9 @@ void launch_prolongate(const Transfer& t, int prec, const void* coarse, void* fi
 void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse, bool accumulate, hipStream_t s,
                      int nr = 1, void* rbuf = nullptr);
 // coarse = P^T fine, fused with the coarse level's first smoothing step from
-// zero: x = d = dinv * coarse * c0 (launch_cheb_first_zero), for all entries
+// zero: x = dinv * coarse * c0 (launch_cheb_first_zero), for all entries
 void launch_restrict_first_zero(const Transfer& t, int prec, const void* fine, void* coarse, const void* dinv,
-                                void* x, void* d, double c0, hipStream_t s, int nr = 1, void* rbuf = nullptr);
+                                void* x, double c0, hipStream_t s, int nr = 1, void* rbuf = nullptr);
 size_t restriction_scratch_bytes(const Transfer& t, int nr);
 // nested polynomial transfer (kernels/pmg.hip): fine += P coarse, and the restriction's per-cell sums
 void launch_pmg_prolongate(const Transfer& t, int prec, const void* coarse, void* fine, int nr, hipStream_t s);
@@ -313,23 +318,24 @@ void launch_pmg_restrict_sums(const Transfer& t, int prec, const void* fine, voi
 // component c of slot k at k * ncomp + c
 void launch_gather_runs(size_t n, int ncomp, const int32_t* off, int prec, const void* elem, size_t plane,
                         void* dst, bool accumulate, hipStream_t s, int nr = 1);
-// launch_gather_runs into f (not accumulating), then x = d = dinv * f * c0 for every value
+// launch_gather_runs into f (not accumulating), then x = dinv * f * c0 for every value
 void launch_gather_runs_first_zero(size_t n, int ncomp, const int32_t* off, int prec, const void* elem,
-                                   size_t plane, void* f, const void* dinv, void* x, void* d, double c0,
-                                   hipStream_t s, int nr = 1);
+                                   size_t plane, void* f, const void* dinv, void* x, double c0, hipStream_t s,
+                                   int nr = 1);
 // entries of one right-hand side's plane of a level's contribution buffer
 size_t contrib_plane(const Level& L);
 
 // vector kernels for the smoother and CG
-// x = d = dinv * f * c0   (first step from a zero guess)
-void launch_cheb_first_zero(int prec, size_t n, const void* f, const void* dinv, void* x, void* d,
-                            double c0, hipStream_t s, int nr = 1);
+// x = dinv * f * c0   (first step from a zero guess; its direction d equals
+// x, which the next step reads in its place: kChebDIsX)
+void launch_cheb_first_zero(int prec, size_t n, const void* f, const void* dinv, void* x, double c0,
+                            hipStream_t s, int nr = 1);
 // f32 = (float) f64, then launch_cheb_first_zero on f32 (float32 vectors)
-void launch_cast_cheb_first_zero(size_t n, const double* f64, float* f32, const float* dinv, float* x, float* d,
-                                 double c0, hipStream_t s, int nr = 1);
-// r = f - ax; ax = 0; d = c1 d + c2 dinv r (c1 = 0 for a first step); x += d
+void launch_cast_cheb_first_zero(size_t n, const double* f64, float* f32, const float* dinv, float* x, double c0,
+                                 hipStream_t s, int nr = 1);
+// r = f - ax; ax = 0; d = c1 d + c2 dinv r (mode: kCheb* above); x += d
 void launch_cheb_step(int prec, size_t n, const void* f, void* ax, const void* dinv, void* x, void* d,
-                      double c1, double c2, hipStream_t s, int nr = 1);
+                      double c1, double c2, int mode, hipStream_t s, int nr = 1);
 // r = f - ax; ax = 0
 void launch_residual(int prec, size_t n, const void* f, void* ax, void* r, hipStream_t s);
 // y += x

@@ -103,11 +103,12 @@ __global__ void gather_kernel(size_t n, const int32_t* __restrict__ off, const T
 // The restriction's sums into the right-hand side f of a level whose
 // smoothing starts from zero right after, fused with that first step: f =
 // the gathered sums (values without contributions, the constrained ones, keep
-// theirs) and x = d = D^-1 f c0, computed as the separate step computes it.
+// theirs) and x = D^-1 f c0, computed as the separate step computes it (the
+// step's direction d equals x, which the next step reads in its place).
 template <int NC, int NR, class T>
 __global__ void gather_first_zero_kernel(size_t n, const int32_t* __restrict__ off, const T* __restrict__ elem,
                                          size_t plane, T* __restrict__ f, const T* __restrict__ dinv,
-                                         T* __restrict__ x, T* __restrict__ d, T c0) {
+                                         T* __restrict__ x, T c0) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const T di = dinv[NR == 1 ? i : i / NR];
         T fi;
@@ -117,25 +118,22 @@ __global__ void gather_first_zero_kernel(size_t n, const int32_t* __restrict__ o
         } else {
             fi = f[i];
         }
-        const T v = di * fi * c0;
-        d[i] = v;
-        x[i] = v;
+        x[i] = di * fi * c0;
     }
 }
 
 void launch_gather_runs_first_zero(size_t n, int ncomp, const int32_t* off, int prec, const void* elem,
-                                   size_t plane, void* f, const void* dinv, void* x, void* d, double c0,
-                                   hipStream_t s, int nr) {
+                                   size_t plane, void* f, const void* dinv, void* x, double c0, hipStream_t s,
+                                   int nr) {
     if (n == 0) return;
     const size_t nv = n * (size_t)nr;
     NNMG_NV_DISPATCH(ncomp, nr, {
         if (prec == NNMG_FP64)
             hipLaunchKernelGGL((gather_first_zero_kernel<NC, NR, double>), grid_n(nv), dim3(256), 0, s, nv, off,
-                               (const double*)elem, plane, (double*)f, (const double*)dinv, (double*)x,
-                               (double*)d, c0);
+                               (const double*)elem, plane, (double*)f, (const double*)dinv, (double*)x, c0);
         else
             hipLaunchKernelGGL((gather_first_zero_kernel<NC, NR, float>), grid_n(nv), dim3(256), 0, s, nv, off,
-                               (const float*)elem, plane, (float*)f, (const float*)dinv, (float*)x, (float*)d,
+                               (const float*)elem, plane, (float*)f, (const float*)dinv, (float*)x,
                                (float)c0);
     });
     NNMG_HIP(hipGetLastError());
@@ -164,39 +162,41 @@ void launch_gather(const Level& L, int prec, const void* elem, void* dst, bool a
 }
 
 // r = f - A x;  d = c1 d + c2 dinv r;  x += d      (Chebyshev step, Saad Alg. 12.1)
-// dinv is per vector DoF, shared by the NR right-hand sides
+// dinv is per vector DoF, shared by the NR right-hand sides.  mode: the
+// previous d is 0 (kChebFirst) or x (kChebDIsX) instead of being read, and
+// the new d is not stored after the last step (kChebLast)
 template <int NC, int NR, class T>
 __global__ void cheb_step_gather_kernel(size_t n, const int32_t* __restrict__ off,
                                         const T* __restrict__ elem, size_t plane, const T* __restrict__ f,
                                         const T* __restrict__ dinv, T* __restrict__ x, T* __restrict__ d, T c1,
-                                        T c2, int first) {
+                                        T c2, int mode) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         // the DoF's own operands are loaded first, so that they arrive with
         // the slots instead of one after another behind them
         const T fi = f[i];
         const T di = dinv[NR == 1 ? i : i / NR];
         const T xi = x[i];
-        const T dp = first ? T(0) : d[i];
+        const T dp = (mode & kChebFirst) ? T(0) : ((mode & kChebDIsX) ? xi : d[i]);
         const T r = fi - gather_sum<NC, NR>(off, elem, plane, i);
-        const T dn = first ? c2 * (di * r) : c1 * dp + c2 * (di * r);
-        d[i] = dn;
+        const T dn = (mode & kChebFirst) ? c2 * (di * r) : c1 * dp + c2 * (di * r);
+        if (!(mode & kChebLast)) d[i] = dn;
         x[i] = xi + dn;
     }
 }
 
 void launch_cheb_step_gather(const Level& L, int prec, const void* elem, const void* f, const void* dinv, void* x,
-                             void* d, double c1, double c2, bool first, hipStream_t s, int nr) {
+                             void* d, double c1, double c2, int mode, hipStream_t s, int nr) {
     const size_t n = (size_t)L.n_dofs * (size_t)nr;
     if (n == 0) return;
     NNMG_NV_DISPATCH(L.ncomp, nr, {
         if (prec == NNMG_FP64)
             hipLaunchKernelGGL((cheb_step_gather_kernel<NC, NR, double>), grid_n(n), dim3(256), 0, s, n,
                                L.inv_off(prec), (const double*)elem, contrib_plane(L), (const double*)f,
-                               (const double*)dinv, (double*)x, (double*)d, c1, c2, (int)first);
+                               (const double*)dinv, (double*)x, (double*)d, c1, c2, mode);
         else
             hipLaunchKernelGGL((cheb_step_gather_kernel<NC, NR, float>), grid_n(n), dim3(256), 0, s, n,
                                L.inv_off(prec), (const float*)elem, contrib_plane(L), (const float*)f,
-                               (const float*)dinv, (float*)x, (float*)d, (float)c1, (float)c2, (int)first);
+                               (const float*)dinv, (float*)x, (float*)d, (float)c1, (float)c2, mode);
     });
     NNMG_HIP(hipGetLastError());
 }

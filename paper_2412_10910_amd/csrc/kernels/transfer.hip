@@ -843,10 +843,10 @@ void launch_restrict(const Transfer& t, int prec, const void* fine, void* coarse
 }
 
 void launch_restrict_first_zero(const Transfer& t, int prec, const void* fine, void* coarse, const void* dinv,
-                                void* x, void* d, double c0, hipStream_t s, int nr, void* rbuf) {
+                                void* x, double c0, hipStream_t s, int nr, void* rbuf) {
     rbuf = restrict_sums(t, prec, fine, coarse, s, nr, rbuf);
     launch_gather_runs_first_zero((size_t)t.coarse->n_dofs, t.coarse->ncomp, t.d_roff.ptr, prec, rbuf,
-                                  t.n_rslots * (size_t)t.coarse->ncomp, coarse, dinv, x, d, c0, s, nr);
+                                  t.n_rslots * (size_t)t.coarse->ncomp, coarse, dinv, x, c0, s, nr);
 }
 
 size_t restriction_scratch_bytes(const Transfer& t, int nr) {

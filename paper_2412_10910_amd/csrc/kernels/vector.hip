@@ -110,78 +110,76 @@ void launch_set_constrained(const int32_t* idx, size_t n, double v, void* dst, i
 // n values; dinv is per vector DoF, shared by the NR interleaved right-hand sides
 template <int NR, class T>
 __global__ void cheb_first_zero_kernel(size_t n, const T* __restrict__ f, const T* __restrict__ dinv,
-                                       T* __restrict__ x, T* __restrict__ d, T c0) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const T v = dinv[NR == 1 ? i : i / NR] * f[i] * c0;
-        d[i] = v;
-        x[i] = v;
-    }
+                                       T* __restrict__ x, T c0) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        x[i] = dinv[NR == 1 ? i : i / NR] * f[i] * c0;
 }
 
 // the same first step on a float32 cycle whose right-hand side arrives in
 // float64: f32 = (float) f64 is stored for the later steps and used at once
 template <int NR>
 __global__ void cast_cheb_first_zero_kernel(size_t n, const double* __restrict__ f64, float* __restrict__ f32,
-                                            const float* __restrict__ dinv, float* __restrict__ x,
-                                            float* __restrict__ d, float c0) {
+                                            const float* __restrict__ dinv, float* __restrict__ x, float c0) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const float f = (float)f64[i];
         f32[i] = f;
-        const float v = dinv[NR == 1 ? i : i / NR] * f * c0;
-        d[i] = v;
-        x[i] = v;
+        x[i] = dinv[NR == 1 ? i : i / NR] * f * c0;
     }
 }
 
-void launch_cast_cheb_first_zero(size_t n, const double* f64, float* f32, const float* dinv, float* x, float* d,
-                                 double c0, hipStream_t s, int nr) {
+void launch_cast_cheb_first_zero(size_t n, const double* f64, float* f32, const float* dinv, float* x, double c0,
+                                 hipStream_t s, int nr) {
     if (n == 0) return;
     const size_t nv = n * (size_t)nr;
     NNMG_NR_DISPATCH(nr, {
         hipLaunchKernelGGL((cast_cheb_first_zero_kernel<NR>), grid_for(nv), dim3(256), 0, s, nv, f64, f32, dinv, x,
-                           d, (float)c0);
+                           (float)c0);
     });
     NNMG_HIP(hipGetLastError());
 }
 
-void launch_cheb_first_zero(int prec, size_t n, const void* f, const void* dinv, void* x, void* d, double c0,
+void launch_cheb_first_zero(int prec, size_t n, const void* f, const void* dinv, void* x, double c0,
                             hipStream_t s, int nr) {
     if (n == 0) return;
     const size_t nv = n * (size_t)nr;
     NNMG_NR_DISPATCH(nr, {
         if (prec == NNMG_FP64)
             hipLaunchKernelGGL((cheb_first_zero_kernel<NR, double>), grid_for(nv), dim3(256), 0, s, nv,
-                               (const double*)f, (const double*)dinv, (double*)x, (double*)d, c0);
+                               (const double*)f, (const double*)dinv, (double*)x, c0);
         else
             hipLaunchKernelGGL((cheb_first_zero_kernel<NR, float>), grid_for(nv), dim3(256), 0, s, nv,
-                               (const float*)f, (const float*)dinv, (float*)x, (float*)d, (float)c0);
+                               (const float*)f, (const float*)dinv, (float*)x, (float)c0);
     });
     NNMG_HIP(hipGetLastError());
 }
 
+// mode: kChebFirst, kChebDIsX, kChebLast (the same step as the gathering one)
 template <int NR, class T>
 __global__ void cheb_step_kernel(size_t n, const T* __restrict__ f, T* __restrict__ ax, const T* __restrict__ dinv,
-                                 T* __restrict__ x, T* __restrict__ d, T c1, T c2) {
+                                 T* __restrict__ x, T* __restrict__ d, T c1, T c2, int mode) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const T r = f[i] - ax[i];
         ax[i] = T(0);
-        const T dn = c1 * d[i] + c2 * (dinv[NR == 1 ? i : i / NR] * r);
-        d[i] = dn;
-        x[i] += dn;
+        const T xi = x[i];
+        const T dp = (mode & kChebFirst) ? T(0) : ((mode & kChebDIsX) ? xi : d[i]);
+        const T dr = c2 * (dinv[NR == 1 ? i : i / NR] * r);
+        const T dn = (mode & kChebFirst) ? dr : c1 * dp + dr;
+        if (!(mode & kChebLast)) d[i] = dn;
+        x[i] = xi + dn;
     }
 }
 
 void launch_cheb_step(int prec, size_t n, const void* f, void* ax, const void* dinv, void* x, void* d, double c1,
-                      double c2, hipStream_t s, int nr) {
+                      double c2, int mode, hipStream_t s, int nr) {
     if (n == 0) return;
     const size_t nv = n * (size_t)nr;
     NNMG_NR_DISPATCH(nr, {
         if (prec == NNMG_FP64)
             hipLaunchKernelGGL((cheb_step_kernel<NR, double>), grid_for(nv), dim3(256), 0, s, nv, (const double*)f,
-                               (double*)ax, (const double*)dinv, (double*)x, (double*)d, c1, c2);
+                               (double*)ax, (const double*)dinv, (double*)x, (double*)d, c1, c2, mode);
         else
             hipLaunchKernelGGL((cheb_step_kernel<NR, float>), grid_for(nv), dim3(256), 0, s, nv, (const float*)f,
-                               (float*)ax, (const float*)dinv, (float*)x, (float*)d, (float)c1, (float)c2);
+                               (float*)ax, (const float*)dinv, (float*)x, (float*)d, (float)c1, (float)c2, mode);
     });
     NNMG_HIP(hipGetLastError());
 }
