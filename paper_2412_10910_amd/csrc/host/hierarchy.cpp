@@ -559,7 +559,7 @@ struct PcgTask {
 
     // z = V(r) on the hierarchy's own vectors, so the launches can be captured
     // once.  A float32 cycle reads r through its first smoothing step and
-    // leaves its result in float32: z is formed by precondition_dot.
+    // leaves its result in float32, which r.z and the direction update read.
     void launches(hipStream_t st) {
         WorkVectors& w32 = H.work[NNMG_FP32][top()];
         if (prec == NNMG_FP64)
@@ -568,8 +568,10 @@ struct PcgTask {
             vcycle_level(H, top(), NNMG_FP32, w32.f.ptr, w32.x.ptr, nr, st, H.r.ptr);
     }
 
-    // z = V(r), then r.z into out (and the CG scalar op on it, op >= 0)
-    void precondition_dot(double* out, int op) {
+    // z = V(r), then r.z into out (and the CG scalar op on it, op >= 0).  The
+    // float32 cycle leaves z in float32; its float64 value goes to z64 if that
+    // is given (the first direction), else the direction update widens it.
+    void precondition_dot(double* out, int op, double* z64 = nullptr) {
         if (graph)
             NNMG_HIP(hipGraphLaunch(H.precond_graph[prec][nr], s));
         else
@@ -578,9 +580,10 @@ struct PcgTask {
         if (prec == NNMG_FP64)
             launch_dot(H.r.ptr, H.z.ptr, n, H.partial.ptr, out, s, nr, kScal, sc, op);
         else
-            launch_cast_dot(H.r.ptr, (const float*)H.work[NNMG_FP32][top()].x.ptr, H.z.ptr, n, H.partial.ptr, out,
-                            s, nr, kScal, sc, op);
+            launch_cast_dot(H.r.ptr, z32(), z64, n, H.partial.ptr, out, s, nr, kScal, sc, op);
     }
+
+    const float* z32() { return (const float*)H.work[NNMG_FP32][top()].x.ptr; }
 
     // scalars to the host, then the event step() waits for
     void fetch_async() {
@@ -691,8 +694,13 @@ struct PcgTask {
             }
             if (n_active == 0 || o.max_it == 0) return done = true;
             push_flags();
-            precondition_dot(sc + 0, -1);
-            NNMG_HIP(hipMemcpyAsync(H.p.ptr, H.z.ptr, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+            // the first direction is z
+            if (prec == NNMG_FP64) {
+                precondition_dot(sc + 0, -1);
+                NNMG_HIP(hipMemcpyAsync(H.p.ptr, H.z.ptr, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+            } else {
+                precondition_dot(sc + 0, -1, H.p.ptr);
+            }
             it = 1;
             iteration_body();
             return false;
@@ -725,7 +733,10 @@ struct PcgTask {
         if (n_active == 0 || it == o.max_it) return done = true;
         if (changed) push_flags();
         precondition_dot(sc + 4, 1);  // and beta
-        launch_cg_direction(n, H.z.ptr, H.p.ptr, sc, s, nr);
+        if (prec == NNMG_FP64)
+            launch_cg_direction(n, H.z.ptr, H.p.ptr, sc, s, nr);
+        else
+            launch_cg_direction32(n, z32(), H.p.ptr, sc, s, nr);
         ++it;
         iteration_body();
         return false;

@@ -344,7 +344,7 @@ void launch_splitmix_vector(double* v, const uint8_t* mask_free, size_t n, uint6
 // float64 reductions: out = sum_i a_i b_i (two-stage, deterministic)
 void launch_dot(const double* a, const double* b, size_t n, double* partial, double* out, hipStream_t s,
                 int nr = 1, size_t ostride = 1, double* scal = nullptr, int scalar_op = -1);
-// z = (double) z32, then out = r . z as launch_dot(r, z, ...) computes it
+// z = (double) z32 (z may be nullptr: not stored), then out = r . z as launch_dot(r, z, ...) computes it
 void launch_cast_dot(const double* r, const float* z32, double* z, size_t n, double* partial, double* out,
                      hipStream_t s, int nr = 1, size_t ostride = 1, double* scal = nullptr, int scalar_op = -1);
 size_t dot_partials(size_t n);
@@ -353,6 +353,8 @@ size_t dot_partials(size_t n);
 void launch_cg_update(size_t n, double* x, double* r, const double* p, const double* q, const double* scal,
                       double* partial, double* rr_out, hipStream_t s, int nr = 1);
 void launch_cg_direction(size_t n, const double* z, double* p, const double* scal, hipStream_t s, int nr = 1);
+// the same with z = (double) z32
+void launch_cg_direction32(size_t n, const float* z32, double* p, const double* scal, hipStream_t s, int nr = 1);
 void launch_jacobi(size_t n, const double* dinv, const double* r, double* z, hipStream_t s);
 void launch_axpy(size_t n, double a_sign, const double* scal_a, int idx, const double* x, double* y,
                  hipStream_t s);

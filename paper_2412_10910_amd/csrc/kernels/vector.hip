@@ -343,7 +343,7 @@ __global__ __launch_bounds__(kRedThreads) void cast_dot_stage1(const double* __r
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const double zv = (double)z32[i * NR + k];
-            z[i * NR + k] = zv;
+            if (z) z[i * NR + k] = zv;
             s[k] += r[i * NR + k] * zv;
         }
     }
@@ -411,22 +411,31 @@ void launch_cg_update(size_t n, double* x, double* r, const double* p, const dou
     launch_sum_partials(partial, g, rr_out, s, nr, kScal);
 }
 
-template <int NR>
-__global__ void cg_direction_kernel(size_t n, const double* __restrict__ z, double* __restrict__ p,
+// p = z + beta p; a float32 z (the float32 V-cycle's result) is widened exactly here
+template <int NR, class Z>
+__global__ void cg_direction_kernel(size_t n, const Z* __restrict__ z, double* __restrict__ p,
                                     const double* __restrict__ scal) {
     double beta[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) beta[k] = scal[k * kScal + 5];
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) p[i * NR + k] = z[i * NR + k] + beta[k] * p[i * NR + k];
+        for (int k = 0; k < NR; ++k) p[i * NR + k] = (double)z[i * NR + k] + beta[k] * p[i * NR + k];
     }
 }
 
 void launch_cg_direction(size_t n, const double* z, double* p, const double* scal, hipStream_t s, int nr) {
     if (n == 0) return;
     NNMG_NR_DISPATCH(nr, {
-        hipLaunchKernelGGL((cg_direction_kernel<NR>), grid_for(n), dim3(256), 0, s, n, z, p, scal);
+        hipLaunchKernelGGL((cg_direction_kernel<NR, double>), grid_for(n), dim3(256), 0, s, n, z, p, scal);
+    });
+    NNMG_HIP(hipGetLastError());
+}
+
+void launch_cg_direction32(size_t n, const float* z32, double* p, const double* scal, hipStream_t s, int nr) {
+    if (n == 0) return;
+    NNMG_NR_DISPATCH(nr, {
+        hipLaunchKernelGGL((cg_direction_kernel<NR, float>), grid_for(n), dim3(256), 0, s, n, z32, p, scal);
     });
     NNMG_HIP(hipGetLastError());
 }
