@@ -270,7 +270,8 @@ int nnmg_level_diagonal(const nnmg_level* level, nnmg_prec prec, void* diag_dev,
  * grid over the grown coarse-cell boxes, Newton inversion of the trilinear
  * cell map, owner = lowest-numbered cell containing the point, otherwise
  * projection onto the nearest reference cell (eq. closest_point); stores the
- * points grouped by owner cell with their clamped reference coordinates.
+ * points grouped by owner cell with their clamped reference coordinates
+ * (the grouping runs on up to eight host threads for more than 2^20 points).
  * opts may be NULL (defaults).  Synchronous (timed setup).
  * Errors: INVALID_ARG (dim/device mismatch), POINT_NOT_FOUND, OOM, HIP. */
 int nnmg_transfer_create(nnmg_ctx* ctx, const nnmg_level* fine, const nnmg_level* coarse,
