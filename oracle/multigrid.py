@@ -136,8 +136,9 @@ class Hierarchy:
     """Levels coarse -> fine: operators A_l, free masks, P_l (level l-1 -> l)."""
 
     def __init__(self, operators, frees, prolongations, eig_start=None, bounds=None,
-                 dtype=np.float64):
+                 dtype=np.float64, cheb_degree=CHEB_DEGREE):
         self.L = len(operators)
+        self.cheb_degree = cheb_degree  # smoothing steps (operator applications) per smoother call
         assert len(prolongations) == self.L - 1
         self.dtype = dtype
         self.A64 = operators
@@ -169,12 +170,12 @@ class Hierarchy:
             return self.coarse.solve(f).astype(self.dtype)
         A, dinv = self.A[l], self.dinv[l]
         lo, hi = self.bounds[l]
-        x = chebyshev(A, dinv, f, None, lo, hi, dtype=self.dtype)
+        x = chebyshev(A, dinv, f, None, lo, hi, degree=self.cheb_degree, dtype=self.dtype)
         r = f - A @ x
         rc = self.R[l - 1] @ r
         dc = self.vcycle(rc, l - 1)
         x = x + self.P[l - 1] @ dc
-        x = chebyshev(A, dinv, f, x, lo, hi, dtype=self.dtype)
+        x = chebyshev(A, dinv, f, x, lo, hi, degree=self.cheb_degree, dtype=self.dtype)
         return x
 
     def pcg(self, b, rtol=1e-8, max_it=200, precondition=True):

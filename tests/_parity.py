@@ -83,10 +83,10 @@ def oracle_prolongation(fine, coarse):
     return P
 
 
-def oracle_hierarchy(pairs, eig_start_orc, dtype=np.float64, bounds=None):
+def oracle_hierarchy(pairs, eig_start_orc, dtype=np.float64, bounds=None, cheb_degree=multigrid.CHEB_DEGREE):
     Ps = [oracle_prolongation(pairs[i + 1], pairs[i]) for i in range(len(pairs) - 1)]
     return multigrid.Hierarchy([p.A for p in pairs], [p.free for p in pairs], Ps, eig_start=eig_start_orc,
-                               bounds=bounds, dtype=dtype)
+                               bounds=bounds, dtype=dtype, cheb_degree=cheb_degree)
 
 
 def eig_starts(pairs, seed=100):

@@ -82,6 +82,47 @@ def test_bounds_vcycle_pcg_parity(ctx, name, cfg, cells, k):
     assert err <= 1e-6, err
 
 
+SMOOTHERS = [(1, "slots"), (2, "slots"), (4, "slots"), (2, "atomic"), (3, "atomic")]
+
+
+@pytest.mark.parametrize("cheb,scatter", SMOOTHERS, ids=[f"degree{c}-{s}" for c, s in SMOOTHERS])
+def test_smoother_degree_and_scatter_against_the_oracle(ctx, cheb, scatter):
+    """Chebyshev smoothers of degree 1, 2 and 4 (the default is 3), and the
+    float-atomic operator with its separate smoothing step: the steps read a
+    zero or x in place of the previous direction and do not store the last
+    one, which must leave the oracle's V-cycle (1e-12) and float64-MG PCG
+    (same iterations, histories within 1e-12) unchanged; float32-MG converges
+    within one iteration of it."""
+    import paper_2412_10910_amd as nn
+    meshes = config_levels(1, cells=[3, 6, 13])
+    pairs = build_pairs(ctx, meshes, 2)
+    starts = eig_starts(pairs)
+    H_orc = oracle_hierarchy(pairs, starts, cheb_degree=cheb)
+    if scatter == "atomic":
+        for p in pairs:
+            p.lib.set_variant(1)  # trilinear geometry, float atomics, both precisions
+    transfers = [nn.Transfer(ctx, pairs[i + 1].lib, pairs[i].lib) for i in range(len(pairs) - 1)]
+    H_lib = nn.Hierarchy(ctx, [p.lib for p in pairs], transfers,
+                         eig_start=[p.to_lib(s) for p, s in zip(pairs, starts)], cheb_degree=cheb)
+    for l in range(1, len(pairs)):
+        H_lib.set_cheb_bounds(l, *H_orc.bounds[l])
+    fine = pairs[-1]
+    r = np.where(fine.orc.free, random_vector(fine.orc.n_dofs, 78), 0.0)
+    z = H_lib.vcycle(fine.to_lib(r))
+    assert rel_err(fine.to_orc(z), H_orc.vcycle(r)) <= 1e-12
+    b_orc = assemble.load_vector(fine.orc, config_source(1))
+    fq = torch.tensor(config_source(1)(fine.lib.quadrature_points()).reshape(-1), dtype=torch.float64, device=DEV)
+    b_lib = fine.lib.assemble_rhs(fq)
+    x_orc, it_orc, hist_orc = H_orc.pcg(b_orc, rtol=1e-8)
+    x_lib, info = H_lib.pcg_solve(b_lib, rtol=1e-8, vcycle_dtype=torch.float64)
+    assert info["iterations"] == it_orc
+    assert np.abs(info["history"] - np.array(hist_orc)).max() <= 1e-12
+    assert rel_err(fine.to_orc(x_lib), x_orc) <= 1e-10
+    x32, info32 = H_lib.pcg_solve(b_lib, rtol=1e-8, vcycle_dtype=torch.float32)
+    assert info32["relres"] <= 1e-8
+    assert abs(info32["iterations"] - it_orc) <= 1
+
+
 def test_zero_rhs_and_not_converged(ctx):
     import paper_2412_10910_amd as nn
     pairs, H_orc, H_lib, b_orc, b_lib = _setup(ctx, 0, [4, 9], 1)

@@ -48,6 +48,27 @@ def test_chebyshev_error_polynomial_closed_form(start):
     assert np.allclose(xs - x, factor * e0, atol=1e-14, rtol=1e-12)
 
 
+@pytest.mark.parametrize("degree", [1, 2, 4, 5])
+@pytest.mark.parametrize("start", ["zero", "nonzero"])
+def test_chebyshev_error_polynomial_any_degree(start, degree):
+    # after k steps the error is T_k((theta - lambda)/delta) / T_k(theta/delta)
+    # times the initial one, T_k from numpy's Chebyshev series
+    lam = np.array([0.05, 0.1, 0.3, 0.7, 1.0, 1.4, 1.9])
+    A = sp.diags(lam).tocsr()
+    rng = np.random.default_rng(degree)
+    xs = rng.normal(size=lam.size)
+    f = A @ xs
+    hi = 2.0
+    lo = hi / 20
+    x0 = None if start == "zero" else rng.normal(size=lam.size)
+    x = multigrid.chebyshev(A, np.ones(lam.size), f, x0, lo, hi, degree=degree)
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    Tk = np.polynomial.chebyshev.Chebyshev.basis(degree)
+    factor = Tk((theta - lam) / delta) / Tk(theta / delta)
+    e0 = xs - (0 if x0 is None else x0)
+    assert np.allclose(xs - x, factor * e0, atol=1e-14, rtol=1e-12)
+
+
 def test_lanczos_exact_on_few_eigenvalues():
     lam = np.array([1.0, 2.0, 2.0, 3.0, 3.0, 3.0, 5.0])
     A = sp.diags(lam).tocsr()
@@ -70,12 +91,12 @@ def test_lanczos_estimate_is_a_tight_lower_bound():
     assert est >= 0.9 * lam_max
 
 
-def _hierarchy(cfg, cells, degree, dtype=np.float64):
+def _hierarchy(cfg, cells, degree, dtype=np.float64, cheb_degree=multigrid.CHEB_DEGREE):
     sps = [space.Space(m, degree) for m in config_levels(cfg, cells=cells)]
     As = [assemble.stiffness(s) for s in sps]
     Ps = [transfer.prolongation(sps[i + 1], sps[i])[0] for i in range(len(sps) - 1)]
     starts = [random_vector(s.n_dofs, 17 + i) for i, s in enumerate(sps)]
-    H = multigrid.Hierarchy(As, [s.free for s in sps], Ps, eig_start=starts, dtype=dtype)
+    H = multigrid.Hierarchy(As, [s.free for s in sps], Ps, eig_start=starts, dtype=dtype, cheb_degree=cheb_degree)
     return sps, H
 
 
@@ -86,9 +107,12 @@ def test_coarse_solve_residual():
     assert np.linalg.norm(H.A64[0] @ x - r) <= 1e-14 * np.linalg.norm(r)
 
 
-@pytest.mark.parametrize("cfg,cells,k", [(0, [3, 7, 16], 1), (1, [2, 4, 7], 2)])
-def test_vcycle_linear_symmetric_positive(cfg, cells, k):
-    sps, H = _hierarchy(cfg, cells, k)
+@pytest.mark.parametrize("cfg,cells,k,cheb", [(0, [3, 7, 16], 1, 3), (1, [2, 4, 7], 2, 3), (1, [2, 4, 7], 2, 1),
+                                              (1, [2, 4, 7], 2, 2), (1, [2, 4, 7], 2, 4)])
+def test_vcycle_linear_symmetric_positive(cfg, cells, k, cheb):
+    # the same smoothing polynomial before and after the coarse correction makes
+    # the V-cycle symmetric for every smoother degree
+    sps, H = _hierarchy(cfg, cells, k, cheb_degree=cheb)
     free = sps[-1].free
     n = sps[-1].n_dofs
     r = np.where(free, random_vector(n, 1), 0.0)
