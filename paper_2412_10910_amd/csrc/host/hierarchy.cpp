@@ -521,7 +521,10 @@ void vcycle(Hierarchy& H, int prec, const void* r, void* z, int nr, hipStream_t 
 // Each right-hand side has its own scalars (scal + r * kScal) and its own
 // stopping test.  One that has converged (or broken down) is frozen: its
 // active flag is cleared, so alpha = beta = 0 from then on and its iterate and
-// residual stay exactly as they were, while the others go on.
+// residual stay exactly as they were, while the others go on.  An iteration
+// updates r at once and x with the next direction (both read the old p there),
+// the last x update being launched when the solve ends: the same operations
+// in another kernel, so the iterates are those of the textbook order.
 //
 // The solve is a resumable task: every stage ends with an asynchronous copy
 // of the scalars to pinned host memory and an event; step() runs when that
@@ -596,7 +599,7 @@ struct PcgTask {
         NNMG_HIP(hipMemcpyAsync(H.scal.ptr, H.hscal, nsc * sizeof(double), hipMemcpyHostToDevice, s));
     }
 
-    // operator product, alpha, update of x and r, and the fetch of the new scalars
+    // operator product, alpha, update of r, and the fetch of the new scalars
     void iteration_body() {
         double* sc = H.scal.ptr;
         Level& lv = L();
@@ -609,8 +612,9 @@ struct PcgTask {
             launch_vmult_contrib(lv, NNMG_FP64, H.p.ptr, cb, s, nr);
             launch_gather_dot(lv, cb, H.p.ptr, H.qv.ptr, H.partial.ptr, sc + 1, s, nr, sc, 0);
         }
-        // (alpha is formed by the reduction of p.q)
-        launch_cg_update(n, x, H.r.ptr, H.p.ptr, H.qv.ptr, sc, H.partial.ptr, sc + 3, s, nr);
+        // (alpha is formed by the reduction of p.q; x += alpha p follows with
+        // the next direction, or at the end of the solve)
+        launch_cg_update(n, H.r.ptr, H.qv.ptr, sc, H.partial.ptr, sc + 3, s, nr);
         fetch_async();
     }
 
@@ -730,13 +734,18 @@ struct PcgTask {
                 changed = true;
             }
         }
-        if (n_active == 0 || it == o.max_it) return done = true;
+        if (n_active == 0 || it == o.max_it) {
+            // the last iteration's x += alpha p (alpha as the iteration formed
+            // it: the scalars on the device are unchanged since)
+            launch_cg_direction(n, nullptr, H.p.ptr, x, sc, s, nr);
+            return done = true;
+        }
         if (changed) push_flags();
         precondition_dot(sc + 4, 1);  // and beta
         if (prec == NNMG_FP64)
-            launch_cg_direction(n, H.z.ptr, H.p.ptr, sc, s, nr);
+            launch_cg_direction(n, H.z.ptr, H.p.ptr, x, sc, s, nr);
         else
-            launch_cg_direction32(n, z32(), H.p.ptr, sc, s, nr);
+            launch_cg_direction32(n, z32(), H.p.ptr, x, sc, s, nr);
         ++it;
         iteration_body();
         return false;
@@ -767,6 +776,7 @@ int pcg(Hierarchy& H, const double* b, double* x, const nnmg_cg_opts& o, nnmg_cg
     do {
         NNMG_HIP(hipEventSynchronize(t.ev));
     } while (!t.step());
+    NNMG_HIP(hipStreamSynchronize(s));  // the final update of x
     return t.overall();
 }
 

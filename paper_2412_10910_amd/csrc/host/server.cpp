@@ -195,7 +195,11 @@ void Server::run() {
             bool fin = false;
             try {
                 fin = pcg_task_step(r->task);
-                if (fin) r->status = pcg_task_status(r->task);
+                if (fin) {
+                    r->status = pcg_task_status(r->task);
+                    // the solve's last launch (the final update of x) ends before its end time
+                    NNMG_HIP(hipStreamSynchronize(streams[(size_t)r->slot]));
+                }
             } catch (const Error& e) {
                 fin = true;
                 r->status = e.code;

@@ -350,11 +350,15 @@ void launch_cast_dot(const double* r, const float* z32, double* z, size_t n, dou
 size_t dot_partials(size_t n);
 // CG kernels; scal layout documented in hierarchy.cpp
 // (n vector DoFs, nr interleaved right-hand sides, scalars of r at scal + r * kScal)
-void launch_cg_update(size_t n, double* x, double* r, const double* p, const double* q, const double* scal,
-                      double* partial, double* rr_out, hipStream_t s, int nr = 1);
-void launch_cg_direction(size_t n, const double* z, double* p, const double* scal, hipStream_t s, int nr = 1);
+// r -= alpha q and r.r into rr_out; the matching x += alpha p is left to the next launch_cg_direction
+void launch_cg_update(size_t n, double* r, const double* q, const double* scal, double* partial, double* rr_out,
+                      hipStream_t s, int nr = 1);
+// x += alpha p (the update cg_update left), then p = z + beta p; z = nullptr: the update of x only
+void launch_cg_direction(size_t n, const double* z, double* p, double* x, const double* scal, hipStream_t s,
+                         int nr = 1);
 // the same with z = (double) z32
-void launch_cg_direction32(size_t n, const float* z32, double* p, const double* scal, hipStream_t s, int nr = 1);
+void launch_cg_direction32(size_t n, const float* z32, double* p, double* x, const double* scal, hipStream_t s,
+                           int nr = 1);
 void launch_jacobi(size_t n, const double* dinv, const double* r, double* z, hipStream_t s);
 void launch_axpy(size_t n, double a_sign, const double* scal_a, int idx, const double* x, double* y,
                  hipStream_t s);

@@ -371,9 +371,10 @@ void launch_dot(const double* a, const double* b, size_t n, double* partial, dou
 
 // CG scalars of right-hand side r at scal + r * kScal:
 // [0] rz, [1] pq, [2] alpha, [3] rr, [4] rz_new, [5] beta, [6] b.b, [7] active (1 or 0)
+// r -= alpha q and the partial sums of r.r; the iterate's update x += alpha p
+// waits for the next direction update (or cg_finish), which reads p anyway
 template <int NR>
-__global__ __launch_bounds__(kRedThreads) void cg_update_stage1(size_t n, double* __restrict__ x,
-                                                                double* __restrict__ r, const double* __restrict__ p,
+__global__ __launch_bounds__(kRedThreads) void cg_update_stage1(size_t n, double* __restrict__ r,
                                                                 const double* __restrict__ q,
                                                                 const double* __restrict__ scal,
                                                                 double* __restrict__ partial) {
@@ -386,12 +387,11 @@ __global__ __launch_bounds__(kRedThreads) void cg_update_stage1(size_t n, double
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
-            // alpha = 0 (frozen or broken down): x and r are left as they are,
-            // even where p or q is not finite
+            // alpha = 0 (frozen or broken down): r is left as it is, even
+            // where q is not finite
             const size_t v = i * NR + k;
             double rn = r[v];
             if (alpha[k] != 0.0) {
-                x[v] += alpha[k] * p[v];
                 rn -= alpha[k] * q[v];
                 r[v] = rn;
             }
@@ -401,41 +401,53 @@ __global__ __launch_bounds__(kRedThreads) void cg_update_stage1(size_t n, double
     block_sums<NR>(s, partial + blockIdx.x * NR, 1);
 }
 
-void launch_cg_update(size_t n, double* x, double* r, const double* p, const double* q, const double* scal,
-                      double* partial, double* rr_out, hipStream_t s, int nr) {
+void launch_cg_update(size_t n, double* r, const double* q, const double* scal, double* partial, double* rr_out,
+                      hipStream_t s, int nr) {
     const size_t g = dot_partials(n);
     NNMG_NR_DISPATCH(nr, {
-        hipLaunchKernelGGL((cg_update_stage1<NR>), dim3((unsigned)g), dim3(kRedThreads), 0, s, n, x, r, p, q, scal,
+        hipLaunchKernelGGL((cg_update_stage1<NR>), dim3((unsigned)g), dim3(kRedThreads), 0, s, n, r, q, scal,
                            partial);
     });
     launch_sum_partials(partial, g, rr_out, s, nr, kScal);
 }
 
-// p = z + beta p; a float32 z (the float32 V-cycle's result) is widened exactly here
+// x += alpha p (the previous iteration's update, alpha = 0 leaving x as it
+// is), then p = z + beta p; a float32 z (the float32 V-cycle's result) is
+// widened exactly here.  z = nullptr: only the update of x (the end of a solve).
 template <int NR, class Z>
 __global__ void cg_direction_kernel(size_t n, const Z* __restrict__ z, double* __restrict__ p,
-                                    const double* __restrict__ scal) {
-    double beta[NR];
+                                    double* __restrict__ x, const double* __restrict__ scal) {
+    double alpha[NR], beta[NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) beta[k] = scal[k * kScal + 5];
+    for (int k = 0; k < NR; ++k) {
+        alpha[k] = scal[k * kScal + 2];
+        beta[k] = scal[k * kScal + 5];
+    }
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) p[i * NR + k] = (double)z[i * NR + k] + beta[k] * p[i * NR + k];
+        for (int k = 0; k < NR; ++k) {
+            const size_t v = i * NR + k;
+            const double pv = p[v];
+            if (alpha[k] != 0.0) x[v] += alpha[k] * pv;
+            if (z) p[v] = (double)z[v] + beta[k] * pv;
+        }
     }
 }
 
-void launch_cg_direction(size_t n, const double* z, double* p, const double* scal, hipStream_t s, int nr) {
+void launch_cg_direction(size_t n, const double* z, double* p, double* x, const double* scal, hipStream_t s,
+                         int nr) {
     if (n == 0) return;
     NNMG_NR_DISPATCH(nr, {
-        hipLaunchKernelGGL((cg_direction_kernel<NR, double>), grid_for(n), dim3(256), 0, s, n, z, p, scal);
+        hipLaunchKernelGGL((cg_direction_kernel<NR, double>), grid_for(n), dim3(256), 0, s, n, z, p, x, scal);
     });
     NNMG_HIP(hipGetLastError());
 }
 
-void launch_cg_direction32(size_t n, const float* z32, double* p, const double* scal, hipStream_t s, int nr) {
+void launch_cg_direction32(size_t n, const float* z32, double* p, double* x, const double* scal, hipStream_t s,
+                           int nr) {
     if (n == 0) return;
     NNMG_NR_DISPATCH(nr, {
-        hipLaunchKernelGGL((cg_direction_kernel<NR, float>), grid_for(n), dim3(256), 0, s, n, z32, p, scal);
+        hipLaunchKernelGGL((cg_direction_kernel<NR, float>), grid_for(n), dim3(256), 0, s, n, z32, p, x, scal);
     });
     NNMG_HIP(hipGetLastError());
 }
